@@ -1,0 +1,387 @@
+/*
+ * oracle.c -- plain, slow, obviously correct CPU reference for the short-range
+ * molecular-dynamics hot path (Lennard-Jones pair forces over a Verlet list,
+ * skin-triggered rebuilds, leapfrog NVE / Nose-Hoover NVT).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the library's product path may include,
+ * link or call this file; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no code, header or table with the
+ * GPU implementation.
+ *
+ * What it computes (all O(N^2), double precision unless stated):
+ *
+ *  - pair sets: the set of ordered pairs (i, j), i != j, whose float32
+ *    squared minimum-image distance is strictly below (r_c,ab + s)^2 rounded once
+ *    to float32.  This is the content of a full (both-direction) Verlet list with
+ *    skin s (paper section 3: neighbours within r_c + s are listed; sections 6 and
+ *    7: strict "<" test against the per-type-pair cut-plus-skin squared; no
+ *    Newton's third law).  The float32 squared distance follows one fixed
+ *    operation sequence (below) built only from correctly rounded IEEE
+ *    operations, so any correct implementation obtains the same bits.
+ *
+ *  - forces / energies / virial: the direct sum over all pairs inside the
+ *    cutoff (a Verlet list with skin is an exact acceleration of this sum, paper
+ *    section 3).  12-6 Lennard-Jones with the three cutoff methods of paper
+ *    section 2 (truncated, shifted potential, shifted force = linear term added).
+ *    Each pair's in/out decision is taken in float32 against r_c,ab^2 rounded to
+ *    float32 (the decision a float32 implementation takes), its value in FP64.
+ *    The potential energy of a particle is half its pair energies (paper, force
+ *    kernel figure: compensation for double counting).
+ *
+ *  - the leapfrog / Nose-Hoover integrator and the displacement criterion that
+ *    triggers a rebuild (paper section 6: rebuild once any particle has moved
+ *    more than half the skin since the last build).
+ *
+ * Float32 squared distance (the specified sequence, per axis k):
+ *      dx   = x_j - x_i                       (float32 subtraction)
+ *      m    = rintf(dx * invL_k)              (float32 product, ties-to-even)
+ *      dx   = fmaf(-m, L_k, dx)
+ *      r2   = fmaf(dz, dz, fmaf(dy, dy, dx * dx))
+ * with L_k the float32 box side and invL_k = (float)(1.0 / (double)L_k).
+ * This file must be compiled with -ffp-contract=off and without fast-math.
+ *
+ * Parity status of every function: pinned (see the test-suite for the pins).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_TRUNC 0
+#define ORACLE_SP 1
+#define ORACLE_SF 2
+
+/* ---- compensated (Neumaier) summation ------------------------------------ */
+typedef struct {
+  double s, c;
+} nsum_t;
+
+static void nsum_add(nsum_t *a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x))
+    a->c += (a->s - t) + x;
+  else
+    a->c += (x - t) + a->s;
+  a->s = t;
+}
+
+static double nsum_value(const nsum_t *a) { return a->s + a->c; }
+
+/* ---- float32 squared distance, the specified sequence -------------------- */
+static float r2_f32(const float *pi, const float *pj, const float *L, const float *invL) {
+  float d[3];
+  for (int k = 0; k < 3; ++k) {
+    float dx = pj[k] - pi[k];
+    float m = rintf(dx * invL[k]);
+    d[k] = fmaf(-m, L[k], dx);
+  }
+  return fmaf(d[2], d[2], fmaf(d[1], d[1], d[0] * d[0]));
+}
+
+static void box_f32(const double *box, float *L, float *invL) {
+  for (int k = 0; k < 3; ++k) {
+    L[k] = (float)box[k];
+    invL[k] = (float)(1.0 / (double)L[k]);
+  }
+}
+
+/* cut-plus-skin squared per type pair, rounded once to float32 */
+void oracle_cut_tables(int ntypes, const double *rc, double skin, float *cs2, float *rc2) {
+  for (int a = 0; a < ntypes * ntypes; ++a) {
+    double rs = rc[a] + skin;
+    cs2[a] = (float)(rs * rs);
+    rc2[a] = (float)(rc[a] * rc[a]);
+  }
+}
+
+/* Neighbours of particle i (ascending j): every j != i with r2_f32 < cs2[t_i][t_j].
+ * Returns the count; writes at most cap indices to out. */
+long long oracle_neighbors_of(int n, const float *pos, const int *type, const double *box, int ntypes,
+                              const float *cs2, int i, int *out, long long cap) {
+  float L[3], invL[3];
+  box_f32(box, L, invL);
+  long long cnt = 0;
+  for (int j = 0; j < n; ++j) {
+    if (j == i) continue;
+    float r2 = r2_f32(pos + 3 * i, pos + 3 * j, L, invL);
+    if (r2 < cs2[type[i] * ntypes + type[j]]) {
+      if (cnt < cap) out[cnt] = j;
+      ++cnt;
+    }
+  }
+  return cnt;
+}
+
+/* Full pair set, lexicographically sorted (i ascending, then j ascending).
+ * pairs has room for 2*cap ints; returns the total count (may exceed cap). */
+long long oracle_pair_set(int n, const float *pos, const int *type, const double *box, int ntypes,
+                          const float *cs2, int *pairs, long long cap) {
+  long long *counts = (long long *)malloc(sizeof(long long) * (size_t)(n + 1));
+  if (!counts) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int i = 0; i < n; ++i) counts[i] = oracle_neighbors_of(n, pos, type, box, ntypes, cs2, i, NULL, 0);
+  long long total = 0;
+  for (int i = 0; i < n; ++i) {
+    long long c = counts[i];
+    counts[i] = total;
+    total += c;
+  }
+  counts[n] = total;
+  if (total <= cap) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < n; ++i) {
+      long long c = counts[i + 1] - counts[i];
+      int *tmp = (int *)malloc(sizeof(int) * (size_t)(c > 0 ? c : 1));
+      oracle_neighbors_of(n, pos, type, box, ntypes, cs2, i, tmp, c);
+      for (long long k = 0; k < c; ++k) {
+        pairs[2 * (counts[i] + k)] = i;
+        pairs[2 * (counts[i] + k) + 1] = tmp[k];
+      }
+      free(tmp);
+    }
+  }
+  free(counts);
+  return total;
+}
+
+/* ---- Lennard-Jones pair function ------------------------------------------ */
+/* U(r) = 4 eps [(sig/r)^12 - (sig/r)^6];  F(r) = -dU/dr = 24 eps [2 (sig/r)^12 - (sig/r)^6] / r */
+static void lj_uf(double r, double sig, double eps, double *u, double *f) {
+  double sr = sig / r;
+  double sr6 = sr * sr * sr * sr * sr * sr;
+  double sr12 = sr6 * sr6;
+  *u = 4.0 * eps * (sr12 - sr6);
+  *f = 24.0 * eps * (2.0 * sr12 - sr6) / r;
+}
+
+/* pair energy and radial force magnitude (positive = repulsive) for a cutoff method */
+void oracle_pair(double r, double sig, double eps, double rc, int method, double *u, double *f) {
+  double ur, fr;
+  lj_uf(r, sig, eps, &ur, &fr);
+  if (method == ORACLE_TRUNC) {
+    *u = ur;
+    *f = fr;
+    return;
+  }
+  double uc, fc;
+  lj_uf(rc, sig, eps, &uc, &fc);
+  if (method == ORACLE_SP) {
+    *u = ur - uc;
+    *f = fr;
+  } else { /* shifted force: U(r) - U(rc) + (r - rc) F(rc);  force F(r) - F(rc) */
+    *u = ur - uc + (r - rc) * fc;
+    *f = fr - fc;
+  }
+}
+
+/* Forces, per-particle energy and per-particle virial on float32 positions.
+ *  sel == NULL: every particle; else the nsel particles listed in sel.
+ *  Outputs (length nsel or n): F[3*k..], pe[k] = 1/2 sum_j u_ij,
+ *  w[k] = 1/2 * 1/3 sum_j (r_i - r_j) . F_ij.   Totals (over the selection):
+ *  totals[0] = sum pe, totals[1] = sum w.  In/out decision: r2_f32 < rc2_f32. */
+void oracle_forces_f32(int n, const float *pos, const int *type, const double *box, int ntypes,
+                       const double *sigma, const double *eps, const double *rc, int method, int nsel,
+                       const int *sel, double *F, double *pe, double *w, double *totals) {
+  float L32[3], invL[3];
+  box_f32(box, L32, invL);
+  double L[3] = {(double)L32[0], (double)L32[1], (double)L32[2]};
+  float *rc2 = (float *)malloc(sizeof(float) * (size_t)(ntypes * ntypes));
+  for (int a = 0; a < ntypes * ntypes; ++a) rc2[a] = (float)(rc[a] * rc[a]);
+  int cnt = sel ? nsel : n;
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int k = 0; k < cnt; ++k) {
+    int i = sel ? sel[k] : k;
+    nsum_t fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, su = {0, 0}, sw = {0, 0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      int ab = type[i] * ntypes + type[j];
+      if (!(r2_f32(pos + 3 * i, pos + 3 * j, L32, invL) < rc2[ab])) continue;
+      double d[3];
+      for (int c = 0; c < 3; ++c) {
+        d[c] = (double)pos[3 * i + c] - (double)pos[3 * j + c]; /* r_i - r_j */
+        d[c] -= L[c] * rint(d[c] / L[c]);
+      }
+      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      double u, f;
+      oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      nsum_add(&fx, f * d[0] / r);
+      nsum_add(&fy, f * d[1] / r);
+      nsum_add(&fz, f * d[2] / r);
+      nsum_add(&su, 0.5 * u);
+      nsum_add(&sw, 0.5 * r * f / 3.0);
+    }
+    F[3 * k] = nsum_value(&fx);
+    F[3 * k + 1] = nsum_value(&fy);
+    F[3 * k + 2] = nsum_value(&fz);
+    pe[k] = nsum_value(&su);
+    w[k] = nsum_value(&sw);
+  }
+  nsum_t tu = {0, 0}, tw = {0, 0};
+  for (int k = 0; k < cnt; ++k) {
+    nsum_add(&tu, pe[k]);
+    nsum_add(&tw, w[k]);
+  }
+  totals[0] = nsum_value(&tu);
+  totals[1] = nsum_value(&tw);
+  free(rc2);
+}
+
+/* Forces on double-precision positions, in/out decision r^2 < rc^2 in FP64.
+ * Used by the reference integrator. */
+void oracle_forces_f64(int n, const double *pos, const int *type, const double *box, int ntypes,
+                       const double *sigma, const double *eps, const double *rc, int method, double *F,
+                       double *pe, double *w, double *totals) {
+#pragma omp parallel for schedule(dynamic, 8)
+  for (int i = 0; i < n; ++i) {
+    nsum_t fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, su = {0, 0}, sw = {0, 0};
+    for (int j = 0; j < n; ++j) {
+      if (j == i) continue;
+      int ab = type[i] * ntypes + type[j];
+      double d[3];
+      for (int c = 0; c < 3; ++c) {
+        d[c] = pos[3 * i + c] - pos[3 * j + c];
+        d[c] -= box[c] * rint(d[c] / box[c]);
+      }
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (!(r2 < rc[ab] * rc[ab])) continue;
+      double r = sqrt(r2);
+      double u, f;
+      oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      nsum_add(&fx, f * d[0] / r);
+      nsum_add(&fy, f * d[1] / r);
+      nsum_add(&fz, f * d[2] / r);
+      nsum_add(&su, 0.5 * u);
+      nsum_add(&sw, 0.5 * r * f / 3.0);
+    }
+    F[3 * i] = nsum_value(&fx);
+    F[3 * i + 1] = nsum_value(&fy);
+    F[3 * i + 2] = nsum_value(&fz);
+    pe[i] = nsum_value(&su);
+    w[i] = nsum_value(&sw);
+  }
+  nsum_t tu = {0, 0}, tw = {0, 0};
+  for (int i = 0; i < n; ++i) {
+    nsum_add(&tu, pe[i]);
+    nsum_add(&tw, w[i]);
+  }
+  totals[0] = nsum_value(&tu);
+  totals[1] = nsum_value(&tw);
+}
+
+/* Kinetic energy 1/2 sum m v^2 (compensated). */
+double oracle_kinetic(int n, const double *vel, const int *type, const double *mass) {
+  nsum_t s = {0, 0};
+  for (int i = 0; i < n; ++i) {
+    double m = mass[type[i]];
+    nsum_add(&s, 0.5 * m * (vel[3 * i] * vel[3 * i] + vel[3 * i + 1] * vel[3 * i + 1] + vel[3 * i + 2] * vel[3 * i + 2]));
+  }
+  return nsum_value(&s);
+}
+
+/* Largest squared minimum-image displacement since the last build, in FP64 from
+ * float32 positions: d = (double)x - (double)x0, d -= L rint(d / L),
+ * d2 = (dx*dx + dy*dy) + dz*dz.  The rebuild fires when this exceeds (s/2)^2. */
+double oracle_max_disp2(int n, const float *pos, const float *pos0, const double *box) {
+  float L32[3], invL[3];
+  box_f32(box, L32, invL);
+  double best = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double d[3];
+    for (int c = 0; c < 3; ++c) {
+      double L = (double)L32[c];
+      d[c] = (double)pos[3 * i + c] - (double)pos0[3 * i + c];
+      d[c] -= L * rint(d[c] / L);
+    }
+    double d2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+    if (d2 > best) best = d2;
+  }
+  return best;
+}
+
+int oracle_rebuild_needed(int n, const float *pos, const float *pos0, const double *box, double skin) {
+  double h = 0.5 * skin;
+  return oracle_max_disp2(n, pos, pos0, box) > h * h;
+}
+
+/*
+ * Leapfrog with a Nose-Hoover thermostat, FP64 state.  With thermostat == 0 the
+ * friction xi stays zero and the scheme is plain leapfrog (NVE).
+ *   v^{n+1/2} = [ v^{n-1/2} (1 - xi^n dt/2) + (F^n / m) dt ] / (1 + xi^n dt/2)
+ *   r^{n+1}   = r^n + v^{n+1/2} dt            (then wrapped into [-L/2, L/2))
+ *   T^{n+1/2} = 2 KE(v^{n+1/2}) / g,          g = 3N - 3
+ *   xi^{n+1}  = xi^n + dt (T^{n+1/2} / T0 - 1) / tau^2
+ *   I^{n+1}   = I^n + dt (xi^n + xi^{n+1}) / 2   (integral of xi)
+ * Thermo of step n (row n of thermo, 9 doubles):
+ *   PE(r^n), KE(v^n) with v^n = (v^{n-1/2} + v^{n+1/2}) / 2, W(r^n), T^n = 2 KE / g,
+ *   P^n = (2 KE / 3 + W) / V, xi^n, I^n, H^n = KE + PE + g T0 (tau^2 xi^2 / 2 + I), KE(v^{n+1/2}).
+ * inv_tau2 = 1/tau^2 (0 means no coupling).  image counts crossings of the box.
+ */
+int oracle_integrate(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
+                     const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
+                     int method, double dt, int thermostat, double T0, double inv_tau2, double *xi,
+                     double *xi_int, int nsteps, double *thermo) {
+  double *F = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+  double *pe = (double *)malloc(sizeof(double) * (size_t)n);
+  double *w = (double *)malloc(sizeof(double) * (size_t)n);
+  double *vnew = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+  double *vmid = (double *)malloc(sizeof(double) * 3 * (size_t)n);
+  if (!F || !pe || !w || !vnew || !vmid) return -1;
+  double g = 3.0 * n - 3.0;
+  double V = box[0] * box[1] * box[2];
+  for (int step = 0; step < nsteps; ++step) {
+    double tot[2];
+    oracle_forces_f64(n, pos, type, box, ntypes, sigma, eps, rc, method, F, pe, w, tot);
+    double x = thermostat ? *xi : 0.0;
+    double a = 1.0 - x * dt / 2.0, b = 1.0 + x * dt / 2.0;
+    for (int i = 0; i < n; ++i) {
+      double m = mass[type[i]];
+      for (int c = 0; c < 3; ++c) {
+        vnew[3 * i + c] = (vel[3 * i + c] * a + F[3 * i + c] / m * dt) / b;
+        vmid[3 * i + c] = 0.5 * (vel[3 * i + c] + vnew[3 * i + c]);
+      }
+    }
+    double ke_half = oracle_kinetic(n, vnew, type, mass);
+    double ke_int = oracle_kinetic(n, vmid, type, mass);
+    if (thermo) {
+      double *row = thermo + 9 * (size_t)step;
+      double T = 2.0 * ke_int / g;
+      row[0] = tot[0];
+      row[1] = ke_int;
+      row[2] = tot[1];
+      row[3] = T;
+      row[4] = (2.0 * ke_int / 3.0 + tot[1]) / V;
+      row[5] = x;
+      row[6] = *xi_int;
+      row[7] = ke_int + tot[0];
+      if (thermostat && inv_tau2 > 0.0) row[7] += g * T0 * (x * x / (2.0 * inv_tau2) + *xi_int);
+      row[8] = ke_half;
+    }
+    for (int i = 0; i < n; ++i) {
+      for (int c = 0; c < 3; ++c) {
+        vel[3 * i + c] = vnew[3 * i + c];
+        double p = pos[3 * i + c] + vnew[3 * i + c] * dt;
+        double h = box[c] / 2.0;
+        if (p >= h) {
+          p -= box[c];
+          image[3 * i + c] += 1;
+        } else if (p < -h) {
+          p += box[c];
+          image[3 * i + c] -= 1;
+        }
+        pos[3 * i + c] = p;
+      }
+    }
+    if (thermostat) {
+      double Th = 2.0 * ke_half / g;
+      double xn = x + dt * (Th / T0 - 1.0) * inv_tau2;
+      *xi_int += dt * (x + xn) / 2.0;
+      *xi = xn;
+    }
+  }
+  free(F);
+  free(pe);
+  free(w);
+  free(vnew);
+  free(vmid);
+  return 0;
+}
