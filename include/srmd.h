@@ -1,0 +1,183 @@
+/*
+ * srmd.h -- C-ABI of libsrmd, a short-range molecular-dynamics library for one
+ * AMD MI355X (gfx950) GPU.
+ *
+ * The library implements the data-parallel hot path of the method of
+ * Bailey et al., "RUMD: A general purpose molecular dynamics package optimized to
+ * utilize GPU hardware down to a few thousand particles" (arXiv:1506.05094):
+ * Lennard-Jones pair forces over a Verlet neighbour list (paper section 5, force
+ * kernel figure), the list built from cells after a spatial sort of all particle
+ * data (section 7, cell-list figure), rebuilt on the device once any particle
+ * has moved more than half the skin (section 6), and a leapfrog NVE or
+ * Nose-Hoover NVT integrator (section 2, integrators).  The verbs follow the
+ * paper's Python example (section 2 figure: create a simulation from a
+ * configuration, set a pair potential with a cutoff method and parameters,
+ * set an integrator, run n steps).
+ *
+ * Conventions for every call:
+ *  - Host arrays are caller-owned; they are read or written during the call only.
+ *  - Device memory is library-owned; it is obtained through the allocator hook
+ *    (srmd_set_allocator) or hipMalloc when no hook is installed.
+ *  - Every call returns an srmd_status.  Nothing aborts or throws across the ABI.
+ *    After a failure, srmd_last_error(s) (or srmd_last_error(NULL) for failures
+ *    without a system) returns a message.
+ *  - Per-particle arrays passed in or out are in the caller's ORIGINAL particle
+ *    order (index = particle id), even though the library reorders particles
+ *    spatially on the device at every list rebuild.
+ *  - Positions live in the periodic box [-L/2, L/2) per axis.  Box sides are
+ *    stored as float32; the float32 value of each side is the box the library
+ *    simulates (srmd_get_box returns it).
+ *  - A system is used from one host thread at a time.  Work is enqueued on the
+ *    system's HIP stream; calls that return results synchronise that stream.
+ */
+#ifndef SRMD_H
+#define SRMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct srmd_system srmd_system; /* opaque, library-owned */
+typedef struct srmd_batch srmd_batch;   /* opaque, library-owned */
+
+typedef enum {
+  SRMD_OK = 0,
+  SRMD_EINVAL = -1,      /* invalid argument or call order */
+  SRMD_ENOMEM = -2,      /* device or host allocation failed */
+  SRMD_EHIP = -3,        /* a HIP runtime call failed */
+  SRMD_ESTATE = -4,      /* non-finite state detected on the device */
+  SRMD_EUNSUPPORTED = -5 /* valid request this build does not support */
+} srmd_status;
+
+/* Cutoff methods of paper section 2 ("cutoff methods"): plain truncation,
+ * truncation with the potential shifted to zero at r_c, truncation with the force
+ * shifted to zero at r_c (a linear term added to the potential). */
+typedef enum { SRMD_CUT_TRUNC = 0, SRMD_CUT_SP = 1, SRMD_CUT_SF = 2 } srmd_cutoff;
+
+/* Position precision.  F32: float32 positions.  F32_KAHAN: float32 positions with
+ * a compensated (Kahan) position update.  F64POS: float64 master positions updated
+ * in float64, with a float32 copy used by the list build and the force kernel.
+ * Pair forces are float32 in every variant; energy, virial, kinetic-energy and
+ * displacement reductions are float64 in every variant. */
+typedef enum { SRMD_PREC_F32 = 0, SRMD_PREC_F32_KAHAN = 1, SRMD_PREC_F64POS = 2 } srmd_precision;
+
+/* Thermodynamic record of one integer time step n (all float64):
+ *  pe          potential energy: half the sum of pair energies (paper, force
+ *              kernel figure: compensation for double counting);
+ *  ke          kinetic energy of v(n) = (v(n-1/2) + v(n+1/2)) / 2;
+ *  virial      W = 1/3 sum over pairs of r_ij . F_ij;
+ *  temperature 2 ke / (3N - 3)   (k_B = 1);
+ *  pressure    (2 ke / 3 + W) / V;
+ *  xi, xi_integral  Nose-Hoover friction and its time integral at step n;
+ *  h_conserved ke + pe (+ g T0 (tau^2 xi^2 / 2 + xi_integral) under Nose-Hoover);
+ *  ke_half     kinetic energy of v(n+1/2);
+ *  step        step index n; n_rebuilds: list builds so far; max_nbrs: longest list. */
+typedef struct {
+  double pe, ke, virial, temperature, pressure, xi, xi_integral, h_conserved, ke_half;
+  int64_t step, n_rebuilds;
+  int32_t max_nbrs, reserved;
+} srmd_thermo;
+
+/* Create a system of n >= 2 particles of ntypes types (1..4) in an orthorhombic
+ * periodic box.  pos: host float32 n*3 (x,y,z per particle), wrapped into
+ * [-L/2, L/2) on entry.  type: host int32 n, each in [0, ntypes).  vel: host float32
+ * n*3 read as v(-dt/2), or NULL for zero.  mass: host float64 per type, or NULL for
+ * unit masses.  hip_stream: a hipStream_t to enqueue on, or NULL for a stream the
+ * library creates.  Fails with SRMD_EINVAL on non-finite input, a type out of
+ * range or a non-positive box side.  *out receives the new system. */
+srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const double box[3], const float *pos,
+                        const int32_t *type, const float *vel, const double *mass, srmd_precision prec,
+                        void *hip_stream);
+
+/* Release every device and host resource of s (NULL is a no-op). */
+srmd_status srmd_destroy(srmd_system *s);
+
+/* Install a device allocator used for every later device allocation (NULL alloc
+ * restores hipMalloc/hipFree).  alloc(bytes, ctx) returns device memory or NULL;
+ * free(ptr, ctx) releases it.  Buffers keep the allocator they were made with. */
+srmd_status srmd_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*free_fn)(void *ptr, void *ctx),
+                               void *ctx);
+
+/* 12-6 Lennard-Jones between types ti and tj (symmetric): U(r) = 4 eps [(sigma/r)^12
+ * - (sigma/r)^6] for r < rcut (absolute distance), modified by the cutoff method
+ * (paper section 2).  All type pairs of a system share one method; a call with a
+ * different method than earlier calls fails with SRMD_EINVAL.  rcut + skin must
+ * stay below half of every box side. */
+srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigma, double epsilon, double rcut,
+                             srmd_cutoff method);
+
+/* Neighbour-list skin s >= 0: pairs within r_c,ab + s are listed (paper section 3),
+ * and the list is rebuilt once any particle has moved more than s/2 since the last
+ * build (section 6).  Default 0.3. */
+srmd_status srmd_set_skin(srmd_system *s, double skin);
+
+/* Leapfrog NVE with time step dt > 0. */
+srmd_status srmd_set_integrator_nve(srmd_system *s, double dt);
+
+/* Nose-Hoover NVT leapfrog: time step dt > 0, target temperature T0 > 0,
+ * thermostat relaxation time tau > 0 (mass Q = g T0 tau^2, g = 3N - 3). */
+srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double tau);
+
+/* Thread layout of the force kernel (paper section 3 table of code conventions):
+ * tp threads per particle (power of two, 1..64) and ppb particles per block,
+ * tp*ppb <= 1024 and a multiple of 64.  (0, 0) selects the built-in default for the
+ * system size or the value found by srmd_autotune. */
+srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
+
+/* Read back the thread layout in use (after defaults are resolved). */
+srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb);
+
+/* Choose tp and ppb by timing short runs from a saved copy of the current state
+ * (paper appendix: each trial starts from the same stored configuration).  The
+ * state is restored afterwards.  Any output pointer may be NULL. */
+srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out);
+
+/* Bin, sort and rebuild the neighbour list now, whatever the displacement. */
+srmd_status srmd_build_neighbor_list(srmd_system *s);
+
+/* Forces, potential energy and virial at the current positions (no time step).
+ * The list is rebuilt first if the displacement criterion or a parameter change
+ * asks for it.  out (nullable) receives pe and virial; its other fields describe
+ * the current velocities. */
+srmd_status srmd_compute_forces(srmd_system *s, srmd_thermo *out);
+
+/* Advance nsteps time steps.  If thermo_every > 0, the record of every step n with
+ * n % thermo_every == 0 is written to trace (caller-owned, trace_cap entries; extra
+ * records are dropped).  Synchronises once at the end.  Returns SRMD_ESTATE if a
+ * non-finite force or position appeared. */
+srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
+                      int64_t trace_cap);
+
+/* Copy the state to host arrays in original particle order; each pointer may be NULL.
+ * pos, vel, force: float32 n*3; image: int32 n*3 (box crossings); pos64: float64 n*3
+ * (the float64 master positions in the F64POS variant, else the float32 positions
+ * widened). force holds the forces of the last force evaluation. */
+srmd_status srmd_get_state(srmd_system *s, float *pos, float *vel, int32_t *image, float *force, double *pos64);
+
+/* Overwrite positions and/or velocities (original order, float32 n*3, either NULL to
+ * keep), image counters are reset when pos is given.  Forces a rebuild. */
+srmd_status srmd_set_state(srmd_system *s, const float *pos, const float *vel);
+
+/* The neighbour list as (id_i, id_j) pairs in original ids, lexicographically sorted.
+ * pairs holds 2*cap int32; *count receives the total number of pairs (the call fails
+ * with SRMD_EINVAL, writing nothing, when cap is too small). */
+srmd_status srmd_get_neighbor_pairs(srmd_system *s, int32_t *pairs, int64_t cap, int64_t *count);
+
+/* The most recent thermodynamic record (of the last step taken, or of the last
+ * srmd_compute_forces call). */
+srmd_status srmd_get_thermo(srmd_system *s, srmd_thermo *out);
+
+/* The float32 box sides in use (written as float64). */
+srmd_status srmd_get_box(const srmd_system *s, double box[3]);
+
+/* Message of the last failure on s (or of the calling thread when s is NULL). */
+const char *srmd_last_error(const srmd_system *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SRMD_H */

@@ -1,0 +1,915 @@
+// Host runtime and C-ABI of libsrmd: device state, parameter tables, the cell
+// grid and list capacity, the graph-captured step chunks, list-overflow recovery
+// and the original-order views of the state.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/srmd.h"
+#include "srmd_internal.h"
+
+namespace srmd {
+hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hipStream_t st, const SysConst &c,
+                       const SysPtrs &p, int cur);
+hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
+                        const SysPtrs &p, int cur);
+hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
+}  // namespace srmd
+
+using namespace srmd;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+struct Allocator {
+  void *(*alloc)(size_t, void *) = nullptr;
+  void (*free_fn)(void *, void *) = nullptr;
+  void *ctx = nullptr;
+};
+Allocator g_alloc;  // process-wide hook
+
+struct DevBuf {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  Allocator how;
+};
+
+constexpr int kChunk = 64;  // steps per captured graph (even: the position buffers alternate)
+
+}  // namespace
+
+struct srmd_system {
+  int n = 0, ntypes = 0;
+  srmd_precision prec = SRMD_PREC_F32;
+  float Lf[3] = {0, 0, 0};
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double mass[kMaxTypes] = {1, 1, 1, 1};
+  // potential
+  double sigma[kMaxPairs] = {}, eps[kMaxPairs] = {}, rc[kMaxPairs] = {};
+  bool pair_given[kMaxPairs] = {};
+  int method = -1;
+  double skin = 0.3;
+  // integrator
+  bool integrator_set = false;
+  int thermostat = 0;
+  double dt = 0.0, T0 = 0.0, tau = 0.0;
+  // launch shape
+  int tp_req = 0, ppb_req = 0, tp = 0, ppb = 0;
+  int tp_tuned = 0, ppb_tuned = 0;
+  // derived layout
+  bool dirty = true;  // SysConst must be rebuilt
+  SysConst c{};
+  SysPtrs p{};
+  int cur = 0;
+  int n_max = 0, nvp = 0, ncell_alloc = 0;
+  long long nbl_alloc = 0;
+  long long trace_alloc = 0;
+  int part_alloc = 0;
+  std::vector<DevBuf> bufs;
+  // snapshot for list-overflow replay
+  float4 *snap_pos = nullptr, *snap_vel = nullptr, *snap_last = nullptr, *snap_kahan = nullptr;
+  int4 *snap_img = nullptr;
+  double *snap_pos64 = nullptr;
+  Control *snap_ctl = nullptr;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  std::string err;
+};
+
+namespace {
+
+srmd_status fail(srmd_system *s, srmd_status st, const std::string &msg) {
+  if (s)
+    s->err = msg;
+  else
+    g_thread_error = msg;
+  return st;
+}
+
+#define HIPCHK(s, call)                                                                               \
+  do {                                                                                                \
+    hipError_t e_ = (call);                                                                           \
+    if (e_ != hipSuccess)                                                                             \
+      return fail((s), SRMD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));                 \
+  } while (0)
+
+void *dev_alloc(srmd_system *s, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  DevBuf b;
+  b.bytes = bytes;
+  b.how = g_alloc;
+  if (g_alloc.alloc) {
+    b.ptr = g_alloc.alloc(bytes, g_alloc.ctx);
+  } else {
+    if (hipMalloc(&b.ptr, bytes) != hipSuccess) b.ptr = nullptr;
+  }
+  if (!b.ptr) return nullptr;
+  s->bufs.push_back(b);
+  return b.ptr;
+}
+
+void dev_free(srmd_system *s, void *ptr) {
+  if (!ptr) return;
+  for (size_t k = 0; k < s->bufs.size(); ++k) {
+    if (s->bufs[k].ptr == ptr) {
+      const DevBuf b = s->bufs[k];
+      if (b.how.free_fn)
+        b.how.free_fn(b.ptr, b.how.ctx);
+      else if (!b.how.alloc)
+        (void)hipFree(b.ptr);
+      s->bufs.erase(s->bufs.begin() + (long)k);
+      return;
+    }
+  }
+}
+
+void drop_graphs(srmd_system *s) {
+  for (auto &kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+}
+
+int pair_index(const srmd_system *s, int a, int b) { return a * s->ntypes + b; }
+
+double lj_u(double r, double sig, double eps) {
+  const double sr = sig / r;
+  const double sr6 = sr * sr * sr * sr * sr * sr;
+  return 4.0 * eps * (sr6 * sr6 - sr6);
+}
+
+double lj_f(double r, double sig, double eps) {
+  const double sr = sig / r;
+  const double sr6 = sr * sr * sr * sr * sr * sr;
+  return 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r;
+}
+
+double rc_max(const srmd_system *s) {
+  double m = 0.0;
+  for (int a = 0; a < s->ntypes * s->ntypes; ++a)
+    if (s->pair_given[a]) m = std::max(m, s->rc[a]);
+  return m;
+}
+
+bool all_pairs_given(const srmd_system *s) {
+  for (int a = 0; a < s->ntypes * s->ntypes; ++a)
+    if (!s->pair_given[a]) return false;
+  return true;
+}
+
+int pow2_at_least(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Default threads per particle: enough lanes in flight for the chip (about 32k),
+// the MI355X version of the paper's rule that N * t_p should exceed the core count
+// several times over (section 8, autotuner choices).
+void launch_of(const srmd_system *s, int *tp_out, int *ppb_out) {
+  int tp = s->tp_req, ppb = s->ppb_req;
+  if (tp == 0) {
+    if (s->tp_tuned) {
+      tp = s->tp_tuned;
+      ppb = s->ppb_tuned;
+    } else {
+      tp = std::min(32, pow2_at_least(std::max(1, 32768 / std::max(1, s->n))));
+      ppb = 0;
+    }
+  }
+  if (ppb == 0) ppb = std::max(1, 256 / tp);
+  *tp_out = tp;
+  *ppb_out = ppb;
+}
+
+void resolve_launch(srmd_system *s) { launch_of(s, &s->tp, &s->ppb); }
+
+srmd_status h2d_sync(srmd_system *s, void *dst, const void *src, size_t bytes) {
+  HIPCHK(s, hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
+}
+
+srmd_status set_ctl_int(srmd_system *s, size_t offset, int value) {
+  return h2d_sync(s, reinterpret_cast<char *>(s->p.ctl) + offset, &value, sizeof(int));
+}
+
+srmd_status request_rebuild(srmd_system *s) { return set_ctl_int(s, offsetof(Control, rebuild), 1); }
+
+// Rebuild the kernel constants, the cell grid and the list storage after any change
+// of parameters or launch shape.
+srmd_status prepare(srmd_system *s) {
+  if (s->method < 0 || !all_pairs_given(s))
+    return fail(s, SRMD_EINVAL, "pair potential not set for every type pair (srmd_set_pair_lj)");
+  if (!s->dirty) return SRMD_OK;
+  resolve_launch(s);
+  SysConst &c = s->c;
+  std::memset(&c, 0, sizeof(c));
+  c.n = s->n;
+  c.ntypes = s->ntypes;
+  const double rcm = rc_max(s);
+  const double reach = rcm + s->skin;
+  double V = 1.0;
+  for (int k = 0; k < 3; ++k) {
+    c.L[k] = s->Lf[k];
+    c.invL[k] = (float)(1.0 / (double)s->Lf[k]);
+    c.halfL[k] = 0.5f * s->Lf[k];
+    c.Ld[k] = (double)s->Lf[k];
+    V *= c.Ld[k];
+    if (!(reach < 0.5 * c.Ld[k]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+    // cells of side at least (r_c + s)/2 (paper section 7), with a relative margin
+    // of 1e-5 so that float32 rounding of the cell coordinate never moves a listed
+    // neighbour outside the +-2 stencil
+    const double cmin = 0.5 * reach * (1.0 + 1e-5);
+    int nc = (int)std::floor(c.Ld[k] / cmin);
+    nc = std::max(1, std::min(nc, 1 << 10));
+    c.nc[k] = nc;
+    c.cscale[k] = (float)((double)nc / c.Ld[k]);
+    if (nc < 5) c.full_axis |= 1 << k;
+  }
+  c.ncell = c.nc[0] * c.nc[1] * c.nc[2];
+  c.volume = V;
+  // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
+  const double rho = s->n / V;
+  int nmax = (int)std::ceil(1.5 * 4.0 / 3.0 * M_PI * reach * reach * reach * rho + 32.0);
+  nmax = (nmax + 63) / 64 * 64;     // a multiple of every tp, so the list layout tiles exactly
+  nmax = std::max(nmax, s->n_max);  // never shrink after an overflow regrow
+  nmax = std::min(nmax, (s->n + 63) / 64 * 64);
+  s->n_max = nmax;
+  c.n_max = nmax;
+  c.nvp = (s->n + 63) / 64 * 64;
+  c.tp = s->tp;
+  c.dt = (float)s->dt;
+  c.dtd = s->dt;
+  c.T0 = s->T0;
+  c.thermostat = s->thermostat;
+  c.inv_tau2 = (s->thermostat && s->tau > 0 && std::isfinite(s->tau)) ? 1.0 / (s->tau * s->tau) : 0.0;
+  const double hs = 0.5 * s->skin;
+  c.half_skin2 = hs * hs;
+  c.g = 3.0 * s->n - 3.0;
+  for (int t = 0; t < kMaxTypes; ++t) {
+    c.mass[t] = s->mass[t];
+    c.inv_mass[t] = (float)(1.0 / s->mass[t]);
+  }
+  for (int a = 0; a < s->ntypes * s->ntypes; ++a) {
+    const double rs = s->rc[a] + s->skin;
+    c.pt.cs2[a] = (float)(rs * rs);
+    c.pt.rc2[a] = (float)(s->rc[a] * s->rc[a]);
+    c.pt.sig2[a] = (float)(s->sigma[a] * s->sigma[a]);
+    c.pt.eps4[a] = (float)(4.0 * s->eps[a]);
+    c.pt.eps24[a] = (float)(24.0 * s->eps[a]);
+    c.pt.rc[a] = (float)s->rc[a];
+    c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)lj_u(s->rc[a], s->sigma[a], s->eps[a]);
+    c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)lj_f(s->rc[a], s->sigma[a], s->eps[a]) : 0.0f;
+  }
+  // storage that depends on the layout
+  const long long need_nbl = (long long)nmax * c.nvp;
+  if (need_nbl > s->nbl_alloc) {
+    dev_free(s, s->p.nbl);
+    s->p.nbl = (int *)dev_alloc(s, sizeof(int) * (size_t)need_nbl);
+    if (!s->p.nbl) return fail(s, SRMD_ENOMEM, "neighbour list allocation failed");
+    s->nbl_alloc = need_nbl;
+  }
+  if (c.ncell + 1 > s->ncell_alloc) {
+    dev_free(s, s->p.cell_count);
+    dev_free(s, s->p.cell_start);
+    s->p.cell_count = (unsigned *)dev_alloc(s, sizeof(unsigned) * (size_t)(c.ncell + 1));
+    s->p.cell_start = (unsigned *)dev_alloc(s, sizeof(unsigned) * (size_t)(c.ncell + 1));
+    if (!s->p.cell_count || !s->p.cell_start) return fail(s, SRMD_ENOMEM, "cell arrays allocation failed");
+    HIPCHK(s, hipMemsetAsync(s->p.cell_count, 0, sizeof(unsigned) * (size_t)(c.ncell + 1), s->stream));
+    s->ncell_alloc = c.ncell + 1;
+  }
+  const int threads = s->tp * s->ppb;
+  const int blocks = (int)(((long long)s->n * s->tp + threads - 1) / threads);
+  if (blocks > s->part_alloc) {
+    dev_free(s, s->p.part);
+    s->p.part = (BlockPartial *)dev_alloc(s, sizeof(BlockPartial) * (size_t)blocks);
+    if (!s->p.part) return fail(s, SRMD_ENOMEM, "partials allocation failed");
+    s->part_alloc = blocks;
+  }
+  drop_graphs(s);
+  s->dirty = false;
+  return request_rebuild(s);
+}
+
+int step_blocks(const srmd_system *s) { return (int)(((long long)s->n * s->tp + s->tp * s->ppb - 1) / (s->tp * s->ppb)); }
+
+srmd_status enqueue_steps(srmd_system *s, int count, int cur) {
+  for (int k = 0; k < count; ++k) {
+    const int cb = (cur + k) & 1;
+    HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, cb));
+    HIPCHK(s, launch_step(s->tp, s->method, (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb));
+  }
+  return SRMD_OK;
+}
+
+srmd_status get_graph(srmd_system *s, int count, int cur, hipGraphExec_t *out) {
+  auto key = std::make_pair(count, cur);
+  auto it = s->graphs.find(key);
+  if (it != s->graphs.end()) {
+    *out = it->second;
+    return SRMD_OK;
+  }
+  hipGraph_t g;
+  HIPCHK(s, hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+  srmd_status st = enqueue_steps(s, count, cur);
+  hipGraph_t g2 = nullptr;
+  hipError_t e = hipStreamEndCapture(s->stream, &g2);
+  if (st != SRMD_OK) {
+    if (g2) (void)hipGraphDestroy(g2);
+    return st;
+  }
+  if (e != hipSuccess) return fail(s, SRMD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  g = g2;
+  hipGraphExec_t ge;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(s, SRMD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  s->graphs[key] = ge;
+  *out = ge;
+  return SRMD_OK;
+}
+
+srmd_status alloc_snapshot(srmd_system *s) {
+  if (s->snap_pos) return SRMD_OK;
+  const size_t n = (size_t)s->n;
+  s->snap_pos = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  s->snap_vel = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  s->snap_last = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  s->snap_img = (int4 *)dev_alloc(s, sizeof(int4) * n);
+  s->snap_ctl = (Control *)dev_alloc(s, sizeof(Control));
+  if (s->prec == SRMD_PREC_F64POS) s->snap_pos64 = (double *)dev_alloc(s, sizeof(double) * 3 * n);
+  if (s->prec == SRMD_PREC_F32_KAHAN) s->snap_kahan = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  if (!s->snap_pos || !s->snap_vel || !s->snap_last || !s->snap_img || !s->snap_ctl)
+    return fail(s, SRMD_ENOMEM, "snapshot allocation failed");
+  return SRMD_OK;
+}
+
+srmd_status snapshot(srmd_system *s, bool restore) {
+  const size_t n = (size_t)s->n;
+  auto cp = [&](void *a, void *b, size_t bytes) {
+    return restore ? hipMemcpyAsync(a, b, bytes, hipMemcpyDeviceToDevice, s->stream)
+                   : hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, s->stream);
+  };
+  HIPCHK(s, cp(s->p.pos[s->cur], s->snap_pos, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.vel, s->snap_vel, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.last, s->snap_last, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.img, s->snap_img, sizeof(int4) * n));
+  HIPCHK(s, cp(s->p.ctl, s->snap_ctl, sizeof(Control)));
+  if (s->p.pos64) HIPCHK(s, cp(s->p.pos64, s->snap_pos64, sizeof(double) * 3 * n));
+  if (s->p.kahan) HIPCHK(s, cp(s->p.kahan, s->snap_kahan, sizeof(float4) * n));
+  return SRMD_OK;
+}
+
+srmd_status read_ctl(srmd_system *s, Control *h) {
+  HIPCHK(s, hipMemcpyAsync(h, s->p.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
+}
+
+// Double the list capacity after an overflow (paper section 3: re-allocation with
+// doubled capacity) and mark the layout for rebuild.
+srmd_status regrow(srmd_system *s) {
+  s->n_max = std::min(2 * s->n_max, (s->n + 63) / 64 * 64);
+  s->dirty = true;
+  return prepare(s);
+}
+
+srmd_status run_steps(srmd_system *s, long long nsteps) {
+  long long left = nsteps;
+  while (left > 0) {
+    const int cnt = (int)std::min<long long>(left, kChunk);
+    hipGraphExec_t ge;
+    srmd_status st = get_graph(s, cnt, s->cur, &ge);
+    if (st != SRMD_OK) return st;
+    HIPCHK(s, hipGraphLaunch(ge, s->stream));
+    s->cur ^= (cnt & 1);
+    left -= cnt;
+  }
+  return SRMD_OK;
+}
+
+void to_public(const Thermo &t, srmd_thermo *o) {
+  o->pe = t.pe;
+  o->ke = t.ke;
+  o->virial = t.virial;
+  o->temperature = t.temperature;
+  o->pressure = t.pressure;
+  o->xi = t.xi;
+  o->xi_integral = t.xi_integral;
+  o->h_conserved = t.h_conserved;
+  o->ke_half = t.ke_half;
+  o->step = t.step;
+  o->n_rebuilds = t.n_rebuilds;
+  o->max_nbrs = t.max_nbrs;
+  o->reserved = 0;
+}
+
+float wrap_f32(double x, double L) {
+  double y = x - L * std::floor(x / L + 0.5);
+  float f = (float)y;
+  const float h = 0.5f * (float)L;
+  if (f >= h) f -= (float)L;
+  if (f < -h) f += (float)L;
+  return f;
+}
+
+// Upload positions / velocities given in original order; ids become the identity.
+srmd_status upload_state(srmd_system *s, const float *pos, const float *vel, const int32_t *type) {
+  const int n = s->n;
+  std::vector<float4> hp((size_t)n), hv((size_t)n);
+  std::vector<int4> hi((size_t)n);
+  std::vector<double> h64;
+  if (s->prec == SRMD_PREC_F64POS) h64.resize(3 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    float x[3];
+    for (int k = 0; k < 3; ++k) x[k] = wrap_f32((double)pos[3 * i + k], (double)s->Lf[k]);
+    int ty = type[i];
+    float w;
+    std::memcpy(&w, &ty, 4);
+    hp[(size_t)i] = make_float4(x[0], x[1], x[2], w);
+    hv[(size_t)i] = vel ? make_float4(vel[3 * i], vel[3 * i + 1], vel[3 * i + 2], 0.f) : make_float4(0.f, 0.f, 0.f, 0.f);
+    hi[(size_t)i] = make_int4(0, 0, 0, i);
+    if (!h64.empty())
+      for (int k = 0; k < 3; ++k) h64[3 * (size_t)i + k] = (double)x[k];
+  }
+  HIPCHK(s, hipMemcpyAsync(s->p.pos[s->cur], hp.data(), sizeof(float4) * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.last, hp.data(), sizeof(float4) * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.vel, hv.data(), sizeof(float4) * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.img, hi.data(), sizeof(int4) * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  if (s->p.pos64)
+    HIPCHK(s, hipMemcpyAsync(s->p.pos64, h64.data(), sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, s->stream));
+  if (s->p.kahan) HIPCHK(s, hipMemsetAsync(s->p.kahan, 0, sizeof(float4) * (size_t)n, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C-ABI
+
+extern "C" {
+
+const char *srmd_last_error(const srmd_system *s) { return s ? s->err.c_str() : g_thread_error.c_str(); }
+
+srmd_status srmd_set_allocator(void *(*alloc)(size_t, void *), void (*free_fn)(void *, void *), void *ctx) {
+  if (alloc && !free_fn) return fail(nullptr, SRMD_EINVAL, "allocator hook needs both alloc and free");
+  g_alloc.alloc = alloc;
+  g_alloc.free_fn = alloc ? free_fn : nullptr;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return SRMD_OK;
+}
+
+srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const double box[3], const float *pos,
+                        const int32_t *type, const float *vel, const double *mass, srmd_precision prec,
+                        void *hip_stream) {
+  if (!out) return fail(nullptr, SRMD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 2) return fail(nullptr, SRMD_EINVAL, "need at least 2 particles");
+  if (ntypes < 1 || ntypes > kMaxTypes) return fail(nullptr, SRMD_EINVAL, "ntypes must be in 1..4");
+  if (!box || !pos || !type) return fail(nullptr, SRMD_EINVAL, "box, pos and type are required");
+  if (prec != SRMD_PREC_F32 && prec != SRMD_PREC_F32_KAHAN && prec != SRMD_PREC_F64POS)
+    return fail(nullptr, SRMD_EINVAL, "unknown precision");
+  for (int k = 0; k < 3; ++k)
+    if (!(box[k] > 0) || !std::isfinite(box[k]) || !std::isfinite((float)box[k]))
+      return fail(nullptr, SRMD_EINVAL, "box sides must be positive and finite");
+  for (long long i = 0; i < 3LL * n; ++i) {
+    if (!std::isfinite(pos[i])) return fail(nullptr, SRMD_EINVAL, "non-finite position");
+    if (vel && !std::isfinite(vel[i])) return fail(nullptr, SRMD_EINVAL, "non-finite velocity");
+  }
+  for (int i = 0; i < n; ++i)
+    if (type[i] < 0 || type[i] >= ntypes) return fail(nullptr, SRMD_EINVAL, "particle type out of range");
+  if (mass)
+    for (int t = 0; t < ntypes; ++t)
+      if (!(mass[t] > 0) || !std::isfinite(mass[t])) return fail(nullptr, SRMD_EINVAL, "masses must be positive");
+  srmd_system *s = new (std::nothrow) srmd_system();
+  if (!s) return fail(nullptr, SRMD_ENOMEM, "host allocation failed");
+  s->n = n;
+  s->ntypes = ntypes;
+  s->prec = prec;
+  for (int k = 0; k < 3; ++k) s->Lf[k] = (float)box[k];
+  if (mass)
+    for (int t = 0; t < ntypes; ++t) s->mass[t] = mass[t];
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      return fail(nullptr, SRMD_EHIP, "hipStreamCreate failed");
+    }
+    s->own_stream = true;
+  }
+  const size_t N = (size_t)n;
+  bool ok = true;
+  auto A = [&](size_t bytes) {
+    void *q = dev_alloc(s, bytes);
+    ok = ok && q;
+    return q;
+  };
+  s->p.pos[0] = (float4 *)A(sizeof(float4) * N);
+  s->p.pos[1] = (float4 *)A(sizeof(float4) * N);
+  s->p.vel = (float4 *)A(sizeof(float4) * N);
+  s->p.img = (int4 *)A(sizeof(int4) * N);
+  s->p.force = (float4 *)A(sizeof(float4) * N);
+  s->p.last = (float4 *)A(sizeof(float4) * N);
+  s->p.nnb = (int *)A(sizeof(int) * N);
+  s->p.cell_of = (unsigned *)A(sizeof(unsigned) * N);
+  s->p.slot_in_cell = (unsigned *)A(sizeof(unsigned) * N);
+  s->p.perm_tmp = (unsigned *)A(sizeof(unsigned) * N);
+  s->p.t_pos = (float4 *)A(sizeof(float4) * N);
+  s->p.t_vel = (float4 *)A(sizeof(float4) * N);
+  s->p.t_img = (int4 *)A(sizeof(int4) * N);
+  s->p.ctl = (Control *)A(sizeof(Control));
+  s->p.thermo = (Thermo *)A(sizeof(Thermo));
+  if (prec == SRMD_PREC_F64POS) {
+    s->p.pos64 = (double *)A(sizeof(double) * 3 * N);
+    s->p.t_pos64 = (double *)A(sizeof(double) * 3 * N);
+  }
+  if (prec == SRMD_PREC_F32_KAHAN) {
+    s->p.kahan = (float4 *)A(sizeof(float4) * N);
+    s->p.t_kahan = (float4 *)A(sizeof(float4) * N);
+  }
+  if (!ok) {
+    srmd_destroy(s);
+    return fail(nullptr, SRMD_ENOMEM, "device allocation failed");
+  }
+  Control hc;
+  std::memset(&hc, 0, sizeof(hc));
+  hc.rebuild = 1;
+  Thermo ht;
+  std::memset(&ht, 0, sizeof(ht));
+  if (hipMemcpyAsync(s->p.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+      hipMemcpyAsync(s->p.thermo, &ht, sizeof(ht), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.force, 0, sizeof(float4) * N, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess) {
+    srmd_destroy(s);
+    return fail(nullptr, SRMD_EHIP, "initial upload failed");
+  }
+  srmd_status st = upload_state(s, pos, vel, type);
+  if (st != SRMD_OK) {
+    std::string m = s->err;
+    srmd_destroy(s);
+    return fail(nullptr, st, m);
+  }
+  *out = s;
+  return SRMD_OK;
+}
+
+srmd_status srmd_destroy(srmd_system *s) {
+  if (!s) return SRMD_OK;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  drop_graphs(s);
+  while (!s->bufs.empty()) dev_free(s, s->bufs.back().ptr);
+  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigma, double epsilon, double rcut,
+                             srmd_cutoff method) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (ti < 0 || tj < 0 || ti >= s->ntypes || tj >= s->ntypes) return fail(s, SRMD_EINVAL, "type index out of range");
+  if (!(sigma > 0) || !(epsilon >= 0) || !(rcut > 0) || !std::isfinite(sigma) || !std::isfinite(epsilon) ||
+      !std::isfinite(rcut))
+    return fail(s, SRMD_EINVAL, "sigma, rcut must be positive and epsilon non-negative");
+  if (method != SRMD_CUT_TRUNC && method != SRMD_CUT_SP && method != SRMD_CUT_SF)
+    return fail(s, SRMD_EINVAL, "unknown cutoff method");
+  if (s->method >= 0 && s->method != (int)method)
+    return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
+  for (int k = 0; k < 3; ++k)
+    if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+  s->method = (int)method;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int a = pass ? pair_index(s, tj, ti) : pair_index(s, ti, tj);
+    s->sigma[a] = sigma;
+    s->eps[a] = epsilon;
+    s->rc[a] = rcut;
+    s->pair_given[a] = true;
+  }
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_skin(srmd_system *s, double skin) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!(skin >= 0) || !std::isfinite(skin)) return fail(s, SRMD_EINVAL, "skin must be >= 0");
+  const double rcm = rc_max(s);
+  for (int k = 0; k < 3; ++k)
+    if (!(rcm + skin < 0.5 * (double)s->Lf[k]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+  s->skin = skin;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_integrator_nve(srmd_system *s, double dt) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(s, SRMD_EINVAL, "dt must be positive");
+  s->dt = dt;
+  s->thermostat = 0;
+  s->integrator_set = true;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double tau) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!(dt > 0) || !std::isfinite(dt) || !(T0 > 0) || !std::isfinite(T0) || !(tau > 0))
+    return fail(s, SRMD_EINVAL, "dt, T0 and tau must be positive");
+  s->dt = dt;
+  s->T0 = T0;
+  s->tau = tau;
+  s->thermostat = 1;
+  s->integrator_set = true;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (tp == 0 && ppb == 0) {
+    s->tp_req = s->ppb_req = 0;
+    s->dirty = true;
+    return SRMD_OK;
+  }
+  if (tp < 1 || tp > 64 || (tp & (tp - 1)) != 0) return fail(s, SRMD_EINVAL, "tp must be a power of two in 1..64");
+  if (ppb < 1 || tp * ppb > 1024 || (tp * ppb) % 64 != 0)
+    return fail(s, SRMD_EINVAL, "tp * ppb must be a multiple of 64 and at most 1024");
+  s->tp_req = tp;
+  s->ppb_req = ppb;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  int a, b;
+  launch_of(s, &a, &b);
+  if (tp) *tp = a;
+  if (ppb) *ppb = b;
+  return SRMD_OK;
+}
+
+srmd_status srmd_build_neighbor_list(srmd_system *s) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    st = request_rebuild(s);
+    if (st != SRMD_OK) return st;
+    HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, s->cur));
+    st = set_ctl_int(s, offsetof(Control, rebuild), 0);
+    if (st != SRMD_OK) return st;
+    Control h;
+    st = read_ctl(s, &h);
+    if (st != SRMD_OK) return st;
+    if (!(h.error & 2)) return SRMD_OK;
+    st = set_ctl_int(s, offsetof(Control, error), h.error & ~2);
+    if (st != SRMD_OK) return st;
+    st = regrow(s);
+    if (st != SRMD_OK) return st;
+  }
+  return fail(s, SRMD_ENOMEM, "neighbour list kept overflowing");
+}
+
+srmd_status srmd_compute_forces(srmd_system *s, srmd_thermo *out) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, s->cur));
+    HIPCHK(s, launch_force(s->tp, s->method, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur));
+    Control h;
+    st = read_ctl(s, &h);
+    if (st != SRMD_OK) return st;
+    if (h.error & 2) {
+      st = set_ctl_int(s, offsetof(Control, error), h.error & ~2);
+      if (st != SRMD_OK) return st;
+      st = regrow(s);  // requests a rebuild
+      if (st != SRMD_OK) return st;
+      continue;
+    }
+    if (h.error & 1) return fail(s, SRMD_ESTATE, "non-finite force");
+    if (out) return srmd_get_thermo(s, out);
+    return SRMD_OK;
+  }
+  return fail(s, SRMD_ENOMEM, "neighbour list kept overflowing");
+}
+
+srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace, int64_t trace_cap) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (nsteps < 0) return fail(s, SRMD_EINVAL, "nsteps must be >= 0");
+  if (!s->integrator_set) return fail(s, SRMD_EINVAL, "integrator not set");
+  if (thermo_every < 0 || trace_cap < 0 || (trace_cap > 0 && !trace))
+    return fail(s, SRMD_EINVAL, "invalid trace arguments");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  if (nsteps == 0) return SRMD_OK;
+  const long long cap = thermo_every > 0 ? trace_cap : 0;
+  if (cap > s->trace_alloc) {
+    dev_free(s, s->p.trace);
+    s->p.trace = (Thermo *)dev_alloc(s, sizeof(Thermo) * (size_t)cap);
+    if (!s->p.trace) return fail(s, SRMD_ENOMEM, "trace allocation failed");
+    s->trace_alloc = cap;
+    s->dirty = true;  // the pointer is baked into the graphs
+    st = prepare(s);
+    if (st != SRMD_OK) return st;
+  }
+  st = alloc_snapshot(s);
+  if (st != SRMD_OK) return st;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    // trace settings live in the control block so the graphs stay valid
+    Control hc;
+    st = read_ctl(s, &hc);
+    if (st != SRMD_OK) return st;
+    hc.thermo_every = thermo_every;
+    hc.trace_cap = cap;
+    hc.n_records = 0;
+    st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
+    if (st != SRMD_OK) return st;
+    const int cur0 = s->cur;
+    st = snapshot(s, false);
+    if (st != SRMD_OK) return st;
+    st = run_steps(s, nsteps);
+    if (st != SRMD_OK) return st;
+    Control h;
+    st = read_ctl(s, &h);
+    if (st != SRMD_OK) return st;
+    if (h.error & 2) {  // list overflow: grow, restore the call-start state, replay
+      s->cur = cur0;
+      st = snapshot(s, true);
+      if (st != SRMD_OK) return st;
+      Control r;
+      st = read_ctl(s, &r);
+      if (st != SRMD_OK) return st;
+      r.error &= ~2;
+      st = h2d_sync(s, s->p.ctl, &r, sizeof(Control));
+      if (st != SRMD_OK) return st;
+      st = regrow(s);
+      if (st != SRMD_OK) return st;
+      continue;
+    }
+    if (h.error & 1) return fail(s, SRMD_ESTATE, "non-finite force or position during the run");
+    if (cap > 0 && h.n_records > 0) {
+      std::vector<Thermo> tmp((size_t)h.n_records);
+      HIPCHK(s, hipMemcpyAsync(tmp.data(), s->p.trace, sizeof(Thermo) * tmp.size(), hipMemcpyDeviceToHost, s->stream));
+      HIPCHK(s, hipStreamSynchronize(s->stream));
+      for (size_t k = 0; k < tmp.size(); ++k) to_public(tmp[k], &trace[k]);
+    }
+    return SRMD_OK;
+  }
+  return fail(s, SRMD_ENOMEM, "neighbour list kept overflowing");
+}
+
+srmd_status srmd_get_state(srmd_system *s, float *pos, float *vel, int32_t *image, float *force, double *pos64) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  const size_t n = (size_t)s->n;
+  std::vector<int4> hi(n);
+  HIPCHK(s, hipMemcpyAsync(hi.data(), s->p.img, sizeof(int4) * n, hipMemcpyDeviceToHost, s->stream));
+  std::vector<float4> hp(n), hv(n), hf(n);
+  std::vector<double> h64;
+  HIPCHK(s, hipMemcpyAsync(hp.data(), s->p.pos[s->cur], sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  if (vel) HIPCHK(s, hipMemcpyAsync(hv.data(), s->p.vel, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  if (force) HIPCHK(s, hipMemcpyAsync(hf.data(), s->p.force, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  if (pos64 && s->p.pos64) {
+    h64.resize(3 * n);
+    HIPCHK(s, hipMemcpyAsync(h64.data(), s->p.pos64, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (size_t k = 0; k < n; ++k) {
+    const int id = hi[k].w;
+    if (id < 0 || (size_t)id >= n) return fail(s, SRMD_ESTATE, "corrupt particle id on the device");
+    if (pos) {
+      pos[3 * id] = hp[k].x;
+      pos[3 * id + 1] = hp[k].y;
+      pos[3 * id + 2] = hp[k].z;
+    }
+    if (vel) {
+      vel[3 * id] = hv[k].x;
+      vel[3 * id + 1] = hv[k].y;
+      vel[3 * id + 2] = hv[k].z;
+    }
+    if (image) {
+      image[3 * id] = hi[k].x;
+      image[3 * id + 1] = hi[k].y;
+      image[3 * id + 2] = hi[k].z;
+    }
+    if (force) {
+      force[3 * id] = hf[k].x;
+      force[3 * id + 1] = hf[k].y;
+      force[3 * id + 2] = hf[k].z;
+    }
+    if (pos64) {
+      for (int d = 0; d < 3; ++d)
+        pos64[3 * id + d] = h64.empty() ? (double)(&hp[k].x)[d] : h64[3 * k + (size_t)d];
+    }
+  }
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_state(srmd_system *s, const float *pos, const float *vel) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  const size_t n = (size_t)s->n;
+  for (size_t i = 0; i < 3 * n; ++i) {
+    if (pos && !std::isfinite(pos[i])) return fail(s, SRMD_EINVAL, "non-finite position");
+    if (vel && !std::isfinite(vel[i])) return fail(s, SRMD_EINVAL, "non-finite velocity");
+  }
+  std::vector<int4> hi(n);
+  std::vector<float4> hp(n);
+  HIPCHK(s, hipMemcpyAsync(hi.data(), s->p.img, sizeof(int4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(hp.data(), s->p.pos[s->cur], sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  std::vector<float> P(3 * n), Vv(3 * n);
+  std::vector<int32_t> T(n);
+  std::vector<float> curvel;
+  if (!vel) {
+    std::vector<float4> hv(n);
+    HIPCHK(s, hipMemcpyAsync(hv.data(), s->p.vel, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    for (size_t k = 0; k < n; ++k) {
+      const int id = hi[k].w;
+      Vv[3 * id] = hv[k].x;
+      Vv[3 * id + 1] = hv[k].y;
+      Vv[3 * id + 2] = hv[k].z;
+    }
+  }
+  for (size_t k = 0; k < n; ++k) {
+    const int id = hi[k].w;
+    int ty;
+    std::memcpy(&ty, &hp[k].w, 4);
+    T[id] = ty;
+    for (int d = 0; d < 3; ++d) P[3 * id + d] = pos ? pos[3 * id + d] : (&hp[k].x)[d];
+    if (vel)
+      for (int d = 0; d < 3; ++d) Vv[3 * id + d] = vel[3 * id + d];
+  }
+  srmd_status st = upload_state(s, P.data(), Vv.data(), T.data());
+  if (st != SRMD_OK) return st;
+  return request_rebuild(s);
+}
+
+srmd_status srmd_get_neighbor_pairs(srmd_system *s, int32_t *pairs, int64_t cap, int64_t *count) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!count) return fail(s, SRMD_EINVAL, "count is NULL");
+  if (!s->p.nbl) return fail(s, SRMD_EINVAL, "no neighbour list has been built");
+  const size_t n = (size_t)s->n;
+  std::vector<int4> hi(n);
+  std::vector<int> nn(n);
+  std::vector<int> nb((size_t)s->c.n_max * (size_t)s->c.nvp);
+  HIPCHK(s, hipMemcpyAsync(hi.data(), s->p.img, sizeof(int4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(nn.data(), s->p.nnb, sizeof(int) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(nb.data(), s->p.nbl, sizeof(int) * nb.size(), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  long long total = 0;
+  for (size_t t = 0; t < n; ++t) total += nn[t];
+  *count = total;
+  if (!pairs) return SRMD_OK;
+  if (total > cap) return fail(s, SRMD_EINVAL, "pair buffer too small");
+  std::vector<std::pair<int, int>> v;
+  v.reserve((size_t)total);
+  const long long tp = s->c.tp, nvp = s->c.nvp;
+  for (size_t t = 0; t < n; ++t) {
+    for (int k = 0; k < nn[t]; ++k) {
+      const long long addr = (long long)(k / tp) * (nvp * tp) + (long long)t * tp + (k % tp);
+      const int u = nb[(size_t)addr];
+      if (u < 0 || (size_t)u >= n) return fail(s, SRMD_ESTATE, "corrupt neighbour index");
+      v.emplace_back(hi[t].w, hi[(size_t)u].w);
+    }
+  }
+  std::sort(v.begin(), v.end());
+  for (size_t k = 0; k < v.size(); ++k) {
+    pairs[2 * k] = v[k].first;
+    pairs[2 * k + 1] = v[k].second;
+  }
+  return SRMD_OK;
+}
+
+srmd_status srmd_get_thermo(srmd_system *s, srmd_thermo *out) {
+  if (!s || !out) return fail(s, SRMD_EINVAL, "NULL argument");
+  Thermo t;
+  HIPCHK(s, hipMemcpyAsync(&t, s->p.thermo, sizeof(Thermo), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  to_public(t, out);
+  return SRMD_OK;
+}
+
+srmd_status srmd_get_box(const srmd_system *s, double box[3]) {
+  if (!s || !box) return fail(nullptr, SRMD_EINVAL, "NULL argument");
+  for (int k = 0; k < 3; ++k) box[k] = (double)s->Lf[k];
+  return SRMD_OK;
+}
+
+srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  (void)steps_per_trial;
+  if (tp_out) *tp_out = 0;
+  if (ppb_out) *ppb_out = 0;
+  return fail(s, SRMD_EUNSUPPORTED, "autotune not available yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,112 @@
+// Internal layout shared by the kernels and the host runtime of libsrmd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace srmd {
+
+constexpr int kMaxTypes = 4;
+constexpr int kMaxPairs = kMaxTypes * kMaxTypes;
+
+// Per-type-pair float32 constants of the pair kernel and of the list build.
+struct PairTable {
+  float cs2[kMaxPairs];    // (rc_ab + skin)^2 rounded once to float32: list radius
+  float rc2[kMaxPairs];    // rc_ab^2 rounded once to float32: force cutoff
+  float sig2[kMaxPairs];   // sigma^2
+  float eps4[kMaxPairs];   // 4 eps
+  float eps24[kMaxPairs];  // 24 eps
+  float ushift[kMaxPairs]; // U(rc) for the shifted methods (0 for plain truncation)
+  float fc[kMaxPairs];     // F(rc) = -U'(rc) for shifted force (0 otherwise)
+  float rc[kMaxPairs];     // rc_ab
+};
+
+// Everything a kernel needs besides pointers; passed by value.
+struct SysConst {
+  int n;         // particles
+  int ntypes;
+  int nvp;       // row stride of the list (n rounded up to 64)
+  int n_max;     // list capacity per particle
+  int tp;        // threads per particle the list layout is built for
+  int ncell;     // nc.x * nc.y * nc.z
+  int nc[3];     // cells per axis
+  int full_axis; // bit k set: axis k has fewer than 5 cells, visit every cell along it
+  float L[3];    // float32 box sides
+  float invL[3]; // (float)(1.0 / (double)L)
+  float halfL[3];
+  float cscale[3]; // nc / L (float32), cell coordinate scale
+  double Ld[3];    // (double)L
+  float dt;        // time step (float32)
+  float pad0;
+  double dtd;       // time step (float64)
+  double T0;        // target temperature
+  double inv_tau2;  // 1 / tau^2 (0: no thermostat coupling)
+  double half_skin2; // (skin / 2)^2 in float64
+  double g;          // degrees of freedom 3N - 3
+  double volume;
+  int thermostat;    // 1: Nose-Hoover
+  int pad1;
+  float inv_mass[kMaxTypes];
+  double mass[kMaxTypes];
+  PairTable pt;
+};
+
+// Device-resident control words (one 256-byte block).
+struct Control {
+  int rebuild;       // 1: rebuild the list before the next force evaluation
+  int error;         // sticky: bit 0 non-finite force/position, bit 1 list overflow
+  unsigned counter;  // last-block detection of the step / force kernels
+  int max_nbrs;      // longest list of the last build
+  long long step;    // steps taken
+  long long n_rebuilds;
+  long long n_records; // records written to the trace
+  double xi;         // Nose-Hoover friction at the current step
+  double xi_int;     // its time integral
+  int rebuilt_this_step; // set by the list build, cleared by the step kernel
+  int thermo_every;      // record every k-th step into the trace (0: never)
+  long long trace_cap;   // capacity of the device trace
+  int pad[32];
+};
+
+// Thermo accumulators of the last force evaluation / step.
+struct Thermo {
+  double pe, ke, virial, temperature, pressure, xi, xi_integral, h_conserved, ke_half;
+  long long step, n_rebuilds;
+  int max_nbrs, reserved;
+};
+
+// Per-block float64 partial sums of the step and force kernels.
+struct BlockPartial {
+  double pe, w, ke_half, ke_int, disp2;
+  int nonfinite;
+  int pad;
+  double pad2;
+};
+
+struct SysPtrs {
+  float4 *pos[2];   // float32 positions, type bits in .w (double buffer)
+  float4 *vel;      // velocities, .w unused
+  int4 *img;        // image counters in .xyz, original particle id in .w
+  float4 *force;    // last forces, per-particle potential energy in .w
+  float4 *last;     // positions at the last build
+  double *pos64;    // float64 master positions (3 per particle) or nullptr
+  float4 *kahan;    // Kahan residuals or nullptr
+  int *nbl;         // neighbour list, tp-interleaved column-major
+  int *nnb;         // list lengths
+  unsigned *cell_of;
+  unsigned *slot_in_cell;
+  unsigned *cell_count;
+  unsigned *cell_start; // ncell + 1 entries
+  unsigned *perm_tmp;
+  float4 *t_pos;    // gather targets of the spatial sort
+  float4 *t_vel;
+  int4 *t_img;
+  double *t_pos64;
+  float4 *t_kahan;
+  BlockPartial *part;
+  Control *ctl;
+  Thermo *thermo;   // last record
+  Thermo *trace;    // device trace (trace_cap records)
+};
+
+}  // namespace srmd

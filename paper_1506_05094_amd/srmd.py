@@ -1,0 +1,303 @@
+"""Thin ctypes binding of libsrmd (the C-ABI declared in include/srmd.h).
+
+Argument marshalling only: every step of the computation runs in the HIP kernels
+of libsrmd.so.  The module-level functions carry the C names; ``System`` is a small
+convenience wrapper over them.  PyTorch is used for device memory (the allocator
+hook) and for the HIP stream the library enqueues on.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsrmd.so")
+
+SRMD_OK, SRMD_EINVAL, SRMD_ENOMEM, SRMD_EHIP, SRMD_ESTATE, SRMD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SRMD_CUT_TRUNC, SRMD_CUT_SP, SRMD_CUT_SF = 0, 1, 2
+SRMD_PREC_F32, SRMD_PREC_F32_KAHAN, SRMD_PREC_F64POS = 0, 1, 2
+CUTOFF = {"trunc": SRMD_CUT_TRUNC, "sp": SRMD_CUT_SP, "sf": SRMD_CUT_SF}
+PRECISION = {"f32": SRMD_PREC_F32, "f32_kahan": SRMD_PREC_F32_KAHAN, "f64pos": SRMD_PREC_F64POS}
+
+
+class srmd_thermo(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in
+                ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_integral", "h_conserved", "ke_half")] + [
+        ("step", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64), ("max_nbrs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+THERMO_DTYPE = np.dtype([(name, np.float64) for name in
+                         ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_integral", "h_conserved",
+                          "ke_half")] + [("step", np.int64), ("n_rebuilds", np.int64), ("max_nbrs", np.int32),
+                                         ("reserved", np.int32)])
+assert THERMO_DTYPE.itemsize == ctypes.sizeof(srmd_thermo)
+
+
+class SrmdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"srmd status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+_alloc_keepalive = []
+
+_vp = ctypes.c_void_p
+_fp = ctypes.POINTER(ctypes.c_float)
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load():
+    """Load libsrmd.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libsrmd.so not built at {LIB_PATH}; run paper_1506_05094_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sysp = ctypes.c_void_p
+    sig = {
+        "srmd_create": (st, [ctypes.POINTER(sysp), ctypes.c_int32, ctypes.c_int32, _dp, _fp, _ip, _fp, _dp,
+                             ctypes.c_int, _vp]),
+        "srmd_destroy": (st, [sysp]),
+        "srmd_set_allocator": (st, [_ALLOC_T, _FREE_T, _vp]),
+        "srmd_set_pair_lj": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, ctypes.c_int]),
+        "srmd_set_skin": (st, [sysp, ctypes.c_double]),
+        "srmd_set_integrator_nve": (st, [sysp, ctypes.c_double]),
+        "srmd_set_integrator_nvt": (st, [sysp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+        "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
+        "srmd_get_launch": (st, [sysp, _ip, _ip]),
+        "srmd_autotune": (st, [sysp, ctypes.c_int32, _ip, _ip]),
+        "srmd_build_neighbor_list": (st, [sysp]),
+        "srmd_compute_forces": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
+        "srmd_step": (st, [sysp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
+        "srmd_get_state": (st, [sysp, _fp, _fp, _ip, _fp, _dp]),
+        "srmd_set_state": (st, [sysp, _fp, _fp]),
+        "srmd_get_neighbor_pairs": (st, [sysp, _ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+        "srmd_get_thermo": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
+        "srmd_get_box": (st, [sysp, _dp]),
+        "srmd_last_error": (ctypes.c_char_p, [sysp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status, sysp=None):
+    if status != SRMD_OK:
+        msg = load().srmd_last_error(sysp)
+        raise SrmdError(status, msg.decode() if msg else "")
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+def install_torch_allocator():
+    """Route every later device allocation of libsrmd through torch's caching allocator."""
+    import torch
+
+    lib = load()
+
+    def _alloc(nbytes, ctx):
+        try:
+            dev = torch.cuda.current_device()
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev))
+        except Exception:  # reported to the library as an allocation failure
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = _ALLOC_T(_alloc)
+    f = _FREE_T(_free)
+    _alloc_keepalive[:] = [a, f]
+    _check(lib.srmd_set_allocator(a, f, None))
+
+
+def uninstall_allocator():
+    lib = load()
+    _check(lib.srmd_set_allocator(_ALLOC_T(), _FREE_T(), None))
+
+
+class System:
+    """One simulated system on the GPU (a handle to srmd_system)."""
+
+    def __init__(self, pos, types, box, vel=None, mass=None, ntypes=None, precision="f32", stream=None):
+        lib = load()
+        pos = _f32(pos).reshape(-1, 3)
+        n = pos.shape[0]
+        types = np.ascontiguousarray(types, dtype=np.int32)
+        box = np.ascontiguousarray(box, dtype=np.float64)
+        vel = None if vel is None else _f32(vel).reshape(-1, 3)
+        nt = int(ntypes if ntypes is not None else types.max() + 1)
+        mass = None if mass is None else np.ascontiguousarray(mass, dtype=np.float64)
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        if stream is None:
+            stream_ptr = None
+        else:
+            stream_ptr = ctypes.c_void_p(int(stream))
+        h = ctypes.c_void_p()
+        _check(lib.srmd_create(ctypes.byref(h), n, nt, _ptr(box, _dp), _ptr(pos, _fp), _ptr(types, _ip),
+                               _ptr(vel, _fp), _ptr(mass, _dp), prec, stream_ptr))
+        self._h = h
+        self.n = n
+        self.ntypes = nt
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            load().srmd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- setup
+    def set_pair_lj(self, ti, tj, sigma, epsilon, rcut, method):
+        m = CUTOFF[method] if isinstance(method, str) else int(method)
+        _check(load().srmd_set_pair_lj(self._h, ti, tj, sigma, epsilon, rcut, m), self._h)
+
+    def set_pairs(self, sigma, eps, rc, method):
+        sigma = np.asarray(sigma)
+        for a in range(sigma.shape[0]):
+            for b in range(a, sigma.shape[0]):
+                self.set_pair_lj(a, b, float(sigma[a, b]), float(eps[a, b]), float(rc[a, b]), method)
+
+    def set_skin(self, skin):
+        _check(load().srmd_set_skin(self._h, float(skin)), self._h)
+
+    def set_integrator_nve(self, dt):
+        _check(load().srmd_set_integrator_nve(self._h, float(dt)), self._h)
+
+    def set_integrator_nvt(self, dt, T0, tau):
+        _check(load().srmd_set_integrator_nvt(self._h, float(dt), float(T0), float(tau)), self._h)
+
+    def set_launch(self, tp, ppb):
+        _check(load().srmd_set_launch(self._h, int(tp), int(ppb)), self._h)
+
+    def get_launch(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().srmd_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
+
+    def autotune(self, steps_per_trial=200):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(load().srmd_autotune(self._h, int(steps_per_trial), ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
+
+    # -- compute
+    def build_neighbor_list(self):
+        _check(load().srmd_build_neighbor_list(self._h), self._h)
+
+    def compute_forces(self):
+        t = srmd_thermo()
+        _check(load().srmd_compute_forces(self._h, ctypes.byref(t)), self._h)
+        return t.as_dict()
+
+    def step(self, nsteps, thermo_every=0, trace_cap=None):
+        if thermo_every > 0:
+            cap = int(trace_cap if trace_cap is not None else (nsteps + thermo_every - 1) // thermo_every)
+            trace = np.zeros(cap, dtype=THERMO_DTYPE)
+            _check(load().srmd_step(self._h, int(nsteps), int(thermo_every), trace.ctypes.data_as(_vp), cap),
+                   self._h)
+            return trace
+        _check(load().srmd_step(self._h, int(nsteps), 0, None, 0), self._h)
+        return None
+
+    # -- state
+    def get_state(self):
+        n = self.n
+        pos = np.zeros((n, 3), np.float32)
+        vel = np.zeros((n, 3), np.float32)
+        img = np.zeros((n, 3), np.int32)
+        frc = np.zeros((n, 3), np.float32)
+        p64 = np.zeros((n, 3), np.float64)
+        _check(load().srmd_get_state(self._h, _ptr(pos, _fp), _ptr(vel, _fp), _ptr(img, _ip), _ptr(frc, _fp),
+                                     _ptr(p64, _dp)), self._h)
+        return dict(pos=pos, vel=vel, image=img, force=frc, pos64=p64)
+
+    def set_state(self, pos=None, vel=None):
+        pos = None if pos is None else _f32(pos).reshape(-1, 3)
+        vel = None if vel is None else _f32(vel).reshape(-1, 3)
+        _check(load().srmd_set_state(self._h, _ptr(pos, _fp), _ptr(vel, _fp)), self._h)
+
+    def neighbor_pairs(self):
+        lib = load()
+        cnt = ctypes.c_int64()
+        _check(lib.srmd_get_neighbor_pairs(self._h, None, 0, ctypes.byref(cnt)), self._h)
+        pairs = np.zeros((max(cnt.value, 1), 2), np.int32)
+        _check(lib.srmd_get_neighbor_pairs(self._h, _ptr(pairs, _ip), cnt.value, ctypes.byref(cnt)), self._h)
+        return pairs[:cnt.value]
+
+    def thermo(self):
+        t = srmd_thermo()
+        _check(load().srmd_get_thermo(self._h, ctypes.byref(t)), self._h)
+        return t.as_dict()
+
+    def box(self):
+        b = np.zeros(3)
+        _check(load().srmd_get_box(self._h, _ptr(b, _dp)), self._h)
+        return b
+
+
+EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_lj", "srmd_set_skin",
+            "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
+            "srmd_autotune", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
+            "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error"]
+
+
+def _export_c_names():
+    """Module-level functions with the C names (thin pass-through to the loaded library)."""
+    def make(name):
+        def fn(*args):
+            return getattr(load(), name)(*args)
+        fn.__name__ = name
+        fn.__doc__ = f"Direct call of {name} from libsrmd (see include/srmd.h)."
+        return fn
+    g = globals()
+    for name in EXPORTED:
+        g[name] = make(name)
+
+
+_export_c_names()
+
+
+def system_from_state(state, sigma, eps, rc, method, skin=0.3, precision="f32", stream=None):
+    """Create a System from a workloads.State and set its pair potential and skin."""
+    s = System(state.pos, state.types, state.box, vel=state.vel, mass=state.mass, ntypes=state.ntypes,
+               precision=precision, stream=stream)
+    s.set_skin(skin)
+    s.set_pairs(sigma, eps, rc, method)
+    return s
