@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the short-range MD hot path on one MI355X.
+
+Default workload: Kob-Andersen 80:20 binary Lennard-Jones mixture, N = 4096,
+density 1.2, Nose-Hoover NVT at T = 0.45 (tau = 0.2), dt = 0.005, shifted-force
+cutoff 2.5 sigma_ab, skin 0.3, float32 positions and forces with float64
+reductions.  Seeded random non-overlapping start, relaxed by an untimed
+2000-step NVT run at dt = 0.001, then W untimed and K timed steps at dt = 0.005.
+A step is one pass of the whole hot path: displacement check, list rebuild when
+due (cell binning, counting sort, reorder, cell-stencil list), pair forces,
+integrator and thermostat.
+
+Prints one JSON line with particle-steps/s (whole job), the roofline position of
+the dominant kernel (the fused force + integrator kernel) and the CPU oracle's
+rate on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/sec & timesteps/sec, LJ/KA N=1k-1M; batched replicas vs single"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(name, n):
+    from workloads import generators as gen
+
+    if name == "ka4096":
+        state = gen.config1_state()
+        sig, eps, rc = gen.ka_params()
+        desc = dict(workload="Kob-Andersen 80:20 NVT", n=state.n, rho=1.2, T0=0.45, tau=0.2, dt=0.005,
+                    cutoff="shifted-force 2.5 sigma_ab", skin=0.3, seed=state.seed, start="random insertion dmin 0.75"
+                    " sigma_ab + 2000 NVT steps dt 0.001")
+        return state, (sig, eps, rc), "sf", ("nvt", 0.005, 0.45, 0.2), desc
+    if name == "lj":
+        state = gen.config2_state(n) if n != 864 else gen.config0_state()
+        sig, eps, rc = gen.lj_params()
+        desc = dict(workload="Lennard-Jones NVE (melting FCC)", n=state.n, rho=0.8442, T=0.722, dt=0.005,
+                    cutoff="shifted-potential 2.5", skin=0.3, seed=state.seed, start="FCC lattice")
+        return state, (sig, eps, rc), "sp", ("nve", 0.005), desc
+    raise SystemExit(f"unknown workload {name}")
+
+
+def step_kernel_bytes(n, list_entries):
+    """Algorithmic bytes of one fused step-kernel launch.
+
+    Per particle: list length (4) + list entries (4 each) + position (16; the
+    spatially sorted position array is counted once, it serves every neighbour read)
+    + velocity (16) + image/id (16) + last-build position (16) read, and position,
+    velocity, image/id and force (4 x 16) written: 132 B + 4 B per list entry.
+    """
+    return 132.0 * n + 4.0 * list_entries
+
+
+def cpu_baseline(state, params, method, integ, budget_s=12.0):
+    """The oracle (FP64, O(N^2), OpenMP over particles) on the host cores."""
+    import oracle
+
+    sig, eps, rc = params
+    kw = {}
+    if integ[0] == "nvt":
+        kw = dict(thermostat=True, T0=integ[2], tau=integ[3])
+    t0 = time.perf_counter()
+    oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1], 1, **kw)
+    t1 = time.perf_counter() - t0
+    steps = int(max(1, min(2000, budget_s / max(t1, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1], steps,
+                     **kw)
+    dt = time.perf_counter() - t0
+    return {"value": state.n * steps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} oracle steps of the same system (N={state.n}, O(N^2) FP64 forces) from the seeded "
+                      f"start, {dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj"])
+    ap.add_argument("--n", type=int, default=864, help="particles for --workload lj")
+    ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
+    ap.add_argument("--ppb", type=int, default=0)
+    ap.add_argument("--profile-steps", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (one process, one MI355X).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1506_05094_amd import srmd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    srmd.load()
+    state, params, method, integ, desc = workload(args.workload, args.n)
+    sig, eps, rc = params
+    s = srmd.system_from_state(state, sig, eps, rc, method, skin=0.3, stream=torch.cuda.current_stream().cuda_stream)
+    if args.tp:
+        s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
+    if integ[0] == "nvt":
+        s.set_integrator_nvt(0.001, integ[2], integ[3])
+        s.step(2000)  # relax the random insertion (untimed)
+        s.set_integrator_nvt(integ[1], integ[2], integ[3])
+    else:
+        s.set_integrator_nve(integ[1])
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    st0 = s.stats()
+    t0 = time.perf_counter()
+    s.step(args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st1 = s.stats()
+    th = s.thermo()
+    n = state.n
+    value = n * args.steps / wall
+    log(f"timed {args.steps} steps in {wall:.4f} s: {value:.4e} particle-steps/s, {args.steps / wall:.1f} steps/s, "
+        f"rebuilds {st1['n_rebuilds'] - st0['n_rebuilds']}, tp {st1['tp']} ppb {st1['ppb']}, T {th['temperature']:.4f}")
+
+    # dominant kernel: the fused force + integrator kernel, timed per launch with HIP events
+    ev_ms, dev_ms, launches = s.profile_step_kernel(args.profile_steps)
+    st2 = s.stats()
+    avg_s = ev_ms / 1e3 / launches
+    dev_avg_s = dev_ms / 1e3 / launches
+    bytes_launch = step_kernel_bytes(n, st2["list_entries"])
+    achieved = bytes_launch / avg_s / 1e9
+    log(f"step kernel: {launches} launches, event avg {avg_s * 1e6:.2f} us, device-clock avg {dev_avg_s * 1e6:.2f} us, "
+        f"{bytes_launch / 1e6:.3f} MB algorithmic per launch -> {achieved:.1f} GB/s")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "k_step (fused pair force + integrator)", "avg_us_events": round(avg_s * 1e6, 3),
+                "avg_us_device_clock": round(dev_avg_s * 1e6, 3), "bytes_per_launch": bytes_launch,
+                "list_entries_per_particle": round(st2["list_entries"] / n, 2)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(state, params, method, integ)
+        log(f"cpu baseline: {cpu}")
+    s.close()
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"]),
+        "timesteps_per_sec": args.steps / wall,
+        "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,6 +127,13 @@ srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double
  * system size or the value found by srmd_autotune. */
 srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
 
+/* Choose how a list rebuild runs (tuning; the resulting list is the same).
+ * sort_mode: 0 automatic, 1 the spatial sort in one workgroup's LDS (systems of up
+ * to 8192 particles and 8192 cells; larger ones fall back to 2), 2 the multi-kernel
+ * counting sort.  list_mode: 0 automatic, 1 one wave per particle, 2 one thread per
+ * particle (the paper's section 7 layout). */
+srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
+
 /* Read back the thread layout in use (after defaults are resolved). */
 srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb);
 
@@ -172,6 +179,25 @@ srmd_status srmd_get_thermo(srmd_system *s, srmd_thermo *out);
 
 /* The float32 box sides in use (written as float64). */
 srmd_status srmd_get_box(const srmd_system *s, double box[3]);
+
+/* Counters of a system: steps taken, list builds, entries of the current list,
+ * the longest list of the last build, the list capacity per particle, the launch
+ * shape in use (tp, ppb, blocks of the step kernel) and the cell grid size. */
+typedef struct {
+  int64_t steps, n_rebuilds, list_entries;
+  int32_t max_nbrs, n_max, tp, ppb, blocks, ncell;
+} srmd_stats;
+
+srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out);
+
+/* Time the fused step kernel: run nsteps steps one launch at a time with a HIP
+ * event recorded on the system's stream immediately before and after every
+ * step-kernel launch.  kernel_ms receives the sum of those event intervals,
+ * device_ms the same launches timed by the device clock (first block start to last
+ * block end), launches the number of step kernels timed.  The steps are real steps
+ * of the simulation (the state advances).  Any output pointer may be NULL. */
+srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *kernel_ms, double *device_ms,
+                                     int64_t *launches);
 
 /* Message of the last failure on s (or of the calling thread when s is NULL). */
 const char *srmd_last_error(const srmd_system *s);

@@ -47,9 +47,22 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 #define ORACLE_TRUNC 0
 #define ORACLE_SP 1
 #define ORACLE_SF 2
+
+/* threads the OpenMP loops of this file use */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ---- compensated (Neumaier) summation ------------------------------------ */
 typedef struct {

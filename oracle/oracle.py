@@ -20,7 +20,7 @@ METHODS = {"trunc": TRUNC, "sp": SP, "sf": SF}
 
 __all__ = [
     "build", "load", "TRUNC", "SP", "SF", "METHODS", "cut_tables", "pair_set", "neighbors_of",
-    "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate",
+    "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads",
 ]
 
 
@@ -75,6 +75,8 @@ def load():
                                      ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                      ctypes.c_double, _dp, _dp, ctypes.c_int, _dp]
     lib.oracle_integrate.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -239,3 +241,8 @@ def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, th
     if rc_ != 0:
         raise MemoryError("oracle_integrate failed")
     return dict(pos=pos, vel=vel, image=image, xi=xi_c.value, xi_int=xi_i.value, thermo=thermo)
+
+
+def num_threads():
+    """Threads the oracle's OpenMP loops use."""
+    return int(load().oracle_num_threads())

@@ -1,21 +1,22 @@
 // Device kernels of libsrmd for gfx950 (MI355X).
 //
-// Hot path of one time step (paper sections 5-7):
-//   list rebuild (only when the device flag asks for it; every kernel of the chain
-//   exits at once otherwise, the paper's device-side rebuild decision of section 6):
-//     k_bin      cell coordinates of every particle, cell histogram
-//     k_scan     exclusive scan of the histogram -> cell start offsets
-//     k_scatter  one slot per particle inside its cell (arrival order)
-//     k_gather   final slot = cell start + rank of the particle id inside the cell
-//                (deterministic order), gather of every per-particle array
-//                (the spatial reorder of section 7)
-//     k_list     Verlet list from the 5x5x5 cell stencil with cells of side
-//                >= (r_c + s)/2 (section 7), copy of the sorted arrays back
-//   k_step      fused pair force (t_p lanes per particle, section 3 and 5) and
-//               leapfrog / Nose-Hoover update, float64 block partials of
-//               potential energy, virial, kinetic energy and the largest
-//               displacement; the last block to finish reduces them in a fixed
-//               order, updates the thermostat and sets the rebuild flag.
+// One time step (paper sections 5-7) is a short chain of kernels captured in a HIP
+// graph; the decision to rebuild the neighbour list lives on the device (the
+// paper's device-side flag of section 6), so no step needs the host:
+//
+//   list rebuild, only when the flag is set (every kernel exits at once otherwise):
+//     small systems: the spatial sort already ran at the end of the previous step
+//                    (k_finish), so only k_list_wave runs here;
+//     large systems: k_bin (cell histogram), k_scan (cell offsets), k_scatter
+//                    (arrival slots), k_gather (deterministic rank by particle id,
+//                    gather of every per-particle array: the reorder of section 7),
+//                    then k_list_thread;
+//   k_step    pair forces with t_p lanes per particle (sections 3 and 5) fused with
+//             the leapfrog / Nose-Hoover update; float64 partial sums per block;
+//   k_finish  one workgroup: fixed-order float64 reduction of the partials,
+//             thermostat update, thermodynamic record, the displacement test that
+//             sets the rebuild flag (section 6), and for small systems the whole
+//             spatial sort in LDS when a rebuild is due.
 #include "srmd_internal.h"
 
 namespace srmd {
@@ -68,6 +69,34 @@ __device__ __forceinline__ long long nbl_addr(int i, int k, int tp, int nvp) {
   return (long long)(k / tp) * ((long long)nvp * tp) + (long long)i * tp + (k % tp);
 }
 
+// The x extent of one stencil row: up to two runs of consecutive cells
+// [a0, a1] and [b0, b1] (the second one only when the +-2 window wraps round the
+// box), in the order dx = -2 .. +2; every cell when the axis has fewer than 5.
+__device__ __forceinline__ void row_runs(int cx, int nx, bool full, int &a0, int &a1, int &b0, int &b1) {
+  b0 = 0;
+  b1 = -1;
+  if (full) {
+    a0 = 0;
+    a1 = nx - 1;
+    return;
+  }
+  const int lo = cx - 2, hi = cx + 2;
+  if (lo < 0) {
+    a0 = lo + nx;
+    a1 = nx - 1;
+    b0 = 0;
+    b1 = hi;
+  } else if (hi >= nx) {
+    a0 = lo;
+    a1 = nx - 1;
+    b0 = 0;
+    b1 = hi - nx;
+  } else {
+    a0 = lo;
+    a1 = hi;
+  }
+}
+
 // Pair table staged in LDS.
 struct SharedPairs {
   float rc2[kMaxPairs], sig2[kMaxPairs], eps4[kMaxPairs], eps24[kMaxPairs], ushift[kMaxPairs], fc[kMaxPairs],
@@ -87,16 +116,36 @@ __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) 
   }
 }
 
+// Position of particle i widened once for the float64 coordinate differences.
+struct Wide {
+  double x, y, z;
+};
+
+__device__ __forceinline__ Wide widen(const float4 p) { return Wide{(double)p.x, (double)p.y, (double)p.z}; }
+
 // One pair contribution (12-6 Lennard-Jones, paper section 2 cutoff methods).
+// The in/out decision uses the specified float32 squared distance (the same bits
+// as the list build and the CPU reference).  The value uses the coordinate
+// differences recomputed in float64 with the same image shift and rounded once to
+// float32: across the periodic boundary x_j - x_i is close to L, and rounding it
+// in float32 first would cost about ulp(L/2) of absolute accuracy.
 // Accumulates the force on i (-fr * d, with fr = F(r)/r and d = r_j - r_i), the
 // pair energy u and fr * r^2 (= r . F) for the virial.
 template <int METHOD>
-__device__ __forceinline__ void pair_acc(const float4 pi, const float4 pj, int ti, int ntypes, const SharedPairs &sp,
-                                         const SysConst &c, float &fx, float &fy, float &fz, float &u, float &w) {
-  float dx, dy, dz;
-  const float r2 = dist2(pi, pj, c, dx, dy, dz);
+__device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const float4 pj, int ti, int ntypes,
+                                         const SharedPairs &sp, const SysConst &c, float &fx, float &fy, float &fz,
+                                         float &u, float &w) {
+  const float ex = pj.x - pi.x, ey = pj.y - pi.y, ez = pj.z - pi.z;
+  const float mx = __builtin_rintf(ex * c.invL[0]), my = __builtin_rintf(ey * c.invL[1]),
+              mz = __builtin_rintf(ez * c.invL[2]);
+  float dx = __builtin_fmaf(-mx, c.L[0], ex), dy = __builtin_fmaf(-my, c.L[1], ey), dz = __builtin_fmaf(-mz, c.L[2], ez);
+  const float r2s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   const int ab = ti * ntypes + ptype(pj);
-  if (r2 < sp.rc2[ab]) {
+  if (r2s < sp.rc2[ab]) {
+    dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
+    dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
+    dz = (float)(((double)pj.z - wi.z) - (double)mz * c.Ld[2]);
+    const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     const float inv_r2 = __builtin_amdgcn_rcpf(r2);
     const float s2 = sp.sig2[ab] * inv_r2;
     const float s6 = s2 * s2 * s2;
@@ -118,28 +167,41 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const float4 pj, int t
 }
 
 // Force on particle i from lane t of its TP lanes (entries k = t, t+TP, ...).
-template <int TP, int METHOD>
+// The lane's entries are taken B at a time: B list indices are loaded together,
+// then the B neighbour positions, so a batch costs two memory round trips instead
+// of two per entry (the paper prefetches one entry ahead, section 5; on MI355X the
+// latency of a dependent load chain dominates, so many loads go in flight).
+template <int TP, int METHOD, int B>
 __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const float4 *__restrict__ pos,
                                            const int *__restrict__ nbl, int nn, const SharedPairs &sp,
                                            const SysConst &c, float &fx, float &fy, float &fz, float &u, float &w) {
   const int ti = ptype(pi);
+  const Wide wi = widen(pi);
   const long long stride = (long long)c.nvp * TP;
   const int *row = nbl + (long long)i * TP + t;
-  int k = t;
-  // two entries per iteration: both indices, then both positions, are in flight together
-  for (; k + TP < nn; k += 2 * TP) {
-    const int j0 = __builtin_nontemporal_load(row + (long long)(k / TP) * stride);
-    const int j1 = __builtin_nontemporal_load(row + (long long)(k / TP + 1) * stride);
-    const float4 p0 = pos[j0];
-    const float4 p1 = pos[j1];
-    pair_acc<METHOD>(pi, p0, ti, c.ntypes, sp, c, fx, fy, fz, u, w);
-    pair_acc<METHOD>(pi, p1, ti, c.ntypes, sp, c, fx, fy, fz, u, w);
-  }
-  if (k < nn) {
-    const int j0 = __builtin_nontemporal_load(row + (long long)(k / TP) * stride);
-    pair_acc<METHOD>(pi, pos[j0], ti, c.ntypes, sp, c, fx, fy, fz, u, w);
+  const int mine = nn > t ? (nn - t + TP - 1) / TP : 0;  // entries of this lane
+  for (int m0 = 0; m0 < mine; m0 += B) {
+    int j[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      // every load is issued (clamped to the lane's last entry) so none waits behind a branch
+      const int mm = min(m0 + b, mine - 1);
+      j[b] = __builtin_nontemporal_load(row + (long long)mm * stride);
+      if (m0 + b >= mine) j[b] = -1;
+    }
+    float4 q[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) q[b] = pos[j[b] >= 0 ? j[b] : i];
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (j[b] >= 0) pair_acc<METHOD>(pi, wi, q[b], ti, c.ntypes, sp, c, fx, fy, fz, u, w);
   }
 }
+
+template <int TP>
+struct Batch {
+  static constexpr int value = TP >= 8 ? 16 : 8;
+};
 
 template <int TP>
 __device__ __forceinline__ float lane_sum(float v) {
@@ -160,8 +222,26 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(v, o, 64);
+    v = y < v ? y : v;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(v, o, 64);
+    v = y > v ? y : v;
+  }
+  return v;
+}
+
 // Block-wide reduction of one BlockPartial (fixed order: lanes by butterfly, then
-// waves in index order), result valid in thread 0.
+// waves in index order), result valid in thread 0.  Every thread must call it.
 __device__ void block_reduce(BlockPartial &v, BlockPartial *s_waves) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   v.pe = wave_sum(v.pe);
@@ -169,6 +249,8 @@ __device__ void block_reduce(BlockPartial &v, BlockPartial *s_waves) {
   v.ke_half = wave_sum(v.ke_half);
   v.ke_int = wave_sum(v.ke_int);
   v.disp2 = wave_max(v.disp2);
+  v.t0 = wave_min_u64(v.t0);
+  v.t1 = wave_max_u64(v.t1);
   int bad = v.nonfinite;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
@@ -184,34 +266,20 @@ __device__ void block_reduce(BlockPartial &v, BlockPartial *s_waves) {
       a.ke_int += s_waves[k].ke_int;
       a.disp2 = fmax(a.disp2, s_waves[k].disp2);
       a.nonfinite |= s_waves[k].nonfinite;
+      a.t0 = s_waves[k].t0 < a.t0 ? s_waves[k].t0 : a.t0;
+      a.t1 = s_waves[k].t1 > a.t1 ? s_waves[k].t1 : a.t1;
     }
     v = a;
   }
 }
 
-// Reduction of the per-block partials by one wave in a fixed order (independent of
-// which block runs it).
-__device__ BlockPartial reduce_partials(const BlockPartial *part, int G) {
-  const int lane = threadIdx.x & 63;
-  BlockPartial a{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0.0};
-  for (int b = lane; b < G; b += 64) {
-    const BlockPartial q = part[b];
-    a.pe += q.pe;
-    a.w += q.w;
-    a.ke_half += q.ke_half;
-    a.ke_int += q.ke_int;
-    a.disp2 = fmax(a.disp2, q.disp2);
-    a.nonfinite |= q.nonfinite;
-  }
-  a.pe = wave_sum(a.pe);
-  a.w = wave_sum(a.w);
-  a.ke_half = wave_sum(a.ke_half);
-  a.ke_int = wave_sum(a.ke_int);
-  a.disp2 = wave_max(a.disp2);
-  int bad = a.nonfinite;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
-  a.nonfinite = bad;
+__device__ __forceinline__ BlockPartial zero_partial() {
+  BlockPartial a;
+  a.pe = a.w = a.ke_half = a.ke_int = a.disp2 = 0.0;
+  a.nonfinite = 0;
+  a.pad = 0;
+  a.t0 = ~0ull;
+  a.t1 = 0ull;
   return a;
 }
 
@@ -219,18 +287,52 @@ __device__ __forceinline__ bool finite3(float a, float b, float c) {
   return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
 }
 
-// ---------------------------------------------------------------- rebuild chain
+__device__ void list_tally(int cnt, Control *ctl) {
+  __shared__ int s_sum[16];
+  int v = cnt;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += s_sum[k];
+    atomicAdd((unsigned long long *)&ctl->list_entries, (unsigned long long)tot);
+  }
+}
 
-__global__ __launch_bounds__(1024) void k_bin(SysConst c, SysPtrs p, int cur) {
+// Copy the sorted arrays of slot t into place and record its build position.
+__device__ __forceinline__ void place_sorted(const SysPtrs &p, int cur, int t, const float4 r) {
+  p.pos[cur][t] = r;
+  p.last[t] = r;
+  p.vel[t] = p.t_vel[t];
+  p.img[t] = p.t_img[t];
+  if (p.kahan) p.kahan[t] = p.t_kahan[t];
+  if (p.pos64) {
+    p.pos64[3 * t] = p.t_pos64[3 * t];
+    p.pos64[3 * t + 1] = p.t_pos64[3 * t + 1];
+    p.pos64[3 * t + 2] = p.t_pos64[3 * t + 2];
+  }
+}
+
+// ---------------------------------------------------------------- multi-kernel sort (large systems)
+
+__device__ __forceinline__ void begin_build(Control *ctl) {
+  ctl->max_nbrs = 0;
+  ctl->list_entries = 0;
+  ctl->n_rebuilds += 1;
+}
+
+__global__ __launch_bounds__(256) void k_bin(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= c.n) return;
-  const float4 r = p.pos[cur][s];
-  int cx, cy, cz;
-  cell_coords(r, c, cx, cy, cz);
-  const unsigned cell = (unsigned)((cz * c.nc[1] + cy) * c.nc[0] + cx);
-  p.cell_of[s] = cell;
-  p.slot_in_cell[s] = atomicAdd(&p.cell_count[cell], 1u);
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x) {
+    const float4 r = p.pos[cur][s];
+    int cx, cy, cz;
+    cell_coords(r, c, cx, cy, cz);
+    const unsigned cell = (unsigned)((cz * c.nc[1] + cy) * c.nc[0] + cx);
+    p.cell_of[s] = cell;
+    p.slot_in_cell[s] = atomicAdd(&p.cell_count[cell], 1u);
+  }
 }
 
 // Exclusive scan of the cell histogram by one block, in tiles of blockDim.x
@@ -242,15 +344,12 @@ __global__ __launch_bounds__(1024) void k_scan(SysConst c, SysPtrs p) {
   const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
   if (t == 0) {
     s_carry = 0;
-    p.ctl->max_nbrs = 0;
-    p.ctl->n_rebuilds += 1;
-    p.ctl->rebuilt_this_step = 1;
+    begin_build(p.ctl);
   }
   __syncthreads();
   for (int base = 0; base < c.ncell; base += blockDim.x) {
     const int idx = base + t;
     const unsigned v = idx < c.ncell ? p.cell_count[idx] : 0u;
-    // inclusive scan inside the wave
     unsigned x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -277,96 +376,320 @@ __global__ __launch_bounds__(1024) void k_scan(SysConst c, SysPtrs p) {
   if (t == 0) p.cell_start[c.ncell] = s_carry;
 }
 
-__global__ __launch_bounds__(1024) void k_scatter(SysConst c, SysPtrs p) {
+__global__ __launch_bounds__(256) void k_scatter(SysConst c, SysPtrs p) {
   if (p.ctl->rebuild == 0) return;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= c.n) return;
-  p.perm_tmp[p.cell_start[p.cell_of[s]] + p.slot_in_cell[s]] = (unsigned)s;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x)
+    p.perm_tmp[p.cell_start[p.cell_of[s]] + p.slot_in_cell[s]] = (unsigned)s;
 }
 
-__global__ __launch_bounds__(1024) void k_gather(SysConst c, SysPtrs p, int cur) {
+__global__ __launch_bounds__(256) void k_gather(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= c.n) return;
-  const unsigned cell = p.cell_of[s];
-  const unsigned beg = p.cell_start[cell], end = p.cell_start[cell + 1];
-  const int4 im = p.img[s];
-  unsigned rank = 0;
-  for (unsigned u = beg; u < end; ++u) rank += (p.img[p.perm_tmp[u]].w < im.w) ? 1u : 0u;
-  const unsigned dst = beg + rank;
-  p.t_pos[dst] = p.pos[cur][s];
-  p.t_vel[dst] = p.vel[s];
-  p.t_img[dst] = im;
-  if (p.pos64) {
-    p.t_pos64[3 * dst] = p.pos64[3 * s];
-    p.t_pos64[3 * dst + 1] = p.pos64[3 * s + 1];
-    p.t_pos64[3 * dst + 2] = p.pos64[3 * s + 2];
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x) {
+    const unsigned cell = p.cell_of[s];
+    const unsigned beg = p.cell_start[cell], end = p.cell_start[cell + 1];
+    const int4 im = p.img[s];
+    unsigned rank = 0;
+    for (unsigned u = beg; u < end; ++u) rank += (p.img[p.perm_tmp[u]].w < im.w) ? 1u : 0u;
+    const unsigned dst = beg + rank;
+    p.t_pos[dst] = p.pos[cur][s];
+    p.t_vel[dst] = p.vel[s];
+    p.t_img[dst] = im;
+    if (p.pos64) {
+      p.t_pos64[3 * dst] = p.pos64[3 * s];
+      p.t_pos64[3 * dst + 1] = p.pos64[3 * s + 1];
+      p.t_pos64[3 * dst + 2] = p.pos64[3 * s + 2];
+    }
+    if (p.kahan) p.t_kahan[dst] = p.kahan[s];
   }
-  if (p.kahan) p.t_kahan[dst] = p.kahan[s];
 }
 
-// Verlet list of particle t (sorted slot) from the cell stencil; also moves the
-// sorted arrays into place and records the build positions.
-__global__ __launch_bounds__(1024) void k_list(SysConst c, SysPtrs p, int cur) {
+// ---------------------------------------------------------------- one-workgroup sort (small systems)
+
+constexpr int kSmallN = 8192;
+constexpr int kSmallCells = 8192;
+
+// The whole spatial sort of a small system by the calling workgroup, in LDS: cell
+// histogram with LDS atomics, exclusive scan (also written to cell_start), the
+// particle ids placed by arrival order in their cell, a deterministic rank by
+// particle id inside each cell, and the gather of every per-particle array to its
+// sorted slot in the t_* arrays (section 7 steps 1-3).  Every thread of the block
+// must call it.
+__device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur) {
+  __shared__ unsigned s_cnt[kSmallCells + 1];
+  __shared__ int s_id[kSmallN];
+  __shared__ unsigned s_w[16];
+  __shared__ unsigned s_carry;
+  constexpr int PER = kSmallN / 1024;
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nthr >> 6;
+  const int ncell = c.ncell;
+  for (int k = tid; k <= ncell; k += nthr) s_cnt[k] = 0u;
+  if (tid == 0) {
+    s_carry = 0u;
+    begin_build(p.ctl);
+  }
+  unsigned my_cell[PER], my_slot[PER];
+  int my_id[PER];
+  float4 my_pos[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int sidx = tid + m * nthr;
+    my_cell[m] = 0u;
+    my_slot[m] = 0u;
+    my_id[m] = 0;
+    my_pos[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (sidx < c.n) {
+      my_pos[m] = p.pos[cur][sidx];
+      my_id[m] = p.img[sidx].w;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int sidx = tid + m * nthr;
+    if (sidx < c.n) {
+      int cx, cy, cz;
+      cell_coords(my_pos[m], c, cx, cy, cz);
+      my_cell[m] = (unsigned)((cz * c.nc[1] + cy) * c.nc[0] + cx);
+      my_slot[m] = atomicAdd(&s_cnt[my_cell[m]], 1u);
+    }
+  }
+  __syncthreads();
+  for (int base = 0; base <= ncell; base += nthr) {
+    const int idx = base + tid;
+    const unsigned v = idx <= ncell ? s_cnt[idx] : 0u;
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wv] = x;
+    __syncthreads();
+    unsigned wbase = 0;
+    for (int k = 0; k < wv; ++k) wbase += s_w[k];
+    if (idx <= ncell) {
+      const unsigned e = s_carry + wbase + x - v;
+      s_cnt[idx] = e;
+      p.cell_start[idx] = e;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned tot = 0;
+      for (int k = 0; k < nw; ++k) tot += s_w[k];
+      s_carry += tot;
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int sidx = tid + m * nthr;
+    if (sidx < c.n) s_id[s_cnt[my_cell[m]] + my_slot[m]] = my_id[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int sidx = tid + m * nthr;
+    if (sidx < c.n) {
+      const unsigned beg = s_cnt[my_cell[m]], end = s_cnt[my_cell[m] + 1];
+      unsigned rank = 0;
+      for (unsigned q = beg; q < end; ++q) rank += (s_id[q] < my_id[m]) ? 1u : 0u;
+      const unsigned dst = beg + rank;
+      p.t_pos[dst] = my_pos[m];
+      p.t_vel[dst] = p.vel[sidx];
+      p.t_img[dst] = p.img[sidx];
+      if (p.pos64) {
+        p.t_pos64[3 * dst] = p.pos64[3 * sidx];
+        p.t_pos64[3 * dst + 1] = p.pos64[3 * sidx + 1];
+        p.t_pos64[3 * dst + 2] = p.pos64[3 * sidx + 2];
+      }
+      if (p.kahan) p.t_kahan[dst] = p.kahan[sidx];
+    }
+  }
+}
+
+// Spatial sort requested from the host (start of a run, new state or parameters).
+__global__ __launch_bounds__(1024) void k_sort_small(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  sort_small_block(c, p, cur);
+}
+
+bool small_sort_fits(int n, int ncell) { return n <= kSmallN && ncell <= kSmallCells; }
+
+// ---------------------------------------------------------------- list builds
+
+constexpr int kWaveCand = 1024;  // candidates per window of the wave builder
+constexpr int kListChunks = 4;   // 64-candidate chunks whose loads are in flight together
+
+// Verlet list of particle t (sorted slot), one wave per particle; for small systems,
+// where one thread per particle (section 7) leaves the chip idle and every thread
+// waits on a long chain of dependent loads.  The 5x5x5 stencil (every cell along
+// an axis with fewer than 5 cells) is cut into rows of consecutive x cells; as
+// particles are sorted by cell index, each row is one or two contiguous slot runs.
+// Lane s loads the bounds of run s, a wave prefix sum gives each run's offset in
+// the candidate sequence, the runs are expanded into LDS, and the candidates are
+// tested 64 at a time; a ballot compacts the hits in candidate order, so the
+// list order is deterministic (stencil row order, then slot order).
+__global__ __launch_bounds__(256) void k_list_wave(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  __shared__ float s_cs2[kMaxPairs];
+  __shared__ unsigned s_cand[4][kWaveCand];
+  if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+  int kept = 0;
+  if (t < c.n) {  // uniform across the wave
+    const float4 r = p.t_pos[t];
+    if (lane == 0) place_sorted(p, cur, t, r);
+    const int ti = ptype(r);
+    int cx, cy, cz;
+    cell_coords(r, c, cx, cy, cz);
+    const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
+    const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
+    const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
+    int a0, a1, b0, b1;
+    row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
+    // run handled by this lane: row = lane / 2, run = lane % 2
+    unsigned run_start = 0, run_len = 0;
+    const int row = lane >> 1;
+    if (row < ny_eff * nz_eff) {
+      const int oy = row % ny_eff, oz = row / ny_eff;
+      const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
+      const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
+      const int rowbase = (zz * ny + yy) * nx;
+      const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
+      if (x1 >= x0) {
+        const unsigned s0 = p.cell_start[rowbase + x0], s1 = p.cell_start[rowbase + x1 + 1];
+        run_start = s0;
+        run_len = s1 - s0;
+      }
+    }
+    unsigned incl = run_len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    const unsigned excl = incl - run_len;
+    const unsigned total = __shfl(incl, 63, 64);
+    const int nmax = c.n_max;
+    int count = 0;
+    unsigned *cand = s_cand[wv];
+    for (unsigned wbase = 0; wbase < total; wbase += kWaveCand) {
+      const unsigned wend = min(total, wbase + (unsigned)kWaveCand);
+      // expand this lane's run into the window
+      const unsigned q0 = max(excl, wbase), q1 = min(excl + run_len, wend);
+      for (unsigned q = q0; q < q1; ++q) cand[q - wbase] = run_start + (q - excl);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const unsigned wlen = wend - wbase;
+      for (unsigned base = 0; base < wlen; base += 64u * kListChunks) {
+        unsigned u[kListChunks];
+        float4 q[kListChunks];
+#pragma unroll
+        for (int cb = 0; cb < kListChunks; ++cb) {
+          const unsigned qi = base + 64u * cb + (unsigned)lane;
+          u[cb] = qi < wlen ? cand[qi] : (unsigned)t;
+          q[cb] = p.t_pos[u[cb]];
+        }
+#pragma unroll
+        for (int cb = 0; cb < kListChunks; ++cb) {
+          bool hit = false;
+          if ((int)u[cb] != t) {
+            float dx, dy, dz;
+            const float r2 = dist2(r, q[cb], c, dx, dy, dz);
+            hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
+          }
+          const unsigned long long mask = __ballot(hit);
+          const int k = count + __popcll(mask & ((1ull << lane) - 1ull));
+          if (hit && k < nmax) p.nbl[nbl_addr(t, k, c.tp, c.nvp)] = (int)u[cb];
+          count += __popcll(mask);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (lane == 0) {
+      kept = min(count, nmax);
+      p.nnb[t] = kept;
+      if (count > nmax) atomicOr(&p.ctl->error, 2);
+      atomicMax(&p.ctl->max_nbrs, count);
+    }
+  }
+  list_tally(kept, p.ctl);  // every thread of the block reaches this barrier once
+}
+
+constexpr int kThreadBatch = 16;  // candidate positions in flight per thread
+
+// Verlet list, one thread per particle (section 7), for large systems where there
+// are enough particles to fill the chip.  Candidates of one stencil row are loaded
+// kThreadBatch at a time so that a row costs about one memory round trip.  Same
+// candidate order, hence the same list, as the wave builder.
+__global__ __launch_bounds__(256) void k_list_thread(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
   if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
   __syncthreads();
-  const int t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (t >= c.n) return;
-  const float4 r = p.t_pos[t];
-  p.pos[cur][t] = r;
-  p.vel[t] = p.t_vel[t];
-  p.img[t] = p.t_img[t];
-  p.last[t] = r;
-  if (p.pos64) {
-    p.pos64[3 * t] = p.t_pos64[3 * t];
-    p.pos64[3 * t + 1] = p.t_pos64[3 * t + 1];
-    p.pos64[3 * t + 2] = p.t_pos64[3 * t + 2];
-  }
-  if (p.kahan) p.kahan[t] = p.t_kahan[t];
-  const int ti = ptype(r);
-  int cx, cy, cz;
-  cell_coords(r, c, cx, cy, cz);
-  const int cc[3] = {cx, cy, cz};
-  int lo[3], hi[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    if (c.full_axis & (1 << k)) {
-      lo[k] = 0;
-      hi[k] = c.nc[k] - 1;
-    } else {
-      lo[k] = cc[k] - 2;
-      hi[k] = cc[k] + 2;
-    }
-  }
-  int cnt = 0;
   const int nmax = c.n_max;
-  for (int oz = lo[2]; oz <= hi[2]; ++oz) {
-    const int zz = (oz + c.nc[2]) % c.nc[2];
-    for (int oy = lo[1]; oy <= hi[1]; ++oy) {
-      const int yy = (oy + c.nc[1]) % c.nc[1];
-      const int rowbase = (zz * c.nc[1] + yy) * c.nc[0];
-      for (int ox = lo[0]; ox <= hi[0]; ++ox) {
-        const int xx = (ox + c.nc[0]) % c.nc[0];
-        const int cell = rowbase + xx;
-        const unsigned beg = p.cell_start[cell], end = p.cell_start[cell + 1];
-        for (unsigned u = beg; u < end; ++u) {
-          if ((int)u == t) continue;
-          const float4 q = p.t_pos[u];
-          float dx, dy, dz;
-          const float r2 = dist2(r, q, c, dx, dy, dz);
-          if (r2 < s_cs2[ti * c.ntypes + ptype(q)]) {
-            if (cnt < nmax) p.nbl[nbl_addr(t, cnt, c.tp, c.nvp)] = (int)u;
-            ++cnt;
+  const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
+  const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
+  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
+  const int stride = gridDim.x * blockDim.x;
+  int kept_sum = 0;
+  for (int t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < c.n; t += stride) {
+    const float4 r = p.t_pos[t];
+    place_sorted(p, cur, t, r);
+    const int ti = ptype(r);
+    int cx, cy, cz;
+    cell_coords(r, c, cx, cy, cz);
+    int a0, a1, b0, b1;
+    row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
+    int count = 0;
+    for (int oz = 0; oz < nz_eff; ++oz) {
+      const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
+      for (int oy = 0; oy < ny_eff; ++oy) {
+        const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
+        const int rowbase = (zz * ny + yy) * nx;
+        const unsigned sa0 = p.cell_start[rowbase + a0], sa1 = p.cell_start[rowbase + a1 + 1];
+        unsigned sb0 = 0, sb1 = 0;
+        if (b1 >= b0) {
+          sb0 = p.cell_start[rowbase + b0];
+          sb1 = p.cell_start[rowbase + b1 + 1];
+        }
+        const unsigned la = sa1 - sa0, lt = la + (sb1 - sb0);
+        for (unsigned base = 0; base < lt; base += kThreadBatch) {
+          unsigned u[kThreadBatch];
+          float4 q[kThreadBatch];
+#pragma unroll
+          for (int b = 0; b < kThreadBatch; ++b) {
+            const unsigned o = base + b;
+            u[b] = o < la ? sa0 + o : sb0 + (o - la);
+            if (o >= lt) u[b] = (unsigned)t;  // past the row: load own slot, skipped below
+            q[b] = p.t_pos[u[b]];
+          }
+#pragma unroll
+          for (int b = 0; b < kThreadBatch; ++b) {
+            if (base + b < lt && (int)u[b] != t) {
+              float dx, dy, dz;
+              const float r2 = dist2(r, q[b], c, dx, dy, dz);
+              if (r2 < s_cs2[ti * c.ntypes + ptype(q[b])]) {
+                if (count < nmax) p.nbl[nbl_addr(t, count, c.tp, c.nvp)] = (int)u[b];
+                ++count;
+              }
+            }
           }
         }
       }
     }
+    const int kept = min(count, nmax);
+    p.nnb[t] = kept;
+    if (count > nmax) atomicOr(&p.ctl->error, 2);
+    atomicMax(&p.ctl->max_nbrs, count);
+    kept_sum += kept;
   }
-  p.nnb[t] = min(cnt, nmax);
-  if (cnt > nmax) atomicOr(&p.ctl->error, 2);
-  atomicMax(&p.ctl->max_nbrs, cnt);
+  list_tally(kept_sum, p.ctl);
 }
 
 // ---------------------------------------------------------------- force only
@@ -375,7 +698,7 @@ template <int TP, int METHOD>
 __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) {
   __shared__ SharedPairs sp;
   __shared__ BlockPartial s_waves[16];
-  __shared__ int s_last;
+  const unsigned long long tstart = wall_clock64();
   stage_pairs(sp, c);
   __syncthreads();
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -384,56 +707,33 @@ __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) 
   const bool active = i < c.n;
   const float4 *pos = p.pos[cur];
   float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
+  float4 vo = make_float4(0.f, 0.f, 0.f, 0.f), pi = vo;
   if (active) {
-    const float4 pi = pos[i];
-    force_lane<TP, METHOD>(i, t, pi, pos, p.nbl, p.nnb[i], sp, c, fx, fy, fz, u, w);
+    pi = pos[i];
+    const int nn = p.nnb[i];
+    if (t == 0) vo = p.vel[i];
+    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, p.nbl, nn, sp, c, fx, fy, fz, u, w);
   }
   fx = lane_sum<TP>(fx);
   fy = lane_sum<TP>(fy);
   fz = lane_sum<TP>(fz);
   u = lane_sum<TP>(u);
   w = lane_sum<TP>(w);
-  BlockPartial v{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0.0};
+  BlockPartial v = zero_partial();
   if (active && t == 0) {
     p.force[i] = make_float4(fx, fy, fz, 0.5f * u);
     v.pe = 0.5 * (double)u;
     v.w = (double)w / 6.0;
-    const float4 vo = p.vel[i];
     const double dvx = vo.x, dvy = vo.y, dvz = vo.z;
-    v.ke_half = 0.5 * c.mass[ptype(pos[i])] * (dvx * dvx + dvy * dvy + dvz * dvz);
+    v.ke_half = 0.5 * c.mass[ptype(pi)] * (dvx * dvx + dvy * dvy + dvz * dvz);
     v.nonfinite = finite3(fx, fy, fz) ? 0 : 1;
   }
+  v.t0 = tstart;
+  v.t1 = wall_clock64();
   block_reduce(v, s_waves);
   if (threadIdx.x == 0) {
     p.part[lb] = v;
-    __threadfence();
-    const unsigned prev = atomicAdd(&p.ctl->counter, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
-  }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if (threadIdx.x < 64) {
-    const BlockPartial a = reduce_partials(p.part, gridDim.x);
-    if (threadIdx.x == 0) {
-      Thermo *th = p.thermo;
-      th->pe = a.pe;
-      th->virial = a.w;
-      th->ke = a.ke_half;  // kinetic energy of the stored (half-step) velocities
-      th->ke_half = a.ke_half;
-      th->temperature = 2.0 * a.ke_half / c.g;
-      th->pressure = (2.0 * a.ke_half / 3.0 + a.w) / c.volume;
-      th->xi = c.thermostat ? p.ctl->xi : 0.0;
-      th->xi_integral = p.ctl->xi_int;
-      th->h_conserved = a.ke_half + a.pe;
-      th->max_nbrs = p.ctl->max_nbrs;
-      th->n_rebuilds = p.ctl->n_rebuilds;
-      th->step = p.ctl->step;
-      if (a.nonfinite) atomicOr(&p.ctl->error, 1);
-      p.ctl->counter = 0u;
-      p.ctl->rebuild = 0;
-      p.ctl->rebuilt_this_step = 0;
-    }
+    if (blockIdx.x == 0) p.ctl->rebuild = 0;  // the list in use is now current
   }
 }
 
@@ -443,7 +743,7 @@ template <int TP, int METHOD, int PREC>
 __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
   __shared__ SharedPairs sp;
   __shared__ BlockPartial s_waves[16];
-  __shared__ int s_last;
+  const unsigned long long tstart = wall_clock64();
   stage_pairs(sp, c);
   __syncthreads();
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -453,37 +753,51 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
   const float4 *pos = p.pos[cur];
   float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  // integrator operands are loaded before the force loop so their latency overlaps it
+  float4 vo = pi, l0 = pi, kc = pi;
+  int4 im = make_int4(0, 0, 0, 0);
+  double x64 = 0.0, y64 = 0.0, z64 = 0.0;
+  const double xi = c.thermostat ? p.ctl->xi : 0.0;
   if (active) {
     pi = pos[i];
-    force_lane<TP, METHOD>(i, t, pi, pos, p.nbl, p.nnb[i], sp, c, fx, fy, fz, u, w);
+    const int nn = p.nnb[i];
+    if (t == 0) {
+      vo = p.vel[i];
+      im = p.img[i];
+      l0 = p.last[i];
+      if (PREC == 1) kc = p.kahan[i];
+      if (PREC == 2) {
+        x64 = p.pos64[3 * i];
+        y64 = p.pos64[3 * i + 1];
+        z64 = p.pos64[3 * i + 2];
+      }
+    }
+    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, p.nbl, nn, sp, c, fx, fy, fz, u, w);
   }
   fx = lane_sum<TP>(fx);
   fy = lane_sum<TP>(fy);
   fz = lane_sum<TP>(fz);
   u = lane_sum<TP>(u);
   w = lane_sum<TP>(w);
-  const double xi = p.ctl->xi;
-  BlockPartial v{0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0.0};
+  BlockPartial v = zero_partial();
   if (active && t == 0) {
     const int ti = ptype(pi);
     // v(n+1/2) = [v(n-1/2) (1 - xi dt/2) + F/m dt] / (1 + xi dt/2); a = b = 1 without thermostat
-    const double hx = c.thermostat ? 0.5 * xi * c.dtd : 0.0;
+    const double hx = 0.5 * xi * c.dtd;
     const float a = (float)(1.0 - hx);
     const float ib = (float)(1.0 / (1.0 + hx));
     const float dtm = c.dt * c.inv_mass[ti];
-    const float4 vo = p.vel[i];
     const float vx = __builtin_fmaf(vo.x, a, fx * dtm) * ib;
     const float vy = __builtin_fmaf(vo.y, a, fy * dtm) * ib;
     const float vz = __builtin_fmaf(vo.z, a, fz * dtm) * ib;
     p.vel[i] = make_float4(vx, vy, vz, vo.w);
     p.force[i] = make_float4(fx, fy, fz, 0.5f * u);
-    int4 im = p.img[i];
     float4 rn;
     rn.w = pi.w;
     if (PREC == 2) {  // float64 master positions
-      double x = p.pos64[3 * i] + (double)vx * c.dtd;
-      double y = p.pos64[3 * i + 1] + (double)vy * c.dtd;
-      double z = p.pos64[3 * i + 2] + (double)vz * c.dtd;
+      double x = x64 + (double)vx * c.dtd;
+      double y = y64 + (double)vy * c.dtd;
+      double z = z64 + (double)vz * c.dtd;
       if (x >= 0.5 * c.Ld[0]) { x -= c.Ld[0]; im.x += 1; } else if (x < -0.5 * c.Ld[0]) { x += c.Ld[0]; im.x -= 1; }
       if (y >= 0.5 * c.Ld[1]) { y -= c.Ld[1]; im.y += 1; } else if (y < -0.5 * c.Ld[1]) { y += c.Ld[1]; im.y -= 1; }
       if (z >= 0.5 * c.Ld[2]) { z -= c.Ld[2]; im.z += 1; } else if (z < -0.5 * c.Ld[2]) { z += c.Ld[2]; im.z -= 1; }
@@ -500,7 +814,6 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
     } else {
       float x, y, z;
       if (PREC == 1) {  // compensated update: y = v dt - c; t = r + y; c = (t - r) - y
-        float4 kc = p.kahan[i];
         const float yx = vx * c.dt - kc.x, yy = vy * c.dt - kc.y, yz = vz * c.dt - kc.z;
         x = pi.x + yx;
         y = pi.y + yy;
@@ -533,7 +846,6 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
     v.pe = 0.5 * (double)u;
     v.w = (double)w / 6.0;
     // displacement since the last build: float64 from the float32 positions
-    const float4 l0 = p.last[i];
     double ddx = (double)rn.x - (double)l0.x, ddy = (double)rn.y - (double)l0.y, ddz = (double)rn.z - (double)l0.z;
     ddx -= c.Ld[0] * rint(ddx / c.Ld[0]);
     ddy -= c.Ld[1] * rint(ddy / c.Ld[1]);
@@ -541,27 +853,66 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
     v.disp2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
     v.nonfinite = (finite3(fx, fy, fz) && finite3(rn.x, rn.y, rn.z)) ? 0 : 1;
   }
+  v.t0 = tstart;
+  v.t1 = wall_clock64();
   block_reduce(v, s_waves);
   if (threadIdx.x == 0) {
     p.part[lb] = v;
-    __threadfence();
-    const unsigned prev = atomicAdd(&p.ctl->counter, 1u);
-    s_last = (prev == gridDim.x - 1) ? 1 : 0;
+    if (blockIdx.x == 0) p.ctl->rebuild = 0;  // the list of this step has been consumed
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  if (threadIdx.x < 64) {
-    const BlockPartial a = reduce_partials(p.part, gridDim.x);
-    if (threadIdx.x == 0) {
-      Control *ctl = p.ctl;
+}
+
+// ---------------------------------------------------------------- end of step
+
+// One workgroup after the step (MODE 0) or force-only (MODE 1) kernel: fixed-order
+// float64 reduction of the G block partials (each thread sums its blocks in index
+// order, then lanes by butterfly and waves in order), the Nose-Hoover update, the
+// thermodynamic record, the displacement test that sets the rebuild flag, and for
+// small systems the spatial sort for the next list build (positions pos[next]).
+template <int MODE>
+__global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, int next) {
+  __shared__ BlockPartial s_waves[16];
+  __shared__ int s_rebuild;
+  BlockPartial a = zero_partial();
+  for (int b = threadIdx.x; b < G; b += blockDim.x) {
+    const BlockPartial q = p.part[b];
+    a.pe += q.pe;
+    a.w += q.w;
+    a.ke_half += q.ke_half;
+    a.ke_int += q.ke_int;
+    a.disp2 = fmax(a.disp2, q.disp2);
+    a.nonfinite |= q.nonfinite;
+    a.t0 = q.t0 < a.t0 ? q.t0 : a.t0;
+    a.t1 = q.t1 > a.t1 ? q.t1 : a.t1;
+  }
+  block_reduce(a, s_waves);
+  if (threadIdx.x == 0) {
+    Control *ctl = p.ctl;
+    int rebuild = 0;
+    if (MODE == 1) {
+      Thermo *th = p.thermo;
+      th->pe = a.pe;
+      th->virial = a.w;
+      th->ke = a.ke_half;  // kinetic energy of the stored (half-step) velocities
+      th->ke_half = a.ke_half;
+      th->temperature = 2.0 * a.ke_half / c.g;
+      th->pressure = (2.0 * a.ke_half / 3.0 + a.w) / c.volume;
+      th->xi = c.thermostat ? ctl->xi : 0.0;
+      th->xi_integral = ctl->xi_int;
+      th->h_conserved = a.ke_half + a.pe;
+      th->max_nbrs = ctl->max_nbrs;
+      th->n_rebuilds = ctl->n_rebuilds;
+      th->step = ctl->step;
+      if (a.nonfinite) ctl->error |= 1;
+    } else {
+      const double xi = c.thermostat ? ctl->xi : 0.0;
       Thermo rec;
       rec.pe = a.pe;
       rec.ke = a.ke_int;
       rec.virial = a.w;
       rec.temperature = 2.0 * a.ke_int / c.g;
       rec.pressure = (2.0 * a.ke_int / 3.0 + a.w) / c.volume;
-      rec.xi = c.thermostat ? xi : 0.0;
+      rec.xi = xi;
       rec.xi_integral = ctl->xi_int;
       rec.h_conserved = a.ke_int + a.pe;
       if (c.thermostat && c.inv_tau2 > 0.0)
@@ -583,12 +934,16 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
         ctl->xi = xn;
       }
       ctl->step += 1;
-      ctl->rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
-      ctl->rebuilt_this_step = 0;
+      ctl->prof_ticks += a.t1 - a.t0;
+      ctl->prof_count += 1;
+      rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
+      ctl->rebuild = rebuild;
       if (a.nonfinite) ctl->error |= 1;
-      ctl->counter = 0u;
     }
+    s_rebuild = rebuild;
   }
+  __syncthreads();
+  if (MODE == 0 && s_rebuild && c.small_sort) sort_small_block(c, p, next);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -648,14 +1003,37 @@ hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t
   }
 }
 
+hipError_t launch_finish(int mode, int G, int next, hipStream_t st, const SysConst &c, const SysPtrs &p) {
+  if (mode == 0) hipLaunchKernelGGL((k_finish<0>), dim3(1), dim3(1024), 0, st, c, p, G, next);
+  else hipLaunchKernelGGL((k_finish<1>), dim3(1), dim3(1024), 0, st, c, p, G, next);
+  return hipGetLastError();
+}
+
+// Sort requested by the host for a small system (the multi-kernel sort of large
+// systems always runs at the start of the step, gated on the flag).
+hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur) {
+  if (!c.small_sort) return hipSuccess;
+  hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, st, c, p, cur);
+  return hipGetLastError();
+}
+
+// Start-of-step rebuild chain: list build (small systems; the sort ran earlier) or
+// the multi-kernel sort followed by the list build (large systems).
 hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur) {
   const int tb = 256;
-  const int nb = (c.n + tb - 1) / tb;
-  hipLaunchKernelGGL(k_bin, dim3(nb), dim3(tb), 0, st, c, p, cur);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, c, p);
-  hipLaunchKernelGGL(k_scatter, dim3(nb), dim3(tb), 0, st, c, p);
-  hipLaunchKernelGGL(k_gather, dim3(nb), dim3(tb), 0, st, c, p, cur);
-  hipLaunchKernelGGL(k_list, dim3(nb), dim3(tb), 0, st, c, p, cur);
+  const int gb = c.list_blocks;
+  if (!c.small_sort) {
+    hipLaunchKernelGGL(k_bin, dim3(gb), dim3(tb), 0, st, c, p, cur);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, c, p);
+    hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(tb), 0, st, c, p);
+    hipLaunchKernelGGL(k_gather, dim3(gb), dim3(tb), 0, st, c, p, cur);
+  }
+  if (c.wave_list) {
+    const int lb = (c.n + 3) / 4;
+    hipLaunchKernelGGL(k_list_wave, dim3(lb), dim3(tb), 0, st, c, p, cur);
+  } else {
+    hipLaunchKernelGGL(k_list_thread, dim3(gb), dim3(tb), 0, st, c, p, cur);
+  }
   return hipGetLastError();
 }
 

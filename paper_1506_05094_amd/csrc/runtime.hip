@@ -19,6 +19,9 @@ hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hi
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur);
 hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
+hipError_t launch_finish(int mode, int G, int next, hipStream_t st, const SysConst &c, const SysPtrs &p);
+hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
+bool small_sort_fits(int n, int ncell);
 }  // namespace srmd
 
 using namespace srmd;
@@ -63,6 +66,8 @@ struct srmd_system {
   // launch shape
   int tp_req = 0, ppb_req = 0, tp = 0, ppb = 0;
   int tp_tuned = 0, ppb_tuned = 0;
+  int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread
+  bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   // derived layout
   bool dirty = true;  // SysConst must be rebuilt
   SysConst c{};
@@ -198,7 +203,18 @@ srmd_status set_ctl_int(srmd_system *s, size_t offset, int value) {
   return h2d_sync(s, reinterpret_cast<char *>(s->p.ctl) + offset, &value, sizeof(int));
 }
 
-srmd_status request_rebuild(srmd_system *s) { return set_ctl_int(s, offsetof(Control, rebuild), 1); }
+srmd_status request_rebuild(srmd_system *s) {
+  s->sort_pending = true;
+  return set_ctl_int(s, offsetof(Control, rebuild), 1);
+}
+
+// A host-requested rebuild of a small system needs its sort before the list build.
+srmd_status flush_host_sort(srmd_system *s) {
+  if (!s->sort_pending) return SRMD_OK;
+  s->sort_pending = false;
+  HIPCHK(s, launch_host_sort(s->stream, s->c, s->p, s->cur));
+  return SRMD_OK;
+}
 
 // Rebuild the kernel constants, the cell grid and the list storage after any change
 // of parameters or launch shape.
@@ -234,6 +250,10 @@ srmd_status prepare(srmd_system *s) {
   }
   c.ncell = c.nc[0] * c.nc[1] * c.nc[2];
   c.volume = V;
+  const bool fits = small_sort_fits(s->n, c.ncell);
+  c.small_sort = (s->sort_mode == 0 || s->sort_mode == 1) && fits ? 1 : 0;
+  c.wave_list = s->list_mode == 1 || (s->list_mode == 0 && s->n <= 65536) ? 1 : 0;
+  c.list_blocks = std::max(1, std::min((s->n + 255) / 256, 2048));
   // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
   const double rho = s->n / V;
   int nmax = (int)std::ceil(1.5 * 4.0 / 3.0 * M_PI * reach * reach * reach * rho + 32.0);
@@ -304,6 +324,7 @@ srmd_status enqueue_steps(srmd_system *s, int count, int cur) {
     const int cb = (cur + k) & 1;
     HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, cb));
     HIPCHK(s, launch_step(s->tp, s->method, (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb));
+    HIPCHK(s, launch_finish(0, step_blocks(s), cb ^ 1, s->stream, s->c, s->p));
   }
   return SRMD_OK;
 }
@@ -381,6 +402,8 @@ srmd_status regrow(srmd_system *s) {
 }
 
 srmd_status run_steps(srmd_system *s, long long nsteps) {
+  srmd_status st0 = flush_host_sort(s);
+  if (st0 != SRMD_OK) return st0;
   long long left = nsteps;
   while (left > 0) {
     const int cnt = (int)std::min<long long>(left, kChunk);
@@ -647,6 +670,16 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb) {
   return SRMD_OK;
 }
 
+srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 2)
+    return fail(s, SRMD_EINVAL, "modes must be 0 (auto), 1 or 2");
+  s->sort_mode = sort_mode;
+  s->list_mode = list_mode;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
 srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
   int a, b;
@@ -662,6 +695,8 @@ srmd_status srmd_build_neighbor_list(srmd_system *s) {
   if (st != SRMD_OK) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
     st = request_rebuild(s);
+    if (st != SRMD_OK) return st;
+    st = flush_host_sort(s);
     if (st != SRMD_OK) return st;
     HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, s->cur));
     st = set_ctl_int(s, offsetof(Control, rebuild), 0);
@@ -683,8 +718,11 @@ srmd_status srmd_compute_forces(srmd_system *s, srmd_thermo *out) {
   srmd_status st = prepare(s);
   if (st != SRMD_OK) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
+    st = flush_host_sort(s);
+    if (st != SRMD_OK) return st;
     HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, s->cur));
     HIPCHK(s, launch_force(s->tp, s->method, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur));
+    HIPCHK(s, launch_finish(1, step_blocks(s), s->cur, s->stream, s->c, s->p));
     Control h;
     st = read_ctl(s, &h);
     if (st != SRMD_OK) return st;
@@ -901,6 +939,91 @@ srmd_status srmd_get_thermo(srmd_system *s, srmd_thermo *out) {
 srmd_status srmd_get_box(const srmd_system *s, double box[3]) {
   if (!s || !box) return fail(nullptr, SRMD_EINVAL, "NULL argument");
   for (int k = 0; k < 3; ++k) box[k] = (double)s->Lf[k];
+  return SRMD_OK;
+}
+
+srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out) {
+  if (!s || !out) return fail(s, SRMD_EINVAL, "NULL argument");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  Control h;
+  st = read_ctl(s, &h);
+  if (st != SRMD_OK) return st;
+  out->steps = h.step;
+  out->n_rebuilds = h.n_rebuilds;
+  out->list_entries = h.list_entries;
+  out->max_nbrs = h.max_nbrs;
+  out->n_max = s->c.n_max;
+  out->tp = s->tp;
+  out->ppb = s->ppb;
+  out->blocks = step_blocks(s);
+  out->ncell = s->c.ncell;
+  return SRMD_OK;
+}
+
+srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *kernel_ms, double *device_ms,
+                                     int64_t *launches) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (nsteps < 0) return fail(s, SRMD_EINVAL, "nsteps must be >= 0");
+  if (!s->integrator_set) return fail(s, SRMD_EINVAL, "integrator not set");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  Control h;
+  st = read_ctl(s, &h);
+  if (st != SRMD_OK) return st;
+  h.prof_ticks = 0;
+  h.prof_count = 0;
+  h.thermo_every = 0;
+  h.trace_cap = 0;
+  st = h2d_sync(s, s->p.ctl, &h, sizeof(Control));
+  if (st != SRMD_OK) return st;
+  const int batch = 256;  // events per synchronisation
+  std::vector<hipEvent_t> ev(2 * batch);
+  for (auto &e : ev) HIPCHK(s, hipEventCreate(&e));
+  double total = 0.0;
+  long long done = 0;
+  srmd_status result = SRMD_OK;
+  st = flush_host_sort(s);
+  if (st != SRMD_OK) result = st;
+  while (done < nsteps && result == SRMD_OK) {
+    const int cnt = (int)std::min<long long>(batch, nsteps - done);
+    for (int k = 0; k < cnt && result == SRMD_OK; ++k) {
+      hipError_t e = launch_rebuild(s->stream, s->c, s->p, s->cur);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * k], s->stream);
+      if (e == hipSuccess)
+        e = launch_step(s->tp, s->method, (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s->stream);
+      if (e == hipSuccess) e = launch_finish(0, step_blocks(s), s->cur ^ 1, s->stream, s->c, s->p);
+      if (e != hipSuccess) result = fail(s, SRMD_EHIP, std::string("profiled launch: ") + hipGetErrorString(e));
+      s->cur ^= 1;
+    }
+    if (result != SRMD_OK) break;
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+      result = fail(s, SRMD_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+      break;
+    }
+    for (int k = 0; k < cnt; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+      if (e != hipSuccess) {
+        result = fail(s, SRMD_EHIP, std::string("hipEventElapsedTime: ") + hipGetErrorString(e));
+        break;
+      }
+      total += ms;
+    }
+    done += cnt;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  if (result != SRMD_OK) return result;
+  st = read_ctl(s, &h);
+  if (st != SRMD_OK) return st;
+  if (h.error & 3) return fail(s, SRMD_ESTATE, "list overflow or non-finite state during profiling");
+  int rate_khz = 0;
+  HIPCHK(s, hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, 0));
+  if (kernel_ms) *kernel_ms = total;
+  if (device_ms) *device_ms = rate_khz > 0 ? (double)h.prof_ticks / (double)rate_khz : 0.0;
+  if (launches) *launches = done;
   return SRMD_OK;
 }
 

@@ -45,6 +45,9 @@ struct SysConst {
   double g;          // degrees of freedom 3N - 3
   double volume;
   int thermostat;    // 1: Nose-Hoover
+  int small_sort;    // 1: the spatial sort runs in one workgroup (small systems)
+  int wave_list;     // 1: one wave per particle builds the list; 0: one thread per particle
+  int list_blocks;   // grid of the thread-per-particle list build and the sort kernels
   int pad1;
   float inv_mass[kMaxTypes];
   double mass[kMaxTypes];
@@ -65,7 +68,11 @@ struct Control {
   int rebuilt_this_step; // set by the list build, cleared by the step kernel
   int thermo_every;      // record every k-th step into the trace (0: never)
   long long trace_cap;   // capacity of the device trace
-  int pad[32];
+  long long list_entries;   // total entries of the current list
+  unsigned long long prof_t0;     // device clock at the start of the current step kernel
+  unsigned long long prof_ticks;  // accumulated step-kernel durations (device clock ticks)
+  long long prof_count;           // step kernels accumulated
+  int pad[24];
 };
 
 // Thermo accumulators of the last force evaluation / step.
@@ -75,12 +82,13 @@ struct Thermo {
   int max_nbrs, reserved;
 };
 
-// Per-block float64 partial sums of the step and force kernels.
+// Per-block float64 partial sums of the step and force kernels, and the device
+// clock at the block's start and end (for the kernel's duration).
 struct BlockPartial {
   double pe, w, ke_half, ke_int, disp2;
   int nonfinite;
   int pad;
-  double pad2;
+  unsigned long long t0, t1;
 };
 
 struct SysPtrs {

@@ -32,6 +32,15 @@ class srmd_thermo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class srmd_stats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64), ("list_entries", ctypes.c_int64),
+                ("max_nbrs", ctypes.c_int32), ("n_max", ctypes.c_int32), ("tp", ctypes.c_int32),
+                ("ppb", ctypes.c_int32), ("blocks", ctypes.c_int32), ("ncell", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 THERMO_DTYPE = np.dtype([(name, np.float64) for name in
                          ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_integral", "h_conserved",
                           "ke_half")] + [("step", np.int64), ("n_rebuilds", np.int64), ("max_nbrs", np.int32),
@@ -82,6 +91,7 @@ def load():
         "srmd_set_integrator_nvt": (st, [sysp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_get_launch": (st, [sysp, _ip, _ip]),
+        "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_autotune": (st, [sysp, ctypes.c_int32, _ip, _ip]),
         "srmd_build_neighbor_list": (st, [sysp]),
         "srmd_compute_forces": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
@@ -92,6 +102,8 @@ def load():
         "srmd_get_thermo": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
         "srmd_get_box": (st, [sysp, _dp]),
         "srmd_last_error": (ctypes.c_char_p, [sysp]),
+        "srmd_get_stats": (st, [sysp, ctypes.POINTER(srmd_stats)]),
+        "srmd_profile_step_kernel": (st, [sysp, ctypes.c_int64, _dp, _dp, ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -207,6 +219,9 @@ class System:
     def set_launch(self, tp, ppb):
         _check(load().srmd_set_launch(self._h, int(tp), int(ppb)), self._h)
 
+    def set_rebuild_path(self, sort_mode=0, list_mode=0):
+        _check(load().srmd_set_rebuild_path(self._h, int(sort_mode), int(list_mode)), self._h)
+
     def get_launch(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(load().srmd_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
@@ -266,6 +281,18 @@ class System:
         _check(load().srmd_get_thermo(self._h, ctypes.byref(t)), self._h)
         return t.as_dict()
 
+    def stats(self):
+        t = srmd_stats()
+        _check(load().srmd_get_stats(self._h, ctypes.byref(t)), self._h)
+        return t.as_dict()
+
+    def profile_step_kernel(self, nsteps):
+        """(sum of HIP-event intervals around the step kernel [ms], device-clock sum [ms], launches)."""
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(load().srmd_profile_step_kernel(self._h, int(nsteps), ctypes.byref(a), ctypes.byref(b),
+                                               ctypes.byref(c)), self._h)
+        return a.value, b.value, c.value
+
     def box(self):
         b = np.zeros(3)
         _check(load().srmd_get_box(self._h, _ptr(b, _dp)), self._h)
@@ -275,7 +302,8 @@ class System:
 EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_lj", "srmd_set_skin",
             "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
             "srmd_autotune", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
-            "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error"]
+            "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
+            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path"]
 
 
 def _export_c_names():

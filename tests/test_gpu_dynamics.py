@@ -1,0 +1,323 @@
+"""GPU dynamics: rebuild paths, the skin invariant, the rebuild schedule, list
+overflow recovery, energy drift, thermostat, precision variants, determinism and
+sampled parity at the large sizes of the size sweep."""
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import oracle
+from workloads import generators as gen
+
+from gpu_common import ENERGY_TOL, FORCE_TOL, force_error, make_system, min_image, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1506_05094_amd import srmd
+    srmd.load()
+    oracle.load()
+
+
+def _in_range_pairs(pos, types, box, rc):
+    """Ordered pairs closer than rc_ab (float64 distances from float32 positions)."""
+    p = np.mod(pos.astype(np.float64) + box / 2, box)
+    tree = cKDTree(p, boxsize=box)
+    pr = tree.query_pairs(float(np.max(rc)), output_type="ndarray")
+    d = min_image(p[pr[:, 0]] - p[pr[:, 1]], box)
+    r = np.sqrt((d * d).sum(1))
+    keep = pr[r < rc[types[pr[:, 0]], types[pr[:, 1]]] * (1 - 1e-6)]
+    both = np.concatenate([keep, keep[:, ::-1]])
+    return both[:, 0].astype(np.int64) * len(pos) + both[:, 1]
+
+
+PATHS = [(1, 1), (2, 1), (1, 2), (2, 2)]
+
+
+@pytest.mark.parametrize("paths", PATHS)
+def test_rebuild_paths_same_list(paths):
+    state = gen.jitter_positions(gen.config1_state(), 0.05, 2)
+    sig, eps, rc = gen.ka_params()
+    print(f"paths {paths}", flush=True)
+    with make_system(state, sig, eps, rc, "sf") as s:
+        s.set_rebuild_path(*paths)
+        s.build_neighbor_list()
+        got = s.neighbor_pairs()
+    cs2, _ = oracle.cut_tables(rc, 0.3)
+    ref = oracle.pair_set(state.pos, state.types, state.box, cs2)
+    np.testing.assert_array_equal(got, ref)
+
+
+def test_rebuild_paths_bitwise_same_trajectory():
+    state = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    out = []
+    for paths in PATHS:
+        with make_system(state, sig, eps, rc, "sp") as s:
+            s.set_rebuild_path(*paths)
+            s.set_integrator_nve(0.005)
+            tr = s.step(300, thermo_every=50)
+            st = s.get_state()
+            out.append((st["pos"], st["vel"], tr["pe"], tr["n_rebuilds"]))
+    for o in out[1:]:
+        np.testing.assert_array_equal(o[0], out[0][0])
+        np.testing.assert_array_equal(o[1], out[0][1])
+        np.testing.assert_array_equal(o[2], out[0][2])
+        np.testing.assert_array_equal(o[3], out[0][3])
+    assert out[0][3][-1] >= 3  # several rebuilds happened
+
+
+def test_run_twice_bitwise_and_chunking():
+    state = gen.config1_state()
+    sig, eps, rc = gen.ka_params()
+    res = []
+    for split in ([200], [37, 63, 100], [1] * 10 + [190]):
+        with make_system(state, sig, eps, rc, "sf") as s:
+            s.set_integrator_nvt(0.002, 0.45, 0.2)
+            for k in split:
+                s.step(k)
+            res.append((s.get_state(), s.thermo()))
+    for st, th in res[1:]:
+        np.testing.assert_array_equal(st["pos"], res[0][0]["pos"])
+        np.testing.assert_array_equal(st["vel"], res[0][0]["vel"])
+        np.testing.assert_array_equal(st["image"], res[0][0]["image"])
+        assert th["xi"] == res[0][1]["xi"]
+        assert th["step"] == 199
+
+
+def test_skin_superset_every_step():
+    state = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    with make_system(state, sig, eps, rc, "sp") as s:
+        s.set_integrator_nve(0.005)
+        rebuilds = set()
+        for k in range(150):
+            s.step(1)
+            st = s.get_state()
+            have = s.neighbor_pairs()
+            key = have[:, 0].astype(np.int64) * state.n + have[:, 1]
+            need = _in_range_pairs(st["pos"], state.types, state.box, rc)
+            assert np.isin(need, key).all(), f"step {k}: in-range pair missing from the list"
+            rebuilds.add(s.stats()["n_rebuilds"])
+        assert len(rebuilds) > 3
+
+
+def test_rebuild_schedule_matches_half_skin_criterion():
+    state = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    skin = 0.3
+    with make_system(state, sig, eps, rc, "sp", skin=skin) as s:
+        s.set_integrator_nve(0.005)
+        s.compute_forces()  # builds the list at the initial positions
+        last = s.get_state()["pos"].astype(np.float64)
+        nb = s.stats()["n_rebuilds"]
+        for k in range(200):
+            s.step(1)
+            pos = s.get_state()["pos"].astype(np.float64)
+            d = min_image(pos - last, state.box)
+            d2 = (d[:, 0] ** 2 + d[:, 1] ** 2) + d[:, 2] ** 2
+            due = d2.max() > (0.5 * skin) ** 2
+            s.compute_forces()  # rebuilds iff the device flag is set
+            nb2 = s.stats()["n_rebuilds"]
+            assert (nb2 > nb) == due, f"step {k}: rebuild {nb2 > nb}, criterion {due}"
+            if nb2 > nb:
+                last = pos
+            nb = nb2
+
+
+def test_list_overflow_regrow_and_replay():
+    # a dense cluster inside a dilute gas overflows the capacity sized for the mean density
+    rng = np.random.default_rng(0)
+    L = 14.0
+    g = (np.arange(7) - 3) * 0.55
+    cl = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)  # 343 sites, spacing 0.55
+    cl += rng.uniform(-0.02, 0.02, cl.shape)
+    gas = rng.uniform(-L / 2, L / 2, (2000, 3))
+    gas = gas[np.abs(gas).max(1) > 2.8][:900]  # no gas particle inside or near the cluster
+    pos = np.concatenate([gas, cl]).astype(np.float32)
+    types = np.zeros(len(pos), np.int32)
+    box = np.array([L, L, L])
+    from paper_1506_05094_amd import srmd
+    import torch
+    with srmd.System(pos, types, box, stream=torch.cuda.current_stream().cuda_stream) as s:
+        s.set_skin(0.3)
+        s.set_pair_lj(0, 0, 1.0, 1.0, 2.5, "sp")
+        n_max0 = s.stats()["n_max"]
+        s.build_neighbor_list()
+        st = s.stats()
+        assert st["max_nbrs"] > n_max0
+        assert st["n_max"] >= st["max_nbrs"]
+        got = s.neighbor_pairs()
+        th = s.compute_forces()
+        F = s.get_state()["force"]
+    cs2, _ = oracle.cut_tables(np.array([[2.5]]), 0.3)
+    ref = oracle.pair_set(pos, types, box, cs2)
+    np.testing.assert_array_equal(got, ref)
+    Fr, _, _, U, W = oracle.forces_f32(pos, types, box, np.array([[1.0]]), np.array([[1.0]]), np.array([[2.5]]), "sp")
+    assert force_error(F, Fr) <= FORCE_TOL
+    assert rel(th["pe"], U) <= ENERGY_TOL
+
+
+def test_overflow_during_steps_replays():
+    # a dilute gas that contracts towards the centre: the list capacity is sized for the
+    # starting density and must grow during the run
+    rng = np.random.default_rng(1)
+    L = 12.0
+    g = (np.arange(9) - 4) * (L / 9)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos += rng.uniform(-0.1, 0.1, pos.shape)
+    n = len(pos)
+    vel = (-0.5 * pos).astype(np.float32)
+    pos = pos.astype(np.float32)
+    from paper_1506_05094_amd import srmd
+    import torch
+    with srmd.System(pos, np.zeros(n, np.int32), [L, L, L], vel=vel,
+                     stream=torch.cuda.current_stream().cuda_stream) as s:
+        s.set_skin(0.4)
+        s.set_pair_lj(0, 0, 1.0, 0.05, 2.5, "sp")
+        s.set_integrator_nve(0.002)
+        n0 = s.stats()["n_max"]
+        s.step(400)
+        st = s.stats()
+        th = s.thermo()
+    print("n_max", n0, "->", st["n_max"], "max_nbrs", st["max_nbrs"])
+    assert np.isfinite(th["pe"])
+    assert st["n_max"] > n0            # the capacity grew: an overflow happened and was replayed
+    assert st["n_max"] >= st["max_nbrs"]
+
+
+def test_nve_energy_drift_config0():
+    state = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    steps = 1000
+    with make_system(state, sig, eps, rc, "sp") as s:
+        s.set_integrator_nve(0.005)
+        tr = s.step(steps, thermo_every=1)
+    E = (tr["pe"] + tr["ke"]) / state.n
+    t = np.arange(steps)
+    slope = np.polyfit(t, E, 1)[0]
+    ref = oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, "sp", 0.005, steps)
+    Er = (ref["thermo"][:, 0] + ref["thermo"][:, 1]) / state.n
+    slope_ref = np.polyfit(t, Er, 1)[0]
+    print(f"drift per particle per step: gpu {slope:.3e}, oracle {slope_ref:.3e}; max |E-E0| {np.abs(E - E[0]).max():.3e}")
+    assert abs(slope) <= max(2 * abs(slope_ref), 1e-7)
+    assert np.abs(E - E[0]).max() <= 1e-3
+    # the first steps follow the oracle's thermodynamics closely
+    np.testing.assert_allclose(tr["pe"][:20], ref["thermo"][:20, 0], rtol=1e-5)
+
+
+def test_nvt_reaches_target_temperature_config1():
+    state = gen.config1_state()
+    sig, eps, rc = gen.ka_params()
+    with make_system(state, sig, eps, rc, "sf") as s:
+        s.set_integrator_nvt(0.001, 0.45, 0.2)
+        s.step(2000)
+        s.set_integrator_nvt(0.005, 0.45, 0.2)
+        tr = s.step(4000, thermo_every=1)
+    T = tr["temperature"][1000:]
+    assert np.mean(T) == pytest.approx(0.45, rel=0.03)
+    H = tr["h_conserved"] / state.n
+    slope = np.polyfit(np.arange(len(H)), H, 1)[0]
+    print(f"<T> {np.mean(T):.4f}, H drift per particle per step {slope:.3e}")
+    assert abs(slope) < 2e-6
+
+
+@pytest.mark.parametrize("precision", ["f32_kahan", "f64pos"])
+def test_precision_variants(precision):
+    state = gen.jitter_positions(gen.config0_state(), 0.08, 4)
+    sig, eps, rc = gen.lj_params()
+    with make_system(state, sig, eps, rc, "sp", precision=precision) as s:
+        th = s.compute_forces()
+        F = s.get_state()["force"]
+        Fr, _, _, U, W = oracle.forces_f32(state.pos, state.types, state.box, sig, eps, rc, "sp")
+        assert force_error(F, Fr) <= FORCE_TOL
+        assert rel(th["pe"], U) <= ENERGY_TOL
+        s.set_integrator_nve(0.005)
+        s.step(10)
+        st = s.get_state()
+    ref = oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, "sp", 0.005, 10)
+    d = min_image(st["pos64"] - ref["pos"], state.box)
+    assert np.abs(d).max() <= 1e-4
+
+
+def test_nose_hoover_infinite_tau_equals_nve_bitwise():
+    state = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    res = []
+    for nvt in (False, True):
+        with make_system(state, sig, eps, rc, "sp") as s:
+            if nvt:
+                s.set_integrator_nvt(0.005, 0.7, np.inf)
+            else:
+                s.set_integrator_nve(0.005)
+            s.step(100)
+            res.append(s.get_state())
+    np.testing.assert_array_equal(res[0]["pos"], res[1]["pos"])
+    np.testing.assert_array_equal(res[0]["vel"], res[1]["vel"])
+
+
+@pytest.mark.parametrize("n", [16000, 64000, 256000, 1024000])
+def test_size_sweep_sampled_parity(n):
+    state = gen.jitter_positions(gen.config2_state(n), 0.05, n)
+    sig, eps, rc = gen.lj_params()
+    print(f"N={n}", flush=True)
+    with make_system(state, sig, eps, rc, "sp") as s:
+        th = s.compute_forces()
+        F = s.get_state()["force"]
+        pairs = s.neighbor_pairs() if n <= 256000 else None
+        stats = s.stats()
+    rng = np.random.default_rng(n)
+    sel = np.sort(rng.choice(n, 300, replace=False)).astype(np.int32)
+    Fr, pe, w, _, _ = oracle.forces_f32(state.pos, state.types, state.box, sig, eps, rc, "sp", sel=sel)
+    assert np.abs(F[sel] - Fr).max() <= FORCE_TOL * max(np.abs(Fr).max(), 1.0)
+    # whole-system properties at any size: momentum conservation, energy per particle
+    assert np.abs(F.astype(np.float64).sum(0)).max() <= 1e-5 * np.sqrt(n) * np.abs(F).max()
+    assert -7.0 < th["pe"] / n < -5.0
+    if pairs is None:
+        return
+    cs2, _ = oracle.cut_tables(rc, 0.3)
+    starts = np.searchsorted(pairs[:, 0], sel)
+    ends = np.searchsorted(pairs[:, 0], sel, side="right")
+    for k, i in enumerate(sel[:60]):
+        ref = oracle.neighbors_of(state.pos, state.types, state.box, cs2, int(i))
+        np.testing.assert_array_equal(pairs[starts[k]:ends[k], 1], ref)
+    assert stats["list_entries"] == len(pairs)
+
+
+def test_size_sweep_steps_stay_finite_large():
+    state = gen.config2_state(256000)
+    sig, eps, rc = gen.lj_params()
+    with make_system(state, sig, eps, rc, "sp") as s:
+        s.set_integrator_nve(0.005)
+        tr = s.step(200, thermo_every=10)
+    E = (tr["pe"] + tr["ke"]) / state.n
+    assert np.isfinite(E).all()
+    assert np.ptp(E) < 5e-3
+
+
+def test_invalid_arguments_rejected():
+    from paper_1506_05094_amd import srmd
+    import torch
+    state = gen.config0_state()
+    stream = torch.cuda.current_stream().cuda_stream
+    bad = state.pos.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(srmd.SrmdError) as e:
+        srmd.System(bad, state.types, state.box, stream=stream)
+    assert e.value.status == srmd.SRMD_EINVAL
+    with srmd.System(state.pos, state.types, state.box, stream=stream) as s:
+        with pytest.raises(srmd.SrmdError):
+            s.set_pair_lj(0, 0, 1.0, 1.0, 4.9, "sp")  # rc + skin > L/2
+        with pytest.raises(srmd.SrmdError):
+            s.set_launch(3, 64)
+        with pytest.raises(srmd.SrmdError):
+            s.step(10)  # no integrator yet
+        s.set_pair_lj(0, 0, 1.0, 1.0, 2.5, "sp")
+        with pytest.raises(srmd.SrmdError):
+            s.set_pair_lj(0, 0, 1.0, 1.0, 2.5, "sf")  # one cutoff method per system
+        with pytest.raises(srmd.SrmdError):
+            s.set_state(pos=bad)
