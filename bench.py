@@ -17,6 +17,8 @@ rate on the host cores.
 import argparse
 import json
 import os
+
+import numpy as np
 import sys
 import time
 
@@ -84,12 +86,78 @@ def cpu_baseline(state, params, method, integ, budget_s=12.0):
                       f"start, {dt:.1f} s wall"}
 
 
+def run_replicas(args):
+    """Batched Kob-Andersen replicas: one persistent launch vs one launch chain per system."""
+    import torch
+
+    from paper_1506_05094_amd import srmd
+    from workloads import generators as gen
+
+    t0 = time.perf_counter()
+    states = gen.ka_replica_states(args.replicas, workers=min(16, os.cpu_count() or 1))
+    log(f"generated {len(states)} replicas (N = {sum(s.n for s in states)}) in {time.perf_counter() - t0:.1f} s")
+    sig, eps, rc = gen.ka_params()
+    temps = [T for (_, T, _) in gen.config3_states(args.replicas)]
+    stream = torch.cuda.current_stream().cuda_stream
+    tp, ppb = args.tp or 8, args.ppb or max(1, 256 // (args.tp or 8))
+    systems = []
+    for st, T in zip(states, temps):
+        s = srmd.system_from_state(st, sig, eps, rc, "sf", skin=0.3, stream=stream)
+        s.set_launch(tp, ppb)
+        s.set_integrator_nvt(0.001, T, 0.2)
+        systems.append(s)
+    ntot = sum(s.n for s in systems)
+    batch = srmd.Batch(systems)
+    batch.step(2000)  # relax the random insertion (untimed)
+    for s, T in zip(systems, temps):
+        s.set_integrator_nvt(0.005, T, 0.2)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    trace = batch.step(args.steps, thermo_every=max(1, args.steps // 50))
+    torch.cuda.synchronize()
+    wall_b = time.perf_counter() - t0
+    value_b = ntot * args.steps / wall_b
+    log(f"batched: {args.steps} steps of {len(systems)} replicas in {wall_b:.3f} s -> {value_b:.4e} particle-steps/s")
+    # baseline: the same systems advanced one at a time, each by its own launch chain
+    base_steps = min(args.steps, args.baseline_steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in systems:
+        s.step(base_steps)
+    torch.cuda.synchronize()
+    wall_s = time.perf_counter() - t0
+    value_s = ntot * base_steps / wall_s
+    log(f"one system per launch: {base_steps} steps each in {wall_s:.3f} s -> {value_s:.4e} particle-steps/s; "
+        f"batched / single = {value_b / value_s:.1f}")
+    h = trace["h_conserved"] / np.array([s.n for s in systems])[:, None]
+    steps_axis = np.arange(h.shape[1])
+    drift = np.array([np.polyfit(steps_axis, h[r], 1)[0] for r in range(h.shape[0])]) / max(1, args.steps // 50)
+    batch.close()
+    for s in systems:
+        s.close()
+    out = {
+        "metric": METRIC, "value": value_b, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall_b / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(systems)} Kob-Andersen replicas, N ~ U[500, 8000], T ~ U[0.4, 1.0], NVT "
+                               "dt 0.005, one persistent launch", "n_total": ntot, "tp": tp, "ppb": ppb},
+        "one_launch_per_system": {"value": value_s, "steps": base_steps, "wall_s": wall_s},
+        "batched_over_single": value_b / value_s,
+        "h_drift_per_particle_per_step": {"median_abs": float(np.median(np.abs(drift))),
+                                          "max_abs": float(np.max(np.abs(drift)))},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj"])
+    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "ka-replicas"])
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--baseline-steps", type=int, default=1000)
     ap.add_argument("--n", type=int, default=864, help="particles for --workload lj")
     ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
     ap.add_argument("--ppb", type=int, default=0)
@@ -108,6 +176,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     srmd.load()
+    if args.workload == "ka-replicas":
+        run_replicas(args)
+        return
     state, params, method, integ, desc = workload(args.workload, args.n)
     sig, eps, rc = params
     s = srmd.system_from_state(state, sig, eps, rc, method, skin=0.3, stream=torch.cuda.current_stream().cuda_stream)

@@ -202,6 +202,37 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
 /* Message of the last failure on s (or of the calling thread when s is NULL). */
 const char *srmd_last_error(const srmd_system *s);
 
+/* ---- Batched replicas --------------------------------------------------------
+ * Many independent small systems advanced together by one persistent launch: each
+ * replica is owned by one workgroup that runs every step of the call inside the
+ * kernel (the ensembles of small systems mentioned in the paper's introduction;
+ * the batch removes the per-step launch chain that limits one small system).
+ * The batch borrows the systems: it runs on their own device state, so every
+ * per-system call (srmd_get_state, srmd_get_thermo, srmd_step ...) stays valid
+ * between batch calls, and the systems must outlive the batch.  Requirements: at
+ * least one system; every system has an integrator, float32 positions, at most
+ * 8192 particles and 8192 cells, and all share the cutoff method and the launch
+ * shape (tp, ppb).  A replica advanced in a batch follows the trajectory of the same
+ * system advanced alone by srmd_step bit for bit.  Work is enqueued on the first
+ * system's stream. */
+
+/* Create a batch over count systems (caller-owned array, copied). */
+srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int32_t count);
+
+/* Advance every replica by nsteps steps in one persistent launch (captured in a HIP
+ * graph).  If thermo_every > 0, replica r writes the records of its steps n with
+ * n % thermo_every == 0 to trace[r * trace_cap + k], k < trace_cap (caller-owned
+ * array of count * trace_cap records).  Synchronises at the end; list overflows are
+ * handled by restoring every replica and replaying with grown lists. */
+srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
+                            int64_t trace_cap);
+
+/* Release the batch (not the systems). NULL is a no-op. */
+srmd_status srmd_batch_destroy(srmd_batch *b);
+
+/* Message of the last failure of a batch call (NULL: of the calling thread). */
+const char *srmd_batch_last_error(const srmd_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

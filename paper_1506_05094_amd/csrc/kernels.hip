@@ -17,6 +17,8 @@
 //             thermostat update, thermodynamic record, the displacement test that
 //             sets the rebuild flag (section 6), and for small systems the whole
 //             spatial sort in LDS when a rebuild is due.
+#include <algorithm>
+
 #include "srmd_internal.h"
 
 namespace srmd {
@@ -171,14 +173,14 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
 // then the B neighbour positions, so a batch costs two memory round trips instead
 // of two per entry (the paper prefetches one entry ahead, section 5; on MI355X the
 // latency of a dependent load chain dominates, so many loads go in flight).
-template <int TP, int METHOD, int B>
+template <int TP, int METHOD, int B, class IdxPtr>
 __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const float4 *__restrict__ pos,
-                                           const int *__restrict__ nbl, int nn, const SharedPairs &sp,
+                                           IdxPtr nbl, int nn, const SharedPairs &sp,
                                            const SysConst &c, float &fx, float &fy, float &fz, float &u, float &w) {
   const int ti = ptype(pi);
   const Wide wi = widen(pi);
   const long long stride = (long long)c.nvp * TP;
-  const int *row = nbl + (long long)i * TP + t;
+  const IdxPtr row = nbl + (long long)i * TP + t;
   const int mine = nn > t ? (nn - t + TP - 1) / TP : 0;  // entries of this lane
   for (int m0 = 0; m0 < mine; m0 += B) {
     int j[B];
@@ -240,10 +242,13 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
   return v;
 }
 
-// Block-wide reduction of one BlockPartial (fixed order: lanes by butterfly, then
-// waves in index order), result valid in thread 0.  Every thread must call it.
-__device__ void block_reduce(BlockPartial &v, BlockPartial *s_waves) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+// Reduction of one BlockPartial over groups of `group` threads (a multiple of 64):
+// lanes by butterfly, then the group's waves in index order; the result is valid
+// in the first thread of each group.  Every thread of the block must call it.
+// With group = blockDim.x this is the block-wide reduction; the batched kernel
+// uses groups to reproduce the blocks of the single-system kernels exactly.
+__device__ void group_reduce(BlockPartial &v, BlockPartial *s_waves, int group) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wpg = group >> 6;
   v.pe = wave_sum(v.pe);
   v.w = wave_sum(v.w);
   v.ke_half = wave_sum(v.ke_half);
@@ -257,20 +262,26 @@ __device__ void block_reduce(BlockPartial &v, BlockPartial *s_waves) {
   v.nonfinite = bad;
   if (lane == 0) s_waves[wv] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    BlockPartial a = s_waves[0];
-    for (int k = 1; k < nw; ++k) {
-      a.pe += s_waves[k].pe;
-      a.w += s_waves[k].w;
-      a.ke_half += s_waves[k].ke_half;
-      a.ke_int += s_waves[k].ke_int;
-      a.disp2 = fmax(a.disp2, s_waves[k].disp2);
-      a.nonfinite |= s_waves[k].nonfinite;
-      a.t0 = s_waves[k].t0 < a.t0 ? s_waves[k].t0 : a.t0;
-      a.t1 = s_waves[k].t1 > a.t1 ? s_waves[k].t1 : a.t1;
+  if ((threadIdx.x % group) == 0) {
+    const int w0 = wv;  // first wave of this group
+    BlockPartial a = s_waves[w0];
+    for (int k = 1; k < wpg; ++k) {
+      const BlockPartial &q = s_waves[w0 + k];
+      a.pe += q.pe;
+      a.w += q.w;
+      a.ke_half += q.ke_half;
+      a.ke_int += q.ke_int;
+      a.disp2 = fmax(a.disp2, q.disp2);
+      a.nonfinite |= q.nonfinite;
+      a.t0 = q.t0 < a.t0 ? q.t0 : a.t0;
+      a.t1 = q.t1 > a.t1 ? q.t1 : a.t1;
     }
     v = a;
   }
+}
+
+__device__ __forceinline__ void block_reduce(BlockPartial &v, BlockPartial *s_waves) {
+  group_reduce(v, s_waves, (int)blockDim.x);
 }
 
 __device__ __forceinline__ BlockPartial zero_partial() {
@@ -414,12 +425,11 @@ constexpr int kSmallCells = 8192;
 // particle id inside each cell, and the gather of every per-particle array to its
 // sorted slot in the t_* arrays (section 7 steps 1-3).  Every thread of the block
 // must call it.
-__device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur) {
-  __shared__ unsigned s_cnt[kSmallCells + 1];
-  __shared__ int s_id[kSmallN];
+template <int THREADS>
+__device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur, unsigned *s_cnt, int *s_id) {
   __shared__ unsigned s_w[16];
   __shared__ unsigned s_carry;
-  constexpr int PER = kSmallN / 1024;
+  constexpr int PER = kSmallN / THREADS;
   const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nthr >> 6;
   const int ncell = c.ncell;
   for (int k = tid; k <= ncell; k += nthr) s_cnt[k] = 0u;
@@ -509,8 +519,10 @@ __device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur) {
 
 // Spatial sort requested from the host (start of a run, new state or parameters).
 __global__ __launch_bounds__(1024) void k_sort_small(SysConst c, SysPtrs p, int cur) {
+  __shared__ unsigned s_cnt[kSmallCells + 1];
+  __shared__ int s_id[kSmallN];
   if (p.ctl->rebuild == 0) return;
-  sort_small_block(c, p, cur);
+  sort_small_block<1024>(c, p, cur, s_cnt, s_id);
 }
 
 bool small_sort_fits(int n, int ncell) { return n <= kSmallN && ncell <= kSmallCells; }
@@ -519,6 +531,100 @@ bool small_sort_fits(int n, int ncell) { return n <= kSmallN && ncell <= kSmallC
 
 constexpr int kWaveCand = 1024;  // candidates per window of the wave builder
 constexpr int kListChunks = 4;   // 64-candidate chunks whose loads are in flight together
+
+// Verlet list of particle t (sorted slot), one wave per particle; for small systems,
+// where one thread per particle (section 7) leaves the chip idle and every thread
+// waits on a long chain of dependent loads.  The 5x5x5 stencil (every cell along
+// an axis with fewer than 5 cells) is cut into rows of consecutive x cells; as
+// particles are sorted by cell index, each row is one or two contiguous slot runs.
+// Lane s loads the bounds of run s, a wave prefix sum gives each run's offset in
+// the candidate sequence, the runs are expanded into LDS, and the candidates are
+// tested 64 at a time; a ballot compacts the hits in candidate order, so the
+// list order is deterministic (stencil row order, then slot order).
+// List of one particle t by the calling wave (see k_list_wave); cand is this wave's
+// LDS window of kWaveCand entries.  Returns the number of entries kept (all lanes).
+__device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t, unsigned *cand,
+                             const float *s_cs2) {
+  const int lane = threadIdx.x & 63;
+  const float4 r = p.t_pos[t];
+  if (lane == 0) place_sorted(p, cur, t, r);
+  const int ti = ptype(r);
+  int cx, cy, cz;
+  cell_coords(r, c, cx, cy, cz);
+  const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
+  const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
+  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
+  int a0, a1, b0, b1;
+  row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
+  // run handled by this lane: row = lane / 2, run = lane % 2
+  unsigned run_start = 0, run_len = 0;
+  const int row = lane >> 1;
+  if (row < ny_eff * nz_eff) {
+    const int oy = row % ny_eff, oz = row / ny_eff;
+    const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
+    const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
+    const int rowbase = (zz * ny + yy) * nx;
+    const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
+    if (x1 >= x0) {
+      const unsigned s0 = p.cell_start[rowbase + x0], s1 = p.cell_start[rowbase + x1 + 1];
+      run_start = s0;
+      run_len = s1 - s0;
+    }
+  }
+  unsigned incl = run_len;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const unsigned excl = incl - run_len;
+  const unsigned total = __shfl(incl, 63, 64);
+  const int nmax = c.n_max;
+  int count = 0;
+  for (unsigned wbase = 0; wbase < total; wbase += kWaveCand) {
+    const unsigned wend = min(total, wbase + (unsigned)kWaveCand);
+    // expand this lane's run into the window
+    const unsigned q0 = max(excl, wbase), q1 = min(excl + run_len, wend);
+    for (unsigned q = q0; q < q1; ++q) cand[q - wbase] = run_start + (q - excl);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const unsigned wlen = wend - wbase;
+    for (unsigned base = 0; base < wlen; base += 64u * kListChunks) {
+      unsigned u[kListChunks];
+      float4 q[kListChunks];
+#pragma unroll
+      for (int cb = 0; cb < kListChunks; ++cb) {
+        const unsigned qi = base + 64u * cb + (unsigned)lane;
+        u[cb] = qi < wlen ? cand[qi] : (unsigned)t;
+        q[cb] = p.t_pos[u[cb]];
+      }
+#pragma unroll
+      for (int cb = 0; cb < kListChunks; ++cb) {
+        bool hit = false;
+        if ((int)u[cb] != t) {
+          float dx, dy, dz;
+          const float r2 = dist2(r, q[cb], c, dx, dy, dz);
+          hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
+        }
+        const unsigned long long mask = __ballot(hit);
+        const int k = count + __popcll(mask & ((1ull << lane) - 1ull));
+        if (hit && k < nmax) p.nbl[nbl_addr(t, k, c.tp, c.nvp)] = (int)u[cb];
+        count += __popcll(mask);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  const int kept = min(count, nmax);
+  if (lane == 0) {
+    p.nnb[t] = kept;
+    if (count > nmax) atomicOr(&p.ctl->error, 2);
+    atomicMax(&p.ctl->max_nbrs, count);
+  }
+  return kept;
+}
 
 // Verlet list of particle t (sorted slot), one wave per particle; for small systems,
 // where one thread per particle (section 7) leaves the chip idle and every thread
@@ -539,84 +645,8 @@ __global__ __launch_bounds__(256) void k_list_wave(SysConst c, SysPtrs p, int cu
   const int t = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
   int kept = 0;
   if (t < c.n) {  // uniform across the wave
-    const float4 r = p.t_pos[t];
-    if (lane == 0) place_sorted(p, cur, t, r);
-    const int ti = ptype(r);
-    int cx, cy, cz;
-    cell_coords(r, c, cx, cy, cz);
-    const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
-    const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
-    const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
-    int a0, a1, b0, b1;
-    row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
-    // run handled by this lane: row = lane / 2, run = lane % 2
-    unsigned run_start = 0, run_len = 0;
-    const int row = lane >> 1;
-    if (row < ny_eff * nz_eff) {
-      const int oy = row % ny_eff, oz = row / ny_eff;
-      const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
-      const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
-      const int rowbase = (zz * ny + yy) * nx;
-      const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
-      if (x1 >= x0) {
-        const unsigned s0 = p.cell_start[rowbase + x0], s1 = p.cell_start[rowbase + x1 + 1];
-        run_start = s0;
-        run_len = s1 - s0;
-      }
-    }
-    unsigned incl = run_len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    const unsigned excl = incl - run_len;
-    const unsigned total = __shfl(incl, 63, 64);
-    const int nmax = c.n_max;
-    int count = 0;
-    unsigned *cand = s_cand[wv];
-    for (unsigned wbase = 0; wbase < total; wbase += kWaveCand) {
-      const unsigned wend = min(total, wbase + (unsigned)kWaveCand);
-      // expand this lane's run into the window
-      const unsigned q0 = max(excl, wbase), q1 = min(excl + run_len, wend);
-      for (unsigned q = q0; q < q1; ++q) cand[q - wbase] = run_start + (q - excl);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      const unsigned wlen = wend - wbase;
-      for (unsigned base = 0; base < wlen; base += 64u * kListChunks) {
-        unsigned u[kListChunks];
-        float4 q[kListChunks];
-#pragma unroll
-        for (int cb = 0; cb < kListChunks; ++cb) {
-          const unsigned qi = base + 64u * cb + (unsigned)lane;
-          u[cb] = qi < wlen ? cand[qi] : (unsigned)t;
-          q[cb] = p.t_pos[u[cb]];
-        }
-#pragma unroll
-        for (int cb = 0; cb < kListChunks; ++cb) {
-          bool hit = false;
-          if ((int)u[cb] != t) {
-            float dx, dy, dz;
-            const float r2 = dist2(r, q[cb], c, dx, dy, dz);
-            hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
-          }
-          const unsigned long long mask = __ballot(hit);
-          const int k = count + __popcll(mask & ((1ull << lane) - 1ull));
-          if (hit && k < nmax) p.nbl[nbl_addr(t, k, c.tp, c.nvp)] = (int)u[cb];
-          count += __popcll(mask);
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (lane == 0) {
-      kept = min(count, nmax);
-      p.nnb[t] = kept;
-      if (count > nmax) atomicOr(&p.ctl->error, 2);
-      atomicMax(&p.ctl->max_nbrs, count);
-    }
+    const int k = list_wave_one(c, p, cur, t, s_cand[wv], s_cs2);
+    if (lane == 0) kept = k;
   }
   list_tally(kept, p.ctl);  // every thread of the block reaches this barrier once
 }
@@ -737,50 +767,16 @@ __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) 
   }
 }
 
-// ---------------------------------------------------------------- fused step
-
-template <int TP, int METHOD, int PREC>
-__global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
-  __shared__ SharedPairs sp;
-  __shared__ BlockPartial s_waves[16];
-  const unsigned long long tstart = wall_clock64();
-  stage_pairs(sp, c);
-  __syncthreads();
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int gt = lb * blockDim.x + threadIdx.x;
-  const int i = gt / TP, t = gt % TP;
-  const bool active = i < c.n;
-  const float4 *pos = p.pos[cur];
-  float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
-  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-  // integrator operands are loaded before the force loop so their latency overlaps it
-  float4 vo = pi, l0 = pi, kc = pi;
-  int4 im = make_int4(0, 0, 0, 0);
-  double x64 = 0.0, y64 = 0.0, z64 = 0.0;
-  const double xi = c.thermostat ? p.ctl->xi : 0.0;
-  if (active) {
-    pi = pos[i];
-    const int nn = p.nnb[i];
-    if (t == 0) {
-      vo = p.vel[i];
-      im = p.img[i];
-      l0 = p.last[i];
-      if (PREC == 1) kc = p.kahan[i];
-      if (PREC == 2) {
-        x64 = p.pos64[3 * i];
-        y64 = p.pos64[3 * i + 1];
-        z64 = p.pos64[3 * i + 2];
-      }
-    }
-    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, p.nbl, nn, sp, c, fx, fy, fz, u, w);
-  }
-  fx = lane_sum<TP>(fx);
-  fy = lane_sum<TP>(fy);
-  fz = lane_sum<TP>(fz);
-  u = lane_sum<TP>(u);
-  w = lane_sum<TP>(w);
-  BlockPartial v = zero_partial();
-  if (active && t == 0) {
+// Leapfrog / Nose-Hoover update of particle i (sorted slot) from its force, and
+// its float64 contributions to the step's sums (paper section 2 integrators;
+// kinetic energy at the half step for the thermostat and at the integer step for
+// the thermodynamic record; largest displacement since the last list build for
+// the rebuild test of section 6).
+template <int PREC>
+__device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &p, int cur, int i, const float4 pi,
+                                              const float4 vo, int4 im, const float4 l0, float4 kc, double x64,
+                                              double y64, double z64, double xi, float fx, float fy, float fz,
+                                              float u, float w, BlockPartial &v) {
     const int ti = ptype(pi);
     // v(n+1/2) = [v(n-1/2) (1 - xi dt/2) + F/m dt] / (1 + xi dt/2); a = b = 1 without thermostat
     const double hx = 0.5 * xi * c.dtd;
@@ -852,7 +848,53 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
     ddz -= c.Ld[2] * rint(ddz / c.Ld[2]);
     v.disp2 = (ddx * ddx + ddy * ddy) + ddz * ddz;
     v.nonfinite = (finite3(fx, fy, fz) && finite3(rn.x, rn.y, rn.z)) ? 0 : 1;
+}
+
+// ---------------------------------------------------------------- fused step
+
+template <int TP, int METHOD, int PREC>
+__global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
+  __shared__ SharedPairs sp;
+  __shared__ BlockPartial s_waves[16];
+  const unsigned long long tstart = wall_clock64();
+  stage_pairs(sp, c);
+  __syncthreads();
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int gt = lb * blockDim.x + threadIdx.x;
+  const int i = gt / TP, t = gt % TP;
+  const bool active = i < c.n;
+  const float4 *pos = p.pos[cur];
+  float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
+  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  // integrator operands are loaded before the force loop so their latency overlaps it
+  float4 vo = pi, l0 = pi, kc = pi;
+  int4 im = make_int4(0, 0, 0, 0);
+  double x64 = 0.0, y64 = 0.0, z64 = 0.0;
+  const double xi = c.thermostat ? p.ctl->xi : 0.0;
+  if (active) {
+    pi = pos[i];
+    const int nn = p.nnb[i];
+    if (t == 0) {
+      vo = p.vel[i];
+      im = p.img[i];
+      l0 = p.last[i];
+      if (PREC == 1) kc = p.kahan[i];
+      if (PREC == 2) {
+        x64 = p.pos64[3 * i];
+        y64 = p.pos64[3 * i + 1];
+        z64 = p.pos64[3 * i + 2];
+      }
+    }
+    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, p.nbl, nn, sp, c, fx, fy, fz, u, w);
   }
+  fx = lane_sum<TP>(fx);
+  fy = lane_sum<TP>(fy);
+  fz = lane_sum<TP>(fz);
+  u = lane_sum<TP>(u);
+  w = lane_sum<TP>(w);
+  BlockPartial v = zero_partial();
+  if (active && t == 0)
+    integrate_one<PREC>(c, p, cur, i, pi, vo, im, l0, kc, x64, y64, z64, xi, fx, fy, fz, u, w, v);
   v.t0 = tstart;
   v.t1 = wall_clock64();
   block_reduce(v, s_waves);
@@ -864,6 +906,52 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
 
 // ---------------------------------------------------------------- end of step
 
+// End of a time step, by one thread, from the fully reduced partials a: the
+// thermodynamic record, the Nose-Hoover update, the step counter and the
+// displacement test that sets the rebuild flag.  Returns the flag.
+__device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockPartial &a) {
+  Control *ctl = p.ctl;
+  const double xi = c.thermostat ? ctl->xi : 0.0;
+  Thermo rec;
+  rec.pe = a.pe;
+  rec.ke = a.ke_int;
+  rec.virial = a.w;
+  rec.temperature = 2.0 * a.ke_int / c.g;
+  rec.pressure = (2.0 * a.ke_int / 3.0 + a.w) / c.volume;
+  rec.xi = xi;
+  rec.xi_integral = ctl->xi_int;
+  rec.h_conserved = a.ke_int + a.pe;
+  if (c.thermostat && c.inv_tau2 > 0.0)
+    rec.h_conserved += c.g * c.T0 * (xi * xi / (2.0 * c.inv_tau2) + ctl->xi_int);
+  rec.ke_half = a.ke_half;
+  rec.step = ctl->step;
+  rec.n_rebuilds = ctl->n_rebuilds;
+  rec.max_nbrs = ctl->max_nbrs;
+  rec.reserved = 0;
+  *p.thermo = rec;
+  if (ctl->thermo_every > 0 && (ctl->step % ctl->thermo_every) == 0 && ctl->n_records < ctl->trace_cap) {
+    p.trace[ctl->n_records] = rec;
+    ctl->n_records += 1;
+  }
+  if (c.thermostat) {
+    const double th = 2.0 * a.ke_half / c.g;
+    const double xn = xi + c.dtd * (th / c.T0 - 1.0) * c.inv_tau2;
+    ctl->xi_int += c.dtd * (xi + xn) * 0.5;
+    ctl->xi = xn;
+  }
+  ctl->step += 1;
+  if (a.t1 > a.t0) {
+    ctl->prof_ticks += a.t1 - a.t0;
+    ctl->prof_count += 1;
+  }
+  const int rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
+  ctl->rebuild = rebuild;
+  if (a.nonfinite) ctl->error |= 1;
+  return rebuild;
+}
+
+
+
 // One workgroup after the step (MODE 0) or force-only (MODE 1) kernel: fixed-order
 // float64 reduction of the G block partials (each thread sums its blocks in index
 // order, then lanes by butterfly and waves in order), the Nose-Hoover update, the
@@ -873,6 +961,8 @@ template <int MODE>
 __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, int next) {
   __shared__ BlockPartial s_waves[16];
   __shared__ int s_rebuild;
+  __shared__ unsigned s_cnt[MODE == 0 ? kSmallCells + 1 : 1];
+  __shared__ int s_id[MODE == 0 ? kSmallN : 1];
   BlockPartial a = zero_partial();
   for (int b = threadIdx.x; b < G; b += blockDim.x) {
     const BlockPartial q = p.part[b];
@@ -905,46 +995,247 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
       th->step = ctl->step;
       if (a.nonfinite) ctl->error |= 1;
     } else {
-      const double xi = c.thermostat ? ctl->xi : 0.0;
-      Thermo rec;
-      rec.pe = a.pe;
-      rec.ke = a.ke_int;
-      rec.virial = a.w;
-      rec.temperature = 2.0 * a.ke_int / c.g;
-      rec.pressure = (2.0 * a.ke_int / 3.0 + a.w) / c.volume;
-      rec.xi = xi;
-      rec.xi_integral = ctl->xi_int;
-      rec.h_conserved = a.ke_int + a.pe;
-      if (c.thermostat && c.inv_tau2 > 0.0)
-        rec.h_conserved += c.g * c.T0 * (xi * xi / (2.0 * c.inv_tau2) + ctl->xi_int);
-      rec.ke_half = a.ke_half;
-      rec.step = ctl->step;
-      rec.n_rebuilds = ctl->n_rebuilds;
-      rec.max_nbrs = ctl->max_nbrs;
-      rec.reserved = 0;
-      *p.thermo = rec;
-      if (ctl->thermo_every > 0 && (ctl->step % ctl->thermo_every) == 0 && ctl->n_records < ctl->trace_cap) {
-        p.trace[ctl->n_records] = rec;
-        ctl->n_records += 1;
-      }
-      if (c.thermostat) {
-        const double th = 2.0 * a.ke_half / c.g;
-        const double xn = xi + c.dtd * (th / c.T0 - 1.0) * c.inv_tau2;
-        ctl->xi_int += c.dtd * (xi + xn) * 0.5;
-        ctl->xi = xn;
-      }
-      ctl->step += 1;
-      ctl->prof_ticks += a.t1 - a.t0;
-      ctl->prof_count += 1;
-      rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
-      ctl->rebuild = rebuild;
-      if (a.nonfinite) ctl->error |= 1;
+      rebuild = finish_step(c, p, a);
     }
     s_rebuild = rebuild;
   }
   __syncthreads();
-  if (MODE == 0 && s_rebuild && c.small_sort) sort_small_block(c, p, next);
+  if (MODE == 0 && s_rebuild && c.small_sort) sort_small_block<1024>(c, p, next, s_cnt, s_id);
 }
+
+// ---------------------------------------------------------------- batched replicas
+
+// Many independent small systems in one persistent launch: workgroup b owns replica
+// order[b] and runs every time step of the call without leaving the kernel (the
+// ensembles of small systems the paper's introduction points to; on MI355X one
+// replica per compute unit instead of one launch chain per system).  Positions
+// live in LDS during the force phase; the spatial sort, the list build and the
+// reductions run inside the workgroup with barriers only.  The work of the
+// single-system kernels is reproduced exactly: virtual blocks of vb threads (the
+// single system's block) compute the same per-block partials, which are reduced in
+// the same fixed order, so a replica follows its single-system trajectory bit for
+// bit at the same tp and block size.  Dynamic LDS: max(16 n_max, 64 KiB) bytes.
+// Butterfly of a BlockPartial over the 64 lanes of a wave (the first step of
+// group_reduce), result valid in every lane.
+__device__ __forceinline__ void wave_reduce(BlockPartial &v) {
+  v.pe = wave_sum(v.pe);
+  v.w = wave_sum(v.w);
+  v.ke_half = wave_sum(v.ke_half);
+  v.ke_int = wave_sum(v.ke_int);
+  v.disp2 = wave_max(v.disp2);
+  int bad = v.nonfinite;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
+  v.nonfinite = bad;
+}
+
+// Pointers read from a descriptor in memory are generic to the compiler; route them
+// through the global address space so that loads and stores compile to global
+// (not flat) instructions.
+#define SRMD_GLOBAL __attribute__((address_space(1)))
+
+// A pointer read from a descriptor in memory is generic to the compiler; loads
+// through this global-address-space view compile to global (not flat) loads, which
+// keep the list loads of the force loop pipelined.
+template <class T>
+__device__ __forceinline__ const SRMD_GLOBAL T *global_view(const T *q) {
+  return (const SRMD_GLOBAL T *)q;
+}
+
+typedef float raw_f4 __attribute__((ext_vector_type(4)));
+typedef int raw_i4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 gload(const float4 *q, int i) {
+  const raw_f4 v = ((const SRMD_GLOBAL raw_f4 *)q)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ int4 gload(const int4 *q, int i) {
+  const raw_i4 v = ((const SRMD_GLOBAL raw_i4 *)q)[i];
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ int gload(const int *q, int i) { return ((const SRMD_GLOBAL int *)q)[i]; }
+
+constexpr int kBatchThreads = 512;                  // threads of a batched workgroup
+constexpr int kBatchWaves = kBatchThreads / 64;
+
+template <int TP, int METHOD>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const ReplicaDesc *__restrict__ reps,
+                                                         const int *__restrict__ order, int nsteps, int vb) {
+  extern __shared__ float4 s_dyn[];
+  __shared__ SharedPairs sp;
+  __shared__ BlockPartial s_waves[16];
+  __shared__ float s_cs2[kMaxPairs];
+  __shared__ int s_flag;
+  __shared__ int s_kept[kBatchWaves];
+  const ReplicaDesc &R = reps[order[blockIdx.x]];
+  const SysConst &c = R.c;
+  const SysPtrs &p = R.p;
+  const SRMD_GLOBAL int *nblg = global_view(p.nbl);
+  const int G = R.G;
+  int cur = R.cur;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int wpv = vb >> 6;      // waves per virtual block
+  const int units = G * wpv;    // waves of the single-system step kernel
+  BlockPartial *wpart = p.part + G;  // one partial per wave unit, after the block partials
+  stage_pairs(sp, c);
+  if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
+  __syncthreads();
+  for (int step = 0; step < nsteps; ++step) {
+    if (tid == 0) s_flag = p.ctl->rebuild;
+    __syncthreads();
+    if (s_flag) {
+      // spatial sort of pos[cur] into the t_* arrays (LDS scratch: cell counts, ids)
+      unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
+      sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+      __syncthreads();
+      // list build, one wave per particle (LDS scratch: one candidate window per wave)
+      unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
+      int kept = 0;
+      for (int t = wv; t < c.n; t += kBatchWaves) kept += list_wave_one(c, p, cur, t, cand, s_cs2);
+      if (lane == 0) s_kept[wv] = kept;
+      __syncthreads();
+      if (tid == 0) {
+        long long tot = 0;
+        for (int k = 0; k < kBatchWaves; ++k) tot += s_kept[k];
+        p.ctl->list_entries = tot;
+        p.ctl->rebuild = 0;
+      }
+    }
+    // positions of this step into LDS
+    for (int k = tid; k < c.n; k += kBatchThreads) s_dyn[k] = gload(p.pos[cur], k);
+    __syncthreads();
+    const double xi = c.thermostat ? p.ctl->xi : 0.0;
+    // force + integration, one wave unit (64 threads of the single-system launch) at a time
+    for (int u = wv; u < units; u += kBatchWaves) {
+      const int gt = u * 64 + lane;
+      const int i = gt / TP, t = gt % TP;
+      const bool active = i < c.n;
+      float fx = 0.f, fy = 0.f, fz = 0.f, uu = 0.f, w = 0.f;
+      float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 vo = pi, l0 = pi, kc = pi;
+      int4 im = make_int4(0, 0, 0, 0);
+      if (active) {
+        pi = s_dyn[i];
+        const int nn = gload(p.nnb, i);
+        if (t == 0) {
+          vo = gload(p.vel, i);
+          im = gload(p.img, i);
+          l0 = gload(p.last, i);
+        }
+        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, nn, sp, c, fx, fy, fz, uu, w);
+      }
+      fx = lane_sum<TP>(fx);
+      fy = lane_sum<TP>(fy);
+      fz = lane_sum<TP>(fz);
+      uu = lane_sum<TP>(uu);
+      w = lane_sum<TP>(w);
+      BlockPartial v = zero_partial();
+      if (active && t == 0)
+        integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
+      wave_reduce(v);
+      if (lane == 0) wpart[u] = v;
+    }
+    __syncthreads();
+    // block partials: the waves of each virtual block in index order (as group_reduce)
+    for (int b = tid; b < G; b += kBatchThreads) {
+      BlockPartial a = wpart[b * wpv];
+      for (int k = 1; k < wpv; ++k) {
+        const BlockPartial q = wpart[b * wpv + k];
+        a.pe += q.pe;
+        a.w += q.w;
+        a.ke_half += q.ke_half;
+        a.ke_int += q.ke_int;
+        a.disp2 = fmax(a.disp2, q.disp2);
+        a.nonfinite |= q.nonfinite;
+      }
+      p.part[b] = a;
+    }
+    __syncthreads();
+    // end of step: the reduction of k_finish (1024 threads) with each thread standing
+    // in for threads tid and tid + 512 of that workgroup
+    BlockPartial a0 = zero_partial(), a1 = zero_partial();
+    for (int b = tid; b < G; b += 1024) {
+      const BlockPartial q = p.part[b];
+      a0.pe += q.pe;
+      a0.w += q.w;
+      a0.ke_half += q.ke_half;
+      a0.ke_int += q.ke_int;
+      a0.disp2 = fmax(a0.disp2, q.disp2);
+      a0.nonfinite |= q.nonfinite;
+    }
+    for (int b = tid + kBatchThreads; b < G; b += 1024) {
+      const BlockPartial q = p.part[b];
+      a1.pe += q.pe;
+      a1.w += q.w;
+      a1.ke_half += q.ke_half;
+      a1.ke_int += q.ke_int;
+      a1.disp2 = fmax(a1.disp2, q.disp2);
+      a1.nonfinite |= q.nonfinite;
+    }
+    wave_reduce(a0);
+    wave_reduce(a1);
+    if (lane == 0) {
+      s_waves[wv] = a0;
+      s_waves[wv + kBatchWaves] = a1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      BlockPartial a = s_waves[0];
+      for (int k = 1; k < 16; ++k) {
+        a.pe += s_waves[k].pe;
+        a.w += s_waves[k].w;
+        a.ke_half += s_waves[k].ke_half;
+        a.ke_int += s_waves[k].ke_int;
+        a.disp2 = fmax(a.disp2, s_waves[k].disp2);
+        a.nonfinite |= s_waves[k].nonfinite;
+      }
+      a.t0 = 0ull;
+      a.t1 = 0ull;
+      finish_step(c, p, a);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+template <int TP>
+static hipError_t launch_batch_tp(int method, int count, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                                  const int *order, int nsteps, int vb) {
+  const void *fn = method == 0 ? (const void *)k_batch<TP, 0>
+                   : method == 1 ? (const void *)k_batch<TP, 1>
+                                 : (const void *)k_batch<TP, 2>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (method == 0) hipLaunchKernelGGL((k_batch<TP, 0>), dim3(count), dim3(kBatchThreads), lds, st, reps, order, nsteps, vb);
+  else if (method == 1) hipLaunchKernelGGL((k_batch<TP, 1>), dim3(count), dim3(kBatchThreads), lds, st, reps, order, nsteps, vb);
+  else hipLaunchKernelGGL((k_batch<TP, 2>), dim3(count), dim3(kBatchThreads), lds, st, reps, order, nsteps, vb);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int tp, int method, int count, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                        const int *order, int nsteps, int vb) {
+  switch (tp) {
+    case 1: return launch_batch_tp<1>(method, count, lds, st, reps, order, nsteps, vb);
+    case 2: return launch_batch_tp<2>(method, count, lds, st, reps, order, nsteps, vb);
+    case 4: return launch_batch_tp<4>(method, count, lds, st, reps, order, nsteps, vb);
+    case 8: return launch_batch_tp<8>(method, count, lds, st, reps, order, nsteps, vb);
+    case 16: return launch_batch_tp<16>(method, count, lds, st, reps, order, nsteps, vb);
+    case 32: return launch_batch_tp<32>(method, count, lds, st, reps, order, nsteps, vb);
+    case 64: return launch_batch_tp<64>(method, count, lds, st, reps, order, nsteps, vb);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+size_t batch_lds_bytes(int n_max_particles) {
+  const size_t pos = 16 * (size_t)n_max_particles;
+  const size_t scratch = 4 * (size_t)(kSmallCells + 1 + kSmallN);
+  const size_t cand = 4 * (size_t)(kBatchWaves * kWaveCand);
+  return std::max(pos, std::max(scratch, cand));
+}
+
+int batch_max_particles() { return kSmallN; }
 
 // ---------------------------------------------------------------- launchers
 

@@ -22,6 +22,10 @@ hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, i
 hipError_t launch_finish(int mode, int G, int next, hipStream_t st, const SysConst &c, const SysPtrs &p);
 hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
 bool small_sort_fits(int n, int ncell);
+hipError_t launch_batch(int tp, int method, int count, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                        const int *order, int nsteps, int vb);
+size_t batch_lds_bytes(int n_max_particles);
+int batch_max_particles();
 }  // namespace srmd
 
 using namespace srmd;
@@ -306,11 +310,13 @@ srmd_status prepare(srmd_system *s) {
   }
   const int threads = s->tp * s->ppb;
   const int blocks = (int)(((long long)s->n * s->tp + threads - 1) / threads);
-  if (blocks > s->part_alloc) {
+  // block partials, then one partial per wave (used by the batched kernel)
+  const int nparts = blocks + blocks * (threads / 64);
+  if (nparts > s->part_alloc) {
     dev_free(s, s->p.part);
-    s->p.part = (BlockPartial *)dev_alloc(s, sizeof(BlockPartial) * (size_t)blocks);
+    s->p.part = (BlockPartial *)dev_alloc(s, sizeof(BlockPartial) * (size_t)nparts);
     if (!s->p.part) return fail(s, SRMD_ENOMEM, "partials allocation failed");
-    s->part_alloc = blocks;
+    s->part_alloc = nparts;
   }
   drop_graphs(s);
   s->dirty = false;
@@ -469,6 +475,99 @@ srmd_status upload_state(srmd_system *s, const float *pos, const float *vel, con
     HIPCHK(s, hipMemcpyAsync(s->p.pos64, h64.data(), sizeof(double) * 3 * (size_t)n, hipMemcpyHostToDevice, s->stream));
   if (s->p.kahan) HIPCHK(s, hipMemsetAsync(s->p.kahan, 0, sizeof(float4) * (size_t)n, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
+}
+
+srmd_status ensure_trace(srmd_system *s, long long cap) {
+  if (cap <= s->trace_alloc) return SRMD_OK;
+  dev_free(s, s->p.trace);
+  s->p.trace = (Thermo *)dev_alloc(s, sizeof(Thermo) * (size_t)cap);
+  if (!s->p.trace) return fail(s, SRMD_ENOMEM, "trace allocation failed");
+  s->trace_alloc = cap;
+  s->dirty = true;  // the pointer is baked into the graphs
+  return prepare(s);
+}
+
+}  // namespace
+
+struct srmd_batch {
+  std::vector<srmd_system *> sys;
+  std::vector<ReplicaDesc> host_desc;
+  std::vector<int> order;  // largest replica first
+  ReplicaDesc *d_desc = nullptr;
+  int *d_order = nullptr;
+  hipStream_t stream = nullptr;
+  int tp = 0, vb = 0, method = 0;
+  size_t lds = 0;
+  std::map<long long, hipGraphExec_t> graphs;
+  std::string err;
+};
+
+namespace {
+
+srmd_status bfail(srmd_batch *b, srmd_status st, const std::string &msg) {
+  if (b) b->err = msg;
+  g_thread_error = msg;
+  return st;
+}
+
+void drop_batch_graphs(srmd_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+// Refresh the replica descriptors from the systems (constants, pointers, buffers).
+srmd_status batch_sync_desc(srmd_batch *b) {
+  bool changed = false;
+  for (size_t r = 0; r < b->sys.size(); ++r) {
+    srmd_system *s = b->sys[r];
+    srmd_status st = prepare(s);
+    if (st != SRMD_OK) return bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
+    if (s->tp != b->tp || s->tp * s->ppb != b->vb || s->method != b->method)
+      return bfail(b, SRMD_EINVAL, "replicas must share the cutoff method and the launch shape (tp, ppb)");
+    s->sort_pending = false;  // the batched kernel sorts inside the workgroup
+    ReplicaDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.c = s->c;
+    d.p = s->p;
+    d.cur = s->cur;
+    d.G = step_blocks(s);
+    if (std::memcmp(&d, &b->host_desc[r], sizeof(d)) != 0) {
+      b->host_desc[r] = d;
+      changed = true;
+    }
+  }
+  if (changed) {
+    hipError_t e = hipMemcpyAsync(b->d_desc, b->host_desc.data(), sizeof(ReplicaDesc) * b->host_desc.size(),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("descriptor upload: ") + hipGetErrorString(e));
+  }
+  return SRMD_OK;
+}
+
+srmd_status batch_graph(srmd_batch *b, long long nsteps, hipGraphExec_t *out) {
+  auto it = b->graphs.find(nsteps);
+  if (it != b->graphs.end()) {
+    *out = it->second;
+    return SRMD_OK;
+  }
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("capture: ") + hipGetErrorString(e));
+  hipError_t le = launch_batch(b->tp, b->method, (int)b->sys.size(), b->lds, b->stream, b->d_desc, b->d_order,
+                               (int)nsteps, b->vb);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(b->stream, &g);
+  if (le != hipSuccess || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return bfail(b, SRMD_EHIP, std::string("batched launch capture: ") + hipGetErrorString(le != hipSuccess ? le : e));
+  }
+  hipGraphExec_t ge;
+  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  b->graphs[nsteps] = ge;
+  *out = ge;
   return SRMD_OK;
 }
 
@@ -750,15 +849,8 @@ srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd
   if (st != SRMD_OK) return st;
   if (nsteps == 0) return SRMD_OK;
   const long long cap = thermo_every > 0 ? trace_cap : 0;
-  if (cap > s->trace_alloc) {
-    dev_free(s, s->p.trace);
-    s->p.trace = (Thermo *)dev_alloc(s, sizeof(Thermo) * (size_t)cap);
-    if (!s->p.trace) return fail(s, SRMD_ENOMEM, "trace allocation failed");
-    s->trace_alloc = cap;
-    s->dirty = true;  // the pointer is baked into the graphs
-    st = prepare(s);
-    if (st != SRMD_OK) return st;
-  }
+  st = ensure_trace(s, cap);
+  if (st != SRMD_OK) return st;
   st = alloc_snapshot(s);
   if (st != SRMD_OK) return st;
   for (int attempt = 0; attempt < 8; ++attempt) {
@@ -1034,5 +1126,149 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   if (ppb_out) *ppb_out = 0;
   return fail(s, SRMD_EUNSUPPORTED, "autotune not available yet");
 }
+
+srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int32_t count) {
+  if (!out) return bfail(nullptr, SRMD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!systems || count < 1) return bfail(nullptr, SRMD_EINVAL, "need at least one system");
+  for (int r = 0; r < count; ++r) {
+    srmd_system *s = systems[r];
+    if (!s) return bfail(nullptr, SRMD_EINVAL, "NULL system in the batch");
+    for (int q = 0; q < r; ++q)
+      if (systems[q] == s) return bfail(nullptr, SRMD_EINVAL, "a system appears twice in the batch");
+    if (!s->integrator_set) return bfail(nullptr, SRMD_EINVAL, "every replica needs an integrator");
+    if (s->prec != SRMD_PREC_F32) return bfail(nullptr, SRMD_EUNSUPPORTED, "batched replicas use float32 positions");
+    srmd_status st = prepare(s);
+    if (st != SRMD_OK) return bfail(nullptr, st, s->err);
+    if (s->n > batch_max_particles() || !s->c.small_sort)
+      return bfail(nullptr, SRMD_EUNSUPPORTED, "a batched replica must have at most 8192 particles and 8192 cells");
+  }
+  srmd_batch *b = new (std::nothrow) srmd_batch();
+  if (!b) return bfail(nullptr, SRMD_ENOMEM, "host allocation failed");
+  b->sys.assign(systems, systems + count);
+  b->stream = systems[0]->stream;
+  b->tp = systems[0]->tp;
+  b->vb = systems[0]->tp * systems[0]->ppb;
+  b->method = systems[0]->method;
+  int nmax = 0;
+  for (auto *s : b->sys) nmax = std::max(nmax, s->n);
+  b->lds = batch_lds_bytes(nmax);
+  b->host_desc.assign((size_t)count, ReplicaDesc{});
+  std::memset(b->host_desc.data(), 0xff, sizeof(ReplicaDesc) * (size_t)count);  // forces the first upload
+  b->order.resize((size_t)count);
+  for (int r = 0; r < count; ++r) b->order[(size_t)r] = r;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) { return b->sys[a]->n > b->sys[c]->n; });
+  if (hipMalloc(&b->d_desc, sizeof(ReplicaDesc) * (size_t)count) != hipSuccess ||
+      hipMalloc(&b->d_order, sizeof(int) * (size_t)count) != hipSuccess) {
+    srmd_batch_destroy(b);
+    return bfail(nullptr, SRMD_ENOMEM, "batch descriptor allocation failed");
+  }
+  if (hipMemcpy(b->d_order, b->order.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice) != hipSuccess) {
+    srmd_batch_destroy(b);
+    return bfail(nullptr, SRMD_EHIP, "batch order upload failed");
+  }
+  srmd_status st = batch_sync_desc(b);
+  if (st != SRMD_OK) {
+    std::string m = b->err;
+    srmd_batch_destroy(b);
+    return bfail(nullptr, st, m);
+  }
+  *out = b;
+  return SRMD_OK;
+}
+
+srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
+                            int64_t trace_cap) {
+  if (!b) return bfail(nullptr, SRMD_EINVAL, "batch is NULL");
+  if (nsteps < 0 || nsteps > (1LL << 30)) return bfail(b, SRMD_EINVAL, "nsteps out of range");
+  if (thermo_every < 0 || trace_cap < 0 || (trace_cap > 0 && !trace)) return bfail(b, SRMD_EINVAL, "invalid trace");
+  if (nsteps == 0) return SRMD_OK;
+  const long long cap = thermo_every > 0 ? trace_cap : 0;
+  for (auto *s : b->sys) {
+    srmd_status st = ensure_trace(s, cap);
+    if (st == SRMD_OK) st = alloc_snapshot(s);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+  }
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    srmd_status st = batch_sync_desc(b);
+    if (st != SRMD_OK) return st;
+    for (auto *s : b->sys) {
+      Control hc;
+      st = read_ctl(s, &hc);
+      if (st != SRMD_OK) return bfail(b, st, s->err);
+      hc.thermo_every = thermo_every;
+      hc.trace_cap = cap;
+      hc.n_records = 0;
+      st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
+      if (st == SRMD_OK) st = snapshot(s, false);
+      if (st != SRMD_OK) return bfail(b, st, s->err);
+    }
+    for (auto *s : b->sys)
+      if (hipStreamSynchronize(s->stream) != hipSuccess) return bfail(b, SRMD_EHIP, "replica stream sync failed");
+    hipGraphExec_t ge;
+    st = batch_graph(b, nsteps, &ge);
+    if (st != SRMD_OK) return st;
+    hipError_t e = hipGraphLaunch(ge, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("batched run: ") + hipGetErrorString(e));
+    bool overflow = false;
+    for (auto *s : b->sys) {
+      Control h;
+      st = read_ctl(s, &h);
+      if (st != SRMD_OK) return bfail(b, st, s->err);
+      if (h.error & 1) return bfail(b, SRMD_ESTATE, "non-finite force or position in a replica");
+      if (h.error & 2) overflow = true;
+    }
+    if (overflow) {  // restore every replica, grow the lists that overflowed, replay
+      for (auto *s : b->sys) {
+        Control h;
+        st = read_ctl(s, &h);
+        if (st == SRMD_OK) st = snapshot(s, true);
+        if (st != SRMD_OK) return bfail(b, st, s->err);
+        if (h.error & 2) {
+          Control r;
+          st = read_ctl(s, &r);
+          if (st != SRMD_OK) return bfail(b, st, s->err);
+          r.error &= ~2;
+          st = h2d_sync(s, s->p.ctl, &r, sizeof(Control));
+          if (st == SRMD_OK) st = regrow(s);
+          if (st != SRMD_OK) return bfail(b, st, s->err);
+        }
+      }
+      drop_batch_graphs(b);
+      b->lds = batch_lds_bytes(b->lds / 16);
+      continue;
+    }
+    for (size_t r = 0; r < b->sys.size(); ++r) {
+      srmd_system *s = b->sys[r];
+      s->cur ^= (int)(nsteps & 1);
+      if (cap > 0) {
+        Control h;
+        st = read_ctl(s, &h);
+        if (st != SRMD_OK) return bfail(b, st, s->err);
+        if (h.n_records > 0) {
+          std::vector<Thermo> tmp((size_t)h.n_records);
+          e = hipMemcpy(tmp.data(), s->p.trace, sizeof(Thermo) * tmp.size(), hipMemcpyDeviceToHost);
+          if (e != hipSuccess) return bfail(b, SRMD_EHIP, "trace download failed");
+          for (size_t k = 0; k < tmp.size(); ++k) to_public(tmp[k], &trace[(size_t)r * (size_t)cap + k]);
+        }
+      }
+    }
+    return SRMD_OK;
+  }
+  return bfail(b, SRMD_ENOMEM, "neighbour lists kept overflowing");
+}
+
+srmd_status srmd_batch_destroy(srmd_batch *b) {
+  if (!b) return SRMD_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_batch_graphs(b);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_order) (void)hipFree(b->d_order);
+  delete b;
+  return SRMD_OK;
+}
+
+const char *srmd_batch_last_error(const srmd_batch *b) { return b ? b->err.c_str() : g_thread_error.c_str(); }
 
 }  // extern "C"

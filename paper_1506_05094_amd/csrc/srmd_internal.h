@@ -117,4 +117,14 @@ struct SysPtrs {
   Thermo *trace;    // device trace (trace_cap records)
 };
 
+// One replica of a batch: its constants, its device arrays (the arrays of the
+// single system it came from), the position buffer in use and its partial count.
+struct ReplicaDesc {
+  SysConst c;
+  SysPtrs p;
+  int cur;
+  int G;        // blocks of the single-system step kernel (partials per step)
+  int pad[2];
+};
+
 }  // namespace srmd

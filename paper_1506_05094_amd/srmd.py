@@ -92,6 +92,10 @@ def load():
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_get_launch": (st, [sysp, _ip, _ip]),
         "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
+        "srmd_batch_create": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
+        "srmd_batch_step": (st, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
+        "srmd_batch_destroy": (st, [ctypes.c_void_p]),
+        "srmd_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
         "srmd_autotune": (st, [sysp, ctypes.c_int32, _ip, _ip]),
         "srmd_build_neighbor_list": (st, [sysp]),
         "srmd_compute_forces": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
@@ -299,11 +303,60 @@ class System:
         return b
 
 
+def _bcheck(status, bp=None):
+    if status != SRMD_OK:
+        msg = load().srmd_batch_last_error(bp)
+        raise SrmdError(status, msg.decode() if msg else "")
+
+
+class Batch:
+    """Many systems advanced together by one persistent launch (handle to srmd_batch).
+
+    The systems stay usable on their own; they must outlive the batch."""
+
+    def __init__(self, systems):
+        lib = load()
+        self.systems = list(systems)
+        arr = (ctypes.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
+        h = ctypes.c_void_p()
+        _bcheck(lib.srmd_batch_create(ctypes.byref(h), arr, len(self.systems)))
+        self._h = h
+
+    def step(self, nsteps, thermo_every=0, trace_cap=None):
+        lib = load()
+        if thermo_every > 0:
+            cap = int(trace_cap if trace_cap is not None else (nsteps + thermo_every - 1) // thermo_every)
+            trace = np.zeros((len(self.systems), cap), dtype=THERMO_DTYPE)
+            _bcheck(lib.srmd_batch_step(self._h, int(nsteps), int(thermo_every), trace.ctypes.data_as(_vp), cap),
+                    self._h)
+            return trace
+        _bcheck(lib.srmd_batch_step(self._h, int(nsteps), 0, None, 0), self._h)
+        return None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().srmd_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
 EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_lj", "srmd_set_skin",
             "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
             "srmd_autotune", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path"]
+            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_batch_create",
+            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error"]
 
 
 def _export_c_names():

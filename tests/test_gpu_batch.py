@@ -1,0 +1,160 @@
+"""Batched replicas: one persistent launch over many small systems.  A replica must
+follow its single-system trajectory bit for bit (same launch shape), match the
+oracle over a short horizon, and recover from list overflow."""
+import numpy as np
+import pytest
+
+import oracle
+from workloads import generators as gen
+
+from gpu_common import make_system, min_image
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1506_05094_amd import srmd
+    srmd.load()
+    oracle.load()
+
+
+REPLICAS = [(500, 0.4, 11), (1300, 0.6, 12), (2600, 0.8, 13), (4100, 1.0, 14)]
+
+
+def _replica_states():
+    return [gen.ka_random_state(n, 1.2, T, seed) for (n, T, seed) in REPLICAS]
+
+
+def _make(states, launch=(8, 32), dt=0.002):
+    sig, eps, rc = gen.ka_params()
+    out = []
+    for st, (_, T, _) in zip(states, REPLICAS):
+        s = make_system(st, sig, eps, rc, "sf", launch=launch)
+        s.set_integrator_nvt(dt, T, 0.2)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("launch", [(8, 32), (1, 256), (16, 16)])
+def test_batch_bitwise_equals_single(launch):
+    from paper_1506_05094_amd import srmd
+    states = _replica_states()
+    single = _make(states, launch)
+    batched = _make(states, launch)
+    steps = 300
+    tr_single = [s.step(steps, thermo_every=25) for s in single]
+    with srmd.Batch(batched) as b:
+        tr_batch = b.step(steps, thermo_every=25)
+    for r, (a, c) in enumerate(zip(single, batched)):
+        sa, sc = a.get_state(), c.get_state()
+        np.testing.assert_array_equal(sa["pos"], sc["pos"], err_msg=f"replica {r}")
+        np.testing.assert_array_equal(sa["vel"], sc["vel"], err_msg=f"replica {r}")
+        np.testing.assert_array_equal(sa["image"], sc["image"], err_msg=f"replica {r}")
+        for f in ("pe", "ke", "virial", "xi", "h_conserved"):
+            np.testing.assert_array_equal(tr_single[r][f], tr_batch[r][f], err_msg=f"replica {r} {f}")
+        assert a.thermo()["step"] == c.thermo()["step"] == steps - 1
+    for s in single + batched:
+        s.close()
+
+
+def test_batch_then_single_calls_continue():
+    from paper_1506_05094_amd import srmd
+    states = _replica_states()[:2]
+    a = _make(states)
+    b = _make(states)
+    for s in a:
+        s.step(120)
+    with srmd.Batch(b) as bb:
+        bb.step(50)
+        for s in b:
+            s.step(20)  # single-system calls between batch calls stay valid
+        bb.step(50)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.get_state()["pos"], y.get_state()["pos"])
+    for s in a + b:
+        s.close()
+
+
+def test_batch_short_trajectory_matches_oracle():
+    from paper_1506_05094_amd import srmd
+    states = _replica_states()[:2]
+    sys_ = _make(states, dt=0.002)
+    steps = 10
+    with srmd.Batch(sys_) as b:
+        b.step(steps)
+    sig, eps, rc = gen.ka_params()
+    for st, s, (_, T, _) in zip(states, sys_, REPLICAS):
+        ref = oracle.integrate(st.pos, st.vel, st.types, st.mass, st.box, sig, eps, rc, "sf", 0.002, steps,
+                               thermostat=True, T0=T, tau=0.2)
+        d = min_image(s.get_state()["pos"].astype(np.float64) - ref["pos"], st.box)
+        assert np.abs(d).max() <= 1e-4
+        s.close()
+
+
+def test_batch_rejects_unsupported():
+    from paper_1506_05094_amd import srmd
+    sig, eps, rc = gen.ka_params()
+    big = gen.ka_random_state(9000, 1.2, 0.5, 3)
+    s_big = make_system(big, sig, eps, rc, "sf")
+    s_big.set_integrator_nve(0.002)
+    with pytest.raises(srmd.SrmdError) as e:
+        srmd.Batch([s_big])
+    assert e.value.status == srmd.SRMD_EUNSUPPORTED
+    states = _replica_states()[:2]
+    a = _make(states[:1], launch=(8, 32))
+    b = _make(states[1:2], launch=(4, 64))
+    with pytest.raises(srmd.SrmdError) as e:
+        srmd.Batch(a + b)
+    assert e.value.status == srmd.SRMD_EINVAL
+    st = states[0]
+    p64 = make_system(st, sig, eps, rc, "sf", precision="f64pos")
+    p64.set_integrator_nve(0.002)
+    with pytest.raises(srmd.SrmdError):
+        srmd.Batch([p64])
+    for s in [s_big, p64] + a + b:
+        s.close()
+
+
+def test_batch_list_overflow_replays_like_single():
+    from paper_1506_05094_amd import srmd
+    import torch
+    # replica 1 contracts towards its centre and overflows the list capacity
+    rng = np.random.default_rng(7)
+    L = 12.0
+    g = (np.arange(9) - 4) * (L / 9)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = (pos + rng.uniform(-0.1, 0.1, pos.shape)).astype(np.float32)
+    vel = (-0.5 * pos).astype(np.float32)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def contracting():
+        s = srmd.System(pos, np.zeros(len(pos), np.int32), [L, L, L], vel=vel, stream=stream)
+        s.set_skin(0.4)
+        s.set_pair_lj(0, 0, 1.0, 0.05, 2.5, "sp")
+        s.set_integrator_nve(0.002)
+        s.set_launch(8, 32)
+        return s
+
+    def calm():
+        st = gen.config0_state()
+        sig, eps, rc = gen.lj_params()
+        s = make_system(st, sig, eps, rc, "sp", launch=(8, 32))
+        s.set_integrator_nve(0.002)
+        return s
+
+    single = [calm(), contracting()]
+    batched = [calm(), contracting()]
+    n0 = batched[1].stats()["n_max"]
+    for s in single:
+        s.step(400)
+    with srmd.Batch(batched) as b:
+        b.step(400)
+    assert batched[1].stats()["n_max"] > n0
+    for x, y in zip(single, batched):
+        np.testing.assert_array_equal(x.get_state()["pos"], y.get_state()["pos"])
+        x.close()
+        y.close()

@@ -12,6 +12,7 @@ from .generators import (  # noqa: F401
     fcc_lattice,
     lj_fcc_state,
     ka_random_state,
+    ka_replica_states,
     maxwell_boltzmann,
     jitter_positions,
     lj_params,

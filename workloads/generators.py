@@ -142,12 +142,76 @@ def lj_fcc_state(n: int, rho: float, T: float, seed: int) -> State:
                  ntypes=1, seed=seed, recipe=f"lj_fcc(N={n},rho={rho},T={T},seed={seed})")
 
 
+def _random_insertion(n, L, types, dmin, rng, batch=256):
+    """Random sequential insertion in a periodic cube of side L.
+
+    Candidates are drawn uniformly; candidate k is accepted when it is at least
+    dmin[t_k, t_j] from every particle j placed before it, where t_k = types[number
+    placed so far].  Candidates are drawn and tested against the particles already
+    placed in vectorised batches (through a cell grid), and then accepted one by one
+    in draw order, so the result is that of the one-at-a-time rule.
+    """
+    dmin2 = dmin * dmin
+    dmax = float(dmin.max())
+    nc = max(3, int(L // dmax))
+    cl = L / nc
+    cap = 24
+    grid = -np.ones((nc, nc, nc, cap), dtype=np.int64)
+    cnt = np.zeros((nc, nc, nc), dtype=np.int64)
+    offs = np.array([(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)])
+    pos = np.empty((n, 3))
+    placed = 0
+    draws = 0
+    while placed < n:
+        B = batch
+        cand = rng.uniform(-L / 2, L / 2, size=(B, 3))
+        draws += B
+        if draws > 400 * n + 10000:
+            raise RuntimeError("random insertion did not converge")
+        cc = np.floor((cand + L / 2) / cl).astype(np.int64) % nc
+        nb = (cc[:, None, :] + offs[None, :, :]) % nc
+        idx = grid[nb[..., 0], nb[..., 1], nb[..., 2]].reshape(B, -1)
+        valid = idx >= 0
+        j = np.where(valid, idx, 0)
+        d = pos[j] - cand[:, None, :]
+        d -= L * np.round(d / L)
+        r2 = (d * d).sum(-1)
+        tj = types[j]
+        bad_placed = [(valid & (r2 < dmin2[t][tj])).any(1).tolist() for t in (0, 1)]
+        # earlier candidates of this batch that could conflict with candidate k
+        dd = cand[:, None, :] - cand[None, :, :]
+        dd -= L * np.round(dd / L)
+        rr = (dd * dd).sum(-1)
+        ks, ms = np.nonzero(np.tril(rr < dmax * dmax, -1))
+        earlier = {}
+        for k, m in zip(ks.tolist(), ms.tolist()):
+            earlier.setdefault(k, []).append(m)
+        acc_type = {}
+        for k in range(B):
+            if placed >= n:
+                break
+            t = int(types[placed])
+            if bad_placed[t][k]:
+                continue
+            if k in earlier and any(m in acc_type and rr[k, m] < dmin2[t, acc_type[m]] for m in earlier[k]):
+                continue
+            acc_type[k] = t
+            pos[placed] = cand[k]
+            c0, c1, c2 = cc[k]
+            if cnt[c0, c1, c2] >= cap:
+                raise RuntimeError("insertion grid cell overflow")
+            grid[c0, c1, c2, cnt[c0, c1, c2]] = placed
+            cnt[c0, c1, c2] += 1
+            placed += 1
+    return pos
+
+
 def ka_random_state(n: int, rho: float, T: float, seed: int, min_dist_factor: float = 0.75) -> State:
     """Kob-Andersen 80:20 mixture by random sequential insertion.
 
     N_A = round(0.8 N), N_B = N - N_A, types assigned by a seeded permutation.
-    Particles are inserted one at a time at uniform random points and rejected if
-    closer than ``min_dist_factor`` * sigma_ab to any particle already placed.
+    Particles are inserted at uniform random points, a candidate being rejected if it
+    is closer than ``min_dist_factor`` * sigma_ab to any particle already placed.
     Velocities from ``maxwell_boltzmann`` at T.
     """
     rng = np.random.default_rng(seed)
@@ -157,53 +221,30 @@ def ka_random_state(n: int, rho: float, T: float, seed: int, min_dist_factor: fl
     types = types[rng.permutation(n)]
     L = _f32_side((n / rho) ** (1.0 / 3.0))
     box = np.array([L, L, L])
-    dmin = min_dist_factor * KA_SIGMA
-    dmin2 = dmin * dmin
-    cell_len = float(dmin.max())
-    nc = max(1, int(L // cell_len))
-    cl = L / nc
-    grid: dict = {}
-    pos = np.empty((n, 3), dtype=np.float64)
-    placed = 0
-    attempts = 0
-    batch = rng.uniform(-L / 2, L / 2, size=(4096, 3))
-    bi = 0
-    while placed < n:
-        if bi == batch.shape[0]:
-            batch = rng.uniform(-L / 2, L / 2, size=(4096, 3))
-            bi = 0
-        cand = batch[bi]
-        bi += 1
-        attempts += 1
-        if attempts > 200 * n:
-            raise RuntimeError("random insertion did not converge")
-        t = types[placed]
-        c = tuple(int((cand[k] + L / 2) / cl) % nc for k in range(3))
-        ok = True
-        for dx in (-1, 0, 1):
-            if not ok:
-                break
-            for dy in (-1, 0, 1):
-                if not ok:
-                    break
-                for dz in (-1, 0, 1):
-                    key = ((c[0] + dx) % nc, (c[1] + dy) % nc, (c[2] + dz) % nc)
-                    for j in grid.get(key, ()):
-                        d = pos[j] - cand
-                        d -= L * np.round(d / L)
-                        if d[0] * d[0] + d[1] * d[1] + d[2] * d[2] < dmin2[t, types[j]]:
-                            ok = False
-                            break
-                    if not ok:
-                        break
-        if ok:
-            pos[placed] = cand
-            grid.setdefault(c, []).append(placed)
-            placed += 1
+    pos = _random_insertion(n, L, types, min_dist_factor * KA_SIGMA, rng)
     mass = np.array([1.0, 1.0])
     vel = maxwell_boltzmann(n, T, np.ones(n), seed + 7919).astype(np.float32)
     return State(pos=_wrap_f32(pos, box), vel=vel, types=types, box=box, mass=mass, ntypes=2,
                  seed=seed, recipe=f"ka_random(N={n},rho={rho},T={T},seed={seed},dmin={min_dist_factor})")
+
+
+def _ka_replica(args):
+    n, rho, T, seed = args
+    return ka_random_state(n, rho, T, seed)
+
+
+def ka_replica_states(count: int = 256, master_seed: int = 2026, n_lo: int = 500, n_hi: int = 8000, rho=1.2,
+                      workers: int = 1):
+    """The batched-replica workload: KA systems with N_r ~ U{n_lo..n_hi}, T_r ~ U[0.4, 1.0],
+    replica r seeded 1000 + r.  ``workers`` > 1 generates replicas in worker processes
+    (the result does not depend on it)."""
+    jobs = [(n, rho, T, seed) for (n, T, seed) in config3_states(count, master_seed, n_lo, n_hi)]
+    if workers <= 1:
+        return [_ka_replica(j) for j in jobs]
+    from concurrent.futures import ProcessPoolExecutor
+
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(_ka_replica, jobs, chunksize=4))
 
 
 # ---- the benchmark configurations ------------------------------------------------------
