@@ -161,6 +161,10 @@ def main():
     ap.add_argument("--n", type=int, default=864, help="particles for --workload lj")
     ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
     ap.add_argument("--ppb", type=int, default=0)
+    ap.add_argument("--mode", default="persistent", choices=["persistent", "chain"],
+                    help="persistent: 500 steps per launch of one kernel (systems up to 8192 particles); "
+                         "chain: graph-captured launch chains")
+    ap.add_argument("--groups", type=int, default=-1, help="workgroups of the persistent kernel (-1: automatic)")
     ap.add_argument("--profile-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -184,6 +188,8 @@ def main():
     s = srmd.system_from_state(state, sig, eps, rc, method, skin=0.3, stream=torch.cuda.current_stream().cuda_stream)
     if args.tp:
         s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
+    persistent = args.mode == "persistent" and state.n <= 8192
+    s.set_persistent(args.groups if persistent else 0)
     if integ[0] == "nvt":
         s.set_integrator_nvt(0.001, integ[2], integ[3])
         s.step(2000)  # relax the random insertion (untimed)
@@ -204,18 +210,26 @@ def main():
     log(f"timed {args.steps} steps in {wall:.4f} s: {value:.4e} particle-steps/s, {args.steps / wall:.1f} steps/s, "
         f"rebuilds {st1['n_rebuilds'] - st0['n_rebuilds']}, tp {st1['tp']} ppb {st1['ppb']}, T {th['temperature']:.4f}")
 
-    # dominant kernel: the fused force + integrator kernel, timed per launch with HIP events
+    # dominant kernel, timed per launch with HIP events on the system's stream: the
+    # fused force + integrator kernel (launch chains), or the persistent kernel
     ev_ms, dev_ms, launches = s.profile_step_kernel(args.profile_steps)
+    # entries of a list built at the final positions (the counter of the last build
+    # reads 0 when the run ended on a step that scheduled a rebuild)
+    s.build_neighbor_list()
     st2 = s.stats()
     avg_s = ev_ms / 1e3 / launches
     dev_avg_s = dev_ms / 1e3 / launches
-    bytes_launch = step_kernel_bytes(n, st2["list_entries"])
+    steps_per_launch = args.profile_steps / launches if persistent else 1
+    bytes_launch = step_kernel_bytes(n, st2["list_entries"]) * steps_per_launch
     achieved = bytes_launch / avg_s / 1e9
-    log(f"step kernel: {launches} launches, event avg {avg_s * 1e6:.2f} us, device-clock avg {dev_avg_s * 1e6:.2f} us, "
+    log(f"dominant kernel: {launches} launches of {steps_per_launch:g} steps, event avg {avg_s * 1e6:.2f} us "
+        f"({avg_s * 1e6 / steps_per_launch:.3f} us/step), device-clock avg {dev_avg_s * 1e6:.2f} us, "
         f"{bytes_launch / 1e6:.3f} MB algorithmic per launch -> {achieved:.1f} GB/s")
+    kname = ("k_coop (persistent: list build, sort, pair force, integrator, reductions)" if persistent
+             else "k_step (fused pair force + integrator)")
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "k_step (fused pair force + integrator)", "avg_us_events": round(avg_s * 1e6, 3),
+                "kernel": kname, "steps_per_launch": steps_per_launch, "avg_us_events": round(avg_s * 1e6, 3),
                 "avg_us_device_clock": round(dev_avg_s * 1e6, 3), "bytes_per_launch": bytes_launch,
                 "list_entries_per_particle": round(st2["list_entries"] / n, 2)}
     cpu = None
@@ -227,7 +241,8 @@ def main():
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"]),
+        "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"], mode="persistent" if persistent else "chain",
+                       groups=st1["persistent_groups"]),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],
         "roofline": roofline, "cpu_baseline": cpu,

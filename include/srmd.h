@@ -109,7 +109,7 @@ srmd_status srmd_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*f
 srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigma, double epsilon, double rcut,
                              srmd_cutoff method);
 
-/* Neighbour-list skin s >= 0: pairs within r_c,ab + s are listed (paper section 3),
+/* Neighbour-list skin s >= 0: pairs within r_c,ab + s are listed (paper section 4),
  * and the list is rebuilt once any particle has moved more than s/2 since the last
  * build (section 6).  Default 0.3. */
 srmd_status srmd_set_skin(srmd_system *s, double skin);
@@ -121,7 +121,7 @@ srmd_status srmd_set_integrator_nve(srmd_system *s, double dt);
  * thermostat relaxation time tau > 0 (mass Q = g T0 tau^2, g = 3N - 3). */
 srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double tau);
 
-/* Thread layout of the force kernel (paper section 3 table of code conventions):
+/* Thread layout of the force kernel (paper section 4 table of code conventions):
  * tp threads per particle (power of two, 1..64) and ppb particles per block,
  * tp*ppb <= 1024 and a multiple of 64.  (0, 0) selects the built-in default for the
  * system size or the value found by srmd_autotune. */
@@ -134,11 +134,34 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
  * particle (the paper's section 7 layout). */
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
 
+/* Run the steps of a small system as persistent launches (one launch per 500
+ * steps) instead of graph-captured launch chains (three launches per step).  Small systems are bound by latency, not by
+ * arithmetic (section 3); the paper keeps their whole run on the device without
+ * host round trips (section 6), and this mode also removes the launch boundaries
+ * between the kernels of a step.  groups = 0: launch
+ * chains (the default unless srmd_autotune chose otherwise); groups = -1: persistent,
+ * the library picks the number of workgroups; groups > 0: persistent with exactly
+ * that many workgroups of 512 threads, all of which must fit on the device at once
+ * (SRMD_EUNSUPPORTED at the next step otherwise).  The persistent kernel keeps all
+ * positions of the system in every workgroup's LDS, separates the time steps by a
+ * device-wide barrier and repeats the reductions of the launch chain in the same
+ * order, so the trajectory is the same bit for bit at the same (tp, ppb).  It needs
+ * float32 positions, at most 8192 particles and at most 8192 cells; srmd_step on a
+ * system outside that range returns SRMD_EUNSUPPORTED while groups != 0.  A barrier
+ * that does not complete within about one second (workgroups not co-resident) ends
+ * the launch and the call returns SRMD_EHIP instead of hanging. */
+srmd_status srmd_set_persistent(srmd_system *s, int32_t groups);
+
 /* Read back the thread layout in use (after defaults are resolved). */
 srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb);
 
 /* Choose tp and ppb by timing short runs from a saved copy of the current state
- * (paper appendix: each trial starts from the same stored configuration).  The
+ * (paper appendix: each trial starts from the same stored configuration): phase I
+ * the list-build method at the default layout, phase II block size x tp with the
+ * appendix's stop rules, and for systems the persistent kernel can run (see
+ * srmd_set_persistent) a phase III over tp in persistent mode.  The fastest
+ * layout, list method and mode become the system's defaults; an explicit
+ * srmd_set_launch / srmd_set_rebuild_path / srmd_set_persistent still wins.  The
  * state is restored afterwards.  Any output pointer may be NULL. */
 srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out);
 
@@ -182,10 +205,11 @@ srmd_status srmd_get_box(const srmd_system *s, double box[3]);
 
 /* Counters of a system: steps taken, list builds, entries of the current list,
  * the longest list of the last build, the list capacity per particle, the launch
- * shape in use (tp, ppb, blocks of the step kernel) and the cell grid size. */
+ * shape in use (tp, ppb, blocks of the step kernel), the cell grid size and the
+ * workgroups of the persistent kernel (0 when steps run as launch chains). */
 typedef struct {
   int64_t steps, n_rebuilds, list_entries;
-  int32_t max_nbrs, n_max, tp, ppb, blocks, ncell;
+  int32_t max_nbrs, n_max, tp, ppb, blocks, ncell, persistent_groups, reserved;
 } srmd_stats;
 
 srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out);
@@ -194,8 +218,11 @@ srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out);
  * event recorded on the system's stream immediately before and after every
  * step-kernel launch.  kernel_ms receives the sum of those event intervals,
  * device_ms the same launches timed by the device clock (first block start to last
- * block end), launches the number of step kernels timed.  The steps are real steps
- * of the simulation (the state advances).  Any output pointer may be NULL. */
+ * block end), launches the number of step kernels timed.  In persistent mode
+ * (srmd_set_persistent) the steps run as launches of the persistent kernel of 500
+ * steps each (the last one shorter), each timed the same way; launches is their
+ * number and device_ms is 0.  The steps are real steps of the simulation (the
+ * state advances).  Any output pointer may be NULL. */
 srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *kernel_ms, double *device_ms,
                                      int64_t *launches);
 
@@ -222,8 +249,11 @@ srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int
 /* Advance every replica by nsteps steps in one persistent launch (captured in a HIP
  * graph).  If thermo_every > 0, replica r writes the records of its steps n with
  * n % thermo_every == 0 to trace[r * trace_cap + k], k < trace_cap (caller-owned
- * array of count * trace_cap records).  Synchronises at the end; list overflows are
- * handled by restoring every replica and replaying with grown lists. */
+ * array of count * trace_cap records).  Synchronises at the end.  A replica whose
+ * list overflowed (paper section 4) is restored to its state at the call start, its
+ * list capacity doubled, and its steps replayed on its own by the single-system
+ * path; the other replicas keep their batched result.  On a non-finite replica the
+ * call returns SRMD_ESTATE after finishing every other replica. */
 srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
                             int64_t trace_cap);
 

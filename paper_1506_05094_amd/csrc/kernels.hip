@@ -540,9 +540,9 @@ constexpr int kListChunks = 4;   // 64-candidate chunks whose loads are in fligh
 // Lane s loads the bounds of run s, a wave prefix sum gives each run's offset in
 // the candidate sequence, the runs are expanded into LDS, and the candidates are
 // tested 64 at a time; a ballot compacts the hits in candidate order, so the
-// list order is deterministic (stencil row order, then slot order).
-// List of one particle t by the calling wave (see k_list_wave); cand is this wave's
-// LDS window of kWaveCand entries.  Returns the number of entries kept (all lanes).
+// list order is deterministic (stencil row order, then slot order).  cand is the
+// calling wave's LDS window of kWaveCand entries; returns the number of entries
+// kept (all lanes).
 __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t, unsigned *cand,
                              const float *s_cs2) {
   const int lane = threadIdx.x & 63;
@@ -566,7 +566,9 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
     const int rowbase = (zz * ny + yy) * nx;
     const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
     if (x1 >= x0) {
-      const unsigned s0 = p.cell_start[rowbase + x0], s1 = p.cell_start[rowbase + x1 + 1];
+      // clamped to [0, n]: a run never reaches outside the sorted arrays
+      const unsigned s1 = min(p.cell_start[rowbase + x1 + 1], (unsigned)c.n);
+      const unsigned s0 = min(p.cell_start[rowbase + x0], s1);
       run_start = s0;
       run_len = s1 - s0;
     }
@@ -626,15 +628,7 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
   return kept;
 }
 
-// Verlet list of particle t (sorted slot), one wave per particle; for small systems,
-// where one thread per particle (section 7) leaves the chip idle and every thread
-// waits on a long chain of dependent loads.  The 5x5x5 stencil (every cell along
-// an axis with fewer than 5 cells) is cut into rows of consecutive x cells; as
-// particles are sorted by cell index, each row is one or two contiguous slot runs.
-// Lane s loads the bounds of run s, a wave prefix sum gives each run's offset in
-// the candidate sequence, the runs are expanded into LDS, and the candidates are
-// tested 64 at a time; a ballot compacts the hits in candidate order, so the
-// list order is deterministic (stencil row order, then slot order).
+// One wave per particle (list_wave_one), four particles per block.
 __global__ __launch_bounds__(256) void k_list_wave(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
@@ -682,11 +676,13 @@ __global__ __launch_bounds__(256) void k_list_thread(SysConst c, SysPtrs p, int 
       for (int oy = 0; oy < ny_eff; ++oy) {
         const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
         const int rowbase = (zz * ny + yy) * nx;
-        const unsigned sa0 = p.cell_start[rowbase + a0], sa1 = p.cell_start[rowbase + a1 + 1];
+        // runs clamped to [0, n]: they never reach outside the sorted arrays
+        const unsigned sa1 = min(p.cell_start[rowbase + a1 + 1], (unsigned)c.n);
+        const unsigned sa0 = min(p.cell_start[rowbase + a0], sa1);
         unsigned sb0 = 0, sb1 = 0;
         if (b1 >= b0) {
-          sb0 = p.cell_start[rowbase + b0];
-          sb1 = p.cell_start[rowbase + b1 + 1];
+          sb1 = min(p.cell_start[rowbase + b1 + 1], (unsigned)c.n);
+          sb0 = min(p.cell_start[rowbase + b0], sb1);
         }
         const unsigned la = sa1 - sa0, lt = la + (sb1 - sb0);
         for (unsigned base = 0; base < lt; base += kThreadBatch) {
@@ -906,6 +902,12 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
 
 // ---------------------------------------------------------------- end of step
 
+// Nose-Hoover friction of the next step from the half-step kinetic energy.
+__device__ __forceinline__ double xi_next(const SysConst &c, double xi, double ke_half) {
+  const double th = 2.0 * ke_half / c.g;
+  return xi + c.dtd * (th / c.T0 - 1.0) * c.inv_tau2;
+}
+
 // End of a time step, by one thread, from the fully reduced partials a: the
 // thermodynamic record, the Nose-Hoover update, the step counter and the
 // displacement test that sets the rebuild flag.  Returns the flag.
@@ -934,8 +936,7 @@ __device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockParti
     ctl->n_records += 1;
   }
   if (c.thermostat) {
-    const double th = 2.0 * a.ke_half / c.g;
-    const double xn = xi + c.dtd * (th / c.T0 - 1.0) * c.inv_tau2;
+    const double xn = xi_next(c, xi, a.ke_half);
     ctl->xi_int += c.dtd * (xi + xn) * 0.5;
     ctl->xi = xn;
   }
@@ -1081,15 +1082,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const ReplicaDesc *__re
   BlockPartial *wpart = p.part + G;  // one partial per wave unit, after the block partials
   stage_pairs(sp, c);
   if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
+  // a pending rebuild has had its spatial sort already (host request or end of step)
+  if (tid == 0) s_flag = p.ctl->rebuild;
   __syncthreads();
   for (int step = 0; step < nsteps; ++step) {
-    if (tid == 0) s_flag = p.ctl->rebuild;
-    __syncthreads();
     if (s_flag) {
-      // spatial sort of pos[cur] into the t_* arrays (LDS scratch: cell counts, ids)
-      unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
-      sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
-      __syncthreads();
       // list build, one wave per particle (LDS scratch: one candidate window per wave)
       unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
       int kept = 0;
@@ -1193,11 +1190,249 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const ReplicaDesc *__re
       }
       a.t0 = 0ull;
       a.t1 = 0ull;
-      finish_step(c, p, a);
+      s_flag = finish_step(c, p, a);
     }
     __syncthreads();
     cur ^= 1;
+    if (s_flag) {
+      // spatial sort of the new positions for the next list build, as k_finish does
+      // (LDS scratch: cell counts, ids)
+      unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
+      sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+      __syncthreads();
+    }
   }
+}
+
+// ---------------------------------------------------------------- persistent single system
+
+// Grid-wide barrier of a cooperative launch (every workgroup co-resident).  The last
+// workgroup to arrive resets the count and advances the generation; the others spin
+// on the generation with a bounded wait (about one second of device clock), after
+// which they report an error instead of hanging.  Release / acquire at agent scope
+// make every write before the barrier visible to every workgroup after it.
+__device__ __forceinline__ bool grid_barrier(Control *ctl, unsigned G, unsigned &gen, int *s_ok) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's stores, device-wide
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned g = gen;
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == G - 1) {
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > 100000000ull) {
+          atomicOr(&ctl->error, 4);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    gen = g + 1;
+    *s_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // other workgroups' stores, this wave
+  return *s_ok != 0;
+}
+
+// One small system (N <= 8192) advanced nsteps in a single cooperative launch of
+// gridDim.x workgroups.  Every workgroup keeps all positions in LDS during the force
+// phase, so a neighbour read is an LDS read; the steps are separated by one grid
+// barrier, plus one after the spatial sort (workgroup 0, at the end of a step that
+// decides a rebuild) and one after the list build of the next step.
+// The wave units, the block partials and their reduction are those of the
+// single-system kernels, computed redundantly by every workgroup, so the trajectory
+// is the same bit for bit and no workgroup waits for another to publish the
+// thermostat or the rebuild decision.
+template <int TP, int METHOD>
+__global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, int cur, int nsteps, int G, int vb) {
+  extern __shared__ float4 s_dyn[];
+  __shared__ SharedPairs sp;
+  __shared__ BlockPartial s_waves[16];
+  __shared__ float s_cs2[kMaxPairs];
+  __shared__ int s_ok;
+  __shared__ int s_rebuild;
+  __shared__ int s_kept[kBatchWaves];
+  __shared__ double s_xi;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const unsigned NW = gridDim.x;
+  const int gwave = blockIdx.x * kBatchWaves + wv, nwaves = NW * kBatchWaves;
+  const int wpv = vb >> 6;
+  const int units = G * wpv;
+  const SRMD_GLOBAL int *nblg = global_view(p.nbl);
+  unsigned gen = 0;
+  if (tid == 0) {
+    gen = __hip_atomic_load(&p.ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    s_rebuild = p.ctl->rebuild;
+    s_xi = c.thermostat ? p.ctl->xi : 0.0;
+  }
+  stage_pairs(sp, c);
+  if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
+  __syncthreads();
+  // all workgroups read the barrier generation before anyone can advance it
+  if (!grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+  for (int step = 0; step < nsteps; ++step) {
+    BlockPartial *wpart = p.part + G + (size_t)(step & 1) * units;  // double buffer across steps
+    if (s_rebuild) {  // the spatial sort has been done (host request or end of step)
+      unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
+      int kept = 0;
+      for (int t = gwave; t < c.n; t += nwaves) kept += list_wave_one(c, p, cur, t, cand, s_cs2);
+      if (lane == 0) s_kept[wv] = kept;
+      __syncthreads();
+      if (tid == 0) {
+        long long tot = 0;
+        for (int k = 0; k < kBatchWaves; ++k) tot += s_kept[k];
+        atomicAdd((unsigned long long *)&p.ctl->list_entries, (unsigned long long)tot);
+      }
+      if (!grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+    }
+    for (int k = tid; k < c.n; k += kBatchThreads) s_dyn[k] = gload(p.pos[cur], k);
+    __syncthreads();
+    const double xi = s_xi;
+    for (int u = gwave; u < units; u += nwaves) {
+      const int gt = u * 64 + lane;
+      const int i = gt / TP, t = gt % TP;
+      const bool active = i < c.n;
+      float fx = 0.f, fy = 0.f, fz = 0.f, uu = 0.f, w = 0.f;
+      float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+      float4 vo = pi, l0 = pi, kc = pi;
+      int4 im = make_int4(0, 0, 0, 0);
+      if (active) {
+        pi = s_dyn[i];
+        const int nn = gload(p.nnb, i);
+        if (t == 0) {
+          vo = gload(p.vel, i);
+          im = gload(p.img, i);
+          l0 = gload(p.last, i);
+        }
+        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, nn, sp, c, fx, fy, fz, uu, w);
+      }
+      fx = lane_sum<TP>(fx);
+      fy = lane_sum<TP>(fy);
+      fz = lane_sum<TP>(fz);
+      uu = lane_sum<TP>(uu);
+      w = lane_sum<TP>(w);
+      BlockPartial v = zero_partial();
+      if (active && t == 0)
+        integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
+      wave_reduce(v);
+      if (lane == 0) wpart[u] = v;
+    }
+    if (!grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+    // every workgroup: block partials (waves in order) folded straight into the
+    // reduction of k_finish (1024 threads, each thread here standing in for tid, tid+512)
+    BlockPartial a0 = zero_partial(), a1 = zero_partial();
+    for (int half = 0; half < 2; ++half) {
+      BlockPartial &acc = half ? a1 : a0;
+      for (int b = tid + half * kBatchThreads; b < G; b += 1024) {
+        BlockPartial q = wpart[b * wpv];
+        for (int k = 1; k < wpv; ++k) {
+          const BlockPartial r = wpart[b * wpv + k];
+          q.pe += r.pe;
+          q.w += r.w;
+          q.ke_half += r.ke_half;
+          q.ke_int += r.ke_int;
+          q.disp2 = fmax(q.disp2, r.disp2);
+          q.nonfinite |= r.nonfinite;
+        }
+        acc.pe += q.pe;
+        acc.w += q.w;
+        acc.ke_half += q.ke_half;
+        acc.ke_int += q.ke_int;
+        acc.disp2 = fmax(acc.disp2, q.disp2);
+        acc.nonfinite |= q.nonfinite;
+      }
+    }
+    wave_reduce(a0);
+    wave_reduce(a1);
+    if (lane == 0) {
+      s_waves[wv] = a0;
+      s_waves[wv + kBatchWaves] = a1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      BlockPartial a = s_waves[0];
+      for (int k = 1; k < 16; ++k) {
+        a.pe += s_waves[k].pe;
+        a.w += s_waves[k].w;
+        a.ke_half += s_waves[k].ke_half;
+        a.ke_int += s_waves[k].ke_int;
+        a.disp2 = fmax(a.disp2, s_waves[k].disp2);
+        a.nonfinite |= s_waves[k].nonfinite;
+      }
+      a.t0 = 0ull;
+      a.t1 = 0ull;
+      if (blockIdx.x == 0) {
+        s_rebuild = finish_step(c, p, a);  // the one writer of the control block
+      } else {
+        s_rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
+      }
+      if (c.thermostat) s_xi = xi_next(c, s_xi, a.ke_half);
+    }
+    __syncthreads();
+    cur ^= 1;
+    if (s_rebuild) {
+      // spatial sort of the new positions by workgroup 0, as k_finish does
+      if (blockIdx.x == 0) {
+        unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
+        sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+      }
+      if (step + 1 < nsteps && !grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+    }
+  }
+}
+
+template <int TP>
+static hipError_t launch_coop_tp(int method, int nwg, size_t lds, hipStream_t st, const SysConst &c,
+                                 const SysPtrs &p, int cur, int nsteps, int G, int vb) {
+  const void *fn = method == 0 ? (const void *)k_coop<TP, 0>
+                   : method == 1 ? (const void *)k_coop<TP, 1>
+                                 : (const void *)k_coop<TP, 2>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  SysConst cc = c;
+  SysPtrs pp = p;
+  void *args[] = {&cc, &pp, &cur, &nsteps, &G, &vb};
+  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBatchThreads), args, (unsigned)lds, st);
+}
+
+hipError_t launch_coop(int tp, int method, int nwg, size_t lds, hipStream_t st, const SysConst &c, const SysPtrs &p,
+                       int cur, int nsteps, int G, int vb) {
+  switch (tp) {
+    case 1: return launch_coop_tp<1>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 2: return launch_coop_tp<2>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 4: return launch_coop_tp<4>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 8: return launch_coop_tp<8>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 16: return launch_coop_tp<16>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 32: return launch_coop_tp<32>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 64: return launch_coop_tp<64>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Largest cooperative grid the device can hold for the persistent kernel.
+int coop_max_groups(int tp, int method, size_t lds) {
+  const void *fn = nullptr;
+  switch (tp) {
+#define SRMD_COOP_FN(T) \
+  case T: fn = method == 0 ? (const void *)k_coop<T, 0> : method == 1 ? (const void *)k_coop<T, 1> : (const void *)k_coop<T, 2>; break;
+    SRMD_COOP_FN(1) SRMD_COOP_FN(2) SRMD_COOP_FN(4) SRMD_COOP_FN(8) SRMD_COOP_FN(16) SRMD_COOP_FN(32) SRMD_COOP_FN(64)
+#undef SRMD_COOP_FN
+    default: return 0;
+  }
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, lds) != hipSuccess) return 0;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
 template <int TP>

@@ -26,6 +26,9 @@ hipError_t launch_batch(int tp, int method, int count, size_t lds, hipStream_t s
                         const int *order, int nsteps, int vb);
 size_t batch_lds_bytes(int n_max_particles);
 int batch_max_particles();
+hipError_t launch_coop(int tp, int method, int nwg, size_t lds, hipStream_t st, const SysConst &c, const SysPtrs &p,
+                       int cur, int nsteps, int G, int vb);
+int coop_max_groups(int tp, int method, size_t lds);
 }  // namespace srmd
 
 using namespace srmd;
@@ -48,6 +51,7 @@ struct DevBuf {
 };
 
 constexpr int kChunk = 64;  // steps per captured graph (even: the position buffers alternate)
+constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel
 
 }  // namespace
 
@@ -72,6 +76,11 @@ struct srmd_system {
   int tp_tuned = 0, ppb_tuned = 0;
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
+  int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
+  bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
+  int persist_tuned = 0;             // choice of srmd_autotune
+  int persist_groups = 0;            // resolved workgroup count, 0 = launch chains
+  std::string persist_err;           // why the requested persistent mode cannot run
   // derived layout
   bool dirty = true;  // SysConst must be rebuilt
   SysConst c{};
@@ -220,6 +229,30 @@ srmd_status flush_host_sort(srmd_system *s) {
   return SRMD_OK;
 }
 
+int step_blocks(const srmd_system *s) { return (int)(((long long)s->n * s->tp + s->tp * s->ppb - 1) / (s->tp * s->ppb)); }
+
+// Workgroups of the persistent kernel (0: launch chains): by default one workgroup
+// of 512 threads per 8 waves of the step launch, so each wave takes one wave of it.
+void resolve_persistent(srmd_system *s) {
+  s->persist_groups = 0;
+  s->persist_err.clear();
+  const int preq = s->persist_set ? s->persist_req : s->persist_tuned;
+  if (preq == 0) return;
+  if (s->prec != SRMD_PREC_F32 || !s->c.small_sort) {
+    s->persist_err = "the persistent kernel needs float32 positions, at most 8192 particles and 8192 cells";
+    return;
+  }
+  const int threads = s->tp * s->ppb;
+  const int units = step_blocks(s) * (threads / 64);
+  const int cap = coop_max_groups(s->tp, s->method, batch_lds_bytes(s->n));
+  int want = preq > 0 ? preq : std::max(1, std::min((units + 7) / 8, 256));
+  if (preq < 0) want = std::min(want, cap);
+  if (want < 1 || want > cap)
+    s->persist_err = "the persistent kernel's workgroups do not all fit on the device at once";
+  else
+    s->persist_groups = want;
+}
+
 // Rebuild the kernel constants, the cell grid and the list storage after any change
 // of parameters or launch shape.
 srmd_status prepare(srmd_system *s) {
@@ -306,24 +339,26 @@ srmd_status prepare(srmd_system *s) {
     s->p.cell_start = (unsigned *)dev_alloc(s, sizeof(unsigned) * (size_t)(c.ncell + 1));
     if (!s->p.cell_count || !s->p.cell_start) return fail(s, SRMD_ENOMEM, "cell arrays allocation failed");
     HIPCHK(s, hipMemsetAsync(s->p.cell_count, 0, sizeof(unsigned) * (size_t)(c.ncell + 1), s->stream));
+    HIPCHK(s, hipMemsetAsync(s->p.cell_start, 0, sizeof(unsigned) * (size_t)(c.ncell + 1), s->stream));
     s->ncell_alloc = c.ncell + 1;
   }
   const int threads = s->tp * s->ppb;
   const int blocks = (int)(((long long)s->n * s->tp + threads - 1) / threads);
-  // block partials, then one partial per wave (used by the batched kernel)
-  const int nparts = blocks + blocks * (threads / 64);
+  // block partials, then one partial per wave (used by the batched kernel; two
+  // alternating sets of them in the persistent kernel)
+  const int nparts = blocks + 2 * blocks * (threads / 64);
   if (nparts > s->part_alloc) {
     dev_free(s, s->p.part);
     s->p.part = (BlockPartial *)dev_alloc(s, sizeof(BlockPartial) * (size_t)nparts);
     if (!s->p.part) return fail(s, SRMD_ENOMEM, "partials allocation failed");
     s->part_alloc = nparts;
   }
+  resolve_persistent(s);
   drop_graphs(s);
   s->dirty = false;
   return request_rebuild(s);
 }
 
-int step_blocks(const srmd_system *s) { return (int)(((long long)s->n * s->tp + s->tp * s->ppb - 1) / (s->tp * s->ppb)); }
 
 srmd_status enqueue_steps(srmd_system *s, int count, int cur) {
   for (int k = 0; k < count; ++k) {
@@ -399,7 +434,7 @@ srmd_status read_ctl(srmd_system *s, Control *h) {
   return SRMD_OK;
 }
 
-// Double the list capacity after an overflow (paper section 3: re-allocation with
+// Double the list capacity after an overflow (paper section 4: re-allocation with
 // doubled capacity) and mark the layout for rebuild.
 srmd_status regrow(srmd_system *s) {
   s->n_max = std::min(2 * s->n_max, (s->n + 63) / 64 * 64);
@@ -407,9 +442,43 @@ srmd_status regrow(srmd_system *s) {
   return prepare(s);
 }
 
+// After a persistent launch: a grid barrier that timed out (error bit 2) leaves its
+// arrival count behind; clear both and report the failure.
+srmd_status check_barrier(srmd_system *s, Control *h) {
+  if (!(h->error & 4)) return SRMD_OK;
+  h->error &= ~4;
+  h->bar_count = 0;
+  srmd_status st = h2d_sync(s, s->p.ctl, h, sizeof(Control));
+  if (st != SRMD_OK) return st;
+  return fail(s, SRMD_EHIP, "persistent kernel: a device-wide barrier timed out");
+}
+
+// One launch of the persistent kernel over cnt steps.
+srmd_status launch_persistent(srmd_system *s, int cnt) {
+  HIPCHK(s, launch_coop(s->tp, s->method, s->persist_groups, batch_lds_bytes(s->n), s->stream, s->c, s->p, s->cur,
+                        cnt, step_blocks(s), s->tp * s->ppb));
+  s->cur ^= (cnt & 1);
+  return SRMD_OK;
+}
+
+// Persistent mode runs kPersistChunk steps per launch: launches stay short, and the
+// per-launch cost (a few microseconds) is spread over hundreds of steps.
+srmd_status run_persistent(srmd_system *s, long long nsteps) {
+  long long left = nsteps;
+  while (left > 0) {
+    const int cnt = (int)std::min<long long>(left, kPersistChunk);
+    srmd_status st = launch_persistent(s, cnt);
+    if (st != SRMD_OK) return st;
+    left -= cnt;
+  }
+  return SRMD_OK;
+}
+
 srmd_status run_steps(srmd_system *s, long long nsteps) {
   srmd_status st0 = flush_host_sort(s);
   if (st0 != SRMD_OK) return st0;
+  if (!s->persist_err.empty()) return fail(s, SRMD_EUNSUPPORTED, s->persist_err);
+  if (s->persist_groups > 0) return run_persistent(s, nsteps);
   long long left = nsteps;
   while (left > 0) {
     const int cnt = (int)std::min<long long>(left, kChunk);
@@ -478,6 +547,62 @@ srmd_status upload_state(srmd_system *s, const float *pos, const float *vel, con
   return SRMD_OK;
 }
 
+// A copy of the dynamic state in host memory (the autotuner's stored configuration).
+struct HostState {
+  int cur = 0;
+  std::vector<float4> pos, vel, last, kahan;
+  std::vector<int4> img;
+  std::vector<double> pos64;
+  Control ctl;
+  Thermo thermo;
+};
+
+srmd_status save_host_state(srmd_system *s, HostState *h) {
+  const size_t n = (size_t)s->n;
+  h->cur = s->cur;
+  h->pos.resize(n);
+  h->vel.resize(n);
+  h->last.resize(n);
+  h->img.resize(n);
+  HIPCHK(s, hipMemcpyAsync(h->pos.data(), s->p.pos[s->cur], sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(h->vel.data(), s->p.vel, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(h->last.data(), s->p.last, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(h->img.data(), s->p.img, sizeof(int4) * n, hipMemcpyDeviceToHost, s->stream));
+  if (s->p.pos64) {
+    h->pos64.resize(3 * n);
+    HIPCHK(s, hipMemcpyAsync(h->pos64.data(), s->p.pos64, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s->stream));
+  }
+  if (s->p.kahan) {
+    h->kahan.resize(n);
+    HIPCHK(s, hipMemcpyAsync(h->kahan.data(), s->p.kahan, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  }
+  HIPCHK(s, hipMemcpyAsync(&h->ctl, s->p.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(&h->thermo, s->p.thermo, sizeof(Thermo), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
+}
+
+// Put a stored state back; the list is rebuilt before the next force evaluation.
+srmd_status restore_host_state(srmd_system *s, const HostState &h) {
+  const size_t n = (size_t)s->n;
+  s->cur = h.cur;
+  HIPCHK(s, hipMemcpyAsync(s->p.pos[s->cur], h.pos.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.vel, h.vel.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.last, h.last.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.img, h.img.data(), sizeof(int4) * n, hipMemcpyHostToDevice, s->stream));
+  if (s->p.pos64 && !h.pos64.empty())
+    HIPCHK(s, hipMemcpyAsync(s->p.pos64, h.pos64.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, s->stream));
+  if (s->p.kahan && !h.kahan.empty())
+    HIPCHK(s, hipMemcpyAsync(s->p.kahan, h.kahan.data(), sizeof(float4) * n, hipMemcpyHostToDevice, s->stream));
+  Control c = h.ctl;
+  c.rebuild = 1;
+  HIPCHK(s, hipMemcpyAsync(s->p.ctl, &c, sizeof(Control), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.thermo, &h.thermo, sizeof(Thermo), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  s->sort_pending = true;
+  return SRMD_OK;
+}
+
 srmd_status ensure_trace(srmd_system *s, long long cap) {
   if (cap <= s->trace_alloc) return SRMD_OK;
   dev_free(s, s->p.trace);
@@ -525,7 +650,6 @@ srmd_status batch_sync_desc(srmd_batch *b) {
     if (st != SRMD_OK) return bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
     if (s->tp != b->tp || s->tp * s->ppb != b->vb || s->method != b->method)
       return bfail(b, SRMD_EINVAL, "replicas must share the cutoff method and the launch shape (tp, ppb)");
-    s->sort_pending = false;  // the batched kernel sorts inside the workgroup
     ReplicaDesc d;
     std::memset(&d, 0, sizeof(d));
     d.c = s->c;
@@ -568,6 +692,71 @@ srmd_status batch_graph(srmd_batch *b, long long nsteps, hipGraphExec_t *out) {
   if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   b->graphs[nsteps] = ge;
   *out = ge;
+  return SRMD_OK;
+}
+
+// Put the call-start snapshot back after a list overflow (cur0: the position
+// buffer in use at the call start), clear the overflow bit and double the list
+// capacity (paper section 4); the next run rebuilds the list.
+srmd_status restore_and_regrow(srmd_system *s, int cur0) {
+  s->cur = cur0;
+  srmd_status st = snapshot(s, true);
+  if (st != SRMD_OK) return st;
+  Control r;
+  st = read_ctl(s, &r);
+  if (st != SRMD_OK) return st;
+  r.error &= ~2;
+  st = h2d_sync(s, s->p.ctl, &r, sizeof(Control));
+  if (st != SRMD_OK) return st;
+  return regrow(s);
+}
+
+// nsteps steps of one system with list-overflow recovery: the call-start state is
+// kept in a device snapshot; a run whose list overflowed is restored, its capacity
+// doubled, and replayed, so the trajectory is that of a list that never overflowed.
+// Trace settings live in the control block so the captured graphs stay valid.
+srmd_status run_with_replay(srmd_system *s, long long nsteps, int32_t thermo_every, long long cap) {
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    Control hc;
+    srmd_status st = read_ctl(s, &hc);
+    if (st != SRMD_OK) return st;
+    hc.thermo_every = thermo_every;
+    hc.trace_cap = cap;
+    hc.n_records = 0;
+    st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
+    if (st != SRMD_OK) return st;
+    const int cur0 = s->cur;
+    st = snapshot(s, false);
+    if (st != SRMD_OK) return st;
+    st = run_steps(s, nsteps);
+    if (st != SRMD_OK) return st;
+    Control h;
+    st = read_ctl(s, &h);
+    if (st != SRMD_OK) return st;
+    st = check_barrier(s, &h);
+    if (st != SRMD_OK) return st;
+    if (h.error & 2) {
+      st = restore_and_regrow(s, cur0);
+      if (st != SRMD_OK) return st;
+      continue;
+    }
+    if (h.error & 1) return fail(s, SRMD_ESTATE, "non-finite force or position during the run");
+    return SRMD_OK;
+  }
+  return fail(s, SRMD_ENOMEM, "neighbour list kept overflowing");
+}
+
+// Copy the records of the last run's device trace into trace (cap entries at most).
+srmd_status download_trace(srmd_system *s, long long cap, srmd_thermo *trace) {
+  if (cap <= 0) return SRMD_OK;
+  Control h;
+  srmd_status st = read_ctl(s, &h);
+  if (st != SRMD_OK) return st;
+  if (h.n_records <= 0) return SRMD_OK;
+  std::vector<Thermo> tmp((size_t)std::min<long long>(h.n_records, cap));
+  HIPCHK(s, hipMemcpyAsync(tmp.data(), s->p.trace, sizeof(Thermo) * tmp.size(), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (size_t k = 0; k < tmp.size(); ++k) to_public(tmp[k], &trace[k]);
   return SRMD_OK;
 }
 
@@ -668,7 +857,8 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   if (hipMemcpyAsync(s->p.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipMemcpyAsync(s->p.thermo, &ht, sizeof(ht), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.force, 0, sizeof(float4) * N, s->stream) != hipSuccess ||
-      hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess) {
+      hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.t_pos, 0, sizeof(float4) * N, s->stream) != hipSuccess) {
     srmd_destroy(s);
     return fail(nullptr, SRMD_EHIP, "initial upload failed");
   }
@@ -769,6 +959,17 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb) {
   return SRMD_OK;
 }
 
+srmd_status srmd_set_persistent(srmd_system *s, int32_t groups) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (groups < -1 || groups > 4096) return fail(s, SRMD_EINVAL, "groups must be -1, 0 or 1..4096");
+  s->persist_req = groups;
+  s->persist_set = true;
+  // the layout does not change (the partials buffer always has room for the
+  // persistent kernel), so a switch keeps the list and the trajectory continues
+  if (!s->dirty) resolve_persistent(s);
+  return SRMD_OK;
+}
+
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
   if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 2)
@@ -853,48 +1054,9 @@ srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd
   if (st != SRMD_OK) return st;
   st = alloc_snapshot(s);
   if (st != SRMD_OK) return st;
-  for (int attempt = 0; attempt < 8; ++attempt) {
-    // trace settings live in the control block so the graphs stay valid
-    Control hc;
-    st = read_ctl(s, &hc);
-    if (st != SRMD_OK) return st;
-    hc.thermo_every = thermo_every;
-    hc.trace_cap = cap;
-    hc.n_records = 0;
-    st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
-    if (st != SRMD_OK) return st;
-    const int cur0 = s->cur;
-    st = snapshot(s, false);
-    if (st != SRMD_OK) return st;
-    st = run_steps(s, nsteps);
-    if (st != SRMD_OK) return st;
-    Control h;
-    st = read_ctl(s, &h);
-    if (st != SRMD_OK) return st;
-    if (h.error & 2) {  // list overflow: grow, restore the call-start state, replay
-      s->cur = cur0;
-      st = snapshot(s, true);
-      if (st != SRMD_OK) return st;
-      Control r;
-      st = read_ctl(s, &r);
-      if (st != SRMD_OK) return st;
-      r.error &= ~2;
-      st = h2d_sync(s, s->p.ctl, &r, sizeof(Control));
-      if (st != SRMD_OK) return st;
-      st = regrow(s);
-      if (st != SRMD_OK) return st;
-      continue;
-    }
-    if (h.error & 1) return fail(s, SRMD_ESTATE, "non-finite force or position during the run");
-    if (cap > 0 && h.n_records > 0) {
-      std::vector<Thermo> tmp((size_t)h.n_records);
-      HIPCHK(s, hipMemcpyAsync(tmp.data(), s->p.trace, sizeof(Thermo) * tmp.size(), hipMemcpyDeviceToHost, s->stream));
-      HIPCHK(s, hipStreamSynchronize(s->stream));
-      for (size_t k = 0; k < tmp.size(); ++k) to_public(tmp[k], &trace[k]);
-    }
-    return SRMD_OK;
-  }
-  return fail(s, SRMD_ENOMEM, "neighbour list kept overflowing");
+  st = run_with_replay(s, nsteps, thermo_every, cap);
+  if (st != SRMD_OK) return st;
+  return download_trace(s, cap, trace);
 }
 
 srmd_status srmd_get_state(srmd_system *s, float *pos, float *vel, int32_t *image, float *force, double *pos64) {
@@ -1050,6 +1212,8 @@ srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out) {
   out->ppb = s->ppb;
   out->blocks = step_blocks(s);
   out->ncell = s->c.ncell;
+  out->persistent_groups = s->persist_groups;
+  out->reserved = 0;
   return SRMD_OK;
 }
 
@@ -1077,6 +1241,38 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
   srmd_status result = SRMD_OK;
   st = flush_host_sort(s);
   if (st != SRMD_OK) result = st;
+  if (result == SRMD_OK && !s->persist_err.empty()) result = fail(s, SRMD_EUNSUPPORTED, s->persist_err);
+  if (result == SRMD_OK && s->persist_groups > 0) {
+    // persistent mode: one event pair around each launch of kPersistChunk steps
+    long long nl = 0;
+    while (done < nsteps && result == SRMD_OK) {
+      const int cnt = (int)std::min<long long>(kPersistChunk, nsteps - done);
+      hipError_t e = hipEventRecord(ev[0], s->stream);
+      if (e == hipSuccess) {
+        result = launch_persistent(s, cnt);
+        if (result == SRMD_OK) e = hipEventRecord(ev[1], s->stream);
+      }
+      if (e == hipSuccess && result == SRMD_OK) e = hipEventSynchronize(ev[1]);
+      float ms = 0.f;
+      if (e == hipSuccess && result == SRMD_OK) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+      if (e != hipSuccess && result == SRMD_OK)
+        result = fail(s, SRMD_EHIP, std::string("persistent profiled launch: ") + hipGetErrorString(e));
+      total += ms;
+      done += cnt;
+      ++nl;
+    }
+    for (auto &ev_k : ev) (void)hipEventDestroy(ev_k);
+    if (result != SRMD_OK) return result;
+    st = read_ctl(s, &h);
+    if (st != SRMD_OK) return st;
+    st = check_barrier(s, &h);
+    if (st != SRMD_OK) return st;
+    if (h.error & 3) return fail(s, SRMD_ESTATE, "list overflow or non-finite state during profiling");
+    if (kernel_ms) *kernel_ms = total;
+    if (device_ms) *device_ms = 0.0;
+    if (launches) *launches = nl;
+    return SRMD_OK;
+  }
   while (done < nsteps && result == SRMD_OK) {
     const int cnt = (int)std::min<long long>(batch, nsteps - done);
     for (int k = 0; k < cnt && result == SRMD_OK; ++k) {
@@ -1121,10 +1317,153 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
 
 srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
-  (void)steps_per_trial;
-  if (tp_out) *tp_out = 0;
-  if (ppb_out) *ppb_out = 0;
-  return fail(s, SRMD_EUNSUPPORTED, "autotune not available yet");
+  if (!s->integrator_set) return fail(s, SRMD_EINVAL, "integrator not set");
+  if (steps_per_trial < 1) return fail(s, SRMD_EINVAL, "steps_per_trial must be >= 1");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  HostState saved;
+  st = save_host_state(s, &saved);
+  if (st != SRMD_OK) return st;
+  const int tp0 = s->tp_req, ppb0 = s->ppb_req, list0 = s->list_mode;
+  const int preq0 = s->persist_req;
+  const bool pset0 = s->persist_set;
+  hipEvent_t e0, e1;
+  HIPCHK(s, hipEventCreate(&e0));
+  HIPCHK(s, hipEventCreate(&e1));
+  // one timed trial from the stored state (paper appendix: every run starts from the same configuration)
+  auto trial = [&](int tp, int ppb, int list_mode, bool persistent, double *ms_per_step) -> srmd_status {
+    s->tp_req = tp;
+    s->ppb_req = ppb;
+    s->list_mode = list_mode;
+    s->persist_set = true;
+    s->persist_req = persistent ? -1 : 0;
+    s->dirty = true;
+    srmd_status r = restore_host_state(s, saved);
+    if (r != SRMD_OK) return r;
+    r = prepare(s);
+    if (r != SRMD_OK) return r;
+    if (persistent && s->persist_groups == 0) {  // not available for this system
+      *ms_per_step = 1e30;
+      return SRMD_OK;
+    }
+    r = run_steps(s, 16);  // graph instantiation and the first build, untimed
+    if (r != SRMD_OK) return r;
+    HIPCHK(s, hipEventRecord(e0, s->stream));
+    r = run_steps(s, steps_per_trial);
+    if (r != SRMD_OK) return r;
+    HIPCHK(s, hipEventRecord(e1, s->stream));
+    HIPCHK(s, hipEventSynchronize(e1));
+    Control h;
+    r = read_ctl(s, &h);
+    if (r != SRMD_OK) return r;
+    r = check_barrier(s, &h);
+    if (r != SRMD_OK) return r;
+    float ms = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+    // a trial that overflowed its list or went non-finite does not count
+    *ms_per_step = (h.error & 3) ? 1e30 : (double)ms / steps_per_trial;
+    if (h.error & 3) {
+      h.error &= ~3;
+      r = h2d_sync(s, s->p.ctl, &h, sizeof(Control));
+    }
+    return r;
+  };
+  const int n = s->n;
+  int best_tp = 0, best_ppb = 0, best_list = 0;
+  double best = 1e300;
+  srmd_status result = SRMD_OK;
+  // Phase I: the list-build method at the default layout (paper appendix, step 3)
+  int dtp, dppb;
+  s->tp_req = s->ppb_req = 0;
+  launch_of(s, &dtp, &dppb);
+  for (int lm = 1; lm <= 2 && result == SRMD_OK; ++lm) {
+    double t;
+    result = trial(dtp, dppb, lm, false, &t);
+    if (result == SRMD_OK && t < best) {
+      best = t;
+      best_tp = dtp;
+      best_ppb = dppb;
+      best_list = lm;
+    }
+  }
+  // Phase II: block size x threads per particle (paper appendix, step 4), with its stop
+  // rules: leave the t_p loop after 3 slower trials in a row or one more than 5% slower,
+  // and the block loop once a block size ends more than 10% slower than the best
+  const int blocks[] = {64, 128, 256, 512, 1024};
+  const int tp_max = n > 100000 ? 2 : 64;  // size pruning: large systems only need t_p = 1, 2
+  double prev_block_best = 1e300;
+  for (int bi = 0; bi < 5 && result == SRMD_OK; ++bi) {
+    const int bsz = blocks[bi];
+    double block_best = 1e300;
+    int slower = 0;
+    for (int tp = 1; tp <= tp_max && tp <= bsz && result == SRMD_OK; tp <<= 1) {
+      double t;
+      result = trial(tp, bsz / tp, best_list, false, &t);
+      if (result != SRMD_OK) break;
+      if (t < block_best) {
+        block_best = t;
+        slower = 0;
+      } else {
+        ++slower;
+      }
+      if (t < best) {
+        best = t;
+        best_tp = tp;
+        best_ppb = bsz / tp;
+      }
+      if (slower >= 3 || t > 1.05 * block_best) break;
+    }
+    if (block_best > 1.10 * std::min(best, prev_block_best) && bi > 0) break;
+    prev_block_best = std::min(prev_block_best, block_best);
+  }
+  // Phase III (MI355X): the persistent kernel for small systems, t_p at 256-thread
+  // virtual blocks, with the t_p stop rule of phase II
+  bool best_persist = false;
+  if (result == SRMD_OK && s->prec == SRMD_PREC_F32 && s->c.small_sort) {
+    double pbest = 1e300;
+    int slower = 0;
+    for (int tp = 1; tp <= 64 && result == SRMD_OK; tp <<= 1) {
+      double t;
+      result = trial(tp, 256 / tp, best_list, true, &t);
+      if (result != SRMD_OK) break;
+      if (t >= 1e30) break;
+      if (t < pbest) {
+        pbest = t;
+        slower = 0;
+      } else {
+        ++slower;
+      }
+      if (t < best) {
+        best = t;
+        best_tp = tp;
+        best_ppb = 256 / tp;
+        best_persist = true;
+      }
+      if (slower >= 3 || t > 1.05 * pbest) break;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // keep the user's explicit layout request if there was one; otherwise use the tuned one
+  s->tp_req = tp0;
+  s->ppb_req = ppb0;
+  s->list_mode = list0;
+  s->persist_req = preq0;
+  s->persist_set = pset0;
+  if (result == SRMD_OK && best_tp > 0) {
+    s->tp_tuned = best_tp;
+    s->ppb_tuned = best_ppb;
+    s->persist_tuned = best_persist ? -1 : 0;
+    if (list0 == 0) s->list_mode = best_list;
+  }
+  s->dirty = true;
+  srmd_status r2 = restore_host_state(s, saved);
+  if (result == SRMD_OK) result = r2;
+  if (result == SRMD_OK) result = prepare(s);
+  if (result != SRMD_OK) return result;
+  if (tp_out) *tp_out = best_tp;
+  if (ppb_out) *ppb_out = best_ppb;
+  return SRMD_OK;
 }
 
 srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int32_t count) {
@@ -1189,74 +1528,49 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
     if (st == SRMD_OK) st = alloc_snapshot(s);
     if (st != SRMD_OK) return bfail(b, st, s->err);
   }
-  for (int attempt = 0; attempt < 8; ++attempt) {
-    srmd_status st = batch_sync_desc(b);
-    if (st != SRMD_OK) return st;
-    for (auto *s : b->sys) {
-      Control hc;
-      st = read_ctl(s, &hc);
-      if (st != SRMD_OK) return bfail(b, st, s->err);
-      hc.thermo_every = thermo_every;
-      hc.trace_cap = cap;
-      hc.n_records = 0;
-      st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
-      if (st == SRMD_OK) st = snapshot(s, false);
-      if (st != SRMD_OK) return bfail(b, st, s->err);
-    }
-    for (auto *s : b->sys)
-      if (hipStreamSynchronize(s->stream) != hipSuccess) return bfail(b, SRMD_EHIP, "replica stream sync failed");
-    hipGraphExec_t ge;
-    st = batch_graph(b, nsteps, &ge);
-    if (st != SRMD_OK) return st;
-    hipError_t e = hipGraphLaunch(ge, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("batched run: ") + hipGetErrorString(e));
-    bool overflow = false;
-    for (auto *s : b->sys) {
-      Control h;
-      st = read_ctl(s, &h);
-      if (st != SRMD_OK) return bfail(b, st, s->err);
-      if (h.error & 1) return bfail(b, SRMD_ESTATE, "non-finite force or position in a replica");
-      if (h.error & 2) overflow = true;
-    }
-    if (overflow) {  // restore every replica, grow the lists that overflowed, replay
-      for (auto *s : b->sys) {
-        Control h;
-        st = read_ctl(s, &h);
-        if (st == SRMD_OK) st = snapshot(s, true);
-        if (st != SRMD_OK) return bfail(b, st, s->err);
-        if (h.error & 2) {
-          Control r;
-          st = read_ctl(s, &r);
-          if (st != SRMD_OK) return bfail(b, st, s->err);
-          r.error &= ~2;
-          st = h2d_sync(s, s->p.ctl, &r, sizeof(Control));
-          if (st == SRMD_OK) st = regrow(s);
-          if (st != SRMD_OK) return bfail(b, st, s->err);
-        }
-      }
-      drop_batch_graphs(b);
-      b->lds = batch_lds_bytes(b->lds / 16);
-      continue;
-    }
-    for (size_t r = 0; r < b->sys.size(); ++r) {
-      srmd_system *s = b->sys[r];
-      s->cur ^= (int)(nsteps & 1);
-      if (cap > 0) {
-        Control h;
-        st = read_ctl(s, &h);
-        if (st != SRMD_OK) return bfail(b, st, s->err);
-        if (h.n_records > 0) {
-          std::vector<Thermo> tmp((size_t)h.n_records);
-          e = hipMemcpy(tmp.data(), s->p.trace, sizeof(Thermo) * tmp.size(), hipMemcpyDeviceToHost);
-          if (e != hipSuccess) return bfail(b, SRMD_EHIP, "trace download failed");
-          for (size_t k = 0; k < tmp.size(); ++k) to_public(tmp[k], &trace[(size_t)r * (size_t)cap + k]);
-        }
-      }
-    }
-    return SRMD_OK;
+  srmd_status st = batch_sync_desc(b);
+  if (st != SRMD_OK) return st;
+  for (auto *s : b->sys) {
+    Control hc;
+    st = read_ctl(s, &hc);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+    hc.thermo_every = thermo_every;
+    hc.trace_cap = cap;
+    hc.n_records = 0;
+    st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
+    if (st == SRMD_OK) st = snapshot(s, false);
+    // a host-requested rebuild needs its spatial sort before the batched launch
+    if (st == SRMD_OK) st = flush_host_sort(s);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
   }
-  return bfail(b, SRMD_ENOMEM, "neighbour lists kept overflowing");
+  for (auto *s : b->sys)
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return bfail(b, SRMD_EHIP, "replica stream sync failed");
+  hipGraphExec_t ge;
+  st = batch_graph(b, nsteps, &ge);
+  if (st != SRMD_OK) return st;
+  hipError_t e = hipGraphLaunch(ge, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("batched run: ") + hipGetErrorString(e));
+  // a replica whose list overflowed is restored to the call start, its capacity
+  // doubled, and replayed on its own (the single-system path follows the batched
+  // trajectory bit for bit); the other replicas keep their batched result
+  srmd_status result = SRMD_OK;
+  for (size_t r = 0; r < b->sys.size(); ++r) {
+    srmd_system *s = b->sys[r];
+    Control h;
+    st = read_ctl(s, &h);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+    if (h.error & 2) {
+      st = restore_and_regrow(s, s->cur);
+      if (st == SRMD_OK) st = run_with_replay(s, nsteps, thermo_every, cap);
+    } else {
+      s->cur ^= (int)(nsteps & 1);
+      if (h.error & 1) st = fail(s, SRMD_ESTATE, "non-finite force or position during the run");
+    }
+    if (st == SRMD_OK) st = download_trace(s, cap, trace ? trace + r * (size_t)cap : nullptr);
+    if (st != SRMD_OK && result == SRMD_OK) result = bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
+  }
+  return result;
 }
 
 srmd_status srmd_batch_destroy(srmd_batch *b) {

@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 namespace srmd {
@@ -57,23 +58,27 @@ struct SysConst {
 // Device-resident control words (one 256-byte block).
 struct Control {
   int rebuild;       // 1: rebuild the list before the next force evaluation
-  int error;         // sticky: bit 0 non-finite force/position, bit 1 list overflow
-  unsigned counter;  // last-block detection of the step / force kernels
+  int error;         // sticky: bit 0 non-finite force/position, bit 1 list overflow,
+                     // bit 2 a grid barrier of the persistent kernel timed out
   int max_nbrs;      // longest list of the last build
+  int thermo_every;  // record every k-th step into the trace (0: never)
   long long step;    // steps taken
   long long n_rebuilds;
-  long long n_records; // records written to the trace
-  double xi;         // Nose-Hoover friction at the current step
-  double xi_int;     // its time integral
-  int rebuilt_this_step; // set by the list build, cleared by the step kernel
-  int thermo_every;      // record every k-th step into the trace (0: never)
-  long long trace_cap;   // capacity of the device trace
-  long long list_entries;   // total entries of the current list
-  unsigned long long prof_t0;     // device clock at the start of the current step kernel
+  long long n_records;     // records written to the trace
+  long long trace_cap;     // capacity of the device trace
+  long long list_entries;  // total entries of the current list
+  double xi;               // Nose-Hoover friction at the current step
+  double xi_int;           // its time integral
   unsigned long long prof_ticks;  // accumulated step-kernel durations (device clock ticks)
   long long prof_count;           // step kernels accumulated
-  int pad[24];
+  // grid barrier of the persistent kernel, on a cache line of its own so that no
+  // plain store to the fields above shares a line with the barrier's atomics
+  alignas(128) unsigned bar_count;  // arrivals
+  unsigned bar_gen;                 // generation
+  int pad[30];
 };
+
+static_assert(sizeof(Control) == 256 && offsetof(Control, bar_count) == 128, "control block layout");
 
 // Thermo accumulators of the last force evaluation / step.
 struct Thermo {

@@ -35,7 +35,8 @@ class srmd_thermo(ctypes.Structure):
 class srmd_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64), ("list_entries", ctypes.c_int64),
                 ("max_nbrs", ctypes.c_int32), ("n_max", ctypes.c_int32), ("tp", ctypes.c_int32),
-                ("ppb", ctypes.c_int32), ("blocks", ctypes.c_int32), ("ncell", ctypes.c_int32)]
+                ("ppb", ctypes.c_int32), ("blocks", ctypes.c_int32), ("ncell", ctypes.c_int32),
+                ("persistent_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -92,6 +93,7 @@ def load():
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_get_launch": (st, [sysp, _ip, _ip]),
         "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
+        "srmd_set_persistent": (st, [sysp, ctypes.c_int32]),
         "srmd_batch_create": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
         "srmd_batch_step": (st, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
         "srmd_batch_destroy": (st, [ctypes.c_void_p]),
@@ -226,6 +228,11 @@ class System:
     def set_rebuild_path(self, sort_mode=0, list_mode=0):
         _check(load().srmd_set_rebuild_path(self._h, int(sort_mode), int(list_mode)), self._h)
 
+    def set_persistent(self, groups=-1):
+        """Run steps as persistent launches of 500 steps each (groups > 0 workgroups,
+        or -1 for the library's choice); 0 returns to graph-captured launch chains."""
+        _check(load().srmd_set_persistent(self._h, int(groups)), self._h)
+
     def get_launch(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(load().srmd_get_launch(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
@@ -355,7 +362,8 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
             "srmd_autotune", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_batch_create",
+            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_set_persistent",
+            "srmd_batch_create",
             "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error"]
 
 

@@ -321,3 +321,24 @@ def test_invalid_arguments_rejected():
             s.set_pair_lj(0, 0, 1.0, 1.0, 2.5, "sf")  # one cutoff method per system
         with pytest.raises(srmd.SrmdError):
             s.set_state(pos=bad)
+
+
+def test_autotune_restores_state_and_keeps_parity():
+    state = gen.config1_state()
+    sig, eps, rc = gen.ka_params()
+    with make_system(state, sig, eps, rc, "sf") as s:
+        s.set_integrator_nvt(0.002, 0.45, 0.2)
+        s.step(50)
+        before = s.get_state()
+        tp, ppb = s.autotune(60)
+        print(f"tuned tp={tp} ppb={ppb} persistent_groups={s.stats()['persistent_groups']}")
+        assert tp in (1, 2, 4, 8, 16, 32, 64) and (tp * ppb) % 64 == 0 and tp * ppb <= 1024
+        assert s.get_launch() == (tp, ppb)
+        after = s.get_state()
+        np.testing.assert_array_equal(before["pos"], after["pos"])
+        np.testing.assert_array_equal(before["vel"], after["vel"])
+        th = s.compute_forces()
+        F = s.get_state()["force"]
+    Fr, _, _, U, W = oracle.forces_f32(after["pos"], state.types, state.box, sig, eps, rc, "sf")
+    assert force_error(F, Fr) <= FORCE_TOL
+    assert rel(th["pe"], U) <= ENERGY_TOL

@@ -46,6 +46,7 @@ def test_binding_covers_header():
 def test_thermo_struct_layout():
     from paper_1506_05094_amd import srmd
     assert ctypes.sizeof(srmd.srmd_thermo) == 9 * 8 + 2 * 8 + 2 * 4
+    assert ctypes.sizeof(srmd.srmd_stats) == 3 * 8 + 8 * 4
 
 
 def test_null_arguments_rejected_without_gpu(lib):
@@ -57,6 +58,7 @@ def test_null_arguments_rejected_without_gpu(lib):
     assert b"particles" in lib.srmd_last_error(None)
     assert lib.srmd_set_skin(None, 0.3) == srmd.SRMD_EINVAL
     assert lib.srmd_step(None, 10, 0, None, 0) == srmd.SRMD_EINVAL
+    assert lib.srmd_set_persistent(None, -1) == srmd.SRMD_EINVAL
     assert lib.srmd_destroy(None) == srmd.SRMD_OK
 
 
