@@ -167,6 +167,9 @@ def main():
     ap.add_argument("--groups", type=int, default=-1, help="workgroups of the persistent kernel (-1: automatic)")
     ap.add_argument("--profile-steps", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB between two device buffers three times (a plain copy of known "
+                         "size, the reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (one process, one MI355X).",
@@ -180,6 +183,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     srmd.load()
+    if args.copy_calibration > 0:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {nbytes} bytes")
+        del src, dst
     if args.workload == "ka-replicas":
         run_replicas(args)
         return
@@ -200,7 +212,12 @@ def main():
     torch.cuda.synchronize()
     st0 = s.stats()
     t0 = time.perf_counter()
-    s.step(args.steps)
+    if persistent:
+        # the timed steps themselves, with a HIP event pair around every launch of
+        # the persistent kernel (500 steps per launch) on the system's stream
+        ev_ms, dev_ms, launches = s.profile_step_kernel(args.steps)
+    else:
+        s.step(args.steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st1 = s.stats()
@@ -208,18 +225,20 @@ def main():
     n = state.n
     value = n * args.steps / wall
     log(f"timed {args.steps} steps in {wall:.4f} s: {value:.4e} particle-steps/s, {args.steps / wall:.1f} steps/s, "
-        f"rebuilds {st1['n_rebuilds'] - st0['n_rebuilds']}, tp {st1['tp']} ppb {st1['ppb']}, T {th['temperature']:.4f}")
-
-    # dominant kernel, timed per launch with HIP events on the system's stream: the
-    # fused force + integrator kernel (launch chains), or the persistent kernel
-    ev_ms, dev_ms, launches = s.profile_step_kernel(args.profile_steps)
+        f"rebuilds {st1['n_rebuilds'] - st0['n_rebuilds']}, tp {st1['tp']} ppb {st1['ppb']}, "
+        f"groups {st1['persistent_groups']}, T {th['temperature']:.4f}")
+    if persistent:
+        steps_per_launch = args.steps / launches
+    else:
+        # launch chains: the fused step kernel timed per launch in a profiled pass
+        ev_ms, dev_ms, launches = s.profile_step_kernel(args.profile_steps)
+        steps_per_launch = 1
     # entries of a list built at the final positions (the counter of the last build
     # reads 0 when the run ended on a step that scheduled a rebuild)
     s.build_neighbor_list()
     st2 = s.stats()
     avg_s = ev_ms / 1e3 / launches
     dev_avg_s = dev_ms / 1e3 / launches
-    steps_per_launch = args.profile_steps / launches if persistent else 1
     bytes_launch = step_kernel_bytes(n, st2["list_entries"]) * steps_per_launch
     achieved = bytes_launch / avg_s / 1e9
     log(f"dominant kernel: {launches} launches of {steps_per_launch:g} steps, event avg {avg_s * 1e6:.2f} us "

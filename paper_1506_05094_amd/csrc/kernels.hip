@@ -99,22 +99,30 @@ __device__ __forceinline__ void row_runs(int cx, int nx, bool full, int &a0, int
   }
 }
 
-// Pair table staged in LDS.
+// Pair table staged in LDS, one 32-byte row per type pair so that a pair's
+// constants arrive in two 16-byte LDS reads.
+struct alignas(16) PairRow {
+  float rc2, sig2, eps24, eps4;  // rc^2, sigma^2, 24 eps, 4 eps
+  float ushift, fc, rc, pad;     // U(rc), F(rc), rc
+};
+
 struct SharedPairs {
-  float rc2[kMaxPairs], sig2[kMaxPairs], eps4[kMaxPairs], eps24[kMaxPairs], ushift[kMaxPairs], fc[kMaxPairs],
-      rc[kMaxPairs];
+  PairRow row[kMaxPairs];
 };
 
 __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) {
   const int t = threadIdx.x;
   if (t < kMaxPairs) {
-    sp.rc2[t] = c.pt.rc2[t];
-    sp.sig2[t] = c.pt.sig2[t];
-    sp.eps4[t] = c.pt.eps4[t];
-    sp.eps24[t] = c.pt.eps24[t];
-    sp.ushift[t] = c.pt.ushift[t];
-    sp.fc[t] = c.pt.fc[t];
-    sp.rc[t] = c.pt.rc[t];
+    PairRow r;
+    r.rc2 = c.pt.rc2[t];
+    r.sig2 = c.pt.sig2[t];
+    r.eps24 = c.pt.eps24[t];
+    r.eps4 = c.pt.eps4[t];
+    r.ushift = c.pt.ushift[t];
+    r.fc = c.pt.fc[t];
+    r.rc = c.pt.rc[t];
+    r.pad = 0.f;
+    sp.row[t] = r;
   }
 }
 
@@ -142,23 +150,23 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
               mz = __builtin_rintf(ez * c.invL[2]);
   float dx = __builtin_fmaf(-mx, c.L[0], ex), dy = __builtin_fmaf(-my, c.L[1], ey), dz = __builtin_fmaf(-mz, c.L[2], ez);
   const float r2s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-  const int ab = ti * ntypes + ptype(pj);
-  if (r2s < sp.rc2[ab]) {
+  const PairRow &pr = sp.row[ti * ntypes + ptype(pj)];
+  if (r2s < pr.rc2) {
     dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
     dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
     dz = (float)(((double)pj.z - wi.z) - (double)mz * c.Ld[2]);
     const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
     const float inv_r2 = __builtin_amdgcn_rcpf(r2);
-    const float s2 = sp.sig2[ab] * inv_r2;
+    const float s2 = pr.sig2 * inv_r2;
     const float s6 = s2 * s2 * s2;
     const float s12 = s6 * s6;
-    float fr = sp.eps24[ab] * __builtin_fmaf(2.0f, s12, -s6) * inv_r2;
-    float e = __builtin_fmaf(sp.eps4[ab], s12 - s6, -sp.ushift[ab]);
+    float fr = pr.eps24 * __builtin_fmaf(2.0f, s12, -s6) * inv_r2;
+    float e = __builtin_fmaf(pr.eps4, s12 - s6, -pr.ushift);
     if (METHOD == 2) {  // shifted force: F(r) - F(rc); U(r) - U(rc) + (r - rc) F(rc)
       const float inv_r = __builtin_amdgcn_rsqf(r2);
       const float r = r2 * inv_r;
-      fr = __builtin_fmaf(-sp.fc[ab], inv_r, fr);
-      e = __builtin_fmaf(r - sp.rc[ab], sp.fc[ab], e);
+      fr = __builtin_fmaf(-pr.fc, inv_r, fr);
+      e = __builtin_fmaf(r - pr.rc, pr.fc, e);
     }
     fx = __builtin_fmaf(-fr, dx, fx);
     fy = __builtin_fmaf(-fr, dy, fy);
@@ -172,25 +180,35 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
 // The lane's entries are taken B at a time: B list indices are loaded together,
 // then the B neighbour positions, so a batch costs two memory round trips instead
 // of two per entry (the paper prefetches one entry ahead, section 5; on MI355X the
-// latency of a dependent load chain dominates, so many loads go in flight).
+// latency of a dependent load chain dominates, so many loads go in flight).  The
+// first batch is issued before the list length arrives (clamped to the capacity
+// n_max / TP of a lane), so the length and the first indices share a round trip.
 template <int TP, int METHOD, int B, class IdxPtr>
 __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const float4 *__restrict__ pos,
-                                           IdxPtr nbl, int nn, const SharedPairs &sp,
-                                           const SysConst &c, float &fx, float &fy, float &fz, float &u, float &w) {
+                                           IdxPtr nbl, IdxPtr nnb, const SharedPairs &sp, const SysConst &c,
+                                           float &fx, float &fy, float &fz, float &u, float &w) {
   const int ti = ptype(pi);
   const Wide wi = widen(pi);
   const long long stride = (long long)c.nvp * TP;
   const IdxPtr row = nbl + (long long)i * TP + t;
+  const int cap = c.n_max / TP;  // entries of one lane the list can hold
+  int j[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) j[b] = __builtin_nontemporal_load(row + (long long)min(b, cap - 1) * stride);
+  const int nn = nnb[i];
   const int mine = nn > t ? (nn - t + TP - 1) / TP : 0;  // entries of this lane
   for (int m0 = 0; m0 < mine; m0 += B) {
-    int j[B];
+    if (m0 > 0) {
 #pragma unroll
-    for (int b = 0; b < B; ++b) {
-      // every load is issued (clamped to the lane's last entry) so none waits behind a branch
-      const int mm = min(m0 + b, mine - 1);
-      j[b] = __builtin_nontemporal_load(row + (long long)mm * stride);
-      if (m0 + b >= mine) j[b] = -1;
+      for (int b = 0; b < B; ++b) {
+        // every load is issued (clamped to the lane's last entry) so none waits behind a branch
+        const int mm = min(m0 + b, mine - 1);
+        j[b] = __builtin_nontemporal_load(row + (long long)mm * stride);
+      }
     }
+#pragma unroll
+    for (int b = 0; b < B; ++b)
+      if (m0 + b >= mine) j[b] = -1;
     float4 q[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) q[b] = pos[j[b] >= 0 ? j[b] : i];
@@ -736,9 +754,9 @@ __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) 
   float4 vo = make_float4(0.f, 0.f, 0.f, 0.f), pi = vo;
   if (active) {
     pi = pos[i];
-    const int nn = p.nnb[i];
     if (t == 0) vo = p.vel[i];
-    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, p.nbl, nn, sp, c, fx, fy, fz, u, w);
+    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
+                                             fz, u, w);
   }
   fx = lane_sum<TP>(fx);
   fy = lane_sum<TP>(fy);
@@ -869,7 +887,6 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
   const double xi = c.thermostat ? p.ctl->xi : 0.0;
   if (active) {
     pi = pos[i];
-    const int nn = p.nnb[i];
     if (t == 0) {
       vo = p.vel[i];
       im = p.img[i];
@@ -881,7 +898,8 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
         z64 = p.pos64[3 * i + 2];
       }
     }
-    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, p.nbl, nn, sp, c, fx, fy, fz, u, w);
+    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
+                                             fz, u, w);
   }
   fx = lane_sum<TP>(fx);
   fy = lane_sum<TP>(fy);
@@ -1115,13 +1133,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const ReplicaDesc *__re
       int4 im = make_int4(0, 0, 0, 0);
       if (active) {
         pi = s_dyn[i];
-        const int nn = gload(p.nnb, i);
         if (t == 0) {
           vo = gload(p.vel, i);
           im = gload(p.img, i);
           l0 = gload(p.last, i);
         }
-        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, nn, sp, c, fx, fy, fz, uu, w);
+        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, global_view(p.nnb), sp, c, fx, fy, fz, uu,
+                                                 w);
       }
       fx = lane_sum<TP>(fx);
       fy = lane_sum<TP>(fy);
@@ -1206,79 +1224,119 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const ReplicaDesc *__re
 
 // ---------------------------------------------------------------- persistent single system
 
-// Grid-wide barrier of a cooperative launch (every workgroup co-resident).  The last
-// workgroup to arrive resets the count and advances the generation; the others spin
-// on the generation with a bounded wait (about one second of device clock), after
-// which they report an error instead of hanging.  Release / acquire at agent scope
-// make every write before the barrier visible to every workgroup after it.
-__device__ __forceinline__ bool grid_barrier(Control *ctl, unsigned G, unsigned &gen, int *s_ok) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // this wave's stores, device-wide
+constexpr int kCoopMaxGroups = 256;  // workgroups of the persistent kernel (one per CU at most)
+constexpr int kCoopMaxUnits = 64;    // wave units of one workgroup per step (LDS partials)
+
+// Grid-wide barrier k (k = 1, 2, ... in one launch) over an array of arrival words,
+// one per workgroup and barrier parity, cleared by the host before the launch.
+// Workgroup b publishes (k << 1) | bit in its word: an arrival costs one store and no
+// read-modify-write on a shared counter, and bit carries a flag whose OR over the
+// workgroups every workgroup receives (the rebuild decision).  The first wave polls
+// all words of parity k & 1 until each holds barrier k; two parities suffice because
+// no workgroup can reach barrier k + 2 before every workgroup has left barrier k.
+// The wait is bounded (about one second of the 100 MHz device clock): on time-out
+// the workgroup sets error bit 2 and the kernel ends instead of hanging.  Release /
+// acquire fences at agent scope order every store before the barrier against every
+// load after it.  They are issued once per workgroup: each wave first waits for its
+// own stores to complete, and the L2 write-back / invalidate act on the whole cache
+// (and the invalidate on the compute unit's L1) for every wave of the workgroup.
+__device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsigned k, int bit, Control *ctl,
+                                             int *s_ok, int *s_any) {
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
   __syncthreads();
+  unsigned *slot = flags + (k & 1u) * kCoopMaxGroups;
   if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_store(slot + blockIdx.x, (k << 1) | (unsigned)(bit != 0), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (threadIdx.x < 64) {
+    const unsigned long long t0 = wall_clock64();
     int ok = 1;
-    const unsigned g = gen;
-    const unsigned arrived =
-        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == G - 1) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t0 > 100000000ull) {
-          atomicOr(&ctl->error, 4);
-          ok = 0;
-          break;
-        }
+    bool any = false;
+    while (true) {
+      bool done = true, mine = false;
+      for (unsigned l = threadIdx.x; l < G; l += 64) {
+        const unsigned f = __hip_atomic_load(slot + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        done = done && (f >> 1) >= k;
+        mine = mine || (f & 1u);
+      }
+      if (__all(done)) {
+        any = __any(mine);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > 100000000ull) {
+        ok = 0;
+        break;
       }
     }
-    gen = g + 1;
-    *s_ok = ok;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (threadIdx.x == 0) {
+      if (!ok) atomicOr(&ctl->error, 4);
+      *s_ok = ok;
+      *s_any = any ? 1 : 0;
+    }
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");  // other workgroups' stores, this wave
   return *s_ok != 0;
 }
 
-// One small system (N <= 8192) advanced nsteps in a single cooperative launch of
-// gridDim.x workgroups.  Every workgroup keeps all positions in LDS during the force
-// phase, so a neighbour read is an LDS read; the steps are separated by one grid
-// barrier, plus one after the spatial sort (workgroup 0, at the end of a step that
-// decides a rebuild) and one after the list build of the next step.
-// The wave units, the block partials and their reduction are those of the
-// single-system kernels, computed redundantly by every workgroup, so the trajectory
-// is the same bit for bit and no workgroup waits for another to publish the
-// thermostat or the rebuild decision.
+// Positions of all n particles into LDS, eight loads in flight per thread.
+__device__ __forceinline__ void fill_positions(float4 *dst, const float4 *src, int n) {
+  for (int base = 0; base < n; base += 8 * kBatchThreads) {
+    float4 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = gload(src, min(base + m * kBatchThreads + (int)threadIdx.x, n - 1));
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int k = base + m * kBatchThreads + (int)threadIdx.x;
+      if (k < n) dst[k] = v[m];
+    }
+  }
+}
+
+// One small system (N <= 8192) advanced nsteps in one cooperative launch of
+// gridDim.x workgroups.  Workgroup w owns the virtual blocks w, w + G', ... of the
+// single-system step launch (vb threads each, G of them): its waves run their wave
+// units (64 threads of that launch: the same particles, t_p lanes and list entries)
+// with all positions of the step in LDS, and the workgroup folds each owned block's
+// wave partials in order into that block's partial, as the step kernel does.  After
+// the barrier every workgroup reads the G block partials and repeats the fixed-order
+// reduction of k_finish, so the thermostat needs no second barrier; workgroup 0 alone
+// writes the record and the control block.  The rebuild decision travels with the
+// barrier.  On a step that decides a rebuild, workgroup 0 sorts (as k_finish does),
+// a barrier follows, every workgroup builds lists of particles t = wave, wave + 8G',
+// ..., and another barrier follows.  The trajectory is the launch chain's bit for bit.
 template <int TP, int METHOD>
-__global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, int cur, int nsteps, int G, int vb) {
+__global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, int cur, int nsteps, int G, int vb,
+                                                         unsigned *flags) {
   extern __shared__ float4 s_dyn[];
   __shared__ SharedPairs sp;
   __shared__ BlockPartial s_waves[16];
+  __shared__ BlockPartial s_wp[kCoopMaxUnits];
   __shared__ float s_cs2[kMaxPairs];
-  __shared__ int s_ok;
-  __shared__ int s_rebuild;
+  __shared__ int s_ok, s_any, s_rebuild, s_bit;
   __shared__ int s_kept[kBatchWaves];
   __shared__ double s_xi;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const unsigned NW = gridDim.x;
-  const int gwave = blockIdx.x * kBatchWaves + wv, nwaves = NW * kBatchWaves;
   const int wpv = vb >> 6;
-  const int units = G * wpv;
+  const int my_blocks = G > (int)blockIdx.x ? (G - (int)blockIdx.x + (int)NW - 1) / (int)NW : 0;
+  const int my_units = my_blocks * wpv;  // <= kCoopMaxUnits (checked by the host)
+  const int gwave = blockIdx.x * kBatchWaves + wv, nwaves = NW * kBatchWaves;
   const SRMD_GLOBAL int *nblg = global_view(p.nbl);
-  unsigned gen = 0;
+  unsigned k = 0;  // barriers passed in this launch
   if (tid == 0) {
-    gen = __hip_atomic_load(&p.ctl->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     s_rebuild = p.ctl->rebuild;
     s_xi = c.thermostat ? p.ctl->xi : 0.0;
   }
   stage_pairs(sp, c);
   if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
   __syncthreads();
-  // all workgroups read the barrier generation before anyone can advance it
-  if (!grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+  // every workgroup reads the control block before workgroup 0 can write it
+  if (!coop_barrier(flags, NW, ++k, 0, p.ctl, &s_ok, &s_any)) return;
   for (int step = 0; step < nsteps; ++step) {
-    BlockPartial *wpart = p.part + G + (size_t)(step & 1) * units;  // double buffer across steps
     if (s_rebuild) {  // the spatial sort has been done (host request or end of step)
       unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
       int kept = 0;
@@ -1287,16 +1345,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, i
       __syncthreads();
       if (tid == 0) {
         long long tot = 0;
-        for (int k = 0; k < kBatchWaves; ++k) tot += s_kept[k];
+        for (int q = 0; q < kBatchWaves; ++q) tot += s_kept[q];
         atomicAdd((unsigned long long *)&p.ctl->list_entries, (unsigned long long)tot);
       }
-      if (!grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+      if (!coop_barrier(flags, NW, ++k, 0, p.ctl, &s_ok, &s_any)) return;
     }
-    for (int k = tid; k < c.n; k += kBatchThreads) s_dyn[k] = gload(p.pos[cur], k);
+    fill_positions(s_dyn, p.pos[cur], c.n);
+    if (tid == 0) s_bit = 0;
     __syncthreads();
     const double xi = s_xi;
-    for (int u = gwave; u < units; u += nwaves) {
-      const int gt = u * 64 + lane;
+    // this workgroup's wave units: unit q is wave j = q % wpv of owned block q / wpv
+    for (int q = wv; q < my_units; q += kBatchWaves) {
+      const int b = (int)blockIdx.x + (q / wpv) * (int)NW;
+      const int gt = b * vb + (q % wpv) * 64 + lane;
       const int i = gt / TP, t = gt % TP;
       const bool active = i < c.n;
       float fx = 0.f, fy = 0.f, fz = 0.f, uu = 0.f, w = 0.f;
@@ -1305,13 +1366,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, i
       int4 im = make_int4(0, 0, 0, 0);
       if (active) {
         pi = s_dyn[i];
-        const int nn = gload(p.nnb, i);
         if (t == 0) {
           vo = gload(p.vel, i);
           im = gload(p.img, i);
           l0 = gload(p.last, i);
         }
-        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, nn, sp, c, fx, fy, fz, uu, w);
+        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, global_view(p.nnb), sp, c, fx, fy, fz, uu,
+                                                 w);
       }
       fx = lane_sum<TP>(fx);
       fy = lane_sum<TP>(fy);
@@ -1322,25 +1383,34 @@ __global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, i
       if (active && t == 0)
         integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
       wave_reduce(v);
-      if (lane == 0) wpart[u] = v;
+      if (lane == 0) {
+        s_wp[q] = v;
+        if (v.disp2 > c.half_skin2) s_bit = 1;
+      }
     }
-    if (!grid_barrier(p.ctl, NW, gen, &s_ok)) return;
-    // every workgroup: block partials (waves in order) folded straight into the
-    // reduction of k_finish (1024 threads, each thread here standing in for tid, tid+512)
+    __syncthreads();
+    // owned block partials: the block's waves in index order (as group_reduce)
+    for (int r = tid; r < my_blocks; r += kBatchThreads) {
+      BlockPartial a = s_wp[r * wpv];
+      for (int j = 1; j < wpv; ++j) {
+        const BlockPartial q = s_wp[r * wpv + j];
+        a.pe += q.pe;
+        a.w += q.w;
+        a.ke_half += q.ke_half;
+        a.ke_int += q.ke_int;
+        a.disp2 = fmax(a.disp2, q.disp2);
+        a.nonfinite |= q.nonfinite;
+      }
+      p.part[blockIdx.x + r * NW] = a;
+    }
+    if (!coop_barrier(flags, NW, ++k, s_bit, p.ctl, &s_ok, &s_any)) return;
+    // every workgroup: the reduction of k_finish (1024 threads, each thread here
+    // standing in for threads tid and tid + 512 of that workgroup)
     BlockPartial a0 = zero_partial(), a1 = zero_partial();
     for (int half = 0; half < 2; ++half) {
       BlockPartial &acc = half ? a1 : a0;
       for (int b = tid + half * kBatchThreads; b < G; b += 1024) {
-        BlockPartial q = wpart[b * wpv];
-        for (int k = 1; k < wpv; ++k) {
-          const BlockPartial r = wpart[b * wpv + k];
-          q.pe += r.pe;
-          q.w += r.w;
-          q.ke_half += r.ke_half;
-          q.ke_int += r.ke_int;
-          q.disp2 = fmax(q.disp2, r.disp2);
-          q.nonfinite |= r.nonfinite;
-        }
+        const BlockPartial q = p.part[b];
         acc.pe += q.pe;
         acc.w += q.w;
         acc.ke_half += q.ke_half;
@@ -1358,22 +1428,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, i
     __syncthreads();
     if (tid == 0) {
       BlockPartial a = s_waves[0];
-      for (int k = 1; k < 16; ++k) {
-        a.pe += s_waves[k].pe;
-        a.w += s_waves[k].w;
-        a.ke_half += s_waves[k].ke_half;
-        a.ke_int += s_waves[k].ke_int;
-        a.disp2 = fmax(a.disp2, s_waves[k].disp2);
-        a.nonfinite |= s_waves[k].nonfinite;
+      for (int q = 1; q < 16; ++q) {
+        a.pe += s_waves[q].pe;
+        a.w += s_waves[q].w;
+        a.ke_half += s_waves[q].ke_half;
+        a.ke_int += s_waves[q].ke_int;
+        a.disp2 = fmax(a.disp2, s_waves[q].disp2);
+        a.nonfinite |= s_waves[q].nonfinite;
       }
       a.t0 = 0ull;
       a.t1 = 0ull;
-      if (blockIdx.x == 0) {
-        s_rebuild = finish_step(c, p, a);  // the one writer of the control block
-      } else {
-        s_rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
-      }
+      if (blockIdx.x == 0) finish_step(c, p, a);  // the one writer of the control block
       if (c.thermostat) s_xi = xi_next(c, s_xi, a.ke_half);
+      s_rebuild = s_any;  // = (max displacement^2 > (skin/2)^2), as finish_step decides
     }
     __syncthreads();
     cur ^= 1;
@@ -1383,14 +1450,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, i
         unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
         sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
       }
-      if (step + 1 < nsteps && !grid_barrier(p.ctl, NW, gen, &s_ok)) return;
+      if (step + 1 < nsteps && !coop_barrier(flags, NW, ++k, 0, p.ctl, &s_ok, &s_any)) return;
     }
   }
 }
 
 template <int TP>
 static hipError_t launch_coop_tp(int method, int nwg, size_t lds, hipStream_t st, const SysConst &c,
-                                 const SysPtrs &p, int cur, int nsteps, int G, int vb) {
+                                 const SysPtrs &p, int cur, int nsteps, int G, int vb, unsigned *flags) {
   const void *fn = method == 0 ? (const void *)k_coop<TP, 0>
                    : method == 1 ? (const void *)k_coop<TP, 1>
                                  : (const void *)k_coop<TP, 2>;
@@ -1398,23 +1465,39 @@ static hipError_t launch_coop_tp(int method, int nwg, size_t lds, hipStream_t st
   if (e != hipSuccess) return e;
   SysConst cc = c;
   SysPtrs pp = p;
-  void *args[] = {&cc, &pp, &cur, &nsteps, &G, &vb};
+  void *args[] = {&cc, &pp, &cur, &nsteps, &G, &vb, &flags};
+  e = hipMemsetAsync(flags, 0, sizeof(unsigned) * 2 * kCoopMaxGroups, st);
+  if (e != hipSuccess) return e;
   return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBatchThreads), args, (unsigned)lds, st);
 }
 
 hipError_t launch_coop(int tp, int method, int nwg, size_t lds, hipStream_t st, const SysConst &c, const SysPtrs &p,
-                       int cur, int nsteps, int G, int vb) {
+                       int cur, int nsteps, int G, int vb, unsigned *flags) {
+  if (nwg < 1 || nwg > kCoopMaxGroups) return hipErrorInvalidValue;
+  // units per workgroup must fit the LDS partials of one step
+  const int wpv = vb / 64, per = (G + nwg - 1) / nwg;
+  if (per * wpv > kCoopMaxUnits) return hipErrorInvalidValue;
   switch (tp) {
-    case 1: return launch_coop_tp<1>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
-    case 2: return launch_coop_tp<2>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
-    case 4: return launch_coop_tp<4>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
-    case 8: return launch_coop_tp<8>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
-    case 16: return launch_coop_tp<16>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
-    case 32: return launch_coop_tp<32>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
-    case 64: return launch_coop_tp<64>(method, nwg, lds, st, c, p, cur, nsteps, G, vb);
+    case 1: return launch_coop_tp<1>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 2: return launch_coop_tp<2>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 4: return launch_coop_tp<4>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 8: return launch_coop_tp<8>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 16: return launch_coop_tp<16>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 32: return launch_coop_tp<32>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 64: return launch_coop_tp<64>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
     default: return hipErrorInvalidValue;
   }
 }
+
+// Fewest workgroups of the persistent kernel for G virtual blocks of vb threads
+// (the LDS partials of one step hold kCoopMaxUnits wave units per workgroup).
+int coop_min_groups(int G, int vb) {
+  const int wpv = vb / 64;
+  const int blocks_per_group = std::max(1, kCoopMaxUnits / wpv);
+  return (G + blocks_per_group - 1) / blocks_per_group;
+}
+
+int coop_max_groups_limit() { return kCoopMaxGroups; }
 
 // Largest cooperative grid the device can hold for the persistent kernel.
 int coop_max_groups(int tp, int method, size_t lds) {
@@ -1432,7 +1515,7 @@ int coop_max_groups(int tp, int method, size_t lds) {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  return per_cu * cus;
+  return std::min(per_cu * cus, kCoopMaxGroups);
 }
 
 template <int TP>

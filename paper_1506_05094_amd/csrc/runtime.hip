@@ -27,8 +27,9 @@ hipError_t launch_batch(int tp, int method, int count, size_t lds, hipStream_t s
 size_t batch_lds_bytes(int n_max_particles);
 int batch_max_particles();
 hipError_t launch_coop(int tp, int method, int nwg, size_t lds, hipStream_t st, const SysConst &c, const SysPtrs &p,
-                       int cur, int nsteps, int G, int vb);
+                       int cur, int nsteps, int G, int vb, unsigned *flags);
 int coop_max_groups(int tp, int method, size_t lds);
+int coop_min_groups(int G, int vb);
 }  // namespace srmd
 
 using namespace srmd;
@@ -245,10 +246,14 @@ void resolve_persistent(srmd_system *s) {
   const int threads = s->tp * s->ppb;
   const int units = step_blocks(s) * (threads / 64);
   const int cap = coop_max_groups(s->tp, s->method, batch_lds_bytes(s->n));
-  int want = preq > 0 ? preq : std::max(1, std::min((units + 7) / 8, 256));
+  const int lo = coop_min_groups(step_blocks(s), threads);
+  int want = preq > 0 ? preq : std::max(lo, (units + 7) / 8);
   if (preq < 0) want = std::min(want, cap);
-  if (want < 1 || want > cap)
+  if (want > cap)
     s->persist_err = "the persistent kernel's workgroups do not all fit on the device at once";
+  else if (want < lo)
+    s->persist_err = "too few workgroups for the persistent kernel at this launch shape (at least " +
+                     std::to_string(lo) + ")";
   else
     s->persist_groups = want;
 }
@@ -442,12 +447,11 @@ srmd_status regrow(srmd_system *s) {
   return prepare(s);
 }
 
-// After a persistent launch: a grid barrier that timed out (error bit 2) leaves its
-// arrival count behind; clear both and report the failure.
+// After a persistent launch: report a grid barrier that timed out (error bit 2) and
+// clear the bit (the arrival words are cleared before every launch).
 srmd_status check_barrier(srmd_system *s, Control *h) {
   if (!(h->error & 4)) return SRMD_OK;
   h->error &= ~4;
-  h->bar_count = 0;
   srmd_status st = h2d_sync(s, s->p.ctl, h, sizeof(Control));
   if (st != SRMD_OK) return st;
   return fail(s, SRMD_EHIP, "persistent kernel: a device-wide barrier timed out");
@@ -456,7 +460,7 @@ srmd_status check_barrier(srmd_system *s, Control *h) {
 // One launch of the persistent kernel over cnt steps.
 srmd_status launch_persistent(srmd_system *s, int cnt) {
   HIPCHK(s, launch_coop(s->tp, s->method, s->persist_groups, batch_lds_bytes(s->n), s->stream, s->c, s->p, s->cur,
-                        cnt, step_blocks(s), s->tp * s->ppb));
+                        cnt, step_blocks(s), s->tp * s->ppb, s->p.bar_flags));
   s->cur ^= (cnt & 1);
   return SRMD_OK;
 }
@@ -837,6 +841,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   s->p.t_img = (int4 *)A(sizeof(int4) * N);
   s->p.ctl = (Control *)A(sizeof(Control));
   s->p.thermo = (Thermo *)A(sizeof(Thermo));
+  s->p.bar_flags = (unsigned *)A(sizeof(unsigned) * 2 * 256);
   if (prec == SRMD_PREC_F64POS) {
     s->p.pos64 = (double *)A(sizeof(double) * 3 * N);
     s->p.t_pos64 = (double *)A(sizeof(double) * 3 * N);
@@ -1243,23 +1248,33 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
   if (st != SRMD_OK) result = st;
   if (result == SRMD_OK && !s->persist_err.empty()) result = fail(s, SRMD_EUNSUPPORTED, s->persist_err);
   if (result == SRMD_OK && s->persist_groups > 0) {
-    // persistent mode: one event pair around each launch of kPersistChunk steps
-    long long nl = 0;
-    while (done < nsteps && result == SRMD_OK) {
+    // persistent mode: one event pair around each launch of kPersistChunk steps, all
+    // enqueued back to back (the launches run as in srmd_step), read at the end
+    const long long nl = (nsteps + kPersistChunk - 1) / kPersistChunk;
+    for (long long k = (long long)ev.size(); k < 2 * nl && result == SRMD_OK; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) result = fail(s, SRMD_EHIP, "hipEventCreate failed");
+      else ev.push_back(e);
+    }
+    for (long long k = 0; k < nl && result == SRMD_OK; ++k) {
       const int cnt = (int)std::min<long long>(kPersistChunk, nsteps - done);
-      hipError_t e = hipEventRecord(ev[0], s->stream);
+      hipError_t e = hipEventRecord(ev[2 * k], s->stream);
       if (e == hipSuccess) {
         result = launch_persistent(s, cnt);
-        if (result == SRMD_OK) e = hipEventRecord(ev[1], s->stream);
+        if (result == SRMD_OK) e = hipEventRecord(ev[2 * k + 1], s->stream);
       }
-      if (e == hipSuccess && result == SRMD_OK) e = hipEventSynchronize(ev[1]);
-      float ms = 0.f;
-      if (e == hipSuccess && result == SRMD_OK) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
       if (e != hipSuccess && result == SRMD_OK)
         result = fail(s, SRMD_EHIP, std::string("persistent profiled launch: ") + hipGetErrorString(e));
-      total += ms;
       done += cnt;
-      ++nl;
+    }
+    if (result == SRMD_OK && nl > 0) {
+      hipError_t e = hipEventSynchronize(ev[2 * nl - 1]);
+      for (long long k = 0; k < nl && e == hipSuccess; ++k) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ev[2 * k], ev[2 * k + 1]);
+        total += ms;
+      }
+      if (e != hipSuccess) result = fail(s, SRMD_EHIP, std::string("persistent profile events: ") + hipGetErrorString(e));
     }
     for (auto &ev_k : ev) (void)hipEventDestroy(ev_k);
     if (result != SRMD_OK) return result;

@@ -71,14 +71,10 @@ struct Control {
   double xi_int;           // its time integral
   unsigned long long prof_ticks;  // accumulated step-kernel durations (device clock ticks)
   long long prof_count;           // step kernels accumulated
-  // grid barrier of the persistent kernel, on a cache line of its own so that no
-  // plain store to the fields above shares a line with the barrier's atomics
-  alignas(128) unsigned bar_count;  // arrivals
-  unsigned bar_gen;                 // generation
-  int pad[30];
+  int pad[42];
 };
 
-static_assert(sizeof(Control) == 256 && offsetof(Control, bar_count) == 128, "control block layout");
+static_assert(sizeof(Control) == 256, "control block layout");
 
 // Thermo accumulators of the last force evaluation / step.
 struct Thermo {
@@ -120,6 +116,7 @@ struct SysPtrs {
   Control *ctl;
   Thermo *thermo;   // last record
   Thermo *trace;    // device trace (trace_cap records)
+  unsigned *bar_flags;  // arrival words of the persistent kernel's grid barrier (2 x 256)
 };
 
 // One replica of a batch: its constants, its device arrays (the arrays of the
