@@ -230,24 +230,35 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
 const char *srmd_last_error(const srmd_system *s);
 
 /* ---- Batched replicas --------------------------------------------------------
- * Many independent small systems advanced together by one persistent launch: each
- * replica is owned by one workgroup that runs every step of the call inside the
- * kernel (the ensembles of small systems mentioned in the paper's introduction;
- * the batch removes the per-step launch chain that limits one small system).
+ * Many independent small systems advanced together by persistent launches (the
+ * ensembles of small systems mentioned in the paper's introduction; the batch
+ * removes the per-step launch chain that limits one small system).  The replicas
+ * are cut into pieces of about the same particle count (a replica of up to about
+ * 1700 particles in a 256-replica batch stays whole; larger ones are split over
+ * several workgroups that synchronise by grid barriers) and the pieces are packed
+ * onto the device's workgroups largest first, so that every compute unit carries
+ * about the same work; every step of a call runs inside the kernel.
  * The batch borrows the systems: it runs on their own device state, so every
  * per-system call (srmd_get_state, srmd_get_thermo, srmd_step ...) stays valid
  * between batch calls, and the systems must outlive the batch.  Requirements: at
  * least one system; every system has an integrator, float32 positions, at most
- * 8192 particles and 8192 cells, and all share the cutoff method and the launch
- * shape (tp, ppb).  A replica advanced in a batch follows the trajectory of the same
- * system advanced alone by srmd_step bit for bit.  Work is enqueued on the first
- * system's stream. */
+ * 8192 particles and 8192 cells, and all share the cutoff method and the threads
+ * per particle.  A replica advanced in a batch follows the trajectory of the same
+ * system advanced alone by srmd_step bit for bit at the same (tp, ppb), however it
+ * is split or packed.  Work is enqueued on the first system's stream. */
 
 /* Create a batch over count systems (caller-owned array, copied). */
 srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int32_t count);
 
-/* Advance every replica by nsteps steps in one persistent launch (captured in a HIP
- * graph).  If thermo_every > 0, replica r writes the records of its steps n with
+/* As srmd_batch_create, using at most max_workgroups workgroups (0: as many as the
+ * device holds at once, at most 256).  With fewer workgroups than pieces, a
+ * workgroup runs several pieces one after the other in every step (for callers
+ * that share the device, and for tests of the packing). */
+srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *systems, int32_t count,
+                                      int32_t max_workgroups);
+
+/* Advance every replica by nsteps steps in persistent launches of 500 steps (the
+ * last one shorter).  If thermo_every > 0, replica r writes the records of its steps n with
  * n % thermo_every == 0 to trace[r * trace_cap + k], k < trace_cap (caller-owned
  * array of count * trace_cap records).  Synchronises at the end.  A replica whose
  * list overflowed (paper section 4) is restored to its state at the call start, its

@@ -1022,18 +1022,8 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
   if (MODE == 0 && s_rebuild && c.small_sort) sort_small_block<1024>(c, p, next, s_cnt, s_id);
 }
 
-// ---------------------------------------------------------------- batched replicas
+// ---------------------------------------------------------------- persistent launches
 
-// Many independent small systems in one persistent launch: workgroup b owns replica
-// order[b] and runs every time step of the call without leaving the kernel (the
-// ensembles of small systems the paper's introduction points to; on MI355X one
-// replica per compute unit instead of one launch chain per system).  Positions
-// live in LDS during the force phase; the spatial sort, the list build and the
-// reductions run inside the workgroup with barriers only.  The work of the
-// single-system kernels is reproduced exactly: virtual blocks of vb threads (the
-// single system's block) compute the same per-block partials, which are reduced in
-// the same fixed order, so a replica follows its single-system trajectory bit for
-// bit at the same tp and block size.  Dynamic LDS: max(16 n_max, 64 KiB) bytes.
 // Butterfly of a BlockPartial over the 64 lanes of a wave (the first step of
 // group_reduce), result valid in every lane.
 __device__ __forceinline__ void wave_reduce(BlockPartial &v) {
@@ -1048,14 +1038,21 @@ __device__ __forceinline__ void wave_reduce(BlockPartial &v) {
   v.nonfinite = bad;
 }
 
-// Pointers read from a descriptor in memory are generic to the compiler; route them
-// through the global address space so that loads and stores compile to global
-// (not flat) instructions.
-#define SRMD_GLOBAL __attribute__((address_space(1)))
+// a += q with the operations of the block and k_finish reductions.
+__device__ __forceinline__ void fold(BlockPartial &a, const BlockPartial &q) {
+  a.pe += q.pe;
+  a.w += q.w;
+  a.ke_half += q.ke_half;
+  a.ke_int += q.ke_int;
+  a.disp2 = fmax(a.disp2, q.disp2);
+  a.nonfinite |= q.nonfinite;
+}
 
 // A pointer read from a descriptor in memory is generic to the compiler; loads
 // through this global-address-space view compile to global (not flat) loads, which
 // keep the list loads of the force loop pipelined.
+#define SRMD_GLOBAL __attribute__((address_space(1)))
+
 template <class T>
 __device__ __forceinline__ const SRMD_GLOBAL T *global_view(const T *q) {
   return (const SRMD_GLOBAL T *)q;
@@ -1076,179 +1073,44 @@ __device__ __forceinline__ int4 gload(const int4 *q, int i) {
 
 __device__ __forceinline__ int gload(const int *q, int i) { return ((const SRMD_GLOBAL int *)q)[i]; }
 
-constexpr int kBatchThreads = 512;                  // threads of a batched workgroup
+constexpr int kBatchThreads = 512;  // threads of a persistent workgroup
 constexpr int kBatchWaves = kBatchThreads / 64;
+constexpr int kCoopMaxGroups = 256;  // workgroups of one system (arrival words per parity)
+constexpr int kMaxJobs = 64;         // jobs of one workgroup
 
-template <int TP, int METHOD>
-__global__ __launch_bounds__(kBatchThreads) void k_batch(const ReplicaDesc *__restrict__ reps,
-                                                         const int *__restrict__ order, int nsteps, int vb) {
-  extern __shared__ float4 s_dyn[];
-  __shared__ SharedPairs sp;
-  __shared__ BlockPartial s_waves[16];
-  __shared__ float s_cs2[kMaxPairs];
-  __shared__ int s_flag;
-  __shared__ int s_kept[kBatchWaves];
-  const ReplicaDesc &R = reps[order[blockIdx.x]];
-  const SysConst &c = R.c;
-  const SysPtrs &p = R.p;
-  const SRMD_GLOBAL int *nblg = global_view(p.nbl);
-  const int G = R.G;
-  int cur = R.cur;
-  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const int wpv = vb >> 6;      // waves per virtual block
-  const int units = G * wpv;    // waves of the single-system step kernel
-  BlockPartial *wpart = p.part + G;  // one partial per wave unit, after the block partials
-  stage_pairs(sp, c);
-  if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
-  // a pending rebuild has had its spatial sort already (host request or end of step)
-  if (tid == 0) s_flag = p.ctl->rebuild;
-  __syncthreads();
-  for (int step = 0; step < nsteps; ++step) {
-    if (s_flag) {
-      // list build, one wave per particle (LDS scratch: one candidate window per wave)
-      unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
-      int kept = 0;
-      for (int t = wv; t < c.n; t += kBatchWaves) kept += list_wave_one(c, p, cur, t, cand, s_cs2);
-      if (lane == 0) s_kept[wv] = kept;
-      __syncthreads();
-      if (tid == 0) {
-        long long tot = 0;
-        for (int k = 0; k < kBatchWaves; ++k) tot += s_kept[k];
-        p.ctl->list_entries = tot;
-        p.ctl->rebuild = 0;
-      }
-    }
-    // positions of this step into LDS
-    for (int k = tid; k < c.n; k += kBatchThreads) s_dyn[k] = gload(p.pos[cur], k);
+// Grid-wide barrier k (k = 1, 2, ... in one launch) of the G workgroups that share
+// one system, over that system's array of arrival words (one per workgroup and
+// barrier parity, cleared by the host before the launch).  Piece w publishes
+// (k << 1) | bit in its word: an arrival costs one store and no read-modify-write on
+// a shared counter, and bit carries a flag whose OR over the pieces every piece
+// receives (the rebuild decision).  The first wave polls the G words of parity k & 1
+// until each holds barrier k; two parities suffice because no piece can reach
+// barrier k + 2 before every piece has left barrier k.  The wait is bounded (about
+// one second of the 100 MHz device clock): on time-out the workgroup sets error bit 2
+// and the kernel ends instead of hanging.  Release / acquire fences at agent scope
+// order every store before the barrier against every load after it.  The release is
+// issued once per workgroup, after each wave has waited for its own stores to
+// complete (the L2 write-back acts on the whole cache), and the arrival store waits
+// for the write-back to complete; the acquire is issued by the polling wave and,
+// after the workgroup barrier, by every other wave, since an invalidate orders only
+// the issuing wave's later loads.  With G = 1 the barrier is the workgroup barrier.
+__device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsigned w, unsigned k, int bit,
+                                             Control *ctl, int *s_ok, int *s_any) {
+  if (G == 1) {
     __syncthreads();
-    const double xi = c.thermostat ? p.ctl->xi : 0.0;
-    // force + integration, one wave unit (64 threads of the single-system launch) at a time
-    for (int u = wv; u < units; u += kBatchWaves) {
-      const int gt = u * 64 + lane;
-      const int i = gt / TP, t = gt % TP;
-      const bool active = i < c.n;
-      float fx = 0.f, fy = 0.f, fz = 0.f, uu = 0.f, w = 0.f;
-      float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 vo = pi, l0 = pi, kc = pi;
-      int4 im = make_int4(0, 0, 0, 0);
-      if (active) {
-        pi = s_dyn[i];
-        if (t == 0) {
-          vo = gload(p.vel, i);
-          im = gload(p.img, i);
-          l0 = gload(p.last, i);
-        }
-        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, global_view(p.nnb), sp, c, fx, fy, fz, uu,
-                                                 w);
-      }
-      fx = lane_sum<TP>(fx);
-      fy = lane_sum<TP>(fy);
-      fz = lane_sum<TP>(fz);
-      uu = lane_sum<TP>(uu);
-      w = lane_sum<TP>(w);
-      BlockPartial v = zero_partial();
-      if (active && t == 0)
-        integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
-      wave_reduce(v);
-      if (lane == 0) wpart[u] = v;
-    }
+    if (threadIdx.x == 0) *s_any = bit;
     __syncthreads();
-    // block partials: the waves of each virtual block in index order (as group_reduce)
-    for (int b = tid; b < G; b += kBatchThreads) {
-      BlockPartial a = wpart[b * wpv];
-      for (int k = 1; k < wpv; ++k) {
-        const BlockPartial q = wpart[b * wpv + k];
-        a.pe += q.pe;
-        a.w += q.w;
-        a.ke_half += q.ke_half;
-        a.ke_int += q.ke_int;
-        a.disp2 = fmax(a.disp2, q.disp2);
-        a.nonfinite |= q.nonfinite;
-      }
-      p.part[b] = a;
-    }
-    __syncthreads();
-    // end of step: the reduction of k_finish (1024 threads) with each thread standing
-    // in for threads tid and tid + 512 of that workgroup
-    BlockPartial a0 = zero_partial(), a1 = zero_partial();
-    for (int b = tid; b < G; b += 1024) {
-      const BlockPartial q = p.part[b];
-      a0.pe += q.pe;
-      a0.w += q.w;
-      a0.ke_half += q.ke_half;
-      a0.ke_int += q.ke_int;
-      a0.disp2 = fmax(a0.disp2, q.disp2);
-      a0.nonfinite |= q.nonfinite;
-    }
-    for (int b = tid + kBatchThreads; b < G; b += 1024) {
-      const BlockPartial q = p.part[b];
-      a1.pe += q.pe;
-      a1.w += q.w;
-      a1.ke_half += q.ke_half;
-      a1.ke_int += q.ke_int;
-      a1.disp2 = fmax(a1.disp2, q.disp2);
-      a1.nonfinite |= q.nonfinite;
-    }
-    wave_reduce(a0);
-    wave_reduce(a1);
-    if (lane == 0) {
-      s_waves[wv] = a0;
-      s_waves[wv + kBatchWaves] = a1;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      BlockPartial a = s_waves[0];
-      for (int k = 1; k < 16; ++k) {
-        a.pe += s_waves[k].pe;
-        a.w += s_waves[k].w;
-        a.ke_half += s_waves[k].ke_half;
-        a.ke_int += s_waves[k].ke_int;
-        a.disp2 = fmax(a.disp2, s_waves[k].disp2);
-        a.nonfinite |= s_waves[k].nonfinite;
-      }
-      a.t0 = 0ull;
-      a.t1 = 0ull;
-      s_flag = finish_step(c, p, a);
-    }
-    __syncthreads();
-    cur ^= 1;
-    if (s_flag) {
-      // spatial sort of the new positions for the next list build, as k_finish does
-      // (LDS scratch: cell counts, ids)
-      unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
-      sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
-      __syncthreads();
-    }
+    return true;
   }
-}
-
-// ---------------------------------------------------------------- persistent single system
-
-constexpr int kCoopMaxGroups = 256;  // workgroups of the persistent kernel (one per CU at most)
-constexpr int kCoopMaxUnits = 64;    // wave units of one workgroup per step (LDS partials)
-
-// Grid-wide barrier k (k = 1, 2, ... in one launch) over an array of arrival words,
-// one per workgroup and barrier parity, cleared by the host before the launch.
-// Workgroup b publishes (k << 1) | bit in its word: an arrival costs one store and no
-// read-modify-write on a shared counter, and bit carries a flag whose OR over the
-// workgroups every workgroup receives (the rebuild decision).  The first wave polls
-// all words of parity k & 1 until each holds barrier k; two parities suffice because
-// no workgroup can reach barrier k + 2 before every workgroup has left barrier k.
-// The wait is bounded (about one second of the 100 MHz device clock): on time-out
-// the workgroup sets error bit 2 and the kernel ends instead of hanging.  Release /
-// acquire fences at agent scope order every store before the barrier against every
-// load after it.  They are issued once per workgroup: each wave first waits for its
-// own stores to complete, and the L2 write-back / invalidate act on the whole cache
-// (and the invalidate on the compute unit's L1) for every wave of the workgroup.
-__device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsigned k, int bit, Control *ctl,
-                                             int *s_ok, int *s_any) {
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
   __syncthreads();
   unsigned *slot = flags + (k & 1u) * kCoopMaxGroups;
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __hip_atomic_store(slot + blockIdx.x, (k << 1) | (unsigned)(bit != 0), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
+    // the L2 write-back must complete before the arrival is visible; the compiler's own
+    // wait after the write-back is dropped when no store of this wave is outstanding
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_store(slot + w, (k << 1) | (unsigned)(bit != 0), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   if (threadIdx.x < 64) {
     const unsigned long long t0 = wall_clock64();
@@ -1279,6 +1141,9 @@ __device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsign
     }
   }
   __syncthreads();
+  // the other waves acquire for themselves: an invalidate orders only the issuing
+  // wave's later loads, and the workgroup barrier does not wait for it to complete
+  if (threadIdx.x >= 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_ok != 0;
 }
 
@@ -1296,217 +1161,217 @@ __device__ __forceinline__ void fill_positions(float4 *dst, const float4 *src, i
   }
 }
 
-// One small system (N <= 8192) advanced nsteps in one cooperative launch of
-// gridDim.x workgroups.  Workgroup w owns the virtual blocks w, w + G', ... of the
-// single-system step launch (vb threads each, G of them): its waves run their wave
+// Small systems (N <= 8192, at most 8192 cells) advanced nsteps in one cooperative
+// launch: one system over many workgroups (a single large enough system), many
+// systems over the workgroups (a batch of replicas: the ensembles of small systems
+// the paper's introduction points to), or both (a batch whose largest replicas are
+// split over several workgroups and whose smallest share one).  Workgroup b runs the
+// jobs jobs[job_off[b] .. job_off[b+1]) one after the other in every step.
+//
+// Piece w of g of a system owns the virtual blocks w, w + g, ... of that system's
+// single-system step launch (G blocks of vb threads): its waves run the blocks' wave
 // units (64 threads of that launch: the same particles, t_p lanes and list entries)
-// with all positions of the step in LDS, and the workgroup folds each owned block's
-// wave partials in order into that block's partial, as the step kernel does.  After
-// the barrier every workgroup reads the G block partials and repeats the fixed-order
-// reduction of k_finish, so the thermostat needs no second barrier; workgroup 0 alone
-// writes the record and the control block.  The rebuild decision travels with the
-// barrier.  On a step that decides a rebuild, workgroup 0 sorts (as k_finish does),
-// a barrier follows, every workgroup builds lists of particles t = wave, wave + 8G',
-// ..., and another barrier follows.  The trajectory is the launch chain's bit for bit.
+// with all positions of the step in LDS, and each block's wave partials are folded in
+// index order into the block partial, as the step kernel does.  The partials buffer
+// of a system holds two sets of G block partials (by step parity) and then one
+// partial per wave unit.  After the barrier
+// every piece reads the G block partials and repeats the fixed-order reduction of
+// k_finish (so the thermostat needs no second barrier); piece 0 alone writes the
+// record and the control block.  The rebuild decision travels with the barrier.  On
+// a step that decides a rebuild, piece 0 sorts (as k_finish does), a barrier follows,
+// the pieces build the lists of particles wave, wave + 8g, ..., and another barrier
+// follows.  A system follows its single-system trajectory bit for bit at the same
+// (tp, ppb), whatever the pieces and the other jobs of its workgroups.
 template <int TP, int METHOD>
-__global__ __launch_bounds__(kBatchThreads) void k_coop(SysConst c, SysPtrs p, int cur, int nsteps, int G, int vb,
-                                                         unsigned *flags) {
+__global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__restrict__ reps,
+                                                         const CoopJob *__restrict__ jobs,
+                                                         const int *__restrict__ job_off, int nsteps) {
   extern __shared__ float4 s_dyn[];
   __shared__ SharedPairs sp;
   __shared__ BlockPartial s_waves[16];
-  __shared__ BlockPartial s_wp[kCoopMaxUnits];
   __shared__ float s_cs2[kMaxPairs];
-  __shared__ int s_ok, s_any, s_rebuild, s_bit;
+  __shared__ int s_ok, s_any, s_bit;
   __shared__ int s_kept[kBatchWaves];
-  __shared__ double s_xi;
+  __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs];
+  __shared__ unsigned s_k[kMaxJobs];
+  __shared__ double s_xi[kMaxJobs];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-  const unsigned NW = gridDim.x;
-  const int wpv = vb >> 6;
-  const int my_blocks = G > (int)blockIdx.x ? (G - (int)blockIdx.x + (int)NW - 1) / (int)NW : 0;
-  const int my_units = my_blocks * wpv;  // <= kCoopMaxUnits (checked by the host)
-  const int gwave = blockIdx.x * kBatchWaves + wv, nwaves = NW * kBatchWaves;
-  const SRMD_GLOBAL int *nblg = global_view(p.nbl);
-  unsigned k = 0;  // barriers passed in this launch
-  if (tid == 0) {
-    s_rebuild = p.ctl->rebuild;
-    s_xi = c.thermostat ? p.ctl->xi : 0.0;
+  const int j0 = job_off[blockIdx.x];
+  const int nj = min(job_off[blockIdx.x + 1] - j0, kMaxJobs);
+  // every piece reads its system's control block before piece 0 can write it
+  for (int j = 0; j < nj; ++j) {
+    const CoopJob J = jobs[j0 + j];
+    const ReplicaDesc &R = reps[J.rep];
+    if (tid == 0) {
+      s_rebuild[j] = R.p.ctl->rebuild;
+      s_xi[j] = R.c.thermostat ? R.p.ctl->xi : 0.0;
+      s_cur[j] = R.cur;
+      s_k[j] = 1u;
+    }
+    if (!coop_barrier(R.p.bar_flags, J.g, J.w, 1u, 0, R.p.ctl, &s_ok, &s_any)) return;
   }
-  stage_pairs(sp, c);
-  if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
-  __syncthreads();
-  // every workgroup reads the control block before workgroup 0 can write it
-  if (!coop_barrier(flags, NW, ++k, 0, p.ctl, &s_ok, &s_any)) return;
   for (int step = 0; step < nsteps; ++step) {
-    if (s_rebuild) {  // the spatial sort has been done (host request or end of step)
-      unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
-      int kept = 0;
-      for (int t = gwave; t < c.n; t += nwaves) kept += list_wave_one(c, p, cur, t, cand, s_cs2);
-      if (lane == 0) s_kept[wv] = kept;
+    for (int j = 0; j < nj; ++j) {
+      const CoopJob J = jobs[j0 + j];
+      const ReplicaDesc &R = reps[J.rep];
+      const SysConst &c = R.c;
+      const SysPtrs &p = R.p;
+      const int G = R.G, vb = R.vb, wpv = vb >> 6;
+      const SRMD_GLOBAL int *nblg = global_view(p.nbl);
+      const SRMD_GLOBAL int *nnbg = global_view(p.nnb);
+      __syncthreads();  // the previous job's LDS use has ended
+      int cur = s_cur[j];
+      unsigned k = s_k[j];
+      const int rebuild = s_rebuild[j];
+      const double xi = s_xi[j];
+      stage_pairs(sp, c);
+      if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
+      if (tid == 0) s_bit = 0;
+      __syncthreads();
+      if (rebuild) {  // the spatial sort has been done (host request or end of step)
+        unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
+        int kept = 0;
+        for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves)
+          kept += list_wave_one(c, p, cur, t, cand, s_cs2);
+        if (lane == 0) s_kept[wv] = kept;
+        __syncthreads();
+        if (tid == 0) {
+          long long tot = 0;
+          for (int q = 0; q < kBatchWaves; ++q) tot += s_kept[q];
+          atomicAdd((unsigned long long *)&p.ctl->list_entries, (unsigned long long)tot);
+        }
+        if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+      }
+      fill_positions(s_dyn, p.pos[cur], c.n);
+      __syncthreads();
+      // this piece's wave units: unit q is wave q % wpv of owned block q / wpv; the
+      // waves run their units without waiting for each other, and the wave partials
+      // go to the system's partials buffer after the G block partials
+      const int my_blocks = G > J.w ? (G - J.w + J.g - 1) / J.g : 0;
+      const int my_units = my_blocks * wpv;
+      // block partials alternate between two sets by step parity: a piece may write
+      // the next step's partials while a slower piece still reads this step's
+      BlockPartial *bpart = p.part + (step & 1) * G;
+      BlockPartial *wpart = p.part + 2 * G;
+      for (int q = wv; q < my_units; q += kBatchWaves) {
+        const int b = J.w + (q / wpv) * J.g;
+        const int u = b * wpv + q % wpv;
+        const int gt = u * 64 + lane;
+        const int i = gt / TP, t = gt % TP;
+        const bool active = i < c.n;
+        float fx = 0.f, fy = 0.f, fz = 0.f, uu = 0.f, w = 0.f;
+        float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 vo = pi, l0 = pi, kc = pi;
+        int4 im = make_int4(0, 0, 0, 0);
+        if (active) {
+          pi = s_dyn[i];
+          if (t == 0) {
+            vo = gload(p.vel, i);
+            im = gload(p.img, i);
+            l0 = gload(p.last, i);
+          }
+          force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, nnbg, sp, c, fx, fy, fz, uu, w);
+        }
+        fx = lane_sum<TP>(fx);
+        fy = lane_sum<TP>(fy);
+        fz = lane_sum<TP>(fz);
+        uu = lane_sum<TP>(uu);
+        w = lane_sum<TP>(w);
+        BlockPartial v = zero_partial();
+        if (active && t == 0)
+          integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
+        wave_reduce(v);
+        if (lane == 0) {
+          wpart[u] = v;
+          if (v.disp2 > c.half_skin2) s_bit = 1;
+        }
+      }
+      __syncthreads();
+      // owned block partials: each block's waves in index order (as group_reduce)
+      for (int r = tid; r < my_blocks; r += kBatchThreads) {
+        const int b = J.w + r * J.g;
+        BlockPartial a = wpart[b * wpv];
+        for (int q = 1; q < wpv; ++q) fold(a, wpart[b * wpv + q]);
+        bpart[b] = a;
+      }
+      if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, s_bit, p.ctl, &s_ok, &s_any)) return;
+      // every piece: the reduction of k_finish (1024 threads, each thread here
+      // standing in for threads tid and tid + 512 of that workgroup)
+      BlockPartial a0 = zero_partial(), a1 = zero_partial();
+      for (int b = tid; b < G; b += 1024) fold(a0, bpart[b]);
+      for (int b = tid + kBatchThreads; b < G; b += 1024) fold(a1, bpart[b]);
+      wave_reduce(a0);
+      wave_reduce(a1);
+      if (lane == 0) {
+        s_waves[wv] = a0;
+        s_waves[wv + kBatchWaves] = a1;
+      }
       __syncthreads();
       if (tid == 0) {
-        long long tot = 0;
-        for (int q = 0; q < kBatchWaves; ++q) tot += s_kept[q];
-        atomicAdd((unsigned long long *)&p.ctl->list_entries, (unsigned long long)tot);
+        BlockPartial a = s_waves[0];
+        for (int q = 1; q < 16; ++q) fold(a, s_waves[q]);
+        a.t0 = 0ull;
+        a.t1 = 0ull;
+        if (J.w == 0) finish_step(c, p, a);  // the one writer of the control block
+        if (c.thermostat) s_xi[j] = xi_next(c, xi, a.ke_half);
+        s_rebuild[j] = s_any;  // = (max displacement^2 > (skin/2)^2), as finish_step decides
       }
-      if (!coop_barrier(flags, NW, ++k, 0, p.ctl, &s_ok, &s_any)) return;
-    }
-    fill_positions(s_dyn, p.pos[cur], c.n);
-    if (tid == 0) s_bit = 0;
-    __syncthreads();
-    const double xi = s_xi;
-    // this workgroup's wave units: unit q is wave j = q % wpv of owned block q / wpv
-    for (int q = wv; q < my_units; q += kBatchWaves) {
-      const int b = (int)blockIdx.x + (q / wpv) * (int)NW;
-      const int gt = b * vb + (q % wpv) * 64 + lane;
-      const int i = gt / TP, t = gt % TP;
-      const bool active = i < c.n;
-      float fx = 0.f, fy = 0.f, fz = 0.f, uu = 0.f, w = 0.f;
-      float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-      float4 vo = pi, l0 = pi, kc = pi;
-      int4 im = make_int4(0, 0, 0, 0);
-      if (active) {
-        pi = s_dyn[i];
-        if (t == 0) {
-          vo = gload(p.vel, i);
-          im = gload(p.img, i);
-          l0 = gload(p.last, i);
+      __syncthreads();
+      cur ^= 1;
+      if (s_rebuild[j]) {
+        // spatial sort of the new positions by piece 0, as k_finish does
+        if (J.w == 0) {
+          unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
+          sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
         }
-        force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, global_view(p.nnb), sp, c, fx, fy, fz, uu,
-                                                 w);
+        if (step + 1 < nsteps && !coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
-      fx = lane_sum<TP>(fx);
-      fy = lane_sum<TP>(fy);
-      fz = lane_sum<TP>(fz);
-      uu = lane_sum<TP>(uu);
-      w = lane_sum<TP>(w);
-      BlockPartial v = zero_partial();
-      if (active && t == 0)
-        integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
-      wave_reduce(v);
-      if (lane == 0) {
-        s_wp[q] = v;
-        if (v.disp2 > c.half_skin2) s_bit = 1;
+      if (tid == 0) {
+        s_cur[j] = cur;
+        s_k[j] = k;
       }
-    }
-    __syncthreads();
-    // owned block partials: the block's waves in index order (as group_reduce)
-    for (int r = tid; r < my_blocks; r += kBatchThreads) {
-      BlockPartial a = s_wp[r * wpv];
-      for (int j = 1; j < wpv; ++j) {
-        const BlockPartial q = s_wp[r * wpv + j];
-        a.pe += q.pe;
-        a.w += q.w;
-        a.ke_half += q.ke_half;
-        a.ke_int += q.ke_int;
-        a.disp2 = fmax(a.disp2, q.disp2);
-        a.nonfinite |= q.nonfinite;
-      }
-      p.part[blockIdx.x + r * NW] = a;
-    }
-    if (!coop_barrier(flags, NW, ++k, s_bit, p.ctl, &s_ok, &s_any)) return;
-    // every workgroup: the reduction of k_finish (1024 threads, each thread here
-    // standing in for threads tid and tid + 512 of that workgroup)
-    BlockPartial a0 = zero_partial(), a1 = zero_partial();
-    for (int half = 0; half < 2; ++half) {
-      BlockPartial &acc = half ? a1 : a0;
-      for (int b = tid + half * kBatchThreads; b < G; b += 1024) {
-        const BlockPartial q = p.part[b];
-        acc.pe += q.pe;
-        acc.w += q.w;
-        acc.ke_half += q.ke_half;
-        acc.ke_int += q.ke_int;
-        acc.disp2 = fmax(acc.disp2, q.disp2);
-        acc.nonfinite |= q.nonfinite;
-      }
-    }
-    wave_reduce(a0);
-    wave_reduce(a1);
-    if (lane == 0) {
-      s_waves[wv] = a0;
-      s_waves[wv + kBatchWaves] = a1;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      BlockPartial a = s_waves[0];
-      for (int q = 1; q < 16; ++q) {
-        a.pe += s_waves[q].pe;
-        a.w += s_waves[q].w;
-        a.ke_half += s_waves[q].ke_half;
-        a.ke_int += s_waves[q].ke_int;
-        a.disp2 = fmax(a.disp2, s_waves[q].disp2);
-        a.nonfinite |= s_waves[q].nonfinite;
-      }
-      a.t0 = 0ull;
-      a.t1 = 0ull;
-      if (blockIdx.x == 0) finish_step(c, p, a);  // the one writer of the control block
-      if (c.thermostat) s_xi = xi_next(c, s_xi, a.ke_half);
-      s_rebuild = s_any;  // = (max displacement^2 > (skin/2)^2), as finish_step decides
-    }
-    __syncthreads();
-    cur ^= 1;
-    if (s_rebuild) {
-      // spatial sort of the new positions by workgroup 0, as k_finish does
-      if (blockIdx.x == 0) {
-        unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
-        sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
-      }
-      if (step + 1 < nsteps && !coop_barrier(flags, NW, ++k, 0, p.ctl, &s_ok, &s_any)) return;
     }
   }
 }
 
 template <int TP>
-static hipError_t launch_coop_tp(int method, int nwg, size_t lds, hipStream_t st, const SysConst &c,
-                                 const SysPtrs &p, int cur, int nsteps, int G, int vb, unsigned *flags) {
-  const void *fn = method == 0 ? (const void *)k_coop<TP, 0>
-                   : method == 1 ? (const void *)k_coop<TP, 1>
-                                 : (const void *)k_coop<TP, 2>;
+static hipError_t launch_multi_tp(int method, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                                  const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative) {
+  const void *fn = method == 0 ? (const void *)k_multi<TP, 0>
+                   : method == 1 ? (const void *)k_multi<TP, 1>
+                                 : (const void *)k_multi<TP, 2>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  SysConst cc = c;
-  SysPtrs pp = p;
-  void *args[] = {&cc, &pp, &cur, &nsteps, &G, &vb, &flags};
-  e = hipMemsetAsync(flags, 0, sizeof(unsigned) * 2 * kCoopMaxGroups, st);
-  if (e != hipSuccess) return e;
-  return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBatchThreads), args, (unsigned)lds, st);
+  void *args[] = {&reps, &jobs, &job_off, &nsteps};
+  if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBatchThreads), args, (unsigned)lds, st);
+  return hipLaunchKernel(fn, dim3(nwg), dim3(kBatchThreads), args, lds, st);
 }
 
-hipError_t launch_coop(int tp, int method, int nwg, size_t lds, hipStream_t st, const SysConst &c, const SysPtrs &p,
-                       int cur, int nsteps, int G, int vb, unsigned *flags) {
-  if (nwg < 1 || nwg > kCoopMaxGroups) return hipErrorInvalidValue;
-  // units per workgroup must fit the LDS partials of one step
-  const int wpv = vb / 64, per = (G + nwg - 1) / nwg;
-  if (per * wpv > kCoopMaxUnits) return hipErrorInvalidValue;
+// Launch k_multi over nwg workgroups.  cooperative: some system is split over
+// several workgroups, which must then all be resident at once.
+hipError_t launch_multi(int tp, int method, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                        const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative) {
+  if (nwg < 1) return hipErrorInvalidValue;
   switch (tp) {
-    case 1: return launch_coop_tp<1>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
-    case 2: return launch_coop_tp<2>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
-    case 4: return launch_coop_tp<4>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
-    case 8: return launch_coop_tp<8>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
-    case 16: return launch_coop_tp<16>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
-    case 32: return launch_coop_tp<32>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
-    case 64: return launch_coop_tp<64>(method, nwg, lds, st, c, p, cur, nsteps, G, vb, flags);
+    case 1: return launch_multi_tp<1>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
+    case 2: return launch_multi_tp<2>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
+    case 4: return launch_multi_tp<4>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
+    case 8: return launch_multi_tp<8>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
+    case 16: return launch_multi_tp<16>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
+    case 32: return launch_multi_tp<32>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
+    case 64: return launch_multi_tp<64>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
     default: return hipErrorInvalidValue;
   }
 }
 
-// Fewest workgroups of the persistent kernel for G virtual blocks of vb threads
-// (the LDS partials of one step hold kCoopMaxUnits wave units per workgroup).
-int coop_min_groups(int G, int vb) {
-  const int wpv = vb / 64;
-  const int blocks_per_group = std::max(1, kCoopMaxUnits / wpv);
-  return (G + blocks_per_group - 1) / blocks_per_group;
-}
-
-int coop_max_groups_limit() { return kCoopMaxGroups; }
-
-// Largest cooperative grid the device can hold for the persistent kernel.
-int coop_max_groups(int tp, int method, size_t lds) {
+// Workgroups of the persistent kernel the device holds at once (at most 256).
+int multi_max_groups(int tp, int method, size_t lds) {
   const void *fn = nullptr;
   switch (tp) {
-#define SRMD_COOP_FN(T) \
-  case T: fn = method == 0 ? (const void *)k_coop<T, 0> : method == 1 ? (const void *)k_coop<T, 1> : (const void *)k_coop<T, 2>; break;
-    SRMD_COOP_FN(1) SRMD_COOP_FN(2) SRMD_COOP_FN(4) SRMD_COOP_FN(8) SRMD_COOP_FN(16) SRMD_COOP_FN(32) SRMD_COOP_FN(64)
-#undef SRMD_COOP_FN
+#define SRMD_MULTI_FN(T) \
+  case T: fn = method == 0 ? (const void *)k_multi<T, 0> : method == 1 ? (const void *)k_multi<T, 1> : (const void *)k_multi<T, 2>; break;
+    SRMD_MULTI_FN(1) SRMD_MULTI_FN(2) SRMD_MULTI_FN(4) SRMD_MULTI_FN(8) SRMD_MULTI_FN(16) SRMD_MULTI_FN(32) SRMD_MULTI_FN(64)
+#undef SRMD_MULTI_FN
     default: return 0;
   }
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
@@ -1518,33 +1383,7 @@ int coop_max_groups(int tp, int method, size_t lds) {
   return std::min(per_cu * cus, kCoopMaxGroups);
 }
 
-template <int TP>
-static hipError_t launch_batch_tp(int method, int count, size_t lds, hipStream_t st, const ReplicaDesc *reps,
-                                  const int *order, int nsteps, int vb) {
-  const void *fn = method == 0 ? (const void *)k_batch<TP, 0>
-                   : method == 1 ? (const void *)k_batch<TP, 1>
-                                 : (const void *)k_batch<TP, 2>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (method == 0) hipLaunchKernelGGL((k_batch<TP, 0>), dim3(count), dim3(kBatchThreads), lds, st, reps, order, nsteps, vb);
-  else if (method == 1) hipLaunchKernelGGL((k_batch<TP, 1>), dim3(count), dim3(kBatchThreads), lds, st, reps, order, nsteps, vb);
-  else hipLaunchKernelGGL((k_batch<TP, 2>), dim3(count), dim3(kBatchThreads), lds, st, reps, order, nsteps, vb);
-  return hipGetLastError();
-}
-
-hipError_t launch_batch(int tp, int method, int count, size_t lds, hipStream_t st, const ReplicaDesc *reps,
-                        const int *order, int nsteps, int vb) {
-  switch (tp) {
-    case 1: return launch_batch_tp<1>(method, count, lds, st, reps, order, nsteps, vb);
-    case 2: return launch_batch_tp<2>(method, count, lds, st, reps, order, nsteps, vb);
-    case 4: return launch_batch_tp<4>(method, count, lds, st, reps, order, nsteps, vb);
-    case 8: return launch_batch_tp<8>(method, count, lds, st, reps, order, nsteps, vb);
-    case 16: return launch_batch_tp<16>(method, count, lds, st, reps, order, nsteps, vb);
-    case 32: return launch_batch_tp<32>(method, count, lds, st, reps, order, nsteps, vb);
-    case 64: return launch_batch_tp<64>(method, count, lds, st, reps, order, nsteps, vb);
-    default: return hipErrorInvalidValue;
-  }
-}
+int multi_max_jobs() { return kMaxJobs; }
 
 size_t batch_lds_bytes(int n_max_particles) {
   const size_t pos = 16 * (size_t)n_max_particles;

@@ -22,14 +22,12 @@ hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, i
 hipError_t launch_finish(int mode, int G, int next, hipStream_t st, const SysConst &c, const SysPtrs &p);
 hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
 bool small_sort_fits(int n, int ncell);
-hipError_t launch_batch(int tp, int method, int count, size_t lds, hipStream_t st, const ReplicaDesc *reps,
-                        const int *order, int nsteps, int vb);
 size_t batch_lds_bytes(int n_max_particles);
 int batch_max_particles();
-hipError_t launch_coop(int tp, int method, int nwg, size_t lds, hipStream_t st, const SysConst &c, const SysPtrs &p,
-                       int cur, int nsteps, int G, int vb, unsigned *flags);
-int coop_max_groups(int tp, int method, size_t lds);
-int coop_min_groups(int G, int vb);
+hipError_t launch_multi(int tp, int method, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                        const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative);
+int multi_max_groups(int tp, int method, size_t lds);
+int multi_max_jobs();
 }  // namespace srmd
 
 using namespace srmd;
@@ -52,7 +50,7 @@ struct DevBuf {
 };
 
 constexpr int kChunk = 64;  // steps per captured graph (even: the position buffers alternate)
-constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel
+constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel (even)
 
 }  // namespace
 
@@ -82,6 +80,12 @@ struct srmd_system {
   int persist_tuned = 0;             // choice of srmd_autotune
   int persist_groups = 0;            // resolved workgroup count, 0 = launch chains
   std::string persist_err;           // why the requested persistent mode cannot run
+  ReplicaDesc *d_desc = nullptr;     // persistent launch tables (one system, persist_groups jobs)
+  CoopJob *d_jobs = nullptr;
+  int *d_job_off = nullptr;
+  int jobs_cap = 0, jobs_g = 0;      // capacity and current size of the job table
+  ReplicaDesc host_desc{};           // last uploaded descriptor
+  bool desc_valid = false;
   // derived layout
   bool dirty = true;  // SysConst must be rebuilt
   SysConst c{};
@@ -245,15 +249,11 @@ void resolve_persistent(srmd_system *s) {
   }
   const int threads = s->tp * s->ppb;
   const int units = step_blocks(s) * (threads / 64);
-  const int cap = coop_max_groups(s->tp, s->method, batch_lds_bytes(s->n));
-  const int lo = coop_min_groups(step_blocks(s), threads);
-  int want = preq > 0 ? preq : std::max(lo, (units + 7) / 8);
+  const int cap = multi_max_groups(s->tp, s->method, batch_lds_bytes(s->n));
+  int want = preq > 0 ? preq : std::max(1, (units + 7) / 8);
   if (preq < 0) want = std::min(want, cap);
-  if (want > cap)
+  if (want > cap || want < 1)
     s->persist_err = "the persistent kernel's workgroups do not all fit on the device at once";
-  else if (want < lo)
-    s->persist_err = "too few workgroups for the persistent kernel at this launch shape (at least " +
-                     std::to_string(lo) + ")";
   else
     s->persist_groups = want;
 }
@@ -349,9 +349,9 @@ srmd_status prepare(srmd_system *s) {
   }
   const int threads = s->tp * s->ppb;
   const int blocks = (int)(((long long)s->n * s->tp + threads - 1) / threads);
-  // block partials, then one partial per wave (used by the batched kernel; two
-  // alternating sets of them in the persistent kernel)
-  const int nparts = blocks + 2 * blocks * (threads / 64);
+  // block partials, a second set of them and one partial per wave unit (the
+  // persistent kernel alternates the two sets of block partials by step parity)
+  const int nparts = 2 * blocks + blocks * (threads / 64);
   if (nparts > s->part_alloc) {
     dev_free(s, s->p.part);
     s->p.part = (BlockPartial *)dev_alloc(s, sizeof(BlockPartial) * (size_t)nparts);
@@ -457,10 +457,56 @@ srmd_status check_barrier(srmd_system *s, Control *h) {
   return fail(s, SRMD_EHIP, "persistent kernel: a device-wide barrier timed out");
 }
 
-// One launch of the persistent kernel over cnt steps.
+// The descriptor of this system for a persistent launch.
+ReplicaDesc make_desc(const srmd_system *s) {
+  ReplicaDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.c = s->c;
+  d.p = s->p;
+  d.cur = s->cur;
+  d.G = step_blocks(s);
+  d.vb = s->tp * s->ppb;
+  return d;
+}
+
+// One launch of the persistent kernel over cnt steps: the system split over
+// persist_groups workgroups (job w of g on workgroup w).
 srmd_status launch_persistent(srmd_system *s, int cnt) {
-  HIPCHK(s, launch_coop(s->tp, s->method, s->persist_groups, batch_lds_bytes(s->n), s->stream, s->c, s->p, s->cur,
-                        cnt, step_blocks(s), s->tp * s->ppb, s->p.bar_flags));
+  const int g = s->persist_groups;
+  if (g > s->jobs_cap) {
+    dev_free(s, s->d_jobs);
+    dev_free(s, s->d_job_off);
+    s->d_jobs = (CoopJob *)dev_alloc(s, sizeof(CoopJob) * (size_t)g);
+    s->d_job_off = (int *)dev_alloc(s, sizeof(int) * (size_t)(g + 1));
+    if (!s->d_jobs || !s->d_job_off) return fail(s, SRMD_ENOMEM, "persistent job table allocation failed");
+    s->jobs_cap = g;
+    s->jobs_g = 0;
+  }
+  if (g != s->jobs_g) {
+    std::vector<CoopJob> hj((size_t)g);
+    std::vector<int> ho((size_t)g + 1);
+    for (int w = 0; w < g; ++w) hj[(size_t)w] = CoopJob{0, w, g, 0};
+    for (int w = 0; w <= g; ++w) ho[(size_t)w] = w;
+    HIPCHK(s, hipMemcpyAsync(s->d_jobs, hj.data(), sizeof(CoopJob) * hj.size(), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipMemcpyAsync(s->d_job_off, ho.data(), sizeof(int) * ho.size(), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->jobs_g = g;
+  }
+  if (!s->d_desc) {
+    s->d_desc = (ReplicaDesc *)dev_alloc(s, sizeof(ReplicaDesc));
+    if (!s->d_desc) return fail(s, SRMD_ENOMEM, "persistent descriptor allocation failed");
+    s->desc_valid = false;
+  }
+  const ReplicaDesc d = make_desc(s);
+  if (!s->desc_valid || std::memcmp(&d, &s->host_desc, sizeof(d)) != 0) {
+    s->host_desc = d;
+    HIPCHK(s, hipMemcpyAsync(s->d_desc, &s->host_desc, sizeof(ReplicaDesc), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    s->desc_valid = true;
+  }
+  if (g > 1) HIPCHK(s, hipMemsetAsync(s->p.bar_flags, 0, sizeof(unsigned) * 2 * 256, s->stream));
+  HIPCHK(s, launch_multi(s->tp, s->method, g, batch_lds_bytes(s->n), s->stream, s->d_desc, s->d_jobs, s->d_job_off,
+                         cnt, g > 1));
   s->cur ^= (cnt & 1);
   return SRMD_OK;
 }
@@ -622,13 +668,17 @@ srmd_status ensure_trace(srmd_system *s, long long cap) {
 struct srmd_batch {
   std::vector<srmd_system *> sys;
   std::vector<ReplicaDesc> host_desc;
-  std::vector<int> order;  // largest replica first
   ReplicaDesc *d_desc = nullptr;
-  int *d_order = nullptr;
+  std::vector<CoopJob> jobs;     // per workgroup, in replica order
+  std::vector<int> job_off;      // workgroup b runs jobs[job_off[b] .. job_off[b + 1])
+  std::vector<int> pieces;       // workgroups of each replica
+  CoopJob *d_jobs = nullptr;
+  int *d_job_off = nullptr;
+  int nwg = 0;
+  bool cooperative = false;      // some replica is split over several workgroups
   hipStream_t stream = nullptr;
-  int tp = 0, vb = 0, method = 0;
+  int tp = 0, method = 0;
   size_t lds = 0;
-  std::map<long long, hipGraphExec_t> graphs;
   std::string err;
 };
 
@@ -640,11 +690,6 @@ srmd_status bfail(srmd_batch *b, srmd_status st, const std::string &msg) {
   return st;
 }
 
-void drop_batch_graphs(srmd_batch *b) {
-  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
-}
-
 // Refresh the replica descriptors from the systems (constants, pointers, buffers).
 srmd_status batch_sync_desc(srmd_batch *b) {
   bool changed = false;
@@ -652,14 +697,9 @@ srmd_status batch_sync_desc(srmd_batch *b) {
     srmd_system *s = b->sys[r];
     srmd_status st = prepare(s);
     if (st != SRMD_OK) return bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
-    if (s->tp != b->tp || s->tp * s->ppb != b->vb || s->method != b->method)
-      return bfail(b, SRMD_EINVAL, "replicas must share the cutoff method and the launch shape (tp, ppb)");
-    ReplicaDesc d;
-    std::memset(&d, 0, sizeof(d));
-    d.c = s->c;
-    d.p = s->p;
-    d.cur = s->cur;
-    d.G = step_blocks(s);
+    if (s->tp != b->tp || s->method != b->method)
+      return bfail(b, SRMD_EINVAL, "replicas must share the cutoff method and the threads per particle");
+    const ReplicaDesc d = make_desc(s);
     if (std::memcmp(&d, &b->host_desc[r], sizeof(d)) != 0) {
       b->host_desc[r] = d;
       changed = true;
@@ -674,28 +714,124 @@ srmd_status batch_sync_desc(srmd_batch *b) {
   return SRMD_OK;
 }
 
-srmd_status batch_graph(srmd_batch *b, long long nsteps, hipGraphExec_t *out) {
-  auto it = b->graphs.find(nsteps);
-  if (it != b->graphs.end()) {
-    *out = it->second;
-    return SRMD_OK;
+// Longest-processing-time packing of items (loads) into nb bins: largest first, each
+// on the least-loaded bin that still takes a job.  Returns the largest bin load, or
+// a negative value if some item found no bin.
+double lpt_pack(const std::vector<std::pair<double, int>> &items, int nb, int max_jobs,
+                std::vector<std::vector<int>> *bins) {
+  std::vector<double> load((size_t)nb, 0.0);
+  if (bins) bins->assign((size_t)nb, {});
+  std::vector<int> count((size_t)nb, 0);
+  for (const auto &it : items) {
+    int best = -1;
+    for (int q = 0; q < nb; ++q)
+      if (count[(size_t)q] < max_jobs && (best < 0 || load[(size_t)q] < load[(size_t)best])) best = q;
+    if (best < 0) return -1.0;
+    load[(size_t)best] += it.first;
+    count[(size_t)best] += 1;
+    if (bins) (*bins)[(size_t)best].push_back(it.second);
   }
-  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("capture: ") + hipGetErrorString(e));
-  hipError_t le = launch_batch(b->tp, b->method, (int)b->sys.size(), b->lds, b->stream, b->d_desc, b->d_order,
-                               (int)nsteps, b->vb);
-  hipGraph_t g = nullptr;
-  e = hipStreamEndCapture(b->stream, &g);
-  if (le != hipSuccess || e != hipSuccess) {
-    if (g) (void)hipGraphDestroy(g);
-    return bfail(b, SRMD_EHIP, std::string("batched launch capture: ") + hipGetErrorString(le != hipSuccess ? le : e));
+  double m = 0.0;
+  for (double l : load) m = std::max(m, l);
+  return m;
+}
+
+// Distribute the replicas over at most W workgroups.  The work of a piece is taken as
+// its particle count plus a fixed cost per step (kJobCost for a whole replica,
+// kPieceCost for a piece of a split one: its grid barrier and its full position
+// load), in particle equivalents.  A replica is either whole, sharing a workgroup
+// with other whole replicas (run one after the other), or split into g_r > 1
+// pieces, each alone on its workgroup (its grid barriers then never wait behind
+// other work).  Starting from all replicas whole, the replica with the largest piece
+// is split one piece further while workgroups remain; the whole replicas go to the
+// remaining workgroups by longest-processing-time packing; the configuration with
+// the smallest largest load is kept.
+constexpr double kJobCost = 50.0, kPieceCost = 150.0;
+
+srmd_status batch_plan(srmd_batch *b, int W) {
+  const int R = (int)b->sys.size();
+  std::vector<int> g((size_t)R, 1), best_g;
+  double best = -1.0;
+  std::vector<int> order((size_t)R);
+  for (int r = 0; r < R; ++r) order[(size_t)r] = r;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->sys[(size_t)a]->n > b->sys[(size_t)c]->n; });
+  for (int it = 0; it <= 2 * W; ++it) {
+    int used = 0;
+    double split_max = 0.0;
+    std::vector<std::pair<double, int>> whole;
+    for (int r : order) {
+      const double n = b->sys[(size_t)r]->n;
+      if (g[(size_t)r] > 1) {
+        used += g[(size_t)r];
+        split_max = std::max(split_max, n / g[(size_t)r] + kPieceCost);
+      } else {
+        whole.push_back({n + kJobCost, r});
+      }
+    }
+    const int free_wg = W - used;
+    if (free_wg < 0 || (free_wg < 1 && !whole.empty())) break;
+    const double packed = whole.empty() ? 0.0 : lpt_pack(whole, free_wg, multi_max_jobs(), nullptr);
+    if (packed >= 0.0) {
+      const double mk = std::max(split_max, packed);
+      if (best < 0.0 || mk < best) {
+        best = mk;
+        best_g = g;
+      }
+    }
+    // split the replica with the largest piece one piece further
+    int rmax = -1;
+    double pmax = 0.0;
+    for (int r = 0; r < R; ++r) {
+      const srmd_system *s = b->sys[(size_t)r];
+      if (g[(size_t)r] >= std::min({step_blocks(s), 256, W})) continue;
+      const double piece = (double)s->n / g[(size_t)r];
+      if (piece > pmax) {
+        pmax = piece;
+        rmax = r;
+      }
+    }
+    if (rmax < 0) break;
+    g[(size_t)rmax] += 1;
   }
-  hipGraphExec_t ge;
-  e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(g);
-  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  b->graphs[nsteps] = ge;
-  *out = ge;
+  if (best < 0.0) return bfail(b, SRMD_EUNSUPPORTED, "too many replicas for the workgroups of one launch");
+  b->pieces = best_g;
+  std::vector<std::vector<CoopJob>> per;
+  std::vector<std::pair<double, int>> whole;
+  for (int r : order) {
+    if (best_g[(size_t)r] > 1)
+      for (int w = 0; w < best_g[(size_t)r]; ++w) per.push_back({CoopJob{r, w, best_g[(size_t)r], 0}});
+    else
+      whole.push_back({(double)b->sys[(size_t)r]->n + kJobCost, r});
+  }
+  if (!whole.empty()) {
+    std::vector<std::vector<int>> bins;
+    const int free_wg = W - (int)per.size();
+    lpt_pack(whole, std::min(free_wg, (int)whole.size()), multi_max_jobs(), &bins);
+    for (auto &bin : bins) {
+      std::vector<CoopJob> v;
+      for (int r : bin) v.push_back(CoopJob{r, 0, 1, 0});
+      std::sort(v.begin(), v.end(), [](const CoopJob &a, const CoopJob &c) { return a.rep < c.rep; });
+      if (!v.empty()) per.push_back(v);
+    }
+  }
+  b->jobs.clear();
+  b->job_off.assign(1, 0);
+  b->cooperative = false;
+  for (auto &v : per) {
+    for (const CoopJob &j : v) {
+      b->jobs.push_back(j);
+      b->cooperative = b->cooperative || j.g > 1;
+    }
+    b->job_off.push_back((int)b->jobs.size());
+  }
+  b->nwg = (int)per.size();
+  hipError_t e = hipMalloc(&b->d_jobs, sizeof(CoopJob) * b->jobs.size());
+  if (e == hipSuccess) e = hipMalloc(&b->d_job_off, sizeof(int) * b->job_off.size());
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(CoopJob) * b->jobs.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(b->d_job_off, b->job_off.data(), sizeof(int) * b->job_off.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return bfail(b, SRMD_ENOMEM, std::string("batch job tables: ") + hipGetErrorString(e));
   return SRMD_OK;
 }
 
@@ -1482,7 +1618,13 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
 }
 
 srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int32_t count) {
+  return srmd_batch_create_limited(out, systems, count, 0);
+}
+
+srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *systems, int32_t count,
+                                      int32_t max_workgroups) {
   if (!out) return bfail(nullptr, SRMD_EINVAL, "out is NULL");
+  if (max_workgroups < 0) return bfail(nullptr, SRMD_EINVAL, "max_workgroups must be >= 0");
   *out = nullptr;
   if (!systems || count < 1) return bfail(nullptr, SRMD_EINVAL, "need at least one system");
   for (int r = 0; r < count; ++r) {
@@ -1502,26 +1644,21 @@ srmd_status srmd_batch_create(srmd_batch **out, srmd_system *const *systems, int
   b->sys.assign(systems, systems + count);
   b->stream = systems[0]->stream;
   b->tp = systems[0]->tp;
-  b->vb = systems[0]->tp * systems[0]->ppb;
   b->method = systems[0]->method;
   int nmax = 0;
   for (auto *s : b->sys) nmax = std::max(nmax, s->n);
   b->lds = batch_lds_bytes(nmax);
   b->host_desc.assign((size_t)count, ReplicaDesc{});
   std::memset(b->host_desc.data(), 0xff, sizeof(ReplicaDesc) * (size_t)count);  // forces the first upload
-  b->order.resize((size_t)count);
-  for (int r = 0; r < count; ++r) b->order[(size_t)r] = r;
-  std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) { return b->sys[a]->n > b->sys[c]->n; });
-  if (hipMalloc(&b->d_desc, sizeof(ReplicaDesc) * (size_t)count) != hipSuccess ||
-      hipMalloc(&b->d_order, sizeof(int) * (size_t)count) != hipSuccess) {
+  if (hipMalloc(&b->d_desc, sizeof(ReplicaDesc) * (size_t)count) != hipSuccess) {
     srmd_batch_destroy(b);
     return bfail(nullptr, SRMD_ENOMEM, "batch descriptor allocation failed");
   }
-  if (hipMemcpy(b->d_order, b->order.data(), sizeof(int) * (size_t)count, hipMemcpyHostToDevice) != hipSuccess) {
-    srmd_batch_destroy(b);
-    return bfail(nullptr, SRMD_EHIP, "batch order upload failed");
-  }
   srmd_status st = batch_sync_desc(b);
+  int W = multi_max_groups(b->tp, b->method, b->lds);
+  if (max_workgroups > 0) W = std::min(W, max_workgroups);
+  if (st == SRMD_OK && W < 1) st = bfail(b, SRMD_EUNSUPPORTED, "the persistent kernel does not fit on the device");
+  if (st == SRMD_OK) st = batch_plan(b, W);
   if (st != SRMD_OK) {
     std::string m = b->err;
     srmd_batch_destroy(b);
@@ -1560,10 +1697,20 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
   }
   for (auto *s : b->sys)
     if (hipStreamSynchronize(s->stream) != hipSuccess) return bfail(b, SRMD_EHIP, "replica stream sync failed");
-  hipGraphExec_t ge;
-  st = batch_graph(b, nsteps, &ge);
-  if (st != SRMD_OK) return st;
-  hipError_t e = hipGraphLaunch(ge, b->stream);
+  hipError_t e = hipSuccess;
+  for (size_t r = 0; r < b->sys.size() && e == hipSuccess; ++r)
+    if (b->pieces[r] > 1) e = hipMemsetAsync(b->sys[r]->p.bar_flags, 0, sizeof(unsigned) * 2 * 256, b->stream);
+  for (long long done = 0; done < nsteps && e == hipSuccess;) {
+    // launches of kPersistChunk steps (an even count: every launch starts on the
+    // position buffer of the call start, which the descriptors hold)
+    const int cnt = (int)std::min<long long>(kPersistChunk, nsteps - done);
+    e = launch_multi(b->tp, b->method, b->nwg, b->lds, b->stream, b->d_desc, b->d_jobs, b->d_job_off, cnt,
+                     b->cooperative);
+    if (e == hipSuccess && done + cnt < nsteps)
+      for (size_t r = 0; r < b->sys.size() && e == hipSuccess; ++r)
+        if (b->pieces[r] > 1) e = hipMemsetAsync(b->sys[r]->p.bar_flags, 0, sizeof(unsigned) * 2 * 256, b->stream);
+    done += cnt;
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("batched run: ") + hipGetErrorString(e));
   // a replica whose list overflowed is restored to the call start, its capacity
@@ -1575,6 +1722,11 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
     Control h;
     st = read_ctl(s, &h);
     if (st != SRMD_OK) return bfail(b, st, s->err);
+    st = check_barrier(s, &h);
+    if (st != SRMD_OK) {
+      if (result == SRMD_OK) result = bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
+      continue;
+    }
     if (h.error & 2) {
       st = restore_and_regrow(s, s->cur);
       if (st == SRMD_OK) st = run_with_replay(s, nsteps, thermo_every, cap);
@@ -1591,9 +1743,9 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
 srmd_status srmd_batch_destroy(srmd_batch *b) {
   if (!b) return SRMD_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  drop_batch_graphs(b);
   if (b->d_desc) (void)hipFree(b->d_desc);
-  if (b->d_order) (void)hipFree(b->d_order);
+  if (b->d_jobs) (void)hipFree(b->d_jobs);
+  if (b->d_job_off) (void)hipFree(b->d_job_off);
   delete b;
   return SRMD_OK;
 }

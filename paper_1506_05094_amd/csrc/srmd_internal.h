@@ -119,14 +119,23 @@ struct SysPtrs {
   unsigned *bar_flags;  // arrival words of the persistent kernel's grid barrier (2 x 256)
 };
 
-// One replica of a batch: its constants, its device arrays (the arrays of the
-// single system it came from), the position buffer in use and its partial count.
+// One system of a persistent launch: its constants, its device arrays, the position
+// buffer in use at the launch and the shape of its single-system step launch.
 struct ReplicaDesc {
   SysConst c;
   SysPtrs p;
   int cur;
-  int G;        // blocks of the single-system step kernel (partials per step)
-  int pad[2];
+  int G;        // blocks of the single-system step kernel (block partials per step)
+  int vb;       // threads per block of that launch (a multiple of 64)
+  int pad;
+};
+
+// One workgroup's share of a persistent launch: piece w of g of system rep.  A
+// workgroup runs its jobs one after the other in every step; a system split over
+// g > 1 workgroups synchronises them with a grid barrier, and such a job is the
+// only job of its workgroups.
+struct CoopJob {
+  int rep, w, g, pad;
 };
 
 }  // namespace srmd

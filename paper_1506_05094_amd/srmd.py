@@ -95,6 +95,8 @@ def load():
         "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_set_persistent": (st, [sysp, ctypes.c_int32]),
         "srmd_batch_create": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
+        "srmd_batch_create_limited": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.c_int32, ctypes.c_int32]),
         "srmd_batch_step": (st, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
         "srmd_batch_destroy": (st, [ctypes.c_void_p]),
         "srmd_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
@@ -317,16 +319,17 @@ def _bcheck(status, bp=None):
 
 
 class Batch:
-    """Many systems advanced together by one persistent launch (handle to srmd_batch).
+    """Many systems advanced together by persistent launches (handle to srmd_batch).
 
-    The systems stay usable on their own; they must outlive the batch."""
+    max_workgroups > 0 caps the workgroups the batch uses.  The systems stay usable on
+    their own; they must outlive the batch."""
 
-    def __init__(self, systems):
+    def __init__(self, systems, max_workgroups=0):
         lib = load()
         self.systems = list(systems)
         arr = (ctypes.c_void_p * len(self.systems))(*[s._h.value for s in self.systems])
         h = ctypes.c_void_p()
-        _bcheck(lib.srmd_batch_create(ctypes.byref(h), arr, len(self.systems)))
+        _bcheck(lib.srmd_batch_create_limited(ctypes.byref(h), arr, len(self.systems), int(max_workgroups)))
         self._h = h
 
     def step(self, nsteps, thermo_every=0, trace_cap=None):
@@ -363,7 +366,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_autotune", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
             "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_set_persistent",
-            "srmd_batch_create",
+            "srmd_batch_create", "srmd_batch_create_limited",
             "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error"]
 
 

@@ -39,15 +39,21 @@ def _make(states, launch=(8, 32), dt=0.002):
     return out
 
 
-@pytest.mark.parametrize("launch", [(8, 32), (1, 256), (16, 16)])
-def test_batch_bitwise_equals_single(launch):
+@pytest.mark.parametrize("launch,groups", [((8, 32), 0), ((1, 256), 0), ((16, 16), 0), ((8, 32), 4), ((8, 32), 3),
+                                           ((8, 32), 1), ((4, 64), 2)])
+def test_batch_bitwise_equals_single(launch, groups):
+    """groups 0: the device's workgroups (every replica split over several); 4: the
+    largest replica split in two beside whole replicas packed two to a workgroup; 3
+    and 2: whole replicas packed; 1: every replica whole, one after the other on one
+    workgroup."""
     from paper_1506_05094_amd import srmd
+    print(f"batch launch={launch} max_workgroups={groups}", flush=True)
     states = _replica_states()
     single = _make(states, launch)
     batched = _make(states, launch)
     steps = 300
     tr_single = [s.step(steps, thermo_every=25) for s in single]
-    with srmd.Batch(batched) as b:
+    with srmd.Batch(batched, max_workgroups=groups) as b:
         tr_batch = b.step(steps, thermo_every=25)
     for r, (a, c) in enumerate(zip(single, batched)):
         sa, sc = a.get_state(), c.get_state()
@@ -108,7 +114,7 @@ def test_batch_rejects_unsupported():
     a = _make(states[:1], launch=(8, 32))
     b = _make(states[1:2], launch=(4, 64))
     with pytest.raises(srmd.SrmdError) as e:
-        srmd.Batch(a + b)
+        srmd.Batch(a + b)  # different threads per particle
     assert e.value.status == srmd.SRMD_EINVAL
     st = states[0]
     p64 = make_system(st, sig, eps, rc, "sf", precision="f64pos")
@@ -154,6 +160,32 @@ def test_batch_list_overflow_replays_like_single():
     with srmd.Batch(batched) as b:
         b.step(400)
     assert batched[1].stats()["n_max"] > n0
+    for x, y in zip(single, batched):
+        np.testing.assert_array_equal(x.get_state()["pos"], y.get_state()["pos"])
+        x.close()
+        y.close()
+
+
+def test_batch_mixed_block_sizes():
+    """Replicas may differ in particles per block (same threads per particle)."""
+    from paper_1506_05094_amd import srmd
+    states = _replica_states()[:3]
+    launches = [(8, 32), (8, 8), (8, 128)]
+    sig, eps, rc = gen.ka_params()
+
+    def make():
+        out = []
+        for st, (_, T, _), la in zip(states, REPLICAS, launches):
+            s = make_system(st, sig, eps, rc, "sf", launch=la)
+            s.set_integrator_nvt(0.002, T, 0.2)
+            out.append(s)
+        return out
+
+    single, batched = make(), make()
+    for s in single:
+        s.step(150)
+    with srmd.Batch(batched) as b:
+        b.step(150)
     for x, y in zip(single, batched):
         np.testing.assert_array_equal(x.get_state()["pos"], y.get_state()["pos"])
         x.close()
