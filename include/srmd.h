@@ -142,7 +142,11 @@ srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t lis
  * chains (the default unless srmd_autotune chose otherwise); groups = -1: persistent,
  * the library picks the number of workgroups; groups > 0: persistent with exactly
  * that many workgroups of 512 threads, all of which must fit on the device at once
- * (SRMD_EUNSUPPORTED at the next step otherwise).  The persistent kernel keeps all
+ * (SRMD_EUNSUPPORTED at the next step otherwise).  Without an explicit
+ * srmd_set_launch, the default tp of the persistent mode is twice that of the launch
+ * chains (64k lanes instead of 32k), so switching modes then changes the layout
+ * and rebuilds the list; at an explicit launch shape a switch keeps the list and the
+ * trajectory continues bit for bit.  The persistent kernel keeps all
  * positions of the system in every workgroup's LDS, separates the time steps by a
  * device-wide barrier and repeats the reductions of the launch chain in the same
  * order, so the trajectory is the same bit for bit at the same (tp, ppb).  It needs

@@ -218,9 +218,11 @@ __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const 
   }
 }
 
+// List entries of one lane taken together: about the entries a lane has at liquid
+// densities (90 per particle / TP), so that few slots of the last batch idle.
 template <int TP>
 struct Batch {
-  static constexpr int value = TP >= 8 ? 16 : 8;
+  static constexpr int value = TP <= 2 ? 16 : TP == 4 ? 8 : TP == 8 ? 16 : TP == 16 ? 8 : TP == 32 ? 4 : 2;
 };
 
 template <int TP>
@@ -316,17 +318,32 @@ __device__ __forceinline__ bool finite3(float a, float b, float c) {
   return __builtin_isfinite(a) && __builtin_isfinite(b) && __builtin_isfinite(c);
 }
 
-__device__ void list_tally(int cnt, Control *ctl) {
-  __shared__ int s_sum[16];
-  int v = cnt;
+// Per-block totals of a list build, one device-scope atomic each: entries kept,
+// the longest list (before capping) and the overflow flag.  Every thread of the
+// block calls it once.
+__device__ void list_tally(int cnt, int longest, int nmax, Control *ctl) {
+  __shared__ int s_sum[16], s_max[16];
+  int v = cnt, m = longest;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = v;
+  for (int o = 32; o > 0; o >>= 1) {
+    v += __shfl_xor(v, o, 64);
+    m = max(m, __shfl_xor(m, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_sum[threadIdx.x >> 6] = v;
+    s_max[threadIdx.x >> 6] = m;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long tot = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) tot += s_sum[k];
+    int mx = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) {
+      tot += s_sum[k];
+      mx = max(mx, s_max[k]);
+    }
     atomicAdd((unsigned long long *)&ctl->list_entries, (unsigned long long)tot);
+    atomicMax(&ctl->max_nbrs, mx);
+    if (mx > nmax) atomicOr(&ctl->error, 2);
   }
 }
 
@@ -559,13 +576,16 @@ constexpr int kListChunks = 4;   // 64-candidate chunks whose loads are in fligh
 // the candidate sequence, the runs are expanded into LDS, and the candidates are
 // tested 64 at a time; a ballot compacts the hits in candidate order, so the
 // list order is deterministic (stencil row order, then slot order).  cand is the
-// calling wave's LDS window of kWaveCand entries; returns the number of entries
-// kept (all lanes).
+// calling wave's LDS window of kWaveCand entries; tpos and cstart are the sorted
+// positions and the cell starts (in device memory, or copies in LDS); PLACE: also
+// copy slot t's sorted data into place.  Returns the number of entries kept (all
+// lanes) and raises longest to the list length before capping.
+template <bool PLACE>
 __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t, unsigned *cand,
-                             const float *s_cs2) {
+                             const float *s_cs2, const float4 *tpos, const unsigned *cstart, int &longest) {
   const int lane = threadIdx.x & 63;
-  const float4 r = p.t_pos[t];
-  if (lane == 0) place_sorted(p, cur, t, r);
+  const float4 r = tpos[t];
+  if (PLACE && lane == 0) place_sorted(p, cur, t, r);
   const int ti = ptype(r);
   int cx, cy, cz;
   cell_coords(r, c, cx, cy, cz);
@@ -585,8 +605,8 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
     const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
     if (x1 >= x0) {
       // clamped to [0, n]: a run never reaches outside the sorted arrays
-      const unsigned s1 = min(p.cell_start[rowbase + x1 + 1], (unsigned)c.n);
-      const unsigned s0 = min(p.cell_start[rowbase + x0], s1);
+      const unsigned s1 = min(cstart[rowbase + x1 + 1], (unsigned)c.n);
+      const unsigned s0 = min(cstart[rowbase + x0], s1);
       run_start = s0;
       run_len = s1 - s0;
     }
@@ -617,7 +637,7 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
       for (int cb = 0; cb < kListChunks; ++cb) {
         const unsigned qi = base + 64u * cb + (unsigned)lane;
         u[cb] = qi < wlen ? cand[qi] : (unsigned)t;
-        q[cb] = p.t_pos[u[cb]];
+        q[cb] = tpos[u[cb]];
       }
 #pragma unroll
       for (int cb = 0; cb < kListChunks; ++cb) {
@@ -638,11 +658,8 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   const int kept = min(count, nmax);
-  if (lane == 0) {
-    p.nnb[t] = kept;
-    if (count > nmax) atomicOr(&p.ctl->error, 2);
-    atomicMax(&p.ctl->max_nbrs, count);
-  }
+  if (lane == 0) p.nnb[t] = kept;
+  longest = max(longest, count);  // the caller reports the longest list and overflow
   return kept;
 }
 
@@ -655,12 +672,12 @@ __global__ __launch_bounds__(256) void k_list_wave(SysConst c, SysPtrs p, int cu
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
-  int kept = 0;
+  int kept = 0, longest = 0;
   if (t < c.n) {  // uniform across the wave
-    const int k = list_wave_one(c, p, cur, t, s_cand[wv], s_cs2);
+    const int k = list_wave_one<true>(c, p, cur, t, s_cand[wv], s_cs2, p.t_pos, p.cell_start, longest);
     if (lane == 0) kept = k;
   }
-  list_tally(kept, p.ctl);  // every thread of the block reaches this barrier once
+  list_tally(kept, longest, c.n_max, p.ctl);  // every thread of the block reaches this barrier once
 }
 
 constexpr int kThreadBatch = 16;  // candidate positions in flight per thread
@@ -679,7 +696,7 @@ __global__ __launch_bounds__(256) void k_list_thread(SysConst c, SysPtrs p, int 
   const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
   const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
   const int stride = gridDim.x * blockDim.x;
-  int kept_sum = 0;
+  int kept_sum = 0, longest = 0;
   for (int t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < c.n; t += stride) {
     const float4 r = p.t_pos[t];
     place_sorted(p, cur, t, r);
@@ -729,11 +746,10 @@ __global__ __launch_bounds__(256) void k_list_thread(SysConst c, SysPtrs p, int 
     }
     const int kept = min(count, nmax);
     p.nnb[t] = kept;
-    if (count > nmax) atomicOr(&p.ctl->error, 2);
-    atomicMax(&p.ctl->max_nbrs, count);
+    longest = max(longest, count);
     kept_sum += kept;
   }
-  list_tally(kept_sum, p.ctl);
+  list_tally(kept_sum, longest, nmax, p.ctl);
 }
 
 // ---------------------------------------------------------------- force only
@@ -929,9 +945,33 @@ __device__ __forceinline__ double xi_next(const SysConst &c, double xi, double k
 // End of a time step, by one thread, from the fully reduced partials a: the
 // thermodynamic record, the Nose-Hoover update, the step counter and the
 // displacement test that sets the rebuild flag.  Returns the flag.
-__device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockPartial &a) {
+// The control words finish_step reads, loaded together (one memory round trip).
+struct CtlView {
+  double xi, xi_int;
+  long long step, n_rebuilds, n_records, trace_cap;
+  int max_nbrs, thermo_every;
+};
+
+__device__ __forceinline__ CtlView load_ctl(const Control *ctl) {
+  CtlView v;
+  v.xi = ctl->xi;
+  v.xi_int = ctl->xi_int;
+  v.step = ctl->step;
+  v.n_rebuilds = ctl->n_rebuilds;
+  v.n_records = ctl->n_records;
+  v.trace_cap = ctl->trace_cap;
+  v.max_nbrs = ctl->max_nbrs;
+  v.thermo_every = ctl->thermo_every;
+  return v;
+}
+
+// End of a time step, by one thread, from the fully reduced partials a and the
+// control words v (loaded after the step's list build): the thermodynamic record,
+// the Nose-Hoover update, the step counter and the displacement test that sets the
+// rebuild flag.  Returns the flag.
+__device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockPartial &a, const CtlView &v) {
   Control *ctl = p.ctl;
-  const double xi = c.thermostat ? ctl->xi : 0.0;
+  const double xi = c.thermostat ? v.xi : 0.0;
   Thermo rec;
   rec.pe = a.pe;
   rec.ke = a.ke_int;
@@ -939,37 +979,35 @@ __device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockParti
   rec.temperature = 2.0 * a.ke_int / c.g;
   rec.pressure = (2.0 * a.ke_int / 3.0 + a.w) / c.volume;
   rec.xi = xi;
-  rec.xi_integral = ctl->xi_int;
+  rec.xi_integral = v.xi_int;
   rec.h_conserved = a.ke_int + a.pe;
   if (c.thermostat && c.inv_tau2 > 0.0)
-    rec.h_conserved += c.g * c.T0 * (xi * xi / (2.0 * c.inv_tau2) + ctl->xi_int);
+    rec.h_conserved += c.g * c.T0 * (xi * xi / (2.0 * c.inv_tau2) + v.xi_int);
   rec.ke_half = a.ke_half;
-  rec.step = ctl->step;
-  rec.n_rebuilds = ctl->n_rebuilds;
-  rec.max_nbrs = ctl->max_nbrs;
+  rec.step = v.step;
+  rec.n_rebuilds = v.n_rebuilds;
+  rec.max_nbrs = v.max_nbrs;
   rec.reserved = 0;
   *p.thermo = rec;
-  if (ctl->thermo_every > 0 && (ctl->step % ctl->thermo_every) == 0 && ctl->n_records < ctl->trace_cap) {
-    p.trace[ctl->n_records] = rec;
-    ctl->n_records += 1;
+  if (v.thermo_every > 0 && (v.step % v.thermo_every) == 0 && v.n_records < v.trace_cap) {
+    p.trace[v.n_records] = rec;
+    ctl->n_records = v.n_records + 1;
   }
   if (c.thermostat) {
     const double xn = xi_next(c, xi, a.ke_half);
-    ctl->xi_int += c.dtd * (xi + xn) * 0.5;
+    ctl->xi_int = v.xi_int + c.dtd * (xi + xn) * 0.5;
     ctl->xi = xn;
   }
-  ctl->step += 1;
+  ctl->step = v.step + 1;
   if (a.t1 > a.t0) {
     ctl->prof_ticks += a.t1 - a.t0;
     ctl->prof_count += 1;
   }
   const int rebuild = (a.disp2 > c.half_skin2) ? 1 : 0;
   ctl->rebuild = rebuild;
-  if (a.nonfinite) ctl->error |= 1;
+  if (a.nonfinite) atomicOr(&ctl->error, 1);
   return rebuild;
 }
-
-
 
 // One workgroup after the step (MODE 0) or force-only (MODE 1) kernel: fixed-order
 // float64 reduction of the G block partials (each thread sums its blocks in index
@@ -1014,7 +1052,7 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
       th->step = ctl->step;
       if (a.nonfinite) ctl->error |= 1;
     } else {
-      rebuild = finish_step(c, p, a);
+      rebuild = finish_step(c, p, a, load_ctl(ctl));
     }
     s_rebuild = rebuild;
   }
@@ -1077,6 +1115,7 @@ constexpr int kBatchThreads = 512;  // threads of a persistent workgroup
 constexpr int kBatchWaves = kBatchThreads / 64;
 constexpr int kCoopMaxGroups = 256;  // workgroups of one system (arrival words per parity)
 constexpr int kMaxJobs = 64;         // jobs of one workgroup
+constexpr int kLdsUnits = 64;        // wave partials of one piece kept in LDS (else in memory)
 
 // Grid-wide barrier k (k = 1, 2, ... in one launch) of the G workgroups that share
 // one system, over that system's array of arrival words (one per workgroup and
@@ -1088,12 +1127,12 @@ constexpr int kMaxJobs = 64;         // jobs of one workgroup
 // barrier k + 2 before every piece has left barrier k.  The wait is bounded (about
 // one second of the 100 MHz device clock): on time-out the workgroup sets error bit 2
 // and the kernel ends instead of hanging.  Release / acquire fences at agent scope
-// order every store before the barrier against every load after it.  The release is
-// issued once per workgroup, after each wave has waited for its own stores to
-// complete (the L2 write-back acts on the whole cache), and the arrival store waits
-// for the write-back to complete; the acquire is issued by the polling wave and,
-// after the workgroup barrier, by every other wave, since an invalidate orders only
-// the issuing wave's later loads.  With G = 1 the barrier is the workgroup barrier.
+// order every store before the barrier against every load after it, once per
+// workgroup: the release after each wave has waited for its own stores to complete
+// (the L2 write-back acts on the whole cache), with the arrival store waiting for the
+// write-back to complete; the acquire by the polling wave, whose invalidate of the
+// compute unit's L1 and of the L2 precedes, through the workgroup barrier, every
+// later load of the other waves.  With G = 1 the barrier is the workgroup barrier.
 __device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsigned w, unsigned k, int bit,
                                              Control *ctl, int *s_ok, int *s_any) {
   if (G == 1) {
@@ -1141,9 +1180,6 @@ __device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsign
     }
   }
   __syncthreads();
-  // the other waves acquire for themselves: an invalidate orders only the issuing
-  // wave's later loads, and the workgroup barrier does not wait for it to complete
-  if (threadIdx.x >= 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_ok != 0;
 }
 
@@ -1185,13 +1221,14 @@ __device__ __forceinline__ void fill_positions(float4 *dst, const float4 *src, i
 template <int TP, int METHOD>
 __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__restrict__ reps,
                                                          const CoopJob *__restrict__ jobs,
-                                                         const int *__restrict__ job_off, int nsteps) {
+                                                         const int *__restrict__ job_off, int nsteps,
+                                                         int lds_bytes) {
   extern __shared__ float4 s_dyn[];
   __shared__ SharedPairs sp;
   __shared__ BlockPartial s_waves[16];
+  __shared__ BlockPartial s_wp[kLdsUnits];
   __shared__ float s_cs2[kMaxPairs];
   __shared__ int s_ok, s_any, s_bit;
-  __shared__ int s_kept[kBatchWaves];
   __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs];
   __shared__ unsigned s_k[kMaxJobs];
   __shared__ double s_xi[kMaxJobs];
@@ -1210,6 +1247,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
     }
     if (!coop_barrier(R.p.bar_flags, J.g, J.w, 1u, 0, R.p.ctl, &s_ok, &s_any)) return;
   }
+  bool prefilled = false;  // the positions of this step are already in LDS
   for (int step = 0; step < nsteps; ++step) {
     for (int j = 0; j < nj; ++j) {
       const CoopJob J = jobs[j0 + j];
@@ -1229,20 +1267,34 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       if (tid == 0) s_bit = 0;
       __syncthreads();
       if (rebuild) {  // the spatial sort has been done (host request or end of step)
+        // the sorted positions and the cell starts go to LDS when they fit beside the
+        // candidate windows, so the list build reads no device memory but its own list
+        const int cs_words = (c.ncell + 1 + 3) & ~3;
+        const bool in_lds = 16 * c.n + 4 * cs_words + 4 * kBatchWaves * kWaveCand <= lds_bytes;
+        const float4 *tpos = p.t_pos;
+        const unsigned *cstart = p.cell_start;
         unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
-        int kept = 0;
-        for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves)
-          kept += list_wave_one(c, p, cur, t, cand, s_cs2);
-        if (lane == 0) s_kept[wv] = kept;
-        __syncthreads();
-        if (tid == 0) {
-          long long tot = 0;
-          for (int q = 0; q < kBatchWaves; ++q) tot += s_kept[q];
-          atomicAdd((unsigned long long *)&p.ctl->list_entries, (unsigned long long)tot);
+        if (in_lds) {
+          fill_positions(s_dyn, p.t_pos, c.n);
+          unsigned *s_cs = reinterpret_cast<unsigned *>(s_dyn + c.n);
+          for (int q = tid; q <= c.ncell; q += kBatchThreads) s_cs[q] = gload((const int *)p.cell_start, q);
+          __syncthreads();
+          tpos = s_dyn;
+          cstart = s_cs;
+          cand = s_cs + cs_words + wv * kWaveCand;
         }
+        // this piece's slots of the sorted arrays into place, coalesced (the list
+        // build below only reads the sorted copies)
+        for (int t = J.w * kBatchThreads + tid; t < c.n; t += J.g * kBatchThreads)
+          place_sorted(p, cur, t, gload(p.t_pos, t));
+        int kept = 0, longest = 0;
+        for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves)
+          kept += list_wave_one<false>(c, p, cur, t, cand, s_cs2, tpos, cstart, longest);
+        list_tally(lane == 0 ? kept : 0, longest, c.n_max, p.ctl);
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
-      fill_positions(s_dyn, p.pos[cur], c.n);
+      if (!prefilled) fill_positions(s_dyn, p.pos[cur], c.n);
+      prefilled = false;
       __syncthreads();
       // this piece's wave units: unit q is wave q % wpv of owned block q / wpv; the
       // waves run their units without waiting for each other, and the wave partials
@@ -1252,6 +1304,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       // block partials alternate between two sets by step parity: a piece may write
       // the next step's partials while a slower piece still reads this step's
       BlockPartial *bpart = p.part + (step & 1) * G;
+      // wave partials: in LDS (indexed by q) when this piece has few units, else in
+      // the system's partials buffer (indexed by the unit)
+      const bool wp_lds = my_units <= kLdsUnits;
       BlockPartial *wpart = p.part + 2 * G;
       for (int q = wv; q < my_units; q += kBatchWaves) {
         const int b = J.w + (q / wpv) * J.g;
@@ -1282,7 +1337,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
           integrate_one<0>(c, p, cur, i, pi, vo, im, l0, kc, 0.0, 0.0, 0.0, xi, fx, fy, fz, uu, w, v);
         wave_reduce(v);
         if (lane == 0) {
-          wpart[u] = v;
+          if (wp_lds)
+            s_wp[q] = v;
+          else
+            wpart[u] = v;
           if (v.disp2 > c.half_skin2) s_bit = 1;
         }
       }
@@ -1290,18 +1348,35 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       // owned block partials: each block's waves in index order (as group_reduce)
       for (int r = tid; r < my_blocks; r += kBatchThreads) {
         const int b = J.w + r * J.g;
-        BlockPartial a = wpart[b * wpv];
-        for (int q = 1; q < wpv; ++q) fold(a, wpart[b * wpv + q]);
+        BlockPartial a = wp_lds ? s_wp[r * wpv] : wpart[b * wpv];
+        for (int q = 1; q < wpv; ++q) fold(a, wp_lds ? s_wp[r * wpv + q] : wpart[b * wpv + q]);
         bpart[b] = a;
       }
       if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, s_bit, p.ctl, &s_ok, &s_any)) return;
+      // piece 0 loads the control words now, beside the partials of the reduction
+      CtlView cv{};
+      if (J.w == 0 && tid == 0) cv = load_ctl(p.ctl);
       // every piece: the reduction of k_finish (1024 threads, each thread here
-      // standing in for threads tid and tid + 512 of that workgroup)
+      // standing in for threads tid and tid + 512 of that workgroup); with at most
+      // 1024 blocks each thread's partials are loaded first, so that the positions
+      // of the next step (loaded now when no rebuild is due and this is the
+      // workgroup's only job) arrive in the same round trip
       BlockPartial a0 = zero_partial(), a1 = zero_partial();
-      for (int b = tid; b < G; b += 1024) fold(a0, bpart[b]);
-      for (int b = tid + kBatchThreads; b < G; b += 1024) fold(a1, bpart[b]);
-      wave_reduce(a0);
-      wave_reduce(a1);
+      if (G <= 1024) {
+        BlockPartial q0 = zero_partial(), q1 = zero_partial();
+        if (tid < G) q0 = bpart[tid];
+        if (tid + kBatchThreads < G) q1 = bpart[tid + kBatchThreads];
+        prefilled = nj == 1 && !s_any && step + 1 < nsteps;
+        if (prefilled) fill_positions(s_dyn, p.pos[cur ^ 1], c.n);
+        if (tid < G) fold(a0, q0);
+        if (tid + kBatchThreads < G) fold(a1, q1);
+      } else {
+        for (int b = tid; b < G; b += 1024) fold(a0, bpart[b]);
+        for (int b = tid + kBatchThreads; b < G; b += 1024) fold(a1, bpart[b]);
+      }
+      // a wave with no blocks holds zero partials, whose butterfly gives zeros again
+      if (wv * 64 < G) wave_reduce(a0);
+      if (kBatchThreads + wv * 64 < G) wave_reduce(a1);
       if (lane == 0) {
         s_waves[wv] = a0;
         s_waves[wv + kBatchWaves] = a1;
@@ -1312,7 +1387,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         for (int q = 1; q < 16; ++q) fold(a, s_waves[q]);
         a.t0 = 0ull;
         a.t1 = 0ull;
-        if (J.w == 0) finish_step(c, p, a);  // the one writer of the control block
+        if (J.w == 0) finish_step(c, p, a, cv);  // the one writer of the control block
         if (c.thermostat) s_xi[j] = xi_next(c, xi, a.ke_half);
         s_rebuild[j] = s_any;  // = (max displacement^2 > (skin/2)^2), as finish_step decides
       }
@@ -1342,7 +1417,8 @@ static hipError_t launch_multi_tp(int method, int nwg, size_t lds, hipStream_t s
                                  : (const void *)k_multi<TP, 2>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  void *args[] = {&reps, &jobs, &job_off, &nsteps};
+  int lds_bytes = (int)lds;
+  void *args[] = {&reps, &jobs, &job_off, &nsteps, &lds_bytes};
   if (cooperative) return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(kBatchThreads), args, (unsigned)lds, st);
   return hipLaunchKernel(fn, dim3(nwg), dim3(kBatchThreads), args, lds, st);
 }
@@ -1385,11 +1461,17 @@ int multi_max_groups(int tp, int method, size_t lds) {
 
 int multi_max_jobs() { return kMaxJobs; }
 
+// Dynamic LDS of the persistent kernel: the positions of a step, the sort's scratch,
+// and where it fits in 150 KiB, the list build's copies of the sorted positions and
+// the cell starts beside the candidate windows (up to 4096 cells counted).
 size_t batch_lds_bytes(int n_max_particles) {
   const size_t pos = 16 * (size_t)n_max_particles;
   const size_t scratch = 4 * (size_t)(kSmallCells + 1 + kSmallN);
   const size_t cand = 4 * (size_t)(kBatchWaves * kWaveCand);
-  return std::max(pos, std::max(scratch, cand));
+  const size_t listing = pos + 4 * (size_t)(4096 + 4) + cand;
+  size_t b = std::max(pos, std::max(scratch, cand));
+  if (listing <= 150 * 1024) b = std::max(b, listing);
+  return b;
 }
 
 int batch_max_particles() { return kSmallN; }

@@ -190,8 +190,9 @@ int pow2_at_least(int x) {
   return p;
 }
 
-// Default threads per particle: enough lanes in flight for the chip (about 32k),
-// the MI355X version of the paper's rule that N * t_p should exceed the core count
+// Default threads per particle: enough lanes in flight for the chip (about 32k, or
+// 64k for the persistent kernel, which then spreads over more compute units), the
+// MI355X version of the paper's rule that N * t_p should exceed the core count
 // several times over (section 8, autotuner choices).
 void launch_of(const srmd_system *s, int *tp_out, int *ppb_out) {
   int tp = s->tp_req, ppb = s->ppb_req;
@@ -200,7 +201,9 @@ void launch_of(const srmd_system *s, int *tp_out, int *ppb_out) {
       tp = s->tp_tuned;
       ppb = s->ppb_tuned;
     } else {
-      tp = std::min(32, pow2_at_least(std::max(1, 32768 / std::max(1, s->n))));
+      const bool persistent = s->persist_set ? s->persist_req != 0 : s->persist_tuned != 0;
+      const int lanes = persistent ? 65536 : 32768;
+      tp = std::min(32, pow2_at_least(std::max(1, lanes / std::max(1, s->n))));
       ppb = 0;
     }
   }
@@ -1105,9 +1108,15 @@ srmd_status srmd_set_persistent(srmd_system *s, int32_t groups) {
   if (groups < -1 || groups > 4096) return fail(s, SRMD_EINVAL, "groups must be -1, 0 or 1..4096");
   s->persist_req = groups;
   s->persist_set = true;
-  // the layout does not change (the partials buffer always has room for the
-  // persistent kernel), so a switch keeps the list and the trajectory continues
-  if (!s->dirty) resolve_persistent(s);
+  int tp, ppb;
+  launch_of(s, &tp, &ppb);
+  if (tp != s->tp || ppb != s->ppb) {
+    s->dirty = true;  // the default launch shape differs between the modes
+  } else if (!s->dirty) {
+    // same layout (the partials buffer always has room for the persistent kernel):
+    // the list is kept and the trajectory continues
+    resolve_persistent(s);
+  }
   return SRMD_OK;
 }
 
