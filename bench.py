@@ -189,12 +189,100 @@ def run_replicas(args):
     print(json.dumps(out), flush=True)
 
 
+def run_precision(args):
+    """Precision study: LJ N = 32768 (melting FCC, config 0 parameters), NVE dt 0.005,
+    float32 / compensated float32 / float64 positions.  Energy drift per particle per
+    step from a linear fit of H/N over the run; force error against the FP64 oracle
+    on a sample of particles at a few frames."""
+    import torch
+
+    import oracle
+    from paper_1506_05094_amd import srmd
+    from workloads import generators as gen
+
+    state = gen.config4_state()
+    sig, eps, rc = gen.lj_params()
+    stream = torch.cuda.current_stream().cuda_stream
+    rng = np.random.default_rng(4)
+    sample = np.sort(rng.choice(state.n, size=256, replace=False)).astype(np.int32)
+    frames = max(1, args.frames)
+    every = max(1, args.steps // 100)
+    out = {"metric": METRIC, "workload": "precision study", "n": state.n, "steps": args.steps, "dt": 0.005,
+           "variants": {}}
+    for prec in ("f32", "f32_kahan", "f64pos"):
+        s = srmd.system_from_state(state, sig, eps, rc, "sp", skin=0.3, precision=prec, stream=stream)
+        if args.tp:
+            s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
+        s.set_integrator_nve(0.005)
+        h, ferr = [], []
+        chunk = args.steps // frames
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(frames):
+            tr = s.step(chunk, thermo_every=every)
+            h.append(tr["h_conserved"] / state.n)
+            s.compute_forces()
+            st = s.get_state()
+            F = st["force"][sample].astype(np.float64)
+            Fr, _, _, _, _ = oracle.forces_f32(st["pos"], state.types, state.box, sig, eps, rc, "sp", sel=sample)
+            ferr.append(float(np.abs(F - Fr).max() / np.abs(Fr).max()))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        h = np.concatenate(h)
+        x = np.arange(h.size) * every
+        slope = float(np.polyfit(x, h, 1)[0])
+        out["variants"][prec] = {"drift_per_particle_per_step": slope, "h0_per_particle": float(h[0]),
+                                 "h_range_per_particle": float(np.ptp(h)), "force_error_max_norm": ferr,
+                                 "steps_per_s_incl_checks": args.steps / wall}
+        log(f"{prec}: drift {slope:.3e} per particle per step, H/N range {np.ptp(h):.3e}, force errors {ferr}")
+        s.close()
+    print(json.dumps(out), flush=True)
+
+
+def run_sweep(args):
+    """Size sweep of the LJ fluid (config 0 parameters): per N, the autotuner's layout,
+    then 2000 timed NVE steps at dt 0.005."""
+    import torch
+
+    from paper_1506_05094_amd import srmd
+    from workloads import generators as gen
+
+    sig, eps, rc = gen.lj_params()
+    stream = torch.cuda.current_stream().cuda_stream
+    rows = []
+    for n in [int(v) for v in args.sizes.split(",")]:
+        state = gen.config2_state(n) if n != 864 else gen.config0_state()
+        s = srmd.system_from_state(state, sig, eps, rc, "sp", skin=0.3, stream=stream)
+        s.set_integrator_nve(0.005)
+        s.step(100)
+        tp, ppb = s.autotune(args.tune_steps)
+        groups = s.stats()["persistent_groups"]
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(args.steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = s.stats()
+        row = {"n": state.n, "tp": tp, "ppb": ppb, "mode": "persistent" if groups else "chain", "groups": groups,
+               "steps_per_s": args.steps / wall, "particle_steps_per_s": state.n * args.steps / wall,
+               "rebuilds": st["n_rebuilds"]}
+        log(row)
+        rows.append(row)
+        s.close()
+    print(json.dumps({"metric": METRIC, "workload": "LJ size sweep (autotuned)", "steps": args.steps, "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "ka-replicas"])
+    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "ka-replicas", "precision", "sweep"])
+    ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
+    ap.add_argument("--sizes", default="1000,4000,16000,64000,256000,1024000", help="N values of the size sweep")
+    ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial in the size sweep")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--baseline-steps", type=int, default=1000)
     ap.add_argument("--n", type=int, default=864, help="particles for --workload lj")
@@ -233,6 +321,12 @@ def main():
         del src, dst
     if args.workload == "ka-replicas":
         run_replicas(args)
+        return
+    if args.workload == "precision":
+        run_precision(args)
+        return
+    if args.workload == "sweep":
+        run_sweep(args)
         return
     state, params, method, integ, desc = workload(args.workload, args.n)
     sig, eps, rc = params
