@@ -81,6 +81,21 @@ def test_group_count_does_not_change_result(groups):
     b.close()
 
 
+@pytest.mark.parametrize("launch", [(8, 32), (2, 128)])
+def test_largest_system_lists_built_from_device_memory(launch):
+    """N = 8192, the largest the persistent kernel takes: its positions fill the LDS, so
+    the list build reads the sorted arrays from device memory instead of LDS copies."""
+    print(f"persistent N=8192 launch={launch}", flush=True)
+    a = _ka(8192, 0.6, 31, launch, 0)
+    b = _ka(8192, 0.6, 31, launch, -1)
+    tra = a.step(120, thermo_every=10)
+    trb = b.step(120, thermo_every=10)
+    assert a.thermo()["n_rebuilds"] > 2
+    _same(a, b, tra, trb, f"N=8192 {launch}")
+    a.close()
+    b.close()
+
+
 def test_mode_switches_mid_run_and_odd_chunks():
     n, T, seed = CASES[0]
     a = _ka(n, T, seed, (8, 32), 0)

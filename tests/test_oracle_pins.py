@@ -417,3 +417,29 @@ def test_initial_states(oracle_lib):
     assert np.all(np.abs(s.pos) <= s.box[0] / 2)
     c0 = gen.config0_state()
     assert c0.n == 864 and c0.box[0] == pytest.approx(10.0776, abs=1e-4)
+
+
+def _paper_values():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")) as f:
+        return json.load(f)
+
+
+def test_pair_count_matches_paper_molten_salt_neighbour_count(oracle_lib):
+    """Section 9 prints ~330 neighbours per particle at density 0.3677 within 6.0 sigma.
+    The oracle's list (r^2 < (r_c + s)^2, skin 0) on a uniform random configuration at
+    that density must count about that many; a dropped square, a wrong minimum image or
+    a wrong radius would miss it by far more than the 3 % allowed for the paper's
+    rounding (the ideal-gas mean is 4/3 pi 6^3 0.3677 = 332.7)."""
+    v = _paper_values()["molten_salt_neighbours"]
+    n = 2000
+    L = (n / v["density"]) ** (1.0 / 3.0)
+    rng = np.random.default_rng(9)
+    pos = rng.uniform(-L / 2, L / 2, size=(n, 3)).astype(np.float32)
+    types = np.zeros(n, np.int32)
+    cs2, _ = oracle.cut_tables(np.array([[v["cutoff"]]]), 0.0)
+    pairs = oracle.pair_set(pos, types, np.array([L, L, L]), cs2)
+    per_particle = len(pairs) / n
+    assert abs(per_particle - v["neighbours_per_particle"]) <= 0.03 * v["neighbours_per_particle"], per_particle
+
