@@ -131,7 +131,9 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
  * sort_mode: 0 automatic, 1 the spatial sort in one workgroup's LDS (systems of up
  * to 8192 particles and 8192 cells; larger ones fall back to 2), 2 the multi-kernel
  * counting sort.  list_mode: 0 automatic, 1 one wave per particle, 2 one thread per
- * particle (the paper's section 7 layout). */
+ * particle (the paper's section 7 layout), 3 one wave per cell (the particles of a
+ * cell share one load of their stencil's candidates).  The persistent kernel always
+ * builds one wave per particle. */
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
 
 /* Run the steps of a small system as persistent launches (one launch per 500

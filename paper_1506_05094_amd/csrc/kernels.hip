@@ -369,34 +369,71 @@ __device__ __forceinline__ void begin_build(Control *ctl) {
   ctl->n_rebuilds += 1;
 }
 
+// Cell of every particle (section 7 step 1), its arrival slot in the cell, and the
+// particle count of every tile of 2^shift cells; lanes of a wave that fall in the
+// same tile add to it once.
 __global__ __launch_bounds__(256) void k_bin(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x) {
-    const float4 r = p.pos[cur][s];
-    int cx, cy, cz;
-    cell_coords(r, c, cx, cy, cz);
-    const unsigned cell = (unsigned)((cz * c.nc[1] + cy) * c.nc[0] + cx);
-    p.cell_of[s] = cell;
-    p.slot_in_cell[s] = atomicAdd(&p.cell_count[cell], 1u);
+  const int shift = scan_tile_shift(c.ncell);
+  const int lane = threadIdx.x & 63;
+  for (int s0 = blockIdx.x * blockDim.x; s0 < c.n; s0 += gridDim.x * blockDim.x) {  // uniform per block
+    const int s = s0 + threadIdx.x;
+    const bool act = s < c.n;
+    unsigned tile = 0u;
+    if (act) {
+      const float4 r = p.pos[cur][s];
+      int cx, cy, cz;
+      cell_coords(r, c, cx, cy, cz);
+      const unsigned cell = (unsigned)((cz * c.nc[1] + cy) * c.nc[0] + cx);
+      p.cell_of[s] = cell;
+      p.slot_in_cell[s] = atomicAdd(&p.cell_count[cell], 1u);
+      tile = cell >> shift;
+    }
+    unsigned long long pend = __ballot(act);
+    while (pend) {
+      const int lead = __ffsll((long long)pend) - 1;
+      const unsigned lt = (unsigned)__builtin_amdgcn_readlane((int)tile, lead);
+      const unsigned long long same = __ballot(act && tile == lt);
+      if (lane == lead) atomicAdd(&p.tile_count[lt], (unsigned)__popcll(same));
+      pend &= ~same;
+    }
   }
 }
 
-// Exclusive scan of the cell histogram by one block, in tiles of blockDim.x
-// cells; clears the histogram for the next build.
-__global__ __launch_bounds__(1024) void k_scan(SysConst c, SysPtrs p) {
+// Exclusive scan of the cell histogram into cell_start (section 7 step 2), one
+// workgroup per tile of 2^shift cells: the workgroup adds the counts of the tiles
+// before its own, then scans its tile 1024 cells at a time (4 per thread).  The
+// histogram is cleared for the next build; the tile counts are cleared by k_scatter.
+__global__ __launch_bounds__(256) void k_scan(SysConst c, SysPtrs p) {
   if (p.ctl->rebuild == 0) return;
-  __shared__ unsigned s_w[16];
-  __shared__ unsigned s_carry;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
-  if (t == 0) {
-    s_carry = 0;
-    begin_build(p.ctl);
-  }
+  __shared__ unsigned s_w[4];
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  const int b = blockIdx.x, shift = scan_tile_shift(c.ncell);
+  if (b == 0 && t == 0) begin_build(p.ctl);
+  unsigned pre = 0;
+  for (int k = t; k < b; k += 256) pre += p.tile_count[k];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
+  if (lane == 0) s_w[wv] = pre;
   __syncthreads();
-  for (int base = 0; base < c.ncell; base += blockDim.x) {
-    const int idx = base + t;
-    const unsigned v = idx < c.ncell ? p.cell_count[idx] : 0u;
-    unsigned x = v;
+  unsigned carry = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  __syncthreads();
+  const int beg = b << shift, end = min(c.ncell, (b + 1) << shift);
+  for (int base = beg; base < end; base += 1024) {
+    const int i0 = base + 4 * t;
+    unsigned v[4];
+    if (i0 + 3 < end) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(p.cell_count + i0);
+      v[0] = q.x;
+      v[1] = q.y;
+      v[2] = q.z;
+      v[3] = q.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = i0 + k < end ? p.cell_count[i0 + k] : 0u;
+    }
+    const unsigned sum = v[0] + v[1] + v[2] + v[3];
+    unsigned x = sum;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const unsigned y = __shfl_up(x, o, 64);
@@ -406,24 +443,36 @@ __global__ __launch_bounds__(1024) void k_scan(SysConst c, SysPtrs p) {
     __syncthreads();
     unsigned wbase = 0;
     for (int k = 0; k < wv; ++k) wbase += s_w[k];
-    const unsigned excl = s_carry + wbase + x - v;
-    if (idx < c.ncell) {
-      p.cell_start[idx] = excl;
-      p.cell_count[idx] = 0u;
+    const unsigned total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    unsigned e = carry + wbase + x - sum;
+    if (i0 + 3 < end) {
+      uint4 o4;
+      o4.x = e;
+      o4.y = e + v[0];
+      o4.z = e + v[0] + v[1];
+      o4.w = e + v[0] + v[1] + v[2];
+      *reinterpret_cast<uint4 *>(p.cell_start + i0) = o4;
+      *reinterpret_cast<uint4 *>(p.cell_count + i0) = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (i0 + k < end) {
+          p.cell_start[i0 + k] = e;
+          p.cell_count[i0 + k] = 0u;
+        }
+        e += v[k];
+      }
     }
-    __syncthreads();
-    if (t == 0) {
-      unsigned tot = 0;
-      for (int k = 0; k < nw; ++k) tot += s_w[k];
-      s_carry += tot;
-    }
-    __syncthreads();
+    carry += total;
+    __syncthreads();  // s_w is rewritten by the next chunk
   }
-  if (t == 0) p.cell_start[c.ncell] = s_carry;
+  if (b == gridDim.x - 1 && t == 0) p.cell_start[c.ncell] = carry;
 }
 
 __global__ __launch_bounds__(256) void k_scatter(SysConst c, SysPtrs p) {
   if (p.ctl->rebuild == 0) return;
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < scan_tiles(c.ncell); k += blockDim.x) p.tile_count[k] = 0u;
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x)
     p.perm_tmp[p.cell_start[p.cell_of[s]] + p.slot_in_cell[s]] = (unsigned)s;
 }
@@ -567,6 +616,48 @@ bool small_sort_fits(int n, int ncell) { return n <= kSmallN && ncell <= kSmallC
 constexpr int kWaveCand = 1024;  // candidates per window of the wave builder
 constexpr int kListChunks = 4;   // 64-candidate chunks whose loads are in flight together
 
+// The stencil of cell (cx, cy, cz) as runs of sorted slots: 5x5x5 cells (every cell
+// along an axis with fewer than 5), cut into rows of consecutive x cells; as
+// particles are sorted by cell index, each row is one or two contiguous slot runs.
+// Lane s of the calling wave gets run s (row s / 2; the second run of a row only
+// when its x window wraps round the box) in the order of the rows, its offset excl
+// in the concatenated candidate sequence and the sequence length total.
+__device__ __forceinline__ void stencil_runs(const SysConst &c, int cx, int cy, int cz, const unsigned *cstart,
+                                             unsigned &run_start, unsigned &run_len, unsigned &excl,
+                                             unsigned &total) {
+  const int lane = threadIdx.x & 63;
+  const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
+  const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
+  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
+  int a0, a1, b0, b1;
+  row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
+  run_start = 0;
+  run_len = 0;
+  const int row = lane >> 1;
+  if (row < ny_eff * nz_eff) {
+    const int oy = row % ny_eff, oz = row / ny_eff;
+    const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
+    const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
+    const int rowbase = (zz * ny + yy) * nx;
+    const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
+    if (x1 >= x0) {
+      // clamped to [0, n]: a run never reaches outside the sorted arrays
+      const unsigned s1 = min(cstart[rowbase + x1 + 1], (unsigned)c.n);
+      const unsigned s0 = min(cstart[rowbase + x0], s1);
+      run_start = s0;
+      run_len = s1 - s0;
+    }
+  }
+  unsigned incl = run_len;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  excl = incl - run_len;
+  total = __shfl(incl, 63, 64);
+}
+
 // Verlet list of particle t (sorted slot), one wave per particle; for small systems,
 // where one thread per particle (section 7) leaves the chip idle and every thread
 // waits on a long chain of dependent loads.  The 5x5x5 stencil (every cell along
@@ -589,36 +680,8 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
   const int ti = ptype(r);
   int cx, cy, cz;
   cell_coords(r, c, cx, cy, cz);
-  const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
-  const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
-  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
-  int a0, a1, b0, b1;
-  row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
-  // run handled by this lane: row = lane / 2, run = lane % 2
-  unsigned run_start = 0, run_len = 0;
-  const int row = lane >> 1;
-  if (row < ny_eff * nz_eff) {
-    const int oy = row % ny_eff, oz = row / ny_eff;
-    const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
-    const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
-    const int rowbase = (zz * ny + yy) * nx;
-    const int x0 = (lane & 1) ? b0 : a0, x1 = (lane & 1) ? b1 : a1;
-    if (x1 >= x0) {
-      // clamped to [0, n]: a run never reaches outside the sorted arrays
-      const unsigned s1 = min(cstart[rowbase + x1 + 1], (unsigned)c.n);
-      const unsigned s0 = min(cstart[rowbase + x0], s1);
-      run_start = s0;
-      run_len = s1 - s0;
-    }
-  }
-  unsigned incl = run_len;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  const unsigned excl = incl - run_len;
-  const unsigned total = __shfl(incl, 63, 64);
+  unsigned run_start, run_len, excl, total;
+  stencil_runs(c, cx, cy, cz, cstart, run_start, run_len, excl, total);
   const int nmax = c.n_max;
   int count = 0;
   for (unsigned wbase = 0; wbase < total; wbase += kWaveCand) {
@@ -681,75 +744,251 @@ __global__ __launch_bounds__(256) void k_list_wave(SysConst c, SysPtrs p, int cu
 }
 
 constexpr int kThreadBatch = 16;  // candidate positions in flight per thread
+constexpr int kRing = 32;         // list slots per lane staged in LDS
+
+__device__ __forceinline__ int wave_min_int(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
 
 // Verlet list, one thread per particle (section 7), for large systems where there
 // are enough particles to fill the chip.  Candidates of one stencil row are loaded
-// kThreadBatch at a time so that a row costs about one memory round trip.  Same
+// kThreadBatch at a time, and the cell bounds of the next row are loaded while the
+// current row is tested, so that a row costs about one memory round trip.  Same
 // candidate order, hence the same list, as the wave builder.
-__global__ __launch_bounds__(256) void k_list_thread(SysConst c, SysPtrs p, int cur) {
+//
+// The list is column-major, so the lanes of a wave write one contiguous span per
+// slot only when they write the same slot together; each lane finds its entries at
+// its own pace, so entries are first staged in a per-wave ring of kRing slots in
+// LDS, and every slot that all lanes of the wave have passed is written out as one
+// span.  A lane that runs kRing slots ahead of the slowest lane writes its later
+// entries directly.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_list_thread(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
+  __shared__ int s_ring[4][kRing][64];
   if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
   __syncthreads();
+  const int lane = threadIdx.x & 63;
+  int(*ring)[64] = s_ring[threadIdx.x >> 6];
   const int nmax = c.n_max;
   const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
   const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
-  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5;
-  const int stride = gridDim.x * blockDim.x;
+  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5, nrows = ny_eff * nz_eff;
+  const unsigned nu = (unsigned)c.n;
   int kept_sum = 0, longest = 0;
-  for (int t = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; t < c.n; t += stride) {
-    const float4 r = p.t_pos[t];
-    place_sorted(p, cur, t, r);
+  for (int t0 = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x; t0 < c.n; t0 += gridDim.x * blockDim.x) {
+    const int t = t0 + threadIdx.x;  // the loop is uniform over the block; lanes past n idle
+    const bool act = t < c.n;
+    const float4 r = p.t_pos[act ? t : t0];
+    if (act) place_sorted(p, cur, t, r);
     const int ti = ptype(r);
     int cx, cy, cz;
     cell_coords(r, c, cx, cy, cz);
     int a0, a1, b0, b1;
     row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
-    int count = 0;
-    for (int oz = 0; oz < nz_eff; ++oz) {
+    const bool two = b1 >= b0;
+    auto row_base = [&](int rr) {
+      const int oz = rr / ny_eff, oy = rr - oz * ny_eff;
       const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
-      for (int oy = 0; oy < ny_eff; ++oy) {
-        const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
-        const int rowbase = (zz * ny + yy) * nx;
-        // runs clamped to [0, n]: they never reach outside the sorted arrays
-        const unsigned sa1 = min(p.cell_start[rowbase + a1 + 1], (unsigned)c.n);
-        const unsigned sa0 = min(p.cell_start[rowbase + a0], sa1);
-        unsigned sb0 = 0, sb1 = 0;
-        if (b1 >= b0) {
-          sb1 = min(p.cell_start[rowbase + b1 + 1], (unsigned)c.n);
-          sb0 = min(p.cell_start[rowbase + b0], sb1);
+      const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
+      return (zz * ny + yy) * nx;
+    };
+    int rb = row_base(0);
+    unsigned ca0 = p.cell_start[rb + a0], ca1 = p.cell_start[rb + a1 + 1], cb0 = 0, cb1 = 0;
+    if (two) {
+      cb0 = p.cell_start[rb + b0];
+      cb1 = p.cell_start[rb + b1 + 1];
+    }
+    int count = 0;      // entries found by this lane
+    int ring_end = 0;   // this lane's entries below it are in the ring (or written)
+    bool spill = false; // this lane writes its later entries directly
+    int flushed = 0;    // uniform: every lane's slots below it are written
+    auto flush = [&](int upto) {
+      for (int k = flushed; k < upto; ++k)
+        if (act && k < ring_end && k < nmax) p.nbl[nbl_addr(t, k, c.tp, c.nvp)] = ring[k % kRing][lane];
+      flushed = upto;
+    };
+    for (int rr = 0; rr < nrows; ++rr) {
+      // runs clamped to [0, n]: they never reach outside the sorted arrays
+      const unsigned sa1 = min(ca1, nu), sa0 = min(ca0, sa1);
+      const unsigned sb1 = two ? min(cb1, nu) : 0u, sb0 = two ? min(cb0, sb1) : 0u;
+      if (rr + 1 < nrows) {
+        rb = row_base(rr + 1);
+        ca0 = p.cell_start[rb + a0];
+        ca1 = p.cell_start[rb + a1 + 1];
+        if (two) {
+          cb0 = p.cell_start[rb + b0];
+          cb1 = p.cell_start[rb + b1 + 1];
         }
-        const unsigned la = sa1 - sa0, lt = la + (sb1 - sb0);
-        for (unsigned base = 0; base < lt; base += kThreadBatch) {
-          unsigned u[kThreadBatch];
-          float4 q[kThreadBatch];
+      }
+      const unsigned la = sa1 - sa0, lt = act ? la + (sb1 - sb0) : 0u;
+      for (unsigned base = 0; base < lt; base += kThreadBatch) {
+        unsigned u[kThreadBatch];
+        float4 q[kThreadBatch];
 #pragma unroll
-          for (int b = 0; b < kThreadBatch; ++b) {
-            const unsigned o = base + b;
-            u[b] = o < la ? sa0 + o : sb0 + (o - la);
-            if (o >= lt) u[b] = (unsigned)t;  // past the row: load own slot, skipped below
-            q[b] = p.t_pos[u[b]];
-          }
+        for (int b = 0; b < kThreadBatch; ++b) {
+          const unsigned o = base + b;
+          u[b] = o < la ? sa0 + o : sb0 + (o - la);
+          if (o >= lt) u[b] = (unsigned)t;  // past the row: load own slot, skipped below
+          q[b] = p.t_pos[u[b]];
+        }
 #pragma unroll
-          for (int b = 0; b < kThreadBatch; ++b) {
-            if (base + b < lt && (int)u[b] != t) {
-              float dx, dy, dz;
-              const float r2 = dist2(r, q[b], c, dx, dy, dz);
-              if (r2 < s_cs2[ti * c.ntypes + ptype(q[b])]) {
+        for (int b = 0; b < kThreadBatch; ++b) {
+          if (base + b < lt && (int)u[b] != t) {
+            float dx, dy, dz;
+            const float r2 = dist2(r, q[b], c, dx, dy, dz);
+            if (r2 < s_cs2[ti * c.ntypes + ptype(q[b])]) {
+              if (!spill && count - flushed >= kRing) spill = true;
+              if (spill) {
                 if (count < nmax) p.nbl[nbl_addr(t, count, c.tp, c.nvp)] = (int)u[b];
-                ++count;
+              } else {
+                ring[count % kRing][lane] = (int)u[b];
+                ring_end = count + 1;
               }
+              ++count;
             }
           }
         }
       }
+      // write out the slots every lane has passed, once half the ring is in use
+      if (__any(act && !spill && count - flushed >= kRing / 2))
+        flush(min(wave_min_int(act && !spill ? count : 0x7fffffff), flushed + kRing));
     }
-    const int kept = min(count, nmax);
-    p.nnb[t] = kept;
-    longest = max(longest, count);
+    flush(flushed + kRing);
+    const int kept = act ? min(count, nmax) : 0;
+    if (act) p.nnb[t] = kept;
+    longest = max(longest, act ? count : 0);
     kept_sum += kept;
   }
   list_tally(kept_sum, longest, nmax, p.ctl);
+}
+
+constexpr int kCellSlots = 32;   // sorted slots per workgroup of the cell builder
+constexpr int kCellStage = 128;  // list entries per particle staged in LDS
+constexpr int kCellChunks = 8;   // 64-candidate chunks held in registers (one window)
+
+// Verlet lists, one wave per cell: every particle of a cell has the same stencil
+// (section 7), hence the same candidates in the same order, so the wave loads them
+// once, 64 slots per chunk from contiguous runs, and tests each particle of the
+// cell against all of them; a ballot compacts the hits in candidate order, so the
+// lists equal the other builders' entry for entry.  A workgroup of two waves takes
+// kCellSlots consecutive sorted slots, split into runs of one cell (a cell that
+// straddles two workgroups is handled by both, each for its own slots).  The lists
+// are staged in LDS as [particle][entry] and then written out by the workgroup in
+// address order, so each entry index of the column-major list is one contiguous
+// span; entries past kCellStage are written directly.
+__global__ __launch_bounds__(128) void k_list_cell(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  __shared__ float s_cs2[kMaxPairs];
+  __shared__ int s_list[kCellSlots][kCellStage + 1];  // +1: entries of one particle fall in distinct banks
+  __shared__ unsigned s_cand[2][64 * kCellChunks];
+  __shared__ int s_cnt[kCellSlots];
+  __shared__ int s_seg[kCellSlots + 1];
+  __shared__ int s_nseg;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int T0 = xcd_remap(blockIdx.x, gridDim.x) * kCellSlots;
+  const int m = min(kCellSlots, c.n - T0);  // slots of this workgroup, >= 1
+  const int nmax = c.n_max;
+  if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
+  if (wv == 0) {
+    // runs of slots in one cell: a segment starts where the cell index changes
+    int cell = -1;
+    if (lane < m) {
+      const float4 r = p.t_pos[T0 + lane];
+      place_sorted(p, cur, T0 + lane, r);
+      int cx, cy, cz;
+      cell_coords(r, c, cx, cy, cz);
+      cell = (cz * c.nc[1] + cy) * c.nc[0] + cx;
+      s_cnt[lane] = 0;
+    }
+    const int prev = __shfl_up(cell, 1, 64);
+    const bool head = lane < m && (lane == 0 || prev != cell);
+    const unsigned long long hm = __ballot(head);
+    if (head) s_seg[__popcll(hm & ((1ull << lane) - 1ull))] = lane;
+    if (lane == 0) {
+      s_nseg = __popcll(hm);
+      s_seg[__popcll(hm)] = m;
+    }
+  }
+  __syncthreads();
+  const int nseg = s_nseg;
+  unsigned *cand = s_cand[wv];
+  for (int sg = wv; sg < nseg; sg += 2) {
+    const int l0 = s_seg[sg], l1 = s_seg[sg + 1];
+    int cx, cy, cz;
+    cell_coords(p.t_pos[T0 + l0], c, cx, cy, cz);
+    unsigned run_start, run_len, excl, total;
+    stencil_runs(c, cx, cy, cz, p.cell_start, run_start, run_len, excl, total);
+    for (unsigned wbase = 0; wbase < total; wbase += 64u * kCellChunks) {
+      const unsigned wend = min(total, wbase + 64u * kCellChunks), wlen = wend - wbase;
+      const unsigned q0 = max(excl, wbase), q1 = min(excl + run_len, wend);
+      for (unsigned q = q0; q < q1; ++q) cand[q - wbase] = run_start + (q - excl);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      unsigned u[kCellChunks];
+      float4 q[kCellChunks];
+#pragma unroll
+      for (int cb = 0; cb < kCellChunks; ++cb) {
+        const unsigned qi = 64u * cb + (unsigned)lane;
+        u[cb] = qi < wlen ? cand[qi] : (unsigned)(T0 + l0);
+        if (64u * cb < wlen) q[cb] = p.t_pos[u[cb]];
+      }
+      for (int l = l0; l < l1; ++l) {
+        const int i = T0 + l;
+        const float4 pi = p.t_pos[i];
+        const int ti = ptype(pi);
+        int count = s_cnt[l];
+#pragma unroll
+        for (int cb = 0; cb < kCellChunks; ++cb) {
+          if (64u * cb < wlen) {  // uniform over the wave
+            bool hit = false;
+            if (64u * cb + (unsigned)lane < wlen && (int)u[cb] != i) {
+              float dx, dy, dz;
+              const float r2 = dist2(pi, q[cb], c, dx, dy, dz);
+              hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
+            }
+            const unsigned long long mask = __ballot(hit);
+            const int k = count + __popcll(mask & ((1ull << lane) - 1ull));
+            if (hit) {
+              if (k < kCellStage)
+                s_list[l][k] = (int)u[cb];
+              else if (k < nmax)
+                p.nbl[nbl_addr(i, k, c.tp, c.nvp)] = (int)u[cb];
+            }
+            count += __popcll(mask);
+          }
+        }
+        if (lane == 0) s_cnt[l] = count;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+  __syncthreads();
+  // write-out in address order: groups of tp entries of consecutive particles are
+  // contiguous in the tp-interleaved column-major list
+  int kmax = 0;
+  for (int l = 0; l < m; ++l) kmax = max(kmax, s_cnt[l]);
+  const int tp = c.tp;
+  const int kst = min(min(kmax, nmax), kCellStage);
+  const int span = kCellSlots * tp;  // elements of one group of tp entries
+  const int groups = (kst + tp - 1) / tp;
+  for (int j = tid; j < groups * span; j += blockDim.x) {
+    const int g = j / span, rr = j - g * span, l = rr / tp, k = g * tp + (rr - l * tp);
+    if (l < m && k < kst && k < s_cnt[l])
+      p.nbl[(long long)g * ((long long)c.nvp * tp) + (long long)(T0 + l) * tp + (rr - l * tp)] = s_list[l][k];
+  }
+  int kept = 0, longest = 0;
+  if (tid < m) {
+    longest = s_cnt[tid];
+    kept = min(longest, nmax);
+    p.nnb[T0 + tid] = kept;
+  }
+  list_tally(kept, longest, nmax, p.ctl);
 }
 
 // ---------------------------------------------------------------- force only
@@ -1554,15 +1793,18 @@ hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, i
   const int gb = c.list_blocks;
   if (!c.small_sort) {
     hipLaunchKernelGGL(k_bin, dim3(gb), dim3(tb), 0, st, c, p, cur);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, c, p);
+    hipLaunchKernelGGL(k_scan, dim3(scan_tiles(c.ncell)), dim3(256), 0, st, c, p);
     hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(tb), 0, st, c, p);
     hipLaunchKernelGGL(k_gather, dim3(gb), dim3(tb), 0, st, c, p, cur);
   }
-  if (c.wave_list) {
+  if (c.list_kind == 1) {
     const int lb = (c.n + 3) / 4;
     hipLaunchKernelGGL(k_list_wave, dim3(lb), dim3(tb), 0, st, c, p, cur);
-  } else {
+  } else if (c.list_kind == 2) {
     hipLaunchKernelGGL(k_list_thread, dim3(gb), dim3(tb), 0, st, c, p, cur);
+  } else {
+    const int lb = (c.n + kCellSlots - 1) / kCellSlots;
+    hipLaunchKernelGGL(k_list_cell, dim3(lb), dim3(128), 0, st, c, p, cur);
   }
   return hipGetLastError();
 }

@@ -73,7 +73,7 @@ struct srmd_system {
   // launch shape
   int tp_req = 0, ppb_req = 0, tp = 0, ppb = 0;
   int tp_tuned = 0, ppb_tuned = 0;
-  int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread
+  int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -297,7 +297,9 @@ srmd_status prepare(srmd_system *s) {
   c.volume = V;
   const bool fits = small_sort_fits(s->n, c.ncell);
   c.small_sort = (s->sort_mode == 0 || s->sort_mode == 1) && fits ? 1 : 0;
-  c.wave_list = s->list_mode == 1 || (s->list_mode == 0 && s->n <= 65536) ? 1 : 0;
+  // measured on MI355X (LJ fluid): the cell builder is fastest from 16k to 64k particles and
+  // the thread builder from 256k on; the autotuner compares all three
+  c.list_kind = s->list_mode != 0 ? s->list_mode : s->n <= 4096 ? 1 : s->n <= 131072 ? 3 : 2;
   c.list_blocks = std::max(1, std::min((s->n + 255) / 256, 2048));
   // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
   const double rho = s->n / V;
@@ -981,6 +983,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   s->p.ctl = (Control *)A(sizeof(Control));
   s->p.thermo = (Thermo *)A(sizeof(Thermo));
   s->p.bar_flags = (unsigned *)A(sizeof(unsigned) * 2 * 256);
+  s->p.tile_count = (unsigned *)A(sizeof(unsigned) * kScanMaxTiles);
   if (prec == SRMD_PREC_F64POS) {
     s->p.pos64 = (double *)A(sizeof(double) * 3 * N);
     s->p.t_pos64 = (double *)A(sizeof(double) * 3 * N);
@@ -1002,6 +1005,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
       hipMemcpyAsync(s->p.thermo, &ht, sizeof(ht), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.force, 0, sizeof(float4) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.tile_count, 0, sizeof(unsigned) * kScanMaxTiles, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.t_pos, 0, sizeof(float4) * N, s->stream) != hipSuccess) {
     srmd_destroy(s);
     return fail(nullptr, SRMD_EHIP, "initial upload failed");
@@ -1122,8 +1126,8 @@ srmd_status srmd_set_persistent(srmd_system *s, int32_t groups) {
 
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
-  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 2)
-    return fail(s, SRMD_EINVAL, "modes must be 0 (auto), 1 or 2");
+  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 3)
+    return fail(s, SRMD_EINVAL, "sort mode must be 0 (auto), 1 or 2 and list mode 0 (auto), 1, 2 or 3");
   s->sort_mode = sort_mode;
   s->list_mode = list_mode;
   s->dirty = true;
@@ -1536,7 +1540,7 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   int dtp, dppb;
   s->tp_req = s->ppb_req = 0;
   launch_of(s, &dtp, &dppb);
-  for (int lm = 1; lm <= 2 && result == SRMD_OK; ++lm) {
+  for (int lm = 1; lm <= 3 && result == SRMD_OK; ++lm) {
     double t;
     result = trial(dtp, dppb, lm, false, &t);
     if (result == SRMD_OK && t < best) {

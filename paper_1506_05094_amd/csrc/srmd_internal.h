@@ -10,6 +10,16 @@ namespace srmd {
 constexpr int kMaxTypes = 4;
 constexpr int kMaxPairs = kMaxTypes * kMaxTypes;
 
+// The cell histogram of a large system is scanned in tiles of 2^shift cells, one
+// workgroup per tile, with at most kScanMaxTiles tiles (shift >= 10).
+constexpr int kScanMaxTiles = 2048;
+__host__ __device__ inline int scan_tile_shift(int ncell) {
+  int s = 10;
+  while (((ncell - 1) >> s) >= kScanMaxTiles) ++s;
+  return s;
+}
+__host__ __device__ inline int scan_tiles(int ncell) { return ((ncell - 1) >> scan_tile_shift(ncell)) + 1; }
+
 // Per-type-pair float32 constants of the pair kernel and of the list build.
 struct PairTable {
   float cs2[kMaxPairs];    // (rc_ab + skin)^2 rounded once to float32: list radius
@@ -47,7 +57,7 @@ struct SysConst {
   double volume;
   int thermostat;    // 1: Nose-Hoover
   int small_sort;    // 1: the spatial sort runs in one workgroup (small systems)
-  int wave_list;     // 1: one wave per particle builds the list; 0: one thread per particle
+  int list_kind;     // list builder of the launch chain: 1 wave per particle, 2 thread per particle, 3 wave per cell
   int list_blocks;   // grid of the thread-per-particle list build and the sort kernels
   int pad1;
   float inv_mass[kMaxTypes];
@@ -106,6 +116,7 @@ struct SysPtrs {
   unsigned *slot_in_cell;
   unsigned *cell_count;
   unsigned *cell_start; // ncell + 1 entries
+  unsigned *tile_count; // particles per tile of cells (kScanMaxTiles entries), for the scan
   unsigned *perm_tmp;
   float4 *t_pos;    // gather targets of the spatial sort
   float4 *t_vel;

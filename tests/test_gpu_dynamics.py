@@ -35,7 +35,7 @@ def _in_range_pairs(pos, types, box, rc):
     return both[:, 0].astype(np.int64) * len(pos) + both[:, 1]
 
 
-PATHS = [(1, 1), (2, 1), (1, 2), (2, 2)]
+PATHS = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 3), (2, 3)]
 
 
 @pytest.mark.parametrize("paths", PATHS)
@@ -50,6 +50,52 @@ def test_rebuild_paths_same_list(paths):
     cs2, _ = oracle.cut_tables(rc, 0.3)
     ref = oracle.pair_set(state.pos, state.types, state.box, cs2)
     np.testing.assert_array_equal(got, ref)
+
+
+def test_multi_kernel_sort_and_thread_builder_mixture():
+    """Kob-Andersen mixture, N = 12000: the multi-kernel sort scans its cell histogram in
+    several tiles (15^3 cells), and in the thread-per-particle builder A and B lanes of a
+    wave find their entries at different rates (about 100 and 65), so entries are both
+    staged and written directly.  The wave, thread and cell list builders must give the
+    oracle's pair set and the same trajectory bit for bit."""
+    state = gen.ka_random_state(12000, 1.2, 0.45, 5)
+    sig, eps, rc = gen.ka_params()
+    cs2, _ = oracle.cut_tables(rc, 0.3)
+    ref = oracle.pair_set(state.pos, state.types, state.box, cs2)
+    out = []
+    for paths in [(2, 1), (2, 2), (2, 3)]:
+        print(f"N=12000 KA paths {paths}", flush=True)
+        with make_system(state, sig, eps, rc, "sf") as s:
+            s.set_rebuild_path(*paths)
+            s.build_neighbor_list()
+            np.testing.assert_array_equal(s.neighbor_pairs(), ref)
+            assert s.stats()["list_entries"] == len(ref)
+            s.set_integrator_nvt(0.005, 0.45, 0.2)
+            tr = s.step(150, thermo_every=50)
+            assert tr["n_rebuilds"][-1] >= 3
+            out.append((s.get_state(), tr["pe"]))
+    for o in out[1:]:
+        np.testing.assert_array_equal(o[0]["pos"], out[0][0]["pos"])
+        np.testing.assert_array_equal(o[0]["vel"], out[0][0]["vel"])
+        np.testing.assert_array_equal(o[1], out[0][1])
+
+
+@pytest.mark.parametrize("tp,skin", [(1, 0.3), (4, 0.3), (32, 0.3), (1, 1.0), (8, 1.0)])
+def test_cell_builder_layouts_and_long_lists(tp, skin):
+    """The cell builder writes each list in the tp-interleaved layout of the force
+    kernel; with skin 1.0 the lists hold about 215 entries, past the 128 staged in LDS."""
+    state = gen.jitter_positions(gen.config1_state(), 0.05, 3)
+    sig, eps, rc = gen.ka_params()
+    print(f"cell builder tp={tp} skin={skin}", flush=True)
+    with make_system(state, sig, eps, rc, "sf", skin=skin) as s:
+        s.set_rebuild_path(2, 3)
+        s.set_launch(tp, 256 // tp)
+        s.build_neighbor_list()
+        got = s.neighbor_pairs()
+        if skin > 0.5:
+            assert s.stats()["max_nbrs"] > 128
+    cs2, _ = oracle.cut_tables(rc, skin)
+    np.testing.assert_array_equal(got, oracle.pair_set(state.pos, state.types, state.box, cs2))
 
 
 def test_rebuild_paths_bitwise_same_trajectory():
