@@ -865,25 +865,79 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   list_tally(kept_sum, longest, nmax, p.ctl);
 }
 
+constexpr int kCellChunks = 8;  // 64-candidate chunks held in registers (one window)
+constexpr int kCellWindow = 64 * kCellChunks;
+
+// Verlet lists of the particles in sorted slots [i0, i1) of cell (cx, cy, cz), by the
+// calling wave.  Every particle of a cell has the same stencil (section 7), hence the
+// same candidates in the same order, so the wave loads them once, kCellWindow at a
+// time (64 per chunk from contiguous slot runs), and tests each particle against
+// them; a ballot compacts the hits in candidate order, so the lists equal those of
+// the particle-by-particle builders entry for entry.  cand: kCellWindow entries of
+// the wave's LDS; cnt[l]: entries found so far for particle i0 + l (LDS, the caller
+// clears it); sink(i, k, j) stores entry k of particle i (called by the hit lanes).
+template <class Sink>
+__device__ void list_cell_particles(const SysConst &c, const SysPtrs &p, int cx, int cy, int cz, int i0, int i1,
+                                    unsigned *cand, int *cnt, const float *s_cs2, const float4 *tpos,
+                                    const unsigned *cstart, Sink sink) {
+  const int lane = threadIdx.x & 63;
+  unsigned run_start, run_len, excl, total;
+  stencil_runs(c, cx, cy, cz, cstart, run_start, run_len, excl, total);
+  for (unsigned wbase = 0; wbase < total; wbase += kCellWindow) {
+    const unsigned wend = min(total, wbase + (unsigned)kCellWindow), wlen = wend - wbase;
+    const unsigned q0 = max(excl, wbase), q1 = min(excl + run_len, wend);
+    for (unsigned q = q0; q < q1; ++q) cand[q - wbase] = run_start + (q - excl);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    unsigned u[kCellChunks];
+    float4 q[kCellChunks];
+#pragma unroll
+    for (int cb = 0; cb < kCellChunks; ++cb) {
+      const unsigned qi = 64u * cb + (unsigned)lane;
+      u[cb] = qi < wlen ? cand[qi] : (unsigned)i0;
+      if (64u * cb < wlen) q[cb] = tpos[u[cb]];
+    }
+    for (int i = i0; i < i1; ++i) {
+      const float4 pi = tpos[i];
+      const int ti = ptype(pi);
+      int count = cnt[i - i0];
+#pragma unroll
+      for (int cb = 0; cb < kCellChunks; ++cb) {
+        if (64u * cb < wlen) {  // uniform over the wave
+          bool hit = false;
+          if (64u * cb + (unsigned)lane < wlen && (int)u[cb] != i) {
+            float dx, dy, dz;
+            const float r2 = dist2(pi, q[cb], c, dx, dy, dz);
+            hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
+          }
+          const unsigned long long mask = __ballot(hit);
+          if (hit) sink(i, count + __popcll(mask & ((1ull << lane) - 1ull)), (int)u[cb]);
+          count += __popcll(mask);
+        }
+      }
+      if (lane == 0) cnt[i - i0] = count;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 constexpr int kCellSlots = 32;   // sorted slots per workgroup of the cell builder
 constexpr int kCellStage = 128;  // list entries per particle staged in LDS
-constexpr int kCellChunks = 8;   // 64-candidate chunks held in registers (one window)
 
-// Verlet lists, one wave per cell: every particle of a cell has the same stencil
-// (section 7), hence the same candidates in the same order, so the wave loads them
-// once, 64 slots per chunk from contiguous runs, and tests each particle of the
-// cell against all of them; a ballot compacts the hits in candidate order, so the
-// lists equal the other builders' entry for entry.  A workgroup of two waves takes
-// kCellSlots consecutive sorted slots, split into runs of one cell (a cell that
-// straddles two workgroups is handled by both, each for its own slots).  The lists
-// are staged in LDS as [particle][entry] and then written out by the workgroup in
-// address order, so each entry index of the column-major list is one contiguous
-// span; entries past kCellStage are written directly.
+// Verlet lists, one wave per cell (list_cell_particles), for the launch chain.  A
+// workgroup of two waves takes kCellSlots consecutive sorted slots, split into runs
+// of one cell (a cell that straddles two workgroups is handled by both, each for its
+// own slots).  The lists are staged in LDS as [particle][entry] and then written out
+// by the workgroup in address order, so each entry index of the column-major list is
+// one contiguous span; entries past kCellStage are written directly.
 __global__ __launch_bounds__(128) void k_list_cell(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
   __shared__ int s_list[kCellSlots][kCellStage + 1];  // +1: entries of one particle fall in distinct banks
-  __shared__ unsigned s_cand[2][64 * kCellChunks];
+  __shared__ unsigned s_cand[2][kCellWindow];
   __shared__ int s_cnt[kCellSlots];
   __shared__ int s_seg[kCellSlots + 1];
   __shared__ int s_nseg;
@@ -914,59 +968,18 @@ __global__ __launch_bounds__(128) void k_list_cell(SysConst c, SysPtrs p, int cu
   }
   __syncthreads();
   const int nseg = s_nseg;
-  unsigned *cand = s_cand[wv];
+  auto stage = [&](int i, int k, int j) {
+    if (k < kCellStage)
+      s_list[i - T0][k] = j;
+    else if (k < nmax)
+      p.nbl[nbl_addr(i, k, c.tp, c.nvp)] = j;
+  };
   for (int sg = wv; sg < nseg; sg += 2) {
     const int l0 = s_seg[sg], l1 = s_seg[sg + 1];
     int cx, cy, cz;
     cell_coords(p.t_pos[T0 + l0], c, cx, cy, cz);
-    unsigned run_start, run_len, excl, total;
-    stencil_runs(c, cx, cy, cz, p.cell_start, run_start, run_len, excl, total);
-    for (unsigned wbase = 0; wbase < total; wbase += 64u * kCellChunks) {
-      const unsigned wend = min(total, wbase + 64u * kCellChunks), wlen = wend - wbase;
-      const unsigned q0 = max(excl, wbase), q1 = min(excl + run_len, wend);
-      for (unsigned q = q0; q < q1; ++q) cand[q - wbase] = run_start + (q - excl);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      unsigned u[kCellChunks];
-      float4 q[kCellChunks];
-#pragma unroll
-      for (int cb = 0; cb < kCellChunks; ++cb) {
-        const unsigned qi = 64u * cb + (unsigned)lane;
-        u[cb] = qi < wlen ? cand[qi] : (unsigned)(T0 + l0);
-        if (64u * cb < wlen) q[cb] = p.t_pos[u[cb]];
-      }
-      for (int l = l0; l < l1; ++l) {
-        const int i = T0 + l;
-        const float4 pi = p.t_pos[i];
-        const int ti = ptype(pi);
-        int count = s_cnt[l];
-#pragma unroll
-        for (int cb = 0; cb < kCellChunks; ++cb) {
-          if (64u * cb < wlen) {  // uniform over the wave
-            bool hit = false;
-            if (64u * cb + (unsigned)lane < wlen && (int)u[cb] != i) {
-              float dx, dy, dz;
-              const float r2 = dist2(pi, q[cb], c, dx, dy, dz);
-              hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
-            }
-            const unsigned long long mask = __ballot(hit);
-            const int k = count + __popcll(mask & ((1ull << lane) - 1ull));
-            if (hit) {
-              if (k < kCellStage)
-                s_list[l][k] = (int)u[cb];
-              else if (k < nmax)
-                p.nbl[nbl_addr(i, k, c.tp, c.nvp)] = (int)u[cb];
-            }
-            count += __popcll(mask);
-          }
-        }
-        if (lane == 0) s_cnt[l] = count;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
+    list_cell_particles(c, p, cx, cy, cz, T0 + l0, T0 + l1, s_cand[wv], s_cnt + l0, s_cs2, p.t_pos, p.cell_start,
+                        stage);
   }
   __syncthreads();
   // write-out in address order: groups of tp entries of consecutive particles are
@@ -1526,10 +1539,42 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         // build below only reads the sorted copies)
         for (int t = J.w * kBatchThreads + tid; t < c.n; t += J.g * kBatchThreads)
           place_sorted(p, cur, t, gload(p.t_pos, t));
+        // one wave per cell (list_cell_particles), cells dealt round-robin over the
+        // waves of all pieces, when each wave gets several cells; with about one cell
+        // per wave the most crowded cell would set the pace, so then one wave per
+        // particle.  The second half of the wave's window holds the counts.
         int kept = 0, longest = 0;
-        for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves)
-          kept += list_wave_one<false>(c, p, cur, t, cand, s_cs2, tpos, cstart, longest);
-        list_tally(lane == 0 ? kept : 0, longest, c.n_max, p.ctl);
+        const bool by_cell = 4 * J.g * kBatchWaves <= c.ncell;
+        int *wcnt = reinterpret_cast<int *>(cand + kCellWindow);
+        auto direct = [&](int i, int kk, int jj) {
+          if (kk < c.n_max) p.nbl[nbl_addr(i, kk, c.tp, c.nvp)] = jj;
+        };
+        for (int t = J.w * kBatchWaves + wv; !by_cell && t < c.n; t += J.g * kBatchWaves) {
+          const int kt = list_wave_one<false>(c, p, cur, t, cand, s_cs2, tpos, cstart, longest);
+          if (lane == 0) kept += kt;
+        }
+        for (int cell = J.w * kBatchWaves + wv; by_cell && cell < c.ncell; cell += J.g * kBatchWaves) {
+          const unsigned e1 = min(cstart[cell + 1], (unsigned)c.n), e0 = min(cstart[cell], e1);
+          const int ne = (int)(e1 - e0);
+          if (ne == 0) continue;  // uniform over the wave
+          if (ne > kWaveCand - kCellWindow) {  // more particles than count slots: one at a time
+            for (unsigned t = e0; t < e1; ++t) {
+              const int kt = list_wave_one<false>(c, p, cur, (int)t, cand, s_cs2, tpos, cstart, longest);
+              if (lane == 0) kept += kt;
+            }
+            continue;
+          }
+          for (int l = lane; l < ne; l += 64) wcnt[l] = 0;
+          const int cx = cell % c.nc[0], cy = (cell / c.nc[0]) % c.nc[1], cz = cell / (c.nc[0] * c.nc[1]);
+          list_cell_particles(c, p, cx, cy, cz, (int)e0, (int)e1, cand, wcnt, s_cs2, tpos, cstart, direct);
+          for (int l = lane; l < ne; l += 64) {
+            const int cn = wcnt[l];
+            p.nnb[e0 + l] = min(cn, c.n_max);
+            kept += min(cn, c.n_max);
+            longest = max(longest, cn);
+          }
+        }
+        list_tally(kept, longest, c.n_max, p.ctl);
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
       if (!prefilled) fill_positions(s_dyn, p.pos[cur], c.n);
