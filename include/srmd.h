@@ -148,12 +148,14 @@ srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t lis
  * srmd_set_launch, the default tp of the persistent mode is twice that of the launch
  * chains (64k lanes instead of 32k), so switching modes then changes the layout
  * and rebuilds the list; at an explicit launch shape a switch keeps the list and the
- * trajectory continues bit for bit.  The persistent kernel keeps all
- * positions of the system in every workgroup's LDS, separates the time steps by a
- * device-wide barrier and repeats the reductions of the launch chain in the same
- * order, so the trajectory is the same bit for bit at the same (tp, ppb).  It needs
- * float32 positions, at most 8192 particles and at most 8192 cells; srmd_step on a
- * system outside that range returns SRMD_EUNSUPPORTED while groups != 0.  A barrier
+ * trajectory continues bit for bit.  The persistent kernel separates the time steps
+ * by a device-wide barrier and repeats the reductions of the launch chain in the
+ * same order, so the trajectory is the same bit for bit at the same (tp, ppb).  A
+ * system of at most 8192 particles and 8192 cells keeps all its positions in every
+ * workgroup's LDS; a larger one reads them from device memory and runs the launch
+ * chain's four-phase sort with a barrier between phases, and then needs tp <= 8.
+ * The persistent kernel needs float32 positions; srmd_step on a system it cannot
+ * run returns SRMD_EUNSUPPORTED while groups != 0.  A barrier
  * that does not complete within about one second (workgroups not co-resident) ends
  * the launch and the call returns SRMD_EHIP instead of hanging. */
 srmd_status srmd_set_persistent(srmd_system *s, int32_t groups);

@@ -369,14 +369,19 @@ __device__ __forceinline__ void begin_build(Control *ctl) {
   ctl->n_rebuilds += 1;
 }
 
-// Cell of every particle (section 7 step 1), its arrival slot in the cell, and the
-// particle count of every tile of 2^shift cells; lanes of a wave that fall in the
-// same tile add to it once.
-__global__ __launch_bounds__(256) void k_bin(SysConst c, SysPtrs p, int cur) {
-  if (p.ctl->rebuild == 0) return;
+// The counting sort of large systems (section 7 steps 1-3) in four phases, each a
+// grid-wide pass over particles or cells: bin, scan, scatter, gather.  The launch
+// chain runs them as four kernels; the persistent kernel runs the same functions
+// with a grid barrier between phases.  Thread ranges: a workgroup of blockDim.x
+// threads starts at particle base and steps by stride.
+
+// Phase 1: cell of every particle, its arrival slot in the cell, and the particle
+// count of every tile of 2^shift cells (lanes of a wave that fall in the same tile
+// add to it once).
+__device__ void sort_bin(const SysConst &c, const SysPtrs &p, int cur, int base, int stride) {
   const int shift = scan_tile_shift(c.ncell);
   const int lane = threadIdx.x & 63;
-  for (int s0 = blockIdx.x * blockDim.x; s0 < c.n; s0 += gridDim.x * blockDim.x) {  // uniform per block
+  for (int s0 = base; s0 < c.n; s0 += stride) {  // uniform over the workgroup
     const int s = s0 + threadIdx.x;
     const bool act = s < c.n;
     unsigned tile = 0u;
@@ -400,26 +405,24 @@ __global__ __launch_bounds__(256) void k_bin(SysConst c, SysPtrs p, int cur) {
   }
 }
 
-// Exclusive scan of the cell histogram into cell_start (section 7 step 2), one
-// workgroup per tile of 2^shift cells: the workgroup adds the counts of the tiles
-// before its own, then scans its tile 1024 cells at a time (4 per thread).  The
-// histogram is cleared for the next build; the tile counts are cleared by k_scatter.
-__global__ __launch_bounds__(256) void k_scan(SysConst c, SysPtrs p) {
-  if (p.ctl->rebuild == 0) return;
-  __shared__ unsigned s_w[4];
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-  const int b = blockIdx.x, shift = scan_tile_shift(c.ncell);
-  if (b == 0 && t == 0) begin_build(p.ctl);
+// Phase 2: exclusive scan of the cell histogram into cell_start for tile b, by the
+// calling workgroup: the counts of the tiles before b, then the tile 4 cells per
+// thread at a time.  The histogram is cleared for the next build (the tile counts
+// are cleared in phase 3).  s_w: 16 words of LDS.
+__device__ void sort_scan_tile(const SysConst &c, const SysPtrs &p, int b, unsigned *s_w) {
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6, nw = blockDim.x >> 6;
+  const int shift = scan_tile_shift(c.ncell);
   unsigned pre = 0;
-  for (int k = t; k < b; k += 256) pre += p.tile_count[k];
+  for (int k = t; k < b; k += blockDim.x) pre += p.tile_count[k];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) pre += __shfl_xor(pre, o, 64);
   if (lane == 0) s_w[wv] = pre;
   __syncthreads();
-  unsigned carry = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  unsigned carry = 0;
+  for (int k = 0; k < nw; ++k) carry += s_w[k];
   __syncthreads();
   const int beg = b << shift, end = min(c.ncell, (b + 1) << shift);
-  for (int base = beg; base < end; base += 1024) {
+  for (int base = beg; base < end; base += 4 * (int)blockDim.x) {
     const int i0 = base + 4 * t;
     unsigned v[4];
     if (i0 + 3 < end) {
@@ -441,9 +444,11 @@ __global__ __launch_bounds__(256) void k_scan(SysConst c, SysPtrs p) {
     }
     if (lane == 63) s_w[wv] = x;
     __syncthreads();
-    unsigned wbase = 0;
-    for (int k = 0; k < wv; ++k) wbase += s_w[k];
-    const unsigned total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    unsigned wbase = 0, total = 0;
+    for (int k = 0; k < nw; ++k) {
+      if (k < wv) wbase += s_w[k];
+      total += s_w[k];
+    }
     unsigned e = carry + wbase + x - sum;
     if (i0 + 3 < end) {
       uint4 o4;
@@ -466,20 +471,21 @@ __global__ __launch_bounds__(256) void k_scan(SysConst c, SysPtrs p) {
     carry += total;
     __syncthreads();  // s_w is rewritten by the next chunk
   }
-  if (b == gridDim.x - 1 && t == 0) p.cell_start[c.ncell] = carry;
+  if (b == scan_tiles(c.ncell) - 1 && t == 0) p.cell_start[c.ncell] = carry;
 }
 
-__global__ __launch_bounds__(256) void k_scatter(SysConst c, SysPtrs p) {
-  if (p.ctl->rebuild == 0) return;
-  if (blockIdx.x == 0)
+// Phase 3: every particle's arrival slot in its cell's range (perm_tmp); the tile
+// counts are cleared for the next build by the threads of clear_tiles.
+__device__ void sort_scatter(const SysConst &c, const SysPtrs &p, int first, int stride, bool clear_tiles) {
+  if (clear_tiles)
     for (int k = threadIdx.x; k < scan_tiles(c.ncell); k += blockDim.x) p.tile_count[k] = 0u;
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x)
-    p.perm_tmp[p.cell_start[p.cell_of[s]] + p.slot_in_cell[s]] = (unsigned)s;
+  for (int s = first; s < c.n; s += stride) p.perm_tmp[p.cell_start[p.cell_of[s]] + p.slot_in_cell[s]] = (unsigned)s;
 }
 
-__global__ __launch_bounds__(256) void k_gather(SysConst c, SysPtrs p, int cur) {
-  if (p.ctl->rebuild == 0) return;
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < c.n; s += gridDim.x * blockDim.x) {
+// Phase 4: deterministic rank by particle id inside each cell, and the gather of
+// every per-particle array to its sorted slot in the t_* arrays.
+__device__ void sort_gather(const SysConst &c, const SysPtrs &p, int cur, int first, int stride) {
+  for (int s = first; s < c.n; s += stride) {
     const unsigned cell = p.cell_of[s];
     const unsigned beg = p.cell_start[cell], end = p.cell_start[cell + 1];
     const int4 im = p.img[s];
@@ -496,6 +502,29 @@ __global__ __launch_bounds__(256) void k_gather(SysConst c, SysPtrs p, int cur) 
     }
     if (p.kahan) p.t_kahan[dst] = p.kahan[s];
   }
+}
+
+__global__ __launch_bounds__(256) void k_bin(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  sort_bin(c, p, cur, blockIdx.x * blockDim.x, gridDim.x * blockDim.x);
+}
+
+// One workgroup per tile of cells.
+__global__ __launch_bounds__(256) void k_scan(SysConst c, SysPtrs p) {
+  if (p.ctl->rebuild == 0) return;
+  __shared__ unsigned s_w[16];
+  if (blockIdx.x == 0 && threadIdx.x == 0) begin_build(p.ctl);
+  sort_scan_tile(c, p, blockIdx.x, s_w);
+}
+
+__global__ __launch_bounds__(256) void k_scatter(SysConst c, SysPtrs p) {
+  if (p.ctl->rebuild == 0) return;
+  sort_scatter(c, p, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x, blockIdx.x == 0);
+}
+
+__global__ __launch_bounds__(256) void k_gather(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  sort_gather(c, p, cur, blockIdx.x * blockDim.x + threadIdx.x, gridDim.x * blockDim.x);
 }
 
 // ---------------------------------------------------------------- one-workgroup sort (small systems)
@@ -1470,7 +1499,12 @@ __device__ __forceinline__ void fill_positions(float4 *dst, const float4 *src, i
 // the pieces build the lists of particles wave, wave + 8g, ..., and another barrier
 // follows.  A system follows its single-system trajectory bit for bit at the same
 // (tp, ppb), whatever the pieces and the other jobs of its workgroups.
-template <int TP, int METHOD>
+//
+// BIG: one larger system alone (more than 8192 particles or cells), positions read
+// from device memory rather than LDS.  Its spatial sort is the four-phase counting
+// sort of the launch chain, run by all pieces at the start of a step that rebuilds,
+// with a grid barrier after each phase.
+template <int TP, int METHOD, bool BIG>
 __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__restrict__ reps,
                                                          const CoopJob *__restrict__ jobs,
                                                          const int *__restrict__ job_off, int nsteps,
@@ -1484,6 +1518,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
   __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs];
   __shared__ unsigned s_k[kMaxJobs];
   __shared__ double s_xi[kMaxJobs];
+  __shared__ unsigned s_scan[16];
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int j0 = job_off[blockIdx.x];
   const int nj = min(job_off[blockIdx.x + 1] - j0, kMaxJobs);
@@ -1518,11 +1553,23 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       if (tid < kMaxPairs) s_cs2[tid] = c.pt.cs2[tid];
       if (tid == 0) s_bit = 0;
       __syncthreads();
-      if (rebuild) {  // the spatial sort has been done (host request or end of step)
+      if (BIG && rebuild) {  // the counting sort of the launch chain, phase by phase
+        const int base = J.w * kBatchThreads, stride = J.g * kBatchThreads;
+        sort_bin(c, p, cur, base, stride);
+        if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+        if (J.w == 0 && tid == 0) begin_build(p.ctl);
+        for (int b = J.w; b < scan_tiles(c.ncell); b += J.g) sort_scan_tile(c, p, b, s_scan);
+        if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+        sort_scatter(c, p, base + tid, stride, J.w == 0);
+        if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+        sort_gather(c, p, cur, base + tid, stride);
+        if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+      }
+      if (rebuild) {  // the spatial sort has been done (host request, end of step, or above)
         // the sorted positions and the cell starts go to LDS when they fit beside the
         // candidate windows, so the list build reads no device memory but its own list
         const int cs_words = (c.ncell + 1 + 3) & ~3;
-        const bool in_lds = 16 * c.n + 4 * cs_words + 4 * kBatchWaves * kWaveCand <= lds_bytes;
+        const bool in_lds = !BIG && 16 * c.n + 4 * cs_words + 4 * kBatchWaves * kWaveCand <= lds_bytes;
         const float4 *tpos = p.t_pos;
         const unsigned *cstart = p.cell_start;
         unsigned *cand = reinterpret_cast<unsigned *>(s_dyn) + wv * kWaveCand;
@@ -1577,9 +1624,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         list_tally(kept, longest, c.n_max, p.ctl);
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
-      if (!prefilled) fill_positions(s_dyn, p.pos[cur], c.n);
+      if (!BIG && !prefilled) fill_positions(s_dyn, p.pos[cur], c.n);
       prefilled = false;
       __syncthreads();
+      // positions of the step: the LDS copy, or device memory for a large system
+      const float4 *spos = BIG ? (const float4 *)global_view(p.pos[cur]) : s_dyn;
       // this piece's wave units: unit q is wave q % wpv of owned block q / wpv; the
       // waves run their units without waiting for each other, and the wave partials
       // go to the system's partials buffer after the G block partials
@@ -1603,13 +1652,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         float4 vo = pi, l0 = pi, kc = pi;
         int4 im = make_int4(0, 0, 0, 0);
         if (active) {
-          pi = s_dyn[i];
+          pi = BIG ? gload(p.pos[cur], i) : s_dyn[i];
           if (t == 0) {
             vo = gload(p.vel, i);
             im = gload(p.img, i);
             l0 = gload(p.last, i);
           }
-          force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, s_dyn, nblg, nnbg, sp, c, fx, fy, fz, uu, w);
+          force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, spos, nblg, nnbg, sp, c, fx, fy, fz, uu, w);
         }
         fx = lane_sum<TP>(fx);
         fy = lane_sum<TP>(fy);
@@ -1650,7 +1699,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         BlockPartial q0 = zero_partial(), q1 = zero_partial();
         if (tid < G) q0 = bpart[tid];
         if (tid + kBatchThreads < G) q1 = bpart[tid + kBatchThreads];
-        prefilled = nj == 1 && !s_any && step + 1 < nsteps;
+        prefilled = !BIG && nj == 1 && !s_any && step + 1 < nsteps;
         if (prefilled) fill_positions(s_dyn, p.pos[cur ^ 1], c.n);
         if (tid < G) fold(a0, q0);
         if (tid + kBatchThreads < G) fold(a1, q1);
@@ -1677,7 +1726,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       }
       __syncthreads();
       cur ^= 1;
-      if (s_rebuild[j]) {
+      if (!BIG && s_rebuild[j]) {
         // spatial sort of the new positions by piece 0, as k_finish does
         if (J.w == 0) {
           unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
@@ -1693,12 +1742,44 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
   }
 }
 
-template <int TP>
-static hipError_t launch_multi_tp(int method, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
-                                  const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative) {
-  const void *fn = method == 0 ? (const void *)k_multi<TP, 0>
-                   : method == 1 ? (const void *)k_multi<TP, 1>
-                                 : (const void *)k_multi<TP, 2>;
+template <int TP, bool BIG>
+static const void *multi_fn(int method) {
+  return method == 0 ? (const void *)k_multi<TP, 0, BIG>
+         : method == 1 ? (const void *)k_multi<TP, 1, BIG>
+                       : (const void *)k_multi<TP, 2, BIG>;
+}
+
+// The persistent kernel for (tp, method); the large-system form exists for tp <= 8.
+static const void *multi_fn_of(int tp, int method, bool big) {
+  if (big) {
+    switch (tp) {
+      case 1: return multi_fn<1, true>(method);
+      case 2: return multi_fn<2, true>(method);
+      case 4: return multi_fn<4, true>(method);
+      case 8: return multi_fn<8, true>(method);
+      default: return nullptr;
+    }
+  }
+  switch (tp) {
+    case 1: return multi_fn<1, false>(method);
+    case 2: return multi_fn<2, false>(method);
+    case 4: return multi_fn<4, false>(method);
+    case 8: return multi_fn<8, false>(method);
+    case 16: return multi_fn<16, false>(method);
+    case 32: return multi_fn<32, false>(method);
+    case 64: return multi_fn<64, false>(method);
+    default: return nullptr;
+  }
+}
+
+bool multi_big_supported(int tp) { return multi_fn_of(tp, 0, true) != nullptr; }
+
+// Launch k_multi over nwg workgroups.  cooperative: some system is split over
+// several workgroups, which must then all be resident at once.
+hipError_t launch_multi(int tp, int method, bool big, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+                        const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative) {
+  const void *fn = multi_fn_of(tp, method, big);
+  if (!fn || nwg < 1) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   int lds_bytes = (int)lds;
@@ -1707,33 +1788,10 @@ static hipError_t launch_multi_tp(int method, int nwg, size_t lds, hipStream_t s
   return hipLaunchKernel(fn, dim3(nwg), dim3(kBatchThreads), args, lds, st);
 }
 
-// Launch k_multi over nwg workgroups.  cooperative: some system is split over
-// several workgroups, which must then all be resident at once.
-hipError_t launch_multi(int tp, int method, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
-                        const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative) {
-  if (nwg < 1) return hipErrorInvalidValue;
-  switch (tp) {
-    case 1: return launch_multi_tp<1>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    case 2: return launch_multi_tp<2>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    case 4: return launch_multi_tp<4>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    case 8: return launch_multi_tp<8>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    case 16: return launch_multi_tp<16>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    case 32: return launch_multi_tp<32>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    case 64: return launch_multi_tp<64>(method, nwg, lds, st, reps, jobs, job_off, nsteps, cooperative);
-    default: return hipErrorInvalidValue;
-  }
-}
-
 // Workgroups of the persistent kernel the device holds at once (at most 256).
-int multi_max_groups(int tp, int method, size_t lds) {
-  const void *fn = nullptr;
-  switch (tp) {
-#define SRMD_MULTI_FN(T) \
-  case T: fn = method == 0 ? (const void *)k_multi<T, 0> : method == 1 ? (const void *)k_multi<T, 1> : (const void *)k_multi<T, 2>; break;
-    SRMD_MULTI_FN(1) SRMD_MULTI_FN(2) SRMD_MULTI_FN(4) SRMD_MULTI_FN(8) SRMD_MULTI_FN(16) SRMD_MULTI_FN(32) SRMD_MULTI_FN(64)
-#undef SRMD_MULTI_FN
-    default: return 0;
-  }
+int multi_max_groups(int tp, int method, bool big, size_t lds) {
+  const void *fn = multi_fn_of(tp, method, big);
+  if (!fn) return 0;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBatchThreads, lds) != hipSuccess) return 0;
@@ -1759,6 +1817,9 @@ size_t batch_lds_bytes(int n_max_particles) {
 }
 
 int batch_max_particles() { return kSmallN; }
+
+// Dynamic LDS of the large-system persistent kernel: the list build's candidate windows.
+size_t big_lds_bytes() { return 4 * (size_t)(kBatchWaves * kWaveCand); }
 
 // ---------------------------------------------------------------- launchers
 

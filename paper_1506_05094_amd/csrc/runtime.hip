@@ -24,9 +24,11 @@ hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p,
 bool small_sort_fits(int n, int ncell);
 size_t batch_lds_bytes(int n_max_particles);
 int batch_max_particles();
-hipError_t launch_multi(int tp, int method, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
+hipError_t launch_multi(int tp, int method, bool big, int nwg, size_t lds, hipStream_t st, const ReplicaDesc *reps,
                         const CoopJob *jobs, const int *job_off, int nsteps, bool cooperative);
-int multi_max_groups(int tp, int method, size_t lds);
+int multi_max_groups(int tp, int method, bool big, size_t lds);
+bool multi_big_supported(int tp);
+size_t big_lds_bytes();
 int multi_max_jobs();
 }  // namespace srmd
 
@@ -239,6 +241,9 @@ srmd_status flush_host_sort(srmd_system *s) {
 
 int step_blocks(const srmd_system *s) { return (int)(((long long)s->n * s->tp + s->tp * s->ppb - 1) / (s->tp * s->ppb)); }
 
+// Dynamic LDS of the persistent kernel for this system.
+size_t persist_lds(const srmd_system *s) { return s->c.small_sort ? batch_lds_bytes(s->n) : big_lds_bytes(); }
+
 // Workgroups of the persistent kernel (0: launch chains): by default one workgroup
 // of 512 threads per 8 waves of the step launch, so each wave takes one wave of it.
 void resolve_persistent(srmd_system *s) {
@@ -246,13 +251,17 @@ void resolve_persistent(srmd_system *s) {
   s->persist_err.clear();
   const int preq = s->persist_set ? s->persist_req : s->persist_tuned;
   if (preq == 0) return;
-  if (s->prec != SRMD_PREC_F32 || !s->c.small_sort) {
-    s->persist_err = "the persistent kernel needs float32 positions, at most 8192 particles and 8192 cells";
+  if (s->prec != SRMD_PREC_F32) {
+    s->persist_err = "the persistent kernel needs float32 positions";
+    return;
+  }
+  if (!s->c.small_sort && !multi_big_supported(s->tp)) {
+    s->persist_err = "the persistent kernel takes a system of more than 8192 particles or cells with tp <= 8 only";
     return;
   }
   const int threads = s->tp * s->ppb;
   const int units = step_blocks(s) * (threads / 64);
-  const int cap = multi_max_groups(s->tp, s->method, batch_lds_bytes(s->n));
+  const int cap = multi_max_groups(s->tp, s->method, !s->c.small_sort, persist_lds(s));
   int want = preq > 0 ? preq : std::max(1, (units + 7) / 8);
   if (preq < 0) want = std::min(want, cap);
   if (want > cap || want < 1)
@@ -510,7 +519,7 @@ srmd_status launch_persistent(srmd_system *s, int cnt) {
     s->desc_valid = true;
   }
   if (g > 1) HIPCHK(s, hipMemsetAsync(s->p.bar_flags, 0, sizeof(unsigned) * 2 * 256, s->stream));
-  HIPCHK(s, launch_multi(s->tp, s->method, g, batch_lds_bytes(s->n), s->stream, s->d_desc, s->d_jobs, s->d_job_off,
+  HIPCHK(s, launch_multi(s->tp, s->method, !s->c.small_sort, g, persist_lds(s), s->stream, s->d_desc, s->d_jobs, s->d_job_off,
                          cnt, g > 1));
   s->cur ^= (cnt & 1);
   return SRMD_OK;
@@ -1580,10 +1589,10 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
     if (block_best > 1.10 * std::min(best, prev_block_best) && bi > 0) break;
     prev_block_best = std::min(prev_block_best, block_best);
   }
-  // Phase III (MI355X): the persistent kernel for small systems, t_p at 256-thread
-  // virtual blocks, with the t_p stop rule of phase II
+  // Phase III (MI355X): the persistent kernel, t_p at 256-thread virtual blocks,
+  // with the t_p stop rule of phase II (tp values it cannot run end the phase)
   bool best_persist = false;
-  if (result == SRMD_OK && s->prec == SRMD_PREC_F32 && s->c.small_sort) {
+  if (result == SRMD_OK && s->prec == SRMD_PREC_F32) {
     double pbest = 1e300;
     int slower = 0;
     for (int tp = 1; tp <= 64 && result == SRMD_OK; tp <<= 1) {
@@ -1668,7 +1677,7 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
     return bfail(nullptr, SRMD_ENOMEM, "batch descriptor allocation failed");
   }
   srmd_status st = batch_sync_desc(b);
-  int W = multi_max_groups(b->tp, b->method, b->lds);
+  int W = multi_max_groups(b->tp, b->method, false, b->lds);
   if (max_workgroups > 0) W = std::min(W, max_workgroups);
   if (st == SRMD_OK && W < 1) st = bfail(b, SRMD_EUNSUPPORTED, "the persistent kernel does not fit on the device");
   if (st == SRMD_OK) st = batch_plan(b, W);
@@ -1717,7 +1726,7 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
     // launches of kPersistChunk steps (an even count: every launch starts on the
     // position buffer of the call start, which the descriptors hold)
     const int cnt = (int)std::min<long long>(kPersistChunk, nsteps - done);
-    e = launch_multi(b->tp, b->method, b->nwg, b->lds, b->stream, b->d_desc, b->d_jobs, b->d_job_off, cnt,
+    e = launch_multi(b->tp, b->method, false, b->nwg, b->lds, b->stream, b->d_desc, b->d_jobs, b->d_job_off, cnt,
                      b->cooperative);
     if (e == hipSuccess && done + cnt < nsteps)
       for (size_t r = 0; r < b->sys.size() && e == hipSuccess; ++r)

@@ -1,7 +1,8 @@
 """Persistent mode: every step of a call in one cooperative launch.  The trajectory
 must be the launch chain's bit for bit at the same launch shape, for any workgroup
 count, across mode switches in the middle of a run and through list-overflow
-replays; systems the kernel cannot run are rejected."""
+replays, for small systems (positions in LDS) and large ones (positions in device
+memory, four-phase sort); systems the kernel cannot run are rejected."""
 import numpy as np
 import pytest
 
@@ -170,11 +171,95 @@ def test_profile_reports_one_launch():
     s.close()
 
 
+@pytest.fixture(scope="module")
+def ka12000():
+    return gen.ka_random_state(12000, 1.2, 0.6, 24)
+
+
+@pytest.mark.parametrize("launch,groups", [((2, 128), -1), ((8, 32), 37), ((1, 256), 256), ((4, 64), 1)])
+def test_large_system_bitwise_equals_chain(ka12000, launch, groups):
+    """N = 12000 (more than 8192 particles): positions from device memory and the
+    four-phase sort with grid barriers, for several workgroup counts (one workgroup
+    runs every phase alone)."""
+    from paper_1506_05094_amd import srmd
+    print(f"large persistent N=12000 launch={launch} groups={groups}", flush=True)
+    sig, eps, rc = gen.ka_params()
+    a = make_system(ka12000, sig, eps, rc, "sf", launch=launch)
+    b = make_system(ka12000, sig, eps, rc, "sf", launch=launch)
+    for s in (a, b):
+        s.set_integrator_nvt(0.003, 0.6, 0.2)
+    b.set_persistent(groups)
+    try:
+        b.step(1)
+    except srmd.SrmdError as e:  # fewer workgroups fit on this device
+        assert e.status == srmd.SRMD_EUNSUPPORTED and groups > 1
+        pytest.skip("workgroup count does not fit")
+    a.step(1)
+    assert b.stats()["persistent_groups"] > 0
+    tra = a.step(300, thermo_every=10)
+    trb = b.step(300, thermo_every=10)
+    assert a.thermo()["n_rebuilds"] > 3
+    _same(a, b, tra, trb, f"N=12000 {launch} groups={groups}")
+    a.close()
+    b.close()
+
+
+def test_large_lj_sweep_size_and_mode_switches():
+    """LJ N = 64000 at t_p = 1: persistent and chain in turns, against the chain alone."""
+    print("large persistent LJ 64000 switches", flush=True)
+    st = gen.config2_state(64000)
+    sig, eps, rc = gen.lj_params()
+    a = make_system(st, sig, eps, rc, "sp", launch=(1, 256))
+    b = make_system(st, sig, eps, rc, "sp", launch=(1, 256))
+    for s in (a, b):
+        s.set_integrator_nve(0.005)
+    a.step(260)
+    for mode, cnt in [(-1, 101), (0, 37), (-1, 1), (0, 1), (-1, 120)]:
+        b.set_persistent(mode)
+        b.step(cnt)
+    assert a.thermo()["n_rebuilds"] > 3
+    _same(a, b, label="LJ 64000 switches")
+    a.close()
+    b.close()
+
+
+def test_large_system_overflow_replays_like_chain():
+    from paper_1506_05094_amd import srmd
+    import torch
+    print("large persistent overflow replay", flush=True)
+    rng = np.random.default_rng(8)
+    m = 21
+    L = 12.0 * m / 9
+    g = (np.arange(m) - m // 2) * (L / m)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = (pos + rng.uniform(-0.1, 0.1, pos.shape)).astype(np.float32)
+    vel = (-0.5 * pos).astype(np.float32)  # the same contraction rate as the small lattice
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def contracting(mode):
+        s = srmd.System(pos, np.zeros(len(pos), np.int32), [L, L, L], vel=vel, stream=stream)
+        s.set_skin(0.4)
+        s.set_pair_lj(0, 0, 1.0, 0.05, 2.5, "sp")
+        s.set_integrator_nve(0.002)
+        s.set_launch(4, 64)
+        s.set_persistent(mode)
+        return s
+
+    a, b = contracting(0), contracting(-1)
+    n0 = b.stats()["n_max"]
+    a.step(400)
+    b.step(400)
+    assert b.stats()["n_max"] > n0
+    _same(a, b, label="large overflow")
+    a.close()
+    b.close()
+
+
 def test_rejections():
     from paper_1506_05094_amd import srmd
     sig, eps, rc = gen.ka_params()
     big = gen.ka_random_state(9000, 1.2, 0.5, 3)
-    s_big = make_system(big, sig, eps, rc, "sf")
+    s_big = make_system(big, sig, eps, rc, "sf", launch=(16, 16))  # t_p > 8 above 8192 particles
     s_big.set_integrator_nve(0.002)
     s_big.set_persistent(-1)
     with pytest.raises(srmd.SrmdError) as e:
