@@ -281,15 +281,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "ka-replicas", "precision", "sweep"])
     ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner (untimed) after the relaxation; the tuned layout and mode are timed")
     ap.add_argument("--sizes", default="1000,4000,16000,64000,256000,1024000", help="N values of the size sweep")
-    ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial in the size sweep")
+    ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial (size sweep, --tune)")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--baseline-steps", type=int, default=1000)
     ap.add_argument("--n", type=int, default=864, help="particles for --workload lj")
     ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
     ap.add_argument("--ppb", type=int, default=0)
     ap.add_argument("--mode", default="persistent", choices=["persistent", "chain"],
-                    help="persistent: 500 steps per launch of one kernel (systems up to 8192 particles); "
+                    help="persistent: 500 steps per launch of one kernel (systems up to 8192 particles here); "
                          "chain: graph-captured launch chains")
     ap.add_argument("--groups", type=int, default=-1, help="workgroups of the persistent kernel (-1: automatic)")
     ap.add_argument("--profile-steps", type=int, default=1000)
@@ -334,13 +336,18 @@ def main():
     if args.tp:
         s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
     persistent = args.mode == "persistent" and state.n <= 8192
-    s.set_persistent(args.groups if persistent else 0)
+    if not args.tune:
+        s.set_persistent(args.groups if persistent else 0)
     if integ[0] == "nvt":
         s.set_integrator_nvt(0.001, integ[2], integ[3])
         s.step(2000)  # relax the random insertion (untimed)
         s.set_integrator_nvt(integ[1], integ[2], integ[3])
     else:
         s.set_integrator_nve(integ[1])
+    if args.tune:
+        # untimed: the autotuner picks layout, list builder and mode from this state
+        s.autotune(args.tune_steps)
+        persistent = s.stats()["persistent_groups"] > 0
     s.step(args.warmup)
     torch.cuda.synchronize()
     st0 = s.stats()

@@ -183,7 +183,7 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
 // latency of a dependent load chain dominates, so many loads go in flight).  The
 // first batch is issued before the list length arrives (clamped to the capacity
 // n_max / TP of a lane), so the length and the first indices share a round trip.
-template <int TP, int METHOD, int B, class IdxPtr>
+template <int TP, int METHOD, int B, bool PF = false, class IdxPtr>
 __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const float4 *__restrict__ pos,
                                            IdxPtr nbl, IdxPtr nnb, const SharedPairs &sp, const SysConst &c,
                                            float &fx, float &fy, float &fz, float &u, float &w) {
@@ -198,7 +198,7 @@ __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const 
   const int nn = nnb[i];
   const int mine = nn > t ? (nn - t + TP - 1) / TP : 0;  // entries of this lane
   for (int m0 = 0; m0 < mine; m0 += B) {
-    if (m0 > 0) {
+    if (!PF && m0 > 0) {
 #pragma unroll
       for (int b = 0; b < B; ++b) {
         // every load is issued (clamped to the lane's last entry) so none waits behind a branch
@@ -212,9 +212,21 @@ __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const 
     float4 q[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) q[b] = pos[j[b] >= 0 ? j[b] : i];
+    // PF: the next batch's indices are issued after this batch's positions, so they
+    // arrive while this batch is evaluated (and a wait for the positions does not wait
+    // for them)
+    int jn[PF ? B : 1];
+    if (PF && m0 + B < mine) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) jn[b] = __builtin_nontemporal_load(row + (long long)min(m0 + B + b, mine - 1) * stride);
+    }
 #pragma unroll
     for (int b = 0; b < B; ++b)
       if (j[b] >= 0) pair_acc<METHOD>(pi, wi, q[b], ti, c.ntypes, sp, c, fx, fy, fz, u, w);
+    if (PF && m0 + B < mine) {
+#pragma unroll
+      for (int b = 0; b < B; ++b) j[b] = jn[b];
+    }
   }
 }
 
@@ -223,6 +235,14 @@ __device__ __forceinline__ void force_lane(int i, int t, const float4 pi, const 
 template <int TP>
 struct Batch {
   static constexpr int value = TP <= 2 ? 16 : TP == 4 ? 8 : TP == 8 ? 16 : TP == 16 ? 8 : TP == 32 ? 4 : 2;
+};
+
+// The launch-chain kernels take at most 8 entries per batch and prefetch the next
+// batch's indices, so two batches' loads are in flight within 128 registers (the
+// persistent kernel, at 2 waves per SIMD, keeps the full batches).
+template <int TP>
+struct StepBatch {
+  static constexpr int value = Batch<TP>::value > 8 ? 8 : Batch<TP>::value;
 };
 
 template <int TP>
@@ -1052,7 +1072,7 @@ __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) 
   if (active) {
     pi = pos[i];
     if (t == 0) vo = p.vel[i];
-    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
+    force_lane<TP, METHOD, StepBatch<TP>::value, true>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
                                              fz, u, w);
   }
   fx = lane_sum<TP>(fx);
@@ -1195,7 +1215,7 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
         z64 = p.pos64[3 * i + 2];
       }
     }
-    force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
+    force_lane<TP, METHOD, StepBatch<TP>::value, true>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
                                              fz, u, w);
   }
   fx = lane_sum<TP>(fx);
@@ -1301,6 +1321,10 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
   __shared__ int s_rebuild;
   __shared__ unsigned s_cnt[MODE == 0 ? kSmallCells + 1 : 1];
   __shared__ int s_id[MODE == 0 ? kSmallN : 1];
+  // the control words are final (the kernels before this one in the stream wrote
+  // them), so they load beside the partials: one memory round trip instead of two
+  CtlView cv{};
+  if (MODE == 0 && threadIdx.x == 0) cv = load_ctl(p.ctl);
   BlockPartial a = zero_partial();
   for (int b = threadIdx.x; b < G; b += blockDim.x) {
     const BlockPartial q = p.part[b];
@@ -1333,7 +1357,7 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
       th->step = ctl->step;
       if (a.nonfinite) ctl->error |= 1;
     } else {
-      rebuild = finish_step(c, p, a, load_ctl(ctl));
+      rebuild = finish_step(c, p, a, cv);
     }
     s_rebuild = rebuild;
   }
@@ -1658,7 +1682,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
             im = gload(p.img, i);
             l0 = gload(p.last, i);
           }
-          force_lane<TP, METHOD, Batch<TP>::value>(i, t, pi, spos, nblg, nnbg, sp, c, fx, fy, fz, uu, w);
+          force_lane<TP, METHOD, Batch<TP>::value, true>(i, t, pi, spos, nblg, nnbg, sp, c, fx, fy, fz, uu, w);
         }
         fx = lane_sum<TP>(fx);
         fy = lane_sum<TP>(fy);

@@ -97,8 +97,11 @@ def test_largest_system_lists_built_from_device_memory(launch):
     b.close()
 
 
-def test_mode_switches_mid_run_and_odd_chunks():
-    n, T, seed = CASES[0]
+@pytest.mark.parametrize("case", [CASES[0], (7000, 0.6, 25)])
+def test_mode_switches_mid_run_and_odd_chunks(case):
+    """Chunks of odd length in both modes, for a system on few and on many workgroups."""
+    n, T, seed = case
+    print(f"mode switches N={n}", flush=True)
     a = _ka(n, T, seed, (8, 32), 0)
     b = _ka(n, T, seed, (8, 32), 0)
     a.step(331)
