@@ -132,8 +132,12 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
  * to 8192 particles and 8192 cells; larger ones fall back to 2), 2 the multi-kernel
  * counting sort.  list_mode: 0 automatic, 1 one wave per particle, 2 one thread per
  * particle (the paper's section 7 layout), 3 one wave per cell (the particles of a
- * cell share one load of their stencil's candidates).  The persistent kernel always
- * builds one wave per particle. */
+ * cell share one load of their stencil's candidates), 4 all pairs (the paper's
+ * O(N^2) builder for small systems, section 6: every particle against every other
+ * in index order, no cells and no spatial sort; systems of at most 8192 particles
+ * and 8192 cells, sort_mode 0 or 1, else SRMD_EINVAL at the next step).  The
+ * persistent kernel builds one wave per particle or per cell for modes 1-3, and all
+ * pairs from its LDS copy of the positions for mode 4. */
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
 
 /* Run the steps of a small system as persistent launches (one launch per 500

@@ -655,6 +655,10 @@ __global__ __launch_bounds__(1024) void k_sort_small(SysConst c, SysPtrs p, int 
   __shared__ unsigned s_cnt[kSmallCells + 1];
   __shared__ int s_id[kSmallN];
   if (p.ctl->rebuild == 0) return;
+  if (c.list_kind == 4) {  // all-pairs lists need no sort, only the build counters reset
+    if (threadIdx.x == 0) begin_build(p.ctl);
+    return;
+  }
   sort_small_block<1024>(c, p, cur, s_cnt, s_id);
 }
 
@@ -773,6 +777,66 @@ __device__ int list_wave_one(const SysConst &c, const SysPtrs &p, int cur, int t
   if (lane == 0) p.nnb[t] = kept;
   longest = max(longest, count);  // the caller reports the longest list and overflow
   return kept;
+}
+
+// Verlet list of particle i against every particle of the system in index order,
+// by the calling wave: the paper's O(N^2) builder for small systems (section 6),
+// which needs no cells and no spatial sort.  Candidates are taken 64 per chunk,
+// kListChunks chunks in flight; a ballot compacts the hits in index order.  pos:
+// the positions of the step (in LDS or device memory).  Also records the position
+// of the build, the reference of the displacement test.  Returns the entries kept
+// (all lanes) and raises longest to the list length before capping.
+__device__ int list_allpairs_one(const SysConst &c, const SysPtrs &p, int i, const float *s_cs2,
+                                 const float4 *pos, int &longest) {
+  const int lane = threadIdx.x & 63;
+  const float4 r = pos[i];
+  if (lane == 0) p.last[i] = r;
+  const int ti = ptype(r);
+  const int nmax = c.n_max;
+  int count = 0;
+  for (int base = 0; base < c.n; base += 64 * kListChunks) {
+    int jj[kListChunks];
+    float4 q[kListChunks];
+#pragma unroll
+    for (int cb = 0; cb < kListChunks; ++cb) {
+      jj[cb] = base + 64 * cb + lane;
+      q[cb] = pos[jj[cb] < c.n ? jj[cb] : i];
+    }
+#pragma unroll
+    for (int cb = 0; cb < kListChunks; ++cb) {
+      bool hit = false;
+      if (jj[cb] < c.n && jj[cb] != i) {
+        float dx, dy, dz;
+        const float r2 = dist2(r, q[cb], c, dx, dy, dz);
+        hit = r2 < s_cs2[ti * c.ntypes + ptype(q[cb])];
+      }
+      const unsigned long long mask = __ballot(hit);
+      const int k = count + __popcll(mask & ((1ull << lane) - 1ull));
+      if (hit && k < nmax) p.nbl[nbl_addr(i, k, c.tp, c.nvp)] = jj[cb];
+      count += __popcll(mask);
+    }
+  }
+  const int kept = min(count, nmax);
+  if (lane == 0) p.nnb[i] = kept;
+  longest = max(longest, count);
+  return kept;
+}
+
+// All-pairs lists for the launch chain, one wave per particle, four per block;
+// the particles keep their order (no sort).
+__global__ __launch_bounds__(256) void k_list_allpairs(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  __shared__ float s_cs2[kMaxPairs];
+  if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+  int kept = 0, longest = 0;
+  if (t < c.n) {  // uniform across the wave
+    const int k = list_allpairs_one(c, p, t, s_cs2, p.pos[cur], longest);
+    if (lane == 0) kept = k;
+  }
+  list_tally(kept, longest, c.n_max, p.ctl);
 }
 
 // One wave per particle (list_wave_one), four particles per block.
@@ -1362,7 +1426,13 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
     s_rebuild = rebuild;
   }
   __syncthreads();
-  if (MODE == 0 && s_rebuild && c.small_sort) sort_small_block<1024>(c, p, next, s_cnt, s_id);
+  if (MODE == 0 && s_rebuild && c.small_sort) {
+    if (c.list_kind == 4) {
+      if (threadIdx.x == 0) begin_build(p.ctl);
+    } else {
+      sort_small_block<1024>(c, p, next, s_cnt, s_id);
+    }
+  }
 }
 
 // ---------------------------------------------------------------- persistent launches
@@ -1589,7 +1659,19 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         sort_gather(c, p, cur, base + tid, stride);
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
-      if (rebuild) {  // the spatial sort has been done (host request, end of step, or above)
+      if (!BIG && rebuild && c.list_kind == 4) {
+        // all pairs from the positions of the step in LDS; no sort, no cells
+        fill_positions(s_dyn, p.pos[cur], c.n);
+        __syncthreads();
+        int kept = 0, longest = 0;
+        for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves) {
+          const int kt = list_allpairs_one(c, p, t, s_cs2, s_dyn, longest);
+          if (lane == 0) kept += kt;
+        }
+        list_tally(kept, longest, c.n_max, p.ctl);
+        if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+        prefilled = true;  // s_dyn holds this step's positions
+      } else if (rebuild) {  // the spatial sort has been done (host request, end of step, or above)
         // the sorted positions and the cell starts go to LDS when they fit beside the
         // candidate windows, so the list build reads no device memory but its own list
         const int cs_words = (c.ncell + 1 + 3) & ~3;
@@ -1753,8 +1835,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       if (!BIG && s_rebuild[j]) {
         // spatial sort of the new positions by piece 0, as k_finish does
         if (J.w == 0) {
-          unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
-          sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+          if (c.list_kind == 4) {  // all-pairs lists need no sort
+            if (tid == 0) begin_build(p.ctl);
+          } else {
+            unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
+            sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+          }
         }
         if (step + 1 < nsteps && !coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
@@ -1927,7 +2013,10 @@ hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, i
     hipLaunchKernelGGL(k_scatter, dim3(gb), dim3(tb), 0, st, c, p);
     hipLaunchKernelGGL(k_gather, dim3(gb), dim3(tb), 0, st, c, p, cur);
   }
-  if (c.list_kind == 1) {
+  if (c.list_kind == 4) {
+    const int lb = (c.n + 3) / 4;
+    hipLaunchKernelGGL(k_list_allpairs, dim3(lb), dim3(tb), 0, st, c, p, cur);
+  } else if (c.list_kind == 1) {
     const int lb = (c.n + 3) / 4;
     hipLaunchKernelGGL(k_list_wave, dim3(lb), dim3(tb), 0, st, c, p, cur);
   } else if (c.list_kind == 2) {

@@ -75,7 +75,7 @@ struct srmd_system {
   // launch shape
   int tp_req = 0, ppb_req = 0, tp = 0, ppb = 0;
   int tp_tuned = 0, ppb_tuned = 0;
-  int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell
+  int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -309,6 +309,9 @@ srmd_status prepare(srmd_system *s) {
   // measured on MI355X (LJ fluid): the cell builder is fastest from 16k to 64k particles and
   // the thread builder from 256k on; the autotuner compares all three
   c.list_kind = s->list_mode != 0 ? s->list_mode : s->n <= 4096 ? 1 : s->n <= 131072 ? 3 : 2;
+  if (c.list_kind == 4 && !c.small_sort)
+    return fail(s, SRMD_EINVAL, "the all-pairs list build takes systems of at most 8192 particles and 8192 cells "
+                                "with the one-workgroup sort mode");
   c.list_blocks = std::max(1, std::min((s->n + 255) / 256, 2048));
   // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
   const double rho = s->n / V;
@@ -1135,8 +1138,8 @@ srmd_status srmd_set_persistent(srmd_system *s, int32_t groups) {
 
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
-  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 3)
-    return fail(s, SRMD_EINVAL, "sort mode must be 0 (auto), 1 or 2 and list mode 0 (auto), 1, 2 or 3");
+  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 4)
+    return fail(s, SRMD_EINVAL, "sort mode must be 0 (auto), 1 or 2 and list mode 0 (auto), 1, 2, 3 or 4");
   s->sort_mode = sort_mode;
   s->list_mode = list_mode;
   s->dirty = true;
@@ -1549,7 +1552,7 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   int dtp, dppb;
   s->tp_req = s->ppb_req = 0;
   launch_of(s, &dtp, &dppb);
-  for (int lm = 1; lm <= 3 && result == SRMD_OK; ++lm) {
+  for (int lm = 1; lm <= (s->c.small_sort ? 4 : 3) && result == SRMD_OK; ++lm) {
     double t;
     result = trial(dtp, dppb, lm, false, &t);
     if (result == SRMD_OK && t < best) {

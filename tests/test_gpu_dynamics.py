@@ -38,7 +38,7 @@ def _in_range_pairs(pos, types, box, rc):
 PATHS = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 3), (2, 3)]
 
 
-@pytest.mark.parametrize("paths", PATHS)
+@pytest.mark.parametrize("paths", PATHS + [(1, 4), (0, 4)])
 def test_rebuild_paths_same_list(paths):
     state = gen.jitter_positions(gen.config1_state(), 0.05, 2)
     sig, eps, rc = gen.ka_params()

@@ -82,7 +82,7 @@ TWO = {
 
 
 @pytest.mark.parametrize("where", list(TWO))
-@pytest.mark.parametrize("paths", [(1, 1), (2, 2), (2, 3)])
+@pytest.mark.parametrize("paths", [(1, 1), (2, 2), (2, 3), (1, 4)])
 def test_two_particles(where, paths):
     print(f"two particles {where} paths={paths}", flush=True)
     st = _state(TWO[where], [0, 0], 8.0, [[0.1, 0.0, -0.05], [-0.1, 0.02, 0.05]], [1.0], f"two {where}")
@@ -170,7 +170,7 @@ def test_fewer_than_five_cells_per_axis():
     the stencil takes every cell of each axis once."""
     print("small box", flush=True)
     st = gen.jitter_positions(gen.lj_fcc_state(200, 0.8442, 0.722, 6), 0.05, 6)
-    for paths in [(1, 1), (2, 2), (2, 3)]:
+    for paths in [(1, 1), (2, 2), (2, 3), (1, 4)]:
         _against_oracle(st, gen.lj_params(), "sp", paths=paths)
     a = _trajectory_vs_oracle(st, gen.lj_params(), "sp", 30, launch=(8, 32))
     b = _trajectory_vs_oracle(st, gen.lj_params(), "sp", 30, launch=(8, 32), persistent=-1)

@@ -174,6 +174,71 @@ def test_profile_reports_one_launch():
     s.close()
 
 
+@pytest.mark.parametrize("launch,groups", [((16, 16), -1), ((8, 32), 13), ((2, 128), 1)])
+def test_all_pairs_lists_persistent_equals_chain(launch, groups):
+    """List mode 4 (all pairs in index order, no sort): the persistent kernel builds
+    from its LDS copy of the positions, the chain from device memory; same lists, same
+    trajectory bit for bit, through rebuilds and a mode switch."""
+    n, T, seed = CASES[2]
+    print(f"all pairs N={n} launch={launch} groups={groups}", flush=True)
+    a = _ka(n, T, seed, launch, 0)
+    b = _ka(n, T, seed, launch, groups)
+    for s in (a, b):
+        s.set_rebuild_path(0, 4)
+    tra = a.step(300, thermo_every=10)
+    trb = b.step(300, thermo_every=10)
+    assert a.thermo()["n_rebuilds"] > 2
+    _same(a, b, tra, trb, f"all pairs {launch}")
+    np.testing.assert_array_equal(a.neighbor_pairs(), b.neighbor_pairs())
+    a.step(57)
+    b.set_persistent(0)
+    b.step(20)
+    b.set_persistent(groups)
+    b.step(37)
+    _same(a, b, label="all pairs after switches")
+    a.close()
+    b.close()
+
+
+def test_all_pairs_overflow_and_rejection():
+    from paper_1506_05094_amd import srmd
+    import torch
+    rng = np.random.default_rng(7)
+    L = 12.0
+    g = (np.arange(9) - 4) * (L / 9)
+    pos = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    pos = (pos + rng.uniform(-0.1, 0.1, pos.shape)).astype(np.float32)
+    vel = (-0.5 * pos).astype(np.float32)
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def contracting(mode):
+        s = srmd.System(pos, np.zeros(len(pos), np.int32), [L, L, L], vel=vel, stream=stream)
+        s.set_skin(0.4)
+        s.set_pair_lj(0, 0, 1.0, 0.05, 2.5, "sp")
+        s.set_integrator_nve(0.002)
+        s.set_launch(8, 32)
+        s.set_rebuild_path(0, 4)
+        s.set_persistent(mode)
+        return s
+
+    a, b = contracting(0), contracting(-1)
+    n0 = b.stats()["n_max"]
+    a.step(400)
+    b.step(400)
+    assert b.stats()["n_max"] > n0
+    _same(a, b, label="all pairs overflow")
+    a.close()
+    b.close()
+    sig, eps, rc = gen.ka_params()
+    big = make_system(gen.ka_random_state(9000, 1.2, 0.5, 3), sig, eps, rc, "sf")
+    big.set_integrator_nve(0.002)
+    big.set_rebuild_path(0, 4)
+    with pytest.raises(srmd.SrmdError) as e:
+        big.step(1)
+    assert e.value.status == srmd.SRMD_EINVAL
+    big.close()
+
+
 @pytest.fixture(scope="module")
 def ka12000():
     return gen.ka_random_state(12000, 1.2, 0.6, 24)
