@@ -1,22 +1,35 @@
 // Device kernels of libsrmd for gfx950 (MI355X).
 //
-// One time step (paper sections 5-7) is a short chain of kernels captured in a HIP
-// graph; the decision to rebuild the neighbour list lives on the device (the
-// paper's device-side flag of section 6), so no step needs the host:
+// One time step (paper sections 5-7) runs in one of two forms with the same
+// per-particle arithmetic in the same order, so both give the same trajectory bit
+// for bit at the same launch shape.
 //
+// Launch chains, captured in HIP graphs; the decision to rebuild the neighbour list
+// lives on the device (the paper's device-side flag of section 6), so no step needs
+// the host:
 //   list rebuild, only when the flag is set (every kernel exits at once otherwise):
 //     small systems: the spatial sort already ran at the end of the previous step
-//                    (k_finish), so only k_list_wave runs here;
-//     large systems: k_bin (cell histogram), k_scan (cell offsets), k_scatter
-//                    (arrival slots), k_gather (deterministic rank by particle id,
-//                    gather of every per-particle array: the reorder of section 7),
-//                    then k_list_thread;
+//                    (k_finish), so only the list kernel runs here;
+//     large systems: k_bin (cells, arrival slots, tile counts), k_scan (cell
+//                    offsets, one workgroup per tile), k_scatter, k_gather
+//                    (deterministic rank by particle id, gather of every
+//                    per-particle array: the reorder of section 7), then the list
+//                    kernel;
+//     list kernels: k_list_wave (a wave per particle), k_list_cell (a wave per
+//                    cell), k_list_thread (a thread per particle), k_list_allpairs
+//                    (all pairs in index order, no sort: the O(N^2) builder of
+//                    section 6);
 //   k_step    pair forces with t_p lanes per particle (sections 3 and 5) fused with
 //             the leapfrog / Nose-Hoover update; float64 partial sums per block;
 //   k_finish  one workgroup: fixed-order float64 reduction of the partials,
 //             thermostat update, thermodynamic record, the displacement test that
 //             sets the rebuild flag (section 6), and for small systems the whole
 //             spatial sort in LDS when a rebuild is due.
+//
+// Persistent (k_multi): every step of a call in one cooperative launch of 500
+// steps, a system split over several workgroups separated by grid barriers, or many
+// systems (a batch of replicas) over the workgroups; the same phases as above run
+// inside it.
 #include <algorithm>
 
 #include "srmd_internal.h"
