@@ -228,6 +228,9 @@ class System:
         _check(load().srmd_set_launch(self._h, int(tp), int(ppb)), self._h)
 
     def set_rebuild_path(self, sort_mode=0, list_mode=0):
+        """sort_mode 0 auto, 1 one-workgroup sort, 2 multi-kernel sort; list_mode 0 auto,
+        1 wave per particle, 2 thread per particle, 3 wave per cell, 4 all pairs (small
+        systems, no sort).  Every mode gives the same pair set."""
         _check(load().srmd_set_rebuild_path(self._h, int(sort_mode), int(list_mode)), self._h)
 
     def set_persistent(self, groups=-1):
