@@ -257,7 +257,12 @@ def run_sweep(args):
         s = srmd.system_from_state(state, sig, eps, rc, "sp", skin=0.3, stream=stream)
         s.set_integrator_nve(0.005)
         s.step(100)
-        tp, ppb = s.autotune(args.tune_steps)
+        tuned = {}
+        if args.tune_full:
+            tuned = s.autotune_full(args.tune_steps, args.tune_cache)
+            tp, ppb = tuned["tp"], tuned["ppb"]
+        else:
+            tp, ppb = s.autotune(args.tune_steps)
         groups = s.stats()["persistent_groups"]
         s.step(args.warmup)
         torch.cuda.synchronize()
@@ -269,6 +274,13 @@ def run_sweep(args):
         row = {"n": state.n, "tp": tp, "ppb": ppb, "mode": "persistent" if groups else "chain", "groups": groups,
                "steps_per_s": args.steps / wall, "particle_steps_per_s": state.n * args.steps / wall,
                "rebuilds": st["n_rebuilds"]}
+        if tuned:
+            row.update({"skin": tuned["skin"], "list_mode": tuned["list_mode"], "trials": tuned["trials"],
+                        "from_cache": tuned["from_cache"],
+                        "trial_steps_per_s_baseline": 1e3 / tuned["baseline_ms_per_step"]
+                        if tuned["baseline_ms_per_step"] > 0 else None,
+                        "trial_steps_per_s_tuned": 1e3 / tuned["tuned_ms_per_step"]
+                        if tuned["tuned_ms_per_step"] > 0 else None})
         log(row)
         rows.append(row)
         s.close()
@@ -285,6 +297,10 @@ def main():
     ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (untimed) after the relaxation; the tuned layout and mode are timed")
+    ap.add_argument("--tune-full", action="store_true",
+                    help="as --tune (and for the size sweep) with the full autotuner: skin optimisation, every "
+                         "list method within 20 %% of the fastest, and the tuned-parameter file of --tune-cache")
+    ap.add_argument("--tune-cache", default=None, help="tuned-parameter file of --tune-full (default: none)")
     ap.add_argument("--sizes", default="1000,4000,16000,64000,256000,1024000", help="N values of the size sweep")
     ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial (size sweep, --tune)")
     ap.add_argument("--replicas", type=int, default=256)
@@ -338,7 +354,7 @@ def main():
     if args.tp:
         s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
     persistent = args.mode == "persistent" and state.n <= 8192
-    if not args.tune:
+    if not (args.tune or args.tune_full):
         s.set_persistent(args.groups if persistent else 0)
     if integ[0] == "nvt":
         s.set_integrator_nvt(0.001, integ[2], integ[3])
@@ -346,7 +362,13 @@ def main():
         s.set_integrator_nvt(integ[1], integ[2], integ[3])
     else:
         s.set_integrator_nve(integ[1])
-    if args.tune:
+    tuned = None
+    if args.tune_full:
+        # untimed: the full autotuner picks layout, list builder, mode and skin
+        tuned = s.autotune_full(args.tune_steps, args.tune_cache)
+        log(f"autotune_full: {tuned}")
+        persistent = s.stats()["persistent_groups"] > 0
+    elif args.tune:
         # untimed: the autotuner picks layout, list builder and mode from this state
         s.autotune(args.tune_steps)
         persistent = s.stats()["persistent_groups"] > 0
@@ -405,7 +427,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"], mode="persistent" if persistent else "chain",
-                       groups=st1["persistent_groups"]),
+                       groups=st1["persistent_groups"], skin=tuned["skin"] if tuned else 0.3),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],
         "roofline": roofline, "cpu_baseline": cpu,

@@ -177,6 +177,74 @@ srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb);
  * state is restored afterwards.  Any output pointer may be NULL. */
 srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out);
 
+/* The "same user parameters" of the paper's appendix (step 8), under which tuned
+ * parameters may be reused: particles of each type, density, temperature,
+ * potential parameters, integrator and time step, and the GPU type.  Pair arrays
+ * are row-major ntypes x ntypes in their first ntypes^2 entries; the rest is zero. */
+typedef struct {
+  char gpu[64];          /* device architecture name (hipDeviceProp_t::gcnArchName) */
+  int32_t compute_units; /* of that device */
+  int32_t precision;     /* srmd_precision */
+  int32_t cutoff_method; /* srmd_cutoff */
+  int32_t thermostat;    /* 0 NVE, 1 Nose-Hoover NVT */
+  int32_t ntypes;
+  int32_t reserved;
+  int64_t count[4];      /* particles of each type */
+  double density;        /* N / V */
+  double temperature;    /* T0 under NVT; under NVE the kinetic temperature 2 KE / (3N - 3) of the state */
+  double dt;
+  double sigma[16], epsilon[16], rcut[16];
+} srmd_tuning_key;
+
+/* Parameters chosen by srmd_autotune_full (or read back from its cache file). */
+typedef struct {
+  int32_t tp, ppb;                /* thread layout, as srmd_set_launch */
+  int32_t list_mode;              /* list-build method, as srmd_set_rebuild_path (1..4) */
+  int32_t persistent;             /* 0 launch chains, -1 the persistent kernel */
+  double skin;                    /* as srmd_set_skin */
+  double baseline_ms_per_step;    /* defaults before tuning (appendix step 2); 0 from the cache */
+  double tuned_ms_per_step;       /* the chosen parameters (appendix step 7); 0 from the cache */
+  int32_t trials;                 /* timed trials run; 0 from the cache */
+  int32_t from_cache;             /* 1: read from the cache file, nothing timed */
+} srmd_tuning;
+
+/* Fill *key with the user parameters of s (integrator and pair potential set).
+ * Reads the velocities back from the device (NVE temperature); no state changes. */
+srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key);
+
+/* Look key up in the tuned-parameter file at path (host code only, no GPU call).
+ * A record matches when the GPU name, compute units, precision, cutoff method,
+ * integrator, type count and particle counts are equal, dt, density and every
+ * pair parameter agree to 1e-6 relative, and the temperature to 2 % relative;
+ * the last matching record wins.  *found = 1 and *out filled on a match, else
+ * *found = 0.  A missing file is no match; unreadable or malformed lines are
+ * skipped.  SRMD_EINVAL for NULL arguments. */
+srmd_status srmd_tuning_cache_find(const char *path, const srmd_tuning_key *key, srmd_tuning *out, int32_t *found);
+
+/* Append one record (key and the tuned parameters of t) to the file at path, one
+ * text line per record (host code only).  SRMD_EINVAL if the file cannot be
+ * opened for appending or an argument is NULL. */
+srmd_status srmd_tuning_cache_store(const char *path, const srmd_tuning_key *key, const srmd_tuning *t);
+
+/* The autotuner of the paper's appendix with its skin optimisation and its
+ * tuned-parameter file.  With cache_path non-NULL and a matching record there
+ * (srmd_tuning_cache_find), the record is applied and nothing is timed.
+ * Otherwise, from a saved copy of the state (every trial starts from it):
+ * a baseline trial at the defaults; phase I, each list-build method at the
+ * default layout with the skin optimised separately in steps of 20 %; phase II,
+ * for each method within 20 % of the fastest, block size x tp with the
+ * appendix's stop rules and the skin re-optimised in steps of 10 % from the
+ * last optimum at every layout; for systems the persistent kernel can run, the
+ * same t_p loop in persistent mode; a final trial of the chosen set.  A skin step
+ * multiplies the current value by 1.2 or 0.8 (1.1 or 0.9) and the search
+ * goes on in the direction that was faster until a trial is slower; skins that
+ * would put r_c + skin past half a box side, or that the chosen list method
+ * cannot run, count as slower.  The chosen layout, list method, mode and skin
+ * are applied as srmd_set_launch, srmd_set_rebuild_path, srmd_set_persistent
+ * and srmd_set_skin would (they override earlier explicit choices), the state
+ * is restored, and with cache_path non-NULL a record is appended.  out may be NULL. */
+srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const char *cache_path, srmd_tuning *out);
+
 /* Bin, sort and rebuild the neighbour list now, whatever the displacement. */
 srmd_status srmd_build_neighbor_list(srmd_system *s);
 

@@ -2,8 +2,10 @@
 // grid and list capacity, the graph-captured step chunks, list-overflow recovery
 // and the original-order views of the state.
 #include <algorithm>
+#include <cctype>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -1639,6 +1641,535 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   if (result != SRMD_OK) return result;
   if (tp_out) *tp_out = best_tp;
   if (ppb_out) *ppb_out = best_ppb;
+  return SRMD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Tuned-parameter file (paper appendix, step 8).  One text line per record:
+//   srmd-tuning-v1 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
+//   count=<c_0,...> dt=<x> temperature=<x> density=<x> sigma=<k*k values>
+//   epsilon=<k*k values> rcut=<k*k values> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x>
+// Floating-point fields are printed with 17 significant digits, so they read back
+// to the same double.
+}  // extern "C"
+
+namespace {
+
+constexpr const char *kTuneTag = "srmd-tuning-v1";
+constexpr double kTuneRelTol = 1e-6;   // dt, density and pair parameters
+constexpr double kTuneTempTol = 0.02;  // temperature
+
+std::string gpu_token(const char *g) {
+  std::string r;
+  for (size_t i = 0; i < sizeof(srmd_tuning_key::gpu) && g[i]; ++i)
+    r += (std::isspace((unsigned char)g[i]) || g[i] == '=' || g[i] == ',') ? '_' : g[i];
+  return r.empty() ? std::string("unknown") : r;
+}
+
+bool rel_close(double a, double b, double tol) { return std::fabs(a - b) <= tol * std::max(std::fabs(a), std::fabs(b)); }
+
+bool key_valid(const srmd_tuning_key &k) { return k.ntypes >= 1 && k.ntypes <= kMaxTypes; }
+
+bool tuning_valid(const srmd_tuning &t) {
+  const bool tp_ok = t.tp >= 1 && t.tp <= 64 && (t.tp & (t.tp - 1)) == 0;
+  const bool ppb_ok = t.ppb >= 1 && (long long)t.tp * t.ppb <= 1024 && (t.tp * t.ppb) % 64 == 0;
+  return tp_ok && ppb_ok && t.list_mode >= 1 && t.list_mode <= 4 && (t.persistent == 0 || t.persistent == -1) &&
+         t.skin >= 0 && std::isfinite(t.skin);
+}
+
+bool key_match(const srmd_tuning_key &a, const srmd_tuning_key &b) {
+  if (gpu_token(a.gpu) != gpu_token(b.gpu) || a.compute_units != b.compute_units || a.precision != b.precision ||
+      a.cutoff_method != b.cutoff_method || a.thermostat != b.thermostat || a.ntypes != b.ntypes)
+    return false;
+  for (int t = 0; t < a.ntypes; ++t)
+    if (a.count[t] != b.count[t]) return false;
+  if (!rel_close(a.dt, b.dt, kTuneRelTol) || !rel_close(a.density, b.density, kTuneRelTol) ||
+      !rel_close(a.temperature, b.temperature, kTuneTempTol))
+    return false;
+  for (int q = 0; q < a.ntypes * a.ntypes; ++q)
+    if (!rel_close(a.sigma[q], b.sigma[q], kTuneRelTol) || !rel_close(a.epsilon[q], b.epsilon[q], kTuneRelTol) ||
+        !rel_close(a.rcut[q], b.rcut[q], kTuneRelTol))
+      return false;
+  return true;
+}
+
+std::string tuning_line(const srmd_tuning_key &k, const srmd_tuning &t) {
+  std::string o = kTuneTag;
+  char buf[64];
+  auto num = [&](double x) {
+    std::snprintf(buf, sizeof buf, "%.17g", x);
+    return std::string(buf);
+  };
+  auto field = [&](const char *name, const std::string &v) {
+    o += ' ';
+    o += name;
+    o += '=';
+    o += v;
+  };
+  auto nums = [&](const double *v, int m) {
+    std::string r;
+    for (int q = 0; q < m; ++q) r += (q ? "," : "") + num(v[q]);
+    return r;
+  };
+  field("gpu", gpu_token(k.gpu));
+  field("cus", std::to_string(k.compute_units));
+  field("prec", std::to_string(k.precision));
+  field("method", std::to_string(k.cutoff_method));
+  field("thermostat", std::to_string(k.thermostat));
+  field("ntypes", std::to_string(k.ntypes));
+  std::string cnt;
+  for (int q = 0; q < k.ntypes; ++q) cnt += (q ? "," : "") + std::to_string((long long)k.count[q]);
+  field("count", cnt);
+  field("dt", num(k.dt));
+  field("temperature", num(k.temperature));
+  field("density", num(k.density));
+  field("sigma", nums(k.sigma, k.ntypes * k.ntypes));
+  field("epsilon", nums(k.epsilon, k.ntypes * k.ntypes));
+  field("rcut", nums(k.rcut, k.ntypes * k.ntypes));
+  field("tp", std::to_string(t.tp));
+  field("ppb", std::to_string(t.ppb));
+  field("list", std::to_string(t.list_mode));
+  field("persistent", std::to_string(t.persistent));
+  field("skin", num(t.skin));
+  return o;
+}
+
+// Split "a,b,c" and parse exactly m numbers (integers when ints is set).
+bool parse_list(const std::string &s, int m, double *d, long long *ll) {
+  size_t pos = 0;
+  for (int q = 0; q < m; ++q) {
+    const size_t end = s.find(',', pos);
+    const std::string tok = s.substr(pos, end == std::string::npos ? std::string::npos : end - pos);
+    if (tok.empty()) return false;
+    char *e = nullptr;
+    if (ll) {
+      ll[q] = std::strtoll(tok.c_str(), &e, 10);
+    } else {
+      d[q] = std::strtod(tok.c_str(), &e);
+      if (!std::isfinite(d[q])) return false;
+    }
+    if (!e || *e != '\0') return false;
+    if ((end == std::string::npos) != (q == m - 1)) return false;
+    pos = end + 1;
+  }
+  return true;
+}
+
+bool parse_tuning_line(const std::string &line, srmd_tuning_key *k, srmd_tuning *t) {
+  std::map<std::string, std::string> kv;
+  size_t pos = 0;
+  bool first = true;
+  while (pos < line.size()) {
+    while (pos < line.size() && std::isspace((unsigned char)line[pos])) ++pos;
+    if (pos >= line.size()) break;
+    size_t end = pos;
+    while (end < line.size() && !std::isspace((unsigned char)line[end])) ++end;
+    const std::string tok = line.substr(pos, end - pos);
+    pos = end;
+    if (first) {
+      if (tok != kTuneTag) return false;
+      first = false;
+      continue;
+    }
+    const size_t eq = tok.find('=');
+    if (eq == std::string::npos || eq == 0) return false;
+    kv[tok.substr(0, eq)] = tok.substr(eq + 1);
+  }
+  if (first) return false;
+  auto one_int = [&](const char *name, long long *v) {
+    auto it = kv.find(name);
+    return it != kv.end() && parse_list(it->second, 1, nullptr, v);
+  };
+  auto one_num = [&](const char *name, double *v) {
+    auto it = kv.find(name);
+    return it != kv.end() && parse_list(it->second, 1, v, nullptr);
+  };
+  std::memset(k, 0, sizeof(*k));
+  std::memset(t, 0, sizeof(*t));
+  long long v[8];
+  auto gi = kv.find("gpu");
+  if (gi == kv.end() || gi->second.empty() || gi->second.size() >= sizeof(k->gpu)) return false;
+  std::memcpy(k->gpu, gi->second.c_str(), gi->second.size());
+  if (!one_int("cus", &v[0]) || !one_int("prec", &v[1]) || !one_int("method", &v[2]) ||
+      !one_int("thermostat", &v[3]) || !one_int("ntypes", &v[4]))
+    return false;
+  if (v[4] < 1 || v[4] > kMaxTypes) return false;
+  k->compute_units = (int32_t)v[0];
+  k->precision = (int32_t)v[1];
+  k->cutoff_method = (int32_t)v[2];
+  k->thermostat = (int32_t)v[3];
+  k->ntypes = (int32_t)v[4];
+  const int nt = k->ntypes;
+  long long cnt[kMaxTypes];
+  auto ci = kv.find("count");
+  if (ci == kv.end() || !parse_list(ci->second, nt, nullptr, cnt)) return false;
+  for (int q = 0; q < nt; ++q) k->count[q] = cnt[q];
+  if (!one_num("dt", &k->dt) || !one_num("temperature", &k->temperature) || !one_num("density", &k->density))
+    return false;
+  const char *arr_names[3] = {"sigma", "epsilon", "rcut"};
+  double *arrs[3] = {k->sigma, k->epsilon, k->rcut};
+  for (int a = 0; a < 3; ++a) {
+    auto it = kv.find(arr_names[a]);
+    if (it == kv.end() || !parse_list(it->second, nt * nt, arrs[a], nullptr)) return false;
+  }
+  if (!one_int("tp", &v[0]) || !one_int("ppb", &v[1]) || !one_int("list", &v[2]) || !one_int("persistent", &v[3]) ||
+      !one_num("skin", &t->skin))
+    return false;
+  for (int q = 0; q < 4; ++q)
+    if (v[q] < -1 || v[q] > 1024) return false;
+  t->tp = (int32_t)v[0];
+  t->ppb = (int32_t)v[1];
+  t->list_mode = (int32_t)v[2];
+  t->persistent = (int32_t)v[3];
+  return tuning_valid(*t);
+}
+
+}  // namespace
+
+extern "C" {
+
+srmd_status srmd_tuning_cache_find(const char *path, const srmd_tuning_key *key, srmd_tuning *out, int32_t *found) {
+  if (!path || !key || !out || !found) return fail(nullptr, SRMD_EINVAL, "path, key, out and found are required");
+  if (!key_valid(*key)) return fail(nullptr, SRMD_EINVAL, "key.ntypes must be in 1..4");
+  *found = 0;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return SRMD_OK;  // no file: nothing tuned yet
+  std::string line;
+  char buf[1024];
+  srmd_tuning best{};
+  while (std::fgets(buf, sizeof buf, f)) {
+    line += buf;
+    if (line.empty() || line.back() != '\n') {
+      if (!std::feof(f)) continue;  // a line longer than the buffer: keep reading it
+    }
+    srmd_tuning_key k;
+    srmd_tuning t;
+    if (parse_tuning_line(line, &k, &t) && key_match(*key, k)) {
+      best = t;
+      *found = 1;
+    }
+    line.clear();
+  }
+  std::fclose(f);
+  if (*found) {
+    best.from_cache = 1;
+    *out = best;
+  }
+  return SRMD_OK;
+}
+
+srmd_status srmd_tuning_cache_store(const char *path, const srmd_tuning_key *key, const srmd_tuning *t) {
+  if (!path || !key || !t) return fail(nullptr, SRMD_EINVAL, "path, key and tuning are required");
+  if (!key_valid(*key)) return fail(nullptr, SRMD_EINVAL, "key.ntypes must be in 1..4");
+  if (!tuning_valid(*t)) return fail(nullptr, SRMD_EINVAL, "tuning values out of range");
+  FILE *f = std::fopen(path, "a");
+  if (!f) return fail(nullptr, SRMD_EINVAL, std::string("cannot open ") + path + " for appending");
+  const std::string line = tuning_line(*key, *t) + "\n";
+  const bool ok = std::fwrite(line.data(), 1, line.size(), f) == line.size();
+  const bool closed = std::fclose(f) == 0;
+  if (!ok || !closed) return fail(nullptr, SRMD_EINVAL, std::string("write to ") + path + " failed");
+  return SRMD_OK;
+}
+
+srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key) {
+  if (!s || !key) return fail(s, SRMD_EINVAL, "system and key are required");
+  if (!s->integrator_set) return fail(s, SRMD_EINVAL, "integrator not set");
+  if (s->method < 0 || !all_pairs_given(s))
+    return fail(s, SRMD_EINVAL, "pair potential not set for every type pair (srmd_set_pair_lj)");
+  std::memset(key, 0, sizeof(*key));
+  int dev = 0;
+  HIPCHK(s, hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIPCHK(s, hipGetDeviceProperties(&prop, dev));
+  const std::string g = gpu_token(prop.gcnArchName);
+  std::memcpy(key->gpu, g.c_str(), std::min(g.size(), sizeof(key->gpu) - 1));
+  key->compute_units = prop.multiProcessorCount;
+  key->precision = (int32_t)s->prec;
+  key->cutoff_method = s->method;
+  key->thermostat = s->thermostat;
+  key->ntypes = s->ntypes;
+  const size_t n = (size_t)s->n;
+  std::vector<float4> pos(n), vel(n);
+  HIPCHK(s, hipMemcpyAsync(pos.data(), s->p.pos[s->cur], sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(vel.data(), s->p.vel, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  double ke = 0.0;
+  for (size_t i = 0; i < n; ++i) {
+    int ty;
+    std::memcpy(&ty, &pos[i].w, 4);  // the type travels in the fourth component
+    if (ty < 0 || ty >= s->ntypes) return fail(s, SRMD_ESTATE, "particle type out of range on the device");
+    key->count[ty] += 1;
+    const double vx = vel[i].x, vy = vel[i].y, vz = vel[i].z;
+    ke += 0.5 * s->mass[ty] * (vx * vx + vy * vy + vz * vz);
+  }
+  key->density = (double)s->n / ((double)s->Lf[0] * (double)s->Lf[1] * (double)s->Lf[2]);
+  key->temperature = s->thermostat ? s->T0 : 2.0 * ke / (3.0 * (double)s->n - 3.0);
+  key->dt = s->dt;
+  for (int a = 0; a < s->ntypes; ++a)
+    for (int b = 0; b < s->ntypes; ++b) {
+      const int q = a * s->ntypes + b, pi = pair_index(s, a, b);
+      key->sigma[q] = s->sigma[pi];
+      key->epsilon[q] = s->eps[pi];
+      key->rcut[q] = s->rc[pi];
+    }
+  return SRMD_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Make t the system's settings, as the explicit setters would.
+void apply_tuning(srmd_system *s, const srmd_tuning &t) {
+  s->tp_req = t.tp;
+  s->ppb_req = t.ppb;
+  s->list_mode = t.list_mode;
+  s->persist_req = t.persistent;
+  s->persist_set = true;
+  s->skin = t.skin;
+  s->dirty = true;
+}
+
+bool skin_fits(const srmd_system *s, double skin) {
+  if (!(skin > 0) || !std::isfinite(skin)) return false;
+  const double rcm = rc_max(s);
+  for (int k = 0; k < 3; ++k)
+    if (!(rcm + skin < 0.5 * (double)s->Lf[k])) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const char *cache_path, srmd_tuning *out) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!s->integrator_set) return fail(s, SRMD_EINVAL, "integrator not set");
+  if (steps_per_trial < 1) return fail(s, SRMD_EINVAL, "steps_per_trial must be >= 1");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  srmd_tuning_key key{};
+  if (cache_path) {
+    st = srmd_tuning_key_of(s, &key);
+    if (st != SRMD_OK) return st;
+    srmd_tuning hit{};
+    int32_t found = 0;
+    st = srmd_tuning_cache_find(cache_path, &key, &hit, &found);
+    if (st != SRMD_OK) return fail(s, st, srmd_last_error(nullptr));
+    if (found && skin_fits(s, hit.skin)) {
+      // a record from the same user parameters: applied without timing anything
+      const int tp0 = s->tp_req, ppb0 = s->ppb_req, lm0 = s->list_mode, pr0 = s->persist_req;
+      const bool ps0 = s->persist_set;
+      const double sk0 = s->skin;
+      apply_tuning(s, hit);
+      st = prepare(s);
+      if (st == SRMD_OK && s->persist_err.empty()) {
+        if (out) *out = hit;
+        return SRMD_OK;
+      }
+      // the record does not fit this system after all (e.g. another box shape): tune
+      s->tp_req = tp0;
+      s->ppb_req = ppb0;
+      s->list_mode = lm0;
+      s->persist_req = pr0;
+      s->persist_set = ps0;
+      s->skin = sk0;
+      s->dirty = true;
+      st = prepare(s);
+      if (st != SRMD_OK) return st;
+    }
+  }
+  HostState saved;
+  st = save_host_state(s, &saved);
+  if (st != SRMD_OK) return st;
+  const int tp0 = s->tp_req, ppb0 = s->ppb_req, list0 = s->list_mode;
+  const int preq0 = s->persist_req;
+  const bool pset0 = s->persist_set;
+  const int nmax0 = s->n_max;
+  const double skin0 = s->skin;
+  const bool persist0 = pset0 ? preq0 != 0 : s->persist_tuned != 0;
+  hipEvent_t e0, e1;
+  HIPCHK(s, hipEventCreate(&e0));
+  HIPCHK(s, hipEventCreate(&e1));
+  int ntrials = 0;
+  // one timed trial from the stored state; settings this system cannot run
+  // (a skin past half a box side, the all-pairs builder over too many cells, the
+  // persistent kernel where it is not available) time as 1e30
+  auto trial = [&](int tp, int ppb, int list_mode, bool persistent, double skin, double *ms_per_step) -> srmd_status {
+    *ms_per_step = 1e30;
+    if (!skin_fits(s, skin)) return SRMD_OK;
+    s->tp_req = tp;
+    s->ppb_req = ppb;
+    s->list_mode = list_mode;
+    s->persist_set = true;
+    s->persist_req = persistent ? -1 : 0;
+    s->skin = skin;
+    s->n_max = nmax0;  // the list capacity follows the trial's skin
+    s->dirty = true;
+    srmd_status r = restore_host_state(s, saved);
+    if (r != SRMD_OK) return r;
+    r = prepare(s);
+    if (r == SRMD_EINVAL) return SRMD_OK;
+    if (r != SRMD_OK) return r;
+    if (persistent && s->persist_groups == 0) return SRMD_OK;
+    if (!s->persist_err.empty()) return SRMD_OK;
+    ++ntrials;
+    r = run_steps(s, 16);  // graph instantiation and the first build, untimed
+    if (r != SRMD_OK) return r;
+    HIPCHK(s, hipEventRecord(e0, s->stream));
+    r = run_steps(s, steps_per_trial);
+    if (r != SRMD_OK) return r;
+    HIPCHK(s, hipEventRecord(e1, s->stream));
+    HIPCHK(s, hipEventSynchronize(e1));
+    Control h;
+    r = read_ctl(s, &h);
+    if (r != SRMD_OK) return r;
+    r = check_barrier(s, &h);
+    if (r != SRMD_OK) return r;
+    float ms = 0.f;
+    HIPCHK(s, hipEventElapsedTime(&ms, e0, e1));
+    *ms_per_step = (h.error & 3) ? 1e30 : (double)ms / steps_per_trial;
+    if (h.error & 3) {
+      h.error &= ~3;
+      r = h2d_sync(s, s->p.ctl, &h, sizeof(Control));
+    }
+    return r;
+  };
+  // the skin line search of the appendix: from start, steps of the factor 1 + step
+  // up, and if the first one up is not faster, 1 - step down, until a trial is slower
+  auto skin_search = [&](int tp, int ppb, int lm, bool persistent, double start, double step, double *skin_best,
+                         double *t_best) -> srmd_status {
+    double t0;
+    srmd_status r = trial(tp, ppb, lm, persistent, start, &t0);
+    double bs = start, bt = t0;
+    for (int dir = 0; dir < 2 && r == SRMD_OK && bt < 1e30; ++dir) {
+      const double f = dir == 0 ? 1.0 + step : 1.0 - step;
+      bool better = false;
+      double sk = bs * f;
+      for (int k = 0; k < 16 && r == SRMD_OK; ++k, sk *= f) {
+        double t;
+        r = trial(tp, ppb, lm, persistent, sk, &t);
+        if (r != SRMD_OK || !(t < bt)) break;
+        bs = sk;
+        bt = t;
+        better = true;
+      }
+      if (better) break;
+    }
+    *skin_best = bs;
+    *t_best = bt;
+    return r;
+  };
+  srmd_status result = SRMD_OK;
+  const double start = skin0 > 0 ? skin0 : 0.3;  // a zero skin starts from the library default
+  // baseline (appendix step 2): the settings in force at the call
+  double t_base = 1e30;
+  result = trial(tp0, ppb0, list0, persist0, skin0 > 0 ? skin0 : start, &t_base);
+  // phase I (step 3): every list method at the default layout, each with its own skin
+  int dtp, dppb;
+  s->tp_req = s->ppb_req = 0;
+  s->persist_set = true;
+  s->persist_req = 0;  // the default layout of the launch chains
+  launch_of(s, &dtp, &dppb);
+  const int n_lm = s->c.small_sort ? 4 : 3;
+  double t1[5] = {1e30, 1e30, 1e30, 1e30, 1e30}, sk1[5] = {start, start, start, start, start};
+  for (int lm = 1; lm <= n_lm && result == SRMD_OK; ++lm) result = skin_search(dtp, dppb, lm, false, start, 0.2, &sk1[lm], &t1[lm]);
+  double t1_best = 1e30;
+  for (int lm = 1; lm <= n_lm; ++lm) t1_best = std::min(t1_best, t1[lm]);
+  srmd_tuning best{};
+  double best_t = 1e30;
+  auto consider = [&](int tp, int ppb, int lm, bool persistent, double skin, double t) {
+    if (t < best_t) {
+      best_t = t;
+      best.tp = tp;
+      best.ppb = ppb;
+      best.list_mode = lm;
+      best.persistent = persistent ? -1 : 0;
+      best.skin = skin;
+    }
+  };
+  for (int lm = 1; lm <= n_lm; ++lm) consider(dtp, dppb, lm, false, sk1[lm], t1[lm]);
+  // phase II (step 4): methods within 20 % of the fastest; block size x t_p with the
+  // stop rules of phase II of srmd_autotune, the skin re-optimised at every layout
+  const int blocks[] = {64, 128, 256, 512, 1024};
+  const int tp_max = s->n > 100000 ? 2 : 64;
+  for (int lm = 1; lm <= n_lm && result == SRMD_OK; ++lm) {
+    if (!(t1[lm] < 1e30) || t1[lm] > 1.2 * t1_best) continue;
+    double skin_last = sk1[lm];
+    double prev_block_best = 1e300, lm_best = t1[lm];
+    for (int bi = 0; bi < 5 && result == SRMD_OK; ++bi) {
+      const int bsz = blocks[bi];
+      double block_best = 1e300;
+      int slower = 0;
+      for (int tp = 1; tp <= tp_max && tp <= bsz && result == SRMD_OK; tp <<= 1) {
+        double t, sk;
+        result = skin_search(tp, bsz / tp, lm, false, skin_last, 0.1, &sk, &t);
+        if (result != SRMD_OK) break;
+        if (t < 1e30) skin_last = sk;
+        if (t < block_best) {
+          block_best = t;
+          slower = 0;
+        } else {
+          ++slower;
+        }
+        consider(tp, bsz / tp, lm, false, sk, t);
+        lm_best = std::min(lm_best, t);
+        if (slower >= 3 || t > 1.05 * block_best) break;
+      }
+      if (block_best > 1.10 * std::min(lm_best, prev_block_best) && bi > 0) break;
+      prev_block_best = std::min(prev_block_best, block_best);
+    }
+  }
+  // the persistent kernel (MI355X): the t_p loop at 256-thread virtual blocks for the
+  // best list method so far, the skin re-optimised from the best skin
+  if (result == SRMD_OK && s->prec == SRMD_PREC_F32 && best_t < 1e30) {
+    const int lm = best.list_mode;
+    double skin_last = best.skin, pbest = 1e300;
+    int slower = 0;
+    for (int tp = 1; tp <= 64 && result == SRMD_OK; tp <<= 1) {
+      double t, sk;
+      result = skin_search(tp, 256 / tp, lm, true, skin_last, 0.1, &sk, &t);
+      if (result != SRMD_OK || !(t < 1e30)) break;
+      skin_last = sk;
+      if (t < pbest) {
+        pbest = t;
+        slower = 0;
+      } else {
+        ++slower;
+      }
+      consider(tp, 256 / tp, lm, true, sk, t);
+      if (slower >= 3 || t > 1.05 * pbest) break;
+    }
+  }
+  // step 7: the chosen set, timed as the baseline was
+  double t_final = 1e30;
+  if (result == SRMD_OK && best_t < 1e30)
+    result = trial(best.tp, best.ppb, best.list_mode, best.persistent != 0, best.skin, &t_final);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  s->tp_req = tp0;
+  s->ppb_req = ppb0;
+  s->list_mode = list0;
+  s->persist_req = preq0;
+  s->persist_set = pset0;
+  s->skin = skin0;
+  s->n_max = nmax0;
+  if (result == SRMD_OK && !(best_t < 1e30)) result = fail(s, SRMD_ESTATE, "no trial of the autotuner completed");
+  if (result == SRMD_OK) apply_tuning(s, best);
+  s->dirty = true;
+  srmd_status r2 = restore_host_state(s, saved);
+  if (result == SRMD_OK) result = r2;
+  if (result == SRMD_OK) result = prepare(s);
+  if (result != SRMD_OK) return result;
+  best.baseline_ms_per_step = t_base < 1e30 ? t_base : 0.0;
+  best.tuned_ms_per_step = t_final < 1e30 ? t_final : 0.0;
+  best.trials = ntrials;
+  best.from_cache = 0;
+  if (cache_path) {
+    st = srmd_tuning_cache_store(cache_path, &key, &best);
+    if (st != SRMD_OK) return fail(s, st, srmd_last_error(nullptr));
+  }
+  if (out) *out = best;
   return SRMD_OK;
 }
 

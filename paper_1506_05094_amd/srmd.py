@@ -42,6 +42,59 @@ class srmd_stats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class srmd_tuning_key(ctypes.Structure):
+    _fields_ = [("gpu", ctypes.c_char * 64), ("compute_units", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("cutoff_method", ctypes.c_int32), ("thermostat", ctypes.c_int32), ("ntypes", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("count", ctypes.c_int64 * 4), ("density", ctypes.c_double),
+                ("temperature", ctypes.c_double), ("dt", ctypes.c_double), ("sigma", ctypes.c_double * 16),
+                ("epsilon", ctypes.c_double * 16), ("rcut", ctypes.c_double * 16)]
+
+    def as_dict(self):
+        k = self.ntypes
+        d = {name: getattr(self, name) for name in ("compute_units", "precision", "cutoff_method", "thermostat",
+                                                    "ntypes", "density", "temperature", "dt")}
+        d["gpu"] = self.gpu.decode()
+        d["count"] = list(self.count[:k])
+        for name in ("sigma", "epsilon", "rcut"):
+            d[name] = np.array(getattr(self, name)[:k * k]).reshape(k, k)
+        return d
+
+    @classmethod
+    def from_dict(cls, d):
+        k = cls()
+        k.gpu = d["gpu"].encode()
+        for name in ("compute_units", "precision", "cutoff_method", "thermostat", "ntypes", "density",
+                     "temperature", "dt"):
+            setattr(k, name, d[name])
+        nt = int(d["ntypes"])
+        for q, c in enumerate(d["count"]):
+            k.count[q] = int(c)
+        for name in ("sigma", "epsilon", "rcut"):
+            a = np.asarray(d[name], np.float64).reshape(-1)
+            assert a.size == nt * nt
+            for q, v in enumerate(a):
+                getattr(k, name)[q] = float(v)
+        return k
+
+
+class srmd_tuning(ctypes.Structure):
+    _fields_ = [("tp", ctypes.c_int32), ("ppb", ctypes.c_int32), ("list_mode", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("skin", ctypes.c_double),
+                ("baseline_ms_per_step", ctypes.c_double), ("tuned_ms_per_step", ctypes.c_double),
+                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for name, _ in cls._fields_:
+            if name in d:
+                setattr(t, name, d[name])
+        return t
+
+
 THERMO_DTYPE = np.dtype([(name, np.float64) for name in
                          ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_integral", "h_conserved",
                           "ke_half")] + [("step", np.int64), ("n_rebuilds", np.int64), ("max_nbrs", np.int32),
@@ -101,6 +154,12 @@ def load():
         "srmd_batch_destroy": (st, [ctypes.c_void_p]),
         "srmd_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
         "srmd_autotune": (st, [sysp, ctypes.c_int32, _ip, _ip]),
+        "srmd_tuning_key_of": (st, [sysp, ctypes.POINTER(srmd_tuning_key)]),
+        "srmd_tuning_cache_find": (st, [ctypes.c_char_p, ctypes.POINTER(srmd_tuning_key),
+                                        ctypes.POINTER(srmd_tuning), _ip]),
+        "srmd_tuning_cache_store": (st, [ctypes.c_char_p, ctypes.POINTER(srmd_tuning_key),
+                                         ctypes.POINTER(srmd_tuning)]),
+        "srmd_autotune_full": (st, [sysp, ctypes.c_int32, ctypes.c_char_p, ctypes.POINTER(srmd_tuning)]),
         "srmd_build_neighbor_list": (st, [sysp]),
         "srmd_compute_forces": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
         "srmd_step": (st, [sysp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
@@ -248,6 +307,20 @@ class System:
         _check(load().srmd_autotune(self._h, int(steps_per_trial), ctypes.byref(a), ctypes.byref(b)), self._h)
         return a.value, b.value
 
+    def autotune_full(self, steps_per_trial=200, cache_path=None):
+        """The appendix's autotuner with skin optimisation; with cache_path, its
+        tuned-parameter file is read first and written after tuning.  Returns the
+        chosen parameters as a dict (srmd_tuning)."""
+        t = srmd_tuning()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(load().srmd_autotune_full(self._h, int(steps_per_trial), path, ctypes.byref(t)), self._h)
+        return t.as_dict()
+
+    def tuning_key(self):
+        k = srmd_tuning_key()
+        _check(load().srmd_tuning_key_of(self._h, ctypes.byref(k)), self._h)
+        return k.as_dict()
+
     # -- compute
     def build_neighbor_list(self):
         _check(load().srmd_build_neighbor_list(self._h), self._h)
@@ -366,7 +439,8 @@ class Batch:
 
 EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_lj", "srmd_set_skin",
             "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
-            "srmd_autotune", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
+            "srmd_autotune", "srmd_tuning_key_of", "srmd_tuning_cache_find", "srmd_tuning_cache_store",
+            "srmd_autotune_full", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
             "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
@@ -387,6 +461,23 @@ def _export_c_names():
 
 
 _export_c_names()
+
+
+def tuning_cache_find(path, key):
+    """Look a key (dict of srmd_tuning_key fields) up in a tuned-parameter file;
+    returns the stored parameters as a dict, or None."""
+    k = srmd_tuning_key.from_dict(key)
+    t = srmd_tuning()
+    found = ctypes.c_int32()
+    _check(load().srmd_tuning_cache_find(os.fsencode(path), ctypes.byref(k), ctypes.byref(t), ctypes.byref(found)))
+    return t.as_dict() if found.value else None
+
+
+def tuning_cache_store(path, key, tuning):
+    """Append a record (key and tuned parameters, both dicts) to a tuned-parameter file."""
+    k = srmd_tuning_key.from_dict(key)
+    t = srmd_tuning.from_dict(tuning)
+    _check(load().srmd_tuning_cache_store(os.fsencode(path), ctypes.byref(k), ctypes.byref(t)))
 
 
 def system_from_state(state, sigma, eps, rc, method, skin=0.3, precision="f32", stream=None):

@@ -1,0 +1,160 @@
+"""CPU checks of the tuned-parameter file (paper appendix, step 8): a record is
+reused only under the same user parameters (particles of each type, density,
+temperature, potential parameters, integrator and time step, GPU type), within
+the stated tolerances; the last matching record wins; damaged lines are skipped.
+These entry points are host code only and run without a GPU."""
+import copy
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def srmd():
+    from paper_1506_05094_amd import srmd as m
+    if not os.path.exists(m.library_path()):
+        from paper_1506_05094_amd import build
+        build.build()
+    m.load()
+    return m
+
+
+def _key():
+    return {
+        "gpu": "gfx950:sramecc+:xnack-", "compute_units": 256, "precision": 0, "cutoff_method": 1, "thermostat": 1,
+        "ntypes": 2, "count": [3277, 819], "density": 1.2, "temperature": 0.8, "dt": 0.005,
+        "sigma": [[1.0, 0.8], [0.8, 0.88]], "epsilon": [[1.0, 1.5], [1.5, 0.5]],
+        "rcut": [[2.5, 2.0], [2.0, 2.2]],
+    }
+
+
+def _tuning(tp=16, ppb=16, skin=0.3 + 1e-13):
+    return {"tp": tp, "ppb": ppb, "list_mode": 1, "persistent": -1, "skin": skin}
+
+
+def test_missing_file_is_no_match(srmd, tmp_path):
+    assert srmd.tuning_cache_find(str(tmp_path / "none.txt"), _key()) is None
+
+
+def test_round_trip_is_exact(srmd, tmp_path):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), _tuning())
+    got = srmd.tuning_cache_find(path, _key())
+    assert got is not None and got["from_cache"] == 1 and got["trials"] == 0
+    assert (got["tp"], got["ppb"], got["list_mode"], got["persistent"]) == (16, 16, 1, -1)
+    assert got["skin"] == 0.3 + 1e-13  # 17 significant digits read back to the same double
+    assert got["baseline_ms_per_step"] == 0.0 and got["tuned_ms_per_step"] == 0.0
+    line = open(path).read()
+    assert line.startswith("srmd-tuning-v1 ") and line.count("\n") == 1 and "count=3277,819" in line
+
+
+@pytest.mark.parametrize("field,value,match", [
+    ("density", 1.2 * (1 + 5e-7), True),
+    ("density", 1.2 * (1 + 1e-4), False),
+    ("dt", 0.005 * (1 - 5e-7), True),
+    ("dt", 0.004, False),
+    ("temperature", 0.8 * 1.015, True),
+    ("temperature", 0.8 * 1.03, False),
+    ("gpu", "gfx942:sramecc+:xnack-", False),
+    ("compute_units", 304, False),
+    ("precision", 2, False),
+    ("cutoff_method", 2, False),
+    ("thermostat", 0, False),
+    ("count", [3276, 820], False),
+])
+def test_tolerances(srmd, tmp_path, field, value, match):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), _tuning())
+    k = _key()
+    k[field] = value
+    assert (srmd.tuning_cache_find(path, k) is not None) == match
+
+
+@pytest.mark.parametrize("name", ["sigma", "epsilon", "rcut"])
+def test_pair_parameters_must_agree(srmd, tmp_path, name):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), _tuning())
+    k = _key()
+    a = np.array(k[name])
+    a[0, 1] = a[1, 0] = a[0, 1] * (1 + 1e-7)
+    k[name] = a
+    assert srmd.tuning_cache_find(path, k) is not None
+    a[0, 1] = a[1, 0] = a[0, 1] * 1.01
+    k[name] = a
+    assert srmd.tuning_cache_find(path, k) is None
+
+
+def test_other_type_count_is_no_match(srmd, tmp_path):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), _tuning())
+    k = {**_key(), "ntypes": 1, "count": [4096], "sigma": [[1.0]], "epsilon": [[1.0]], "rcut": [[2.5]]}
+    assert srmd.tuning_cache_find(path, k) is None
+
+
+def test_last_matching_record_wins(srmd, tmp_path):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), _tuning(tp=4, ppb=64))
+    other = copy.deepcopy(_key())
+    other["density"] = 0.9
+    srmd.tuning_cache_store(path, other, _tuning(tp=1, ppb=256))
+    srmd.tuning_cache_store(path, _key(), _tuning(tp=8, ppb=32))
+    got = srmd.tuning_cache_find(path, _key())
+    assert (got["tp"], got["ppb"]) == (8, 32)
+    got = srmd.tuning_cache_find(path, other)
+    assert (got["tp"], got["ppb"]) == (1, 256)
+
+
+def test_damaged_lines_are_skipped(srmd, tmp_path):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), _tuning(tp=4, ppb=64))
+    good = open(path).read().strip()
+    bad = [
+        "garbage",
+        "",
+        good.replace("srmd-tuning-v1", "srmd-tuning-v0"),
+        good.replace(" tp=4", " tp=3"),              # not a power of two
+        good.replace(" ppb=64", " ppb=40"),          # tp * ppb not a multiple of 64
+        good.replace(" list=1", " list=7"),
+        good.replace(" skin=", " skin=nan#"),
+        good.replace("count=3277,819", "count=3277"),  # too few counts
+        good.replace("count=3277,819", "count=3277,819,5"),
+        good.split(" tp=")[0],                     # record cut short
+        good.replace(" density=", " density=x"),
+        "x" * 5000 + " " + good,                   # a very long line
+    ]
+    with open(path, "a") as f:
+        f.write("\n".join(bad) + "\n")
+    got = srmd.tuning_cache_find(path, _key())
+    assert (got["tp"], got["ppb"]) == (4, 64)
+    # a long valid line after the damage is still read whole
+    srmd.tuning_cache_store(path, _key(), _tuning(tp=2, ppb=32))
+    got = srmd.tuning_cache_find(path, _key())
+    assert (got["tp"], got["ppb"]) == (2, 32)
+
+
+def test_invalid_arguments(srmd, tmp_path):
+    lib = srmd.load()
+    k = srmd.srmd_tuning_key.from_dict(_key())
+    t = srmd.srmd_tuning.from_dict(_tuning())
+    found = ctypes.c_int32(7)
+    path = str(tmp_path / "tuned.txt").encode()
+    assert lib.srmd_tuning_cache_find(None, ctypes.byref(k), ctypes.byref(t), ctypes.byref(found)) == srmd.SRMD_EINVAL
+    assert lib.srmd_tuning_cache_store(path, None, ctypes.byref(t)) == srmd.SRMD_EINVAL
+    k.ntypes = 5
+    assert lib.srmd_tuning_cache_store(path, ctypes.byref(k), ctypes.byref(t)) == srmd.SRMD_EINVAL
+    k.ntypes = 2
+    t.tp = 3
+    assert lib.srmd_tuning_cache_store(path, ctypes.byref(k), ctypes.byref(t)) == srmd.SRMD_EINVAL
+    assert b"out of range" in lib.srmd_last_error(None)
+    t.tp = 16
+    bad_dir = str(tmp_path / "no" / "such" / "dir" / "f.txt").encode()
+    assert lib.srmd_tuning_cache_store(bad_dir, ctypes.byref(k), ctypes.byref(t)) == srmd.SRMD_EINVAL
+    assert lib.srmd_autotune_full(None, 10, None, None) == srmd.SRMD_EINVAL
+    assert lib.srmd_tuning_key_of(None, ctypes.byref(k)) == srmd.SRMD_EINVAL
+
+
+def test_struct_layouts(srmd):
+    assert ctypes.sizeof(srmd.srmd_tuning_key) == 64 + 6 * 4 + 4 * 8 + 3 * 8 + 3 * 16 * 8
+    assert ctypes.sizeof(srmd.srmd_tuning) == 4 * 4 + 3 * 8 + 2 * 4
