@@ -34,21 +34,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name, n):
+def workload(name, n, skin):
     from workloads import generators as gen
 
     if name == "ka4096":
         state = gen.config1_state()
         sig, eps, rc = gen.ka_params()
         desc = dict(workload="Kob-Andersen 80:20 NVT", n=state.n, rho=1.2, T0=0.45, tau=0.2, dt=0.005,
-                    cutoff="shifted-force 2.5 sigma_ab", skin=0.3, seed=state.seed, start="random insertion dmin 0.75"
+                    cutoff="shifted-force 2.5 sigma_ab", skin=skin, seed=state.seed, start="random insertion dmin 0.75"
                     " sigma_ab + 2000 NVT steps dt 0.001")
         return state, (sig, eps, rc), "sf", ("nvt", 0.005, 0.45, 0.2), desc
     if name == "lj":
         state = gen.config2_state(n) if n != 864 else gen.config0_state()
         sig, eps, rc = gen.lj_params()
         desc = dict(workload="Lennard-Jones NVE (melting FCC)", n=state.n, rho=0.8442, T=0.722, dt=0.005,
-                    cutoff="shifted-potential 2.5", skin=0.3, seed=state.seed, start="FCC lattice")
+                    cutoff="shifted-potential 2.5", skin=skin, seed=state.seed, start="FCC lattice")
         return state, (sig, eps, rc), "sp", ("nve", 0.005), desc
     raise SystemExit(f"unknown workload {name}")
 
@@ -64,7 +64,7 @@ def step_kernel_bytes(n, list_entries):
     return 132.0 * n + 4.0 * list_entries
 
 
-def hbm_traffic(workload_name, n, mode, tp, ppb):
+def hbm_traffic(workload_name, n, mode, tp, ppb, skin):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (profiles/traffic.json), or None when they were
     taken with another kernel source or another workload / launch shape."""
@@ -82,7 +82,7 @@ def hbm_traffic(workload_name, n, mode, tp, ppb):
     if table.get("kernels_hip_sha256") != digest:
         return None
     for e in table.get("entries", []):
-        if (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"]) == (workload_name, n, mode, tp, ppb):
+        if (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"]) == (workload_name, n, mode, tp, ppb, skin):
             return 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
     return None
 
@@ -297,6 +297,8 @@ def main():
     ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (untimed) after the relaxation; the tuned layout and mode are timed")
+    ap.add_argument("--skin", type=float, default=0.5,
+                    help="neighbour-list skin of the ka4096 and lj workloads (default: the paper's default, 0.5)")
     ap.add_argument("--tune-full", action="store_true",
                     help="as --tune (and for the size sweep) with the full autotuner: skin optimisation, every "
                          "list method within 20 %% of the fastest, and the tuned-parameter file of --tune-cache")
@@ -348,9 +350,10 @@ def main():
     if args.workload == "sweep":
         run_sweep(args)
         return
-    state, params, method, integ, desc = workload(args.workload, args.n)
+    state, params, method, integ, desc = workload(args.workload, args.n, args.skin)
     sig, eps, rc = params
-    s = srmd.system_from_state(state, sig, eps, rc, method, skin=0.3, stream=torch.cuda.current_stream().cuda_stream)
+    s = srmd.system_from_state(state, sig, eps, rc, method, skin=args.skin,
+                               stream=torch.cuda.current_stream().cuda_stream)
     if args.tp:
         s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
     persistent = args.mode == "persistent" and state.n <= 8192
@@ -367,6 +370,7 @@ def main():
         # untimed: the full autotuner picks layout, list builder, mode and skin
         tuned = s.autotune_full(args.tune_steps, args.tune_cache)
         log(f"autotune_full: {tuned}")
+        desc["skin"] = tuned["skin"]
         persistent = s.stats()["persistent_groups"] > 0
     elif args.tune:
         # untimed: the autotuner picks layout, list builder and mode from this state
@@ -410,7 +414,8 @@ def main():
         f"{bytes_launch / 1e6:.3f} MB algorithmic per launch -> {achieved:.1f} GB/s")
     kname = ("k_multi (persistent: list build, sort, pair force, integrator, reductions)" if persistent
              else "k_step (fused pair force + integrator)")
-    traffic = hbm_traffic(desc["workload"], n, "persistent" if persistent else "chain", st1["tp"], st1["ppb"])
+    traffic = hbm_traffic(desc["workload"], n, "persistent" if persistent else "chain", st1["tp"], st1["ppb"],
+                          desc["skin"])
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
                 "traffic_note": "HBM bytes per launch (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, copy-calibrated)",
@@ -427,7 +432,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"], mode="persistent" if persistent else "chain",
-                       groups=st1["persistent_groups"], skin=tuned["skin"] if tuned else 0.3),
+                       groups=st1["persistent_groups"]),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],
         "roofline": roofline, "cpu_baseline": cpu,
