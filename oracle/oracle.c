@@ -28,6 +28,13 @@
  *    The potential energy of a particle is half its pair energies (paper, force
  *    kernel figure: compensation for double counting).
  *
+ *  - optionally, Coulomb interactions with a shifted-force cutoff (paper section
+ *    9): between charges q_a, q_b (per type, reduced units in which the Coulomb
+ *    constant is one) U(r) = q_a q_b (1/r - 1/r_cc + (r - r_cc)/r_cc^2) and
+ *    F(r) = q_a q_b (1/r^2 - 1/r_cc^2) for r < r_cc, one cutoff r_cc for every
+ *    type pair, added to the Lennard-Jones term of the pair.  The in/out decision
+ *    for this term is r2_f32 < (float)(r_cc^2).
+ *
  *  - the leapfrog / Nose-Hoover integrator and the displacement criterion that
  *    triggers a rebuild (paper section 6: rebuild once any particle has moved
  *    more than half the skin since the last build).
@@ -187,19 +194,30 @@ void oracle_pair(double r, double sig, double eps, double rc, int method, double
   }
 }
 
+/* ---- Coulomb with a shifted-force cutoff (paper section 9) ---------------- */
+/* The plain Coulomb pair force qq / r^2 with its value at r_cc subtracted, and
+ * the potential that integrates it back from r_cc (zero at r_cc):
+ *   F(r) = qq (1/r^2 - 1/r_cc^2),  U(r) = qq (1/r - 1/r_cc + (r - r_cc)/r_cc^2). */
+void oracle_coulomb_sf(double r, double qq, double rcc, double *u, double *f) {
+  *u = qq * (1.0 / r - 1.0 / rcc + (r - rcc) / (rcc * rcc));
+  *f = qq * (1.0 / (r * r) - 1.0 / (rcc * rcc));
+}
+
 /* Forces, per-particle energy and per-particle virial on float32 positions.
  *  sel == NULL: every particle; else the nsel particles listed in sel.
  *  Outputs (length nsel or n): F[3*k..], pe[k] = 1/2 sum_j u_ij,
  *  w[k] = 1/2 * 1/3 sum_j (r_i - r_j) . F_ij.   Totals (over the selection):
  *  totals[0] = sum pe, totals[1] = sum w.  In/out decision: r2_f32 < rc2_f32. */
-void oracle_forces_f32(int n, const float *pos, const int *type, const double *box, int ntypes,
-                       const double *sigma, const double *eps, const double *rc, int method, int nsel,
-                       const int *sel, double *F, double *pe, double *w, double *totals) {
+void oracle_forces_f32_q(int n, const float *pos, const int *type, const double *box, int ntypes,
+                         const double *sigma, const double *eps, const double *rc, int method,
+                         const double *charge, double rcc, int nsel, const int *sel, double *F, double *pe,
+                         double *w, double *totals) {
   float L32[3], invL[3];
   box_f32(box, L32, invL);
   double L[3] = {(double)L32[0], (double)L32[1], (double)L32[2]};
   float *rc2 = (float *)malloc(sizeof(float) * (size_t)(ntypes * ntypes));
   for (int a = 0; a < ntypes * ntypes; ++a) rc2[a] = (float)(rc[a] * rc[a]);
+  const float rcc2 = charge ? (float)(rcc * rcc) : 0.0f;
   int cnt = sel ? nsel : n;
 #pragma omp parallel for schedule(dynamic, 8)
   for (int k = 0; k < cnt; ++k) {
@@ -208,15 +226,23 @@ void oracle_forces_f32(int n, const float *pos, const int *type, const double *b
     for (int j = 0; j < n; ++j) {
       if (j == i) continue;
       int ab = type[i] * ntypes + type[j];
-      if (!(r2_f32(pos + 3 * i, pos + 3 * j, L32, invL) < rc2[ab])) continue;
+      const float r2s = r2_f32(pos + 3 * i, pos + 3 * j, L32, invL);
+      const int in_lj = r2s < rc2[ab], in_c = charge && r2s < rcc2;
+      if (!in_lj && !in_c) continue;
       double d[3];
       for (int c = 0; c < 3; ++c) {
         d[c] = (double)pos[3 * i + c] - (double)pos[3 * j + c]; /* r_i - r_j */
         d[c] -= L[c] * rint(d[c] / L[c]);
       }
       double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-      double u, f;
-      oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      double u = 0.0, f = 0.0;
+      if (in_lj) oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      if (in_c) {
+        double uc, fc;
+        oracle_coulomb_sf(r, charge[type[i]] * charge[type[j]], rcc, &uc, &fc);
+        u += uc;
+        f += fc;
+      }
       nsum_add(&fx, f * d[0] / r);
       nsum_add(&fy, f * d[1] / r);
       nsum_add(&fz, f * d[2] / r);
@@ -239,11 +265,19 @@ void oracle_forces_f32(int n, const float *pos, const int *type, const double *b
   free(rc2);
 }
 
-/* Forces on double-precision positions, in/out decision r^2 < rc^2 in FP64.
+/* The Lennard-Jones-only form (no charges). */
+void oracle_forces_f32(int n, const float *pos, const int *type, const double *box, int ntypes,
+                       const double *sigma, const double *eps, const double *rc, int method, int nsel,
+                       const int *sel, double *F, double *pe, double *w, double *totals) {
+  oracle_forces_f32_q(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, 0.0, nsel, sel, F, pe, w, totals);
+}
+
+/* Forces on double-precision positions, in/out decision r^2 < rc^2 in FP64
+ * (and r^2 < r_cc^2 for the Coulomb term when charge != NULL).
  * Used by the reference integrator. */
-void oracle_forces_f64(int n, const double *pos, const int *type, const double *box, int ntypes,
-                       const double *sigma, const double *eps, const double *rc, int method, double *F,
-                       double *pe, double *w, double *totals) {
+void oracle_forces_f64_q(int n, const double *pos, const int *type, const double *box, int ntypes,
+                         const double *sigma, const double *eps, const double *rc, int method,
+                         const double *charge, double rcc, double *F, double *pe, double *w, double *totals) {
 #pragma omp parallel for schedule(dynamic, 8)
   for (int i = 0; i < n; ++i) {
     nsum_t fx = {0, 0}, fy = {0, 0}, fz = {0, 0}, su = {0, 0}, sw = {0, 0};
@@ -256,10 +290,17 @@ void oracle_forces_f64(int n, const double *pos, const int *type, const double *
         d[c] -= box[c] * rint(d[c] / box[c]);
       }
       double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-      if (!(r2 < rc[ab] * rc[ab])) continue;
+      const int in_lj = r2 < rc[ab] * rc[ab], in_c = charge && r2 < rcc * rcc;
+      if (!in_lj && !in_c) continue;
       double r = sqrt(r2);
-      double u, f;
-      oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      double u = 0.0, f = 0.0;
+      if (in_lj) oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      if (in_c) {
+        double uc, fc;
+        oracle_coulomb_sf(r, charge[type[i]] * charge[type[j]], rcc, &uc, &fc);
+        u += uc;
+        f += fc;
+      }
       nsum_add(&fx, f * d[0] / r);
       nsum_add(&fy, f * d[1] / r);
       nsum_add(&fz, f * d[2] / r);
@@ -279,6 +320,12 @@ void oracle_forces_f64(int n, const double *pos, const int *type, const double *
   }
   totals[0] = nsum_value(&tu);
   totals[1] = nsum_value(&tw);
+}
+
+void oracle_forces_f64(int n, const double *pos, const int *type, const double *box, int ntypes,
+                       const double *sigma, const double *eps, const double *rc, int method, double *F,
+                       double *pe, double *w, double *totals) {
+  oracle_forces_f64_q(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, 0.0, F, pe, w, totals);
 }
 
 /* Kinetic energy 1/2 sum m v^2 (compensated). */
@@ -329,10 +376,10 @@ int oracle_rebuild_needed(int n, const float *pos, const float *pos0, const doub
  *   P^n = (2 KE / 3 + W) / V, xi^n, I^n, H^n = KE + PE + g T0 (tau^2 xi^2 / 2 + I), KE(v^{n+1/2}).
  * inv_tau2 = 1/tau^2 (0 means no coupling).  image counts crossings of the box.
  */
-int oracle_integrate(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
-                     const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
-                     int method, double dt, int thermostat, double T0, double inv_tau2, double *xi,
-                     double *xi_int, int nsteps, double *thermo) {
+int oracle_integrate_q(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
+                       const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
+                       int method, const double *charge, double rcc, double dt, int thermostat, double T0,
+                       double inv_tau2, double *xi, double *xi_int, int nsteps, double *thermo) {
   double *F = (double *)malloc(sizeof(double) * 3 * (size_t)n);
   double *pe = (double *)malloc(sizeof(double) * (size_t)n);
   double *w = (double *)malloc(sizeof(double) * (size_t)n);
@@ -343,7 +390,7 @@ int oracle_integrate(int n, double *pos, double *vel, int *image, const int *typ
   double V = box[0] * box[1] * box[2];
   for (int step = 0; step < nsteps; ++step) {
     double tot[2];
-    oracle_forces_f64(n, pos, type, box, ntypes, sigma, eps, rc, method, F, pe, w, tot);
+    oracle_forces_f64_q(n, pos, type, box, ntypes, sigma, eps, rc, method, charge, rcc, F, pe, w, tot);
     double x = thermostat ? *xi : 0.0;
     double a = 1.0 - x * dt / 2.0, b = 1.0 + x * dt / 2.0;
     for (int i = 0; i < n; ++i) {
@@ -397,4 +444,13 @@ int oracle_integrate(int n, double *pos, double *vel, int *image, const int *typ
   free(vnew);
   free(vmid);
   return 0;
+}
+
+/* The Lennard-Jones-only form (no charges). */
+int oracle_integrate(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
+                     const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
+                     int method, double dt, int thermostat, double T0, double inv_tau2, double *xi,
+                     double *xi_int, int nsteps, double *thermo) {
+  return oracle_integrate_q(n, pos, vel, image, type, mass, box, ntypes, sigma, eps, rc, method, NULL, 0.0, dt,
+                            thermostat, T0, inv_tau2, xi, xi_int, nsteps, thermo);
 }

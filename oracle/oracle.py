@@ -20,7 +20,7 @@ METHODS = {"trunc": TRUNC, "sp": SP, "sf": SF}
 
 __all__ = [
     "build", "load", "TRUNC", "SP", "SF", "METHODS", "cut_tables", "pair_set", "neighbors_of",
-    "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads",
+    "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads", "coulomb_sf",
 ]
 
 
@@ -65,6 +65,18 @@ def load():
     lib.oracle_forces_f64.argtypes = [ctypes.c_int, _dp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
                                       _dp, _dp, _dp, _dp]
     lib.oracle_forces_f64.restype = None
+    lib.oracle_coulomb_sf.argtypes = [ctypes.c_double] * 3 + [_dp, _dp]
+    lib.oracle_coulomb_sf.restype = None
+    lib.oracle_forces_f32_q.argtypes = [ctypes.c_int, _fp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
+                                        _dp, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp, _dp, _dp]
+    lib.oracle_forces_f32_q.restype = None
+    lib.oracle_forces_f64_q.argtypes = [ctypes.c_int, _dp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
+                                        _dp, ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.oracle_forces_f64_q.restype = None
+    lib.oracle_integrate_q.argtypes = [ctypes.c_int, _dp, _dp, _ip, _ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp,
+                                       ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                       ctypes.c_double, ctypes.c_double, _dp, _dp, ctypes.c_int, _dp]
+    lib.oracle_integrate_q.restype = ctypes.c_int
     lib.oracle_kinetic.argtypes = [ctypes.c_int, _dp, _ip, _dp]
     lib.oracle_kinetic.restype = ctypes.c_double
     lib.oracle_max_disp2.argtypes = [ctypes.c_int, _fp, _fp, _dp]
@@ -147,8 +159,26 @@ def pair(r, sigma, eps, rc, method):
     return u.value, f.value
 
 
-def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None):
-    """Forces (k, 3), per-particle PE (k,), per-particle virial (k,), total PE, total W on float32 positions."""
+def coulomb_sf(r, qq, rcc):
+    """(u, f) of the shifted-force Coulomb term of one pair (paper section 9)."""
+    u = ctypes.c_double()
+    f = ctypes.c_double()
+    load().oracle_coulomb_sf(float(r), float(qq), float(rcc), ctypes.byref(u), ctypes.byref(f))
+    return u.value, f.value
+
+
+def _charges(charges, ntypes):
+    if charges is None:
+        return None
+    q = _c(charges, np.float64)
+    if q.shape != (ntypes,):
+        raise ValueError("one charge per type")
+    return q
+
+
+def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, rc_coul=0.0):
+    """Forces (k, 3), per-particle PE (k,), per-particle virial (k,), total PE, total W on float32 positions.
+    With charges (one per type), the shifted-force Coulomb term with cutoff rc_coul is added."""
     pos = _c(pos, np.float32)
     types = _c(types, np.int32)
     box = _c(box, np.float64)
@@ -167,12 +197,14 @@ def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None):
     pe = np.zeros(k)
     w = np.zeros(k)
     tot = np.zeros(2)
-    load().oracle_forces_f32(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
-                             _method(method), k, selp, _p(F), _p(pe), _p(w), _p(tot))
+    q = _charges(charges, sigma.shape[0])
+    load().oracle_forces_f32_q(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
+                               _method(method), None if q is None else _p(q), float(rc_coul), k, selp, _p(F),
+                               _p(pe), _p(w), _p(tot))
     return F, pe, w, float(tot[0]), float(tot[1])
 
 
-def forces_f64(pos, types, box, sigma, eps, rc, method):
+def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.0):
     pos = _c(pos, np.float64)
     types = _c(types, np.int32)
     box = _c(box, np.float64)
@@ -184,8 +216,10 @@ def forces_f64(pos, types, box, sigma, eps, rc, method):
     pe = np.zeros(n)
     w = np.zeros(n)
     tot = np.zeros(2)
-    load().oracle_forces_f64(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
-                             _method(method), _p(F), _p(pe), _p(w), _p(tot))
+    q = _charges(charges, sigma.shape[0])
+    load().oracle_forces_f64_q(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
+                               _method(method), None if q is None else _p(q), float(rc_coul), _p(F), _p(pe),
+                               _p(w), _p(tot))
     return F, pe, w, float(tot[0]), float(tot[1])
 
 
@@ -214,7 +248,7 @@ THERMO_FIELDS = ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_inte
 
 
 def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, thermostat=False, T0=1.0,
-              tau=None, xi=0.0, xi_int=0.0, image=None):
+              tau=None, xi=0.0, xi_int=0.0, image=None, charges=None, rc_coul=0.0):
     """Run nsteps of leapfrog (NVE) or Nose-Hoover leapfrog (NVT) in FP64.
 
     Returns dict(pos, vel, image, xi, xi_int, thermo) with thermo an (nsteps, 9) array whose
@@ -234,10 +268,11 @@ def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, th
     xi_c = ctypes.c_double(xi)
     xi_i = ctypes.c_double(xi_int)
     thermo = np.zeros((nsteps, 9))
-    rc_ = load().oracle_integrate(n, _p(pos), _p(vel), _p(image), _p(types), _p(mass), _p(box), sigma.shape[0],
-                                  _p(sigma), _p(eps), _p(rc), _method(method), float(dt), int(bool(thermostat)),
-                                  float(T0), float(inv_tau2), ctypes.byref(xi_c), ctypes.byref(xi_i), int(nsteps),
-                                  _p(thermo))
+    q = _charges(charges, sigma.shape[0])
+    rc_ = load().oracle_integrate_q(n, _p(pos), _p(vel), _p(image), _p(types), _p(mass), _p(box), sigma.shape[0],
+                                    _p(sigma), _p(eps), _p(rc), _method(method), None if q is None else _p(q),
+                                    float(rc_coul), float(dt), int(bool(thermostat)), float(T0), float(inv_tau2),
+                                    ctypes.byref(xi_c), ctypes.byref(xi_i), int(nsteps), _p(thermo))
     if rc_ != 0:
         raise MemoryError("oracle_integrate failed")
     return dict(pos=pos, vel=vel, image=image, xi=xi_c.value, xi_int=xi_i.value, thermo=thermo)
