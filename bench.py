@@ -50,6 +50,15 @@ def workload(name, n, skin):
         desc = dict(workload="Lennard-Jones NVE (melting FCC)", n=state.n, rho=0.8442, T=0.722, dt=0.005,
                     cutoff="shifted-potential 2.5", skin=skin, seed=state.seed, start="FCC lattice")
         return state, (sig, eps, rc), "sp", ("nve", 0.005), desc
+    if name == "salt":
+        n = 2000 if n == 864 else n
+        state = gen.molten_salt_state(n, n)
+        sig, eps, rc, q, rcc = gen.salt_params()
+        desc = dict(workload="molten salt NVT (charged LJ, shifted-force Coulomb)", n=state.n, rho=gen.SALT_RHO,
+                    T0=gen.SALT_T, tau=0.2, dt=0.004, cutoff="shifted-force LJ 2.5 + shifted-force Coulomb 6.0",
+                    charges="+1/-1", skin=skin, seed=state.seed, start="random insertion dmin 0.8 + 2000 NVT steps "
+                    "dt 0.001")
+        return state, (sig, eps, rc, q, rcc), "sf", ("nvt", 0.004, gen.SALT_T, 0.2), desc
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -91,10 +100,12 @@ def cpu_baseline(state, params, method, integ, budget_s=12.0):
     """The oracle (FP64, O(N^2), OpenMP over particles) on the host cores."""
     import oracle
 
-    sig, eps, rc = params
+    sig, eps, rc = params[:3]
     kw = {}
+    if len(params) == 5:
+        kw = dict(charges=params[3], rc_coul=params[4])
     if integ[0] == "nvt":
-        kw = dict(thermostat=True, T0=integ[2], tau=integ[3])
+        kw.update(thermostat=True, T0=integ[2], tau=integ[3])
     t0 = time.perf_counter()
     oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1], 1, **kw)
     t1 = time.perf_counter() - t0
@@ -293,7 +304,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "ka-replicas", "precision", "sweep"])
+    ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "salt", "ka-replicas", "precision", "sweep"])
     ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (untimed) after the relaxation; the tuned layout and mode are timed")
@@ -307,7 +318,7 @@ def main():
     ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial (size sweep, --tune)")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--baseline-steps", type=int, default=1000)
-    ap.add_argument("--n", type=int, default=864, help="particles for --workload lj")
+    ap.add_argument("--n", type=int, default=864, help="particles for --workload lj (salt: 2000 unless given)")
     ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
     ap.add_argument("--ppb", type=int, default=0)
     ap.add_argument("--mode", default="persistent", choices=["persistent", "chain"],
@@ -351,9 +362,11 @@ def main():
         run_sweep(args)
         return
     state, params, method, integ, desc = workload(args.workload, args.n, args.skin)
-    sig, eps, rc = params
+    sig, eps, rc = params[:3]
     s = srmd.system_from_state(state, sig, eps, rc, method, skin=args.skin,
                                stream=torch.cuda.current_stream().cuda_stream)
+    if len(params) == 5:
+        s.set_coulomb_sf(params[3], params[4])
     if args.tp:
         s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
     persistent = args.mode == "persistent" and state.n <= 8192

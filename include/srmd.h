@@ -109,6 +109,17 @@ srmd_status srmd_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*f
 srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigma, double epsilon, double rcut,
                              srmd_cutoff method);
 
+/* Coulomb interactions with a shifted-force cutoff (paper section 9, the molten
+ * salt benchmark): charge[t] per type (host array of ntypes doubles, reduced units
+ * in which the Coulomb constant is one), one cutoff rcut > 0 for every type pair.
+ * Between types a and b, inside rcut,
+ *   U(r) = q_a q_b (1/r - 1/rcut + (r - rcut)/rcut^2),  F(r) = q_a q_b (1/r^2 - 1/rcut^2),
+ * added to the pair's Lennard-Jones term, which must use SRMD_CUT_SF (other
+ * methods with charges: SRMD_EUNSUPPORTED at the next step).  Pairs are listed
+ * within max(r_c,ab, rcut) + skin.  charge = NULL removes the term.  rcut + skin
+ * must stay below half of every box side (SRMD_EINVAL). */
+srmd_status srmd_set_coulomb_sf(srmd_system *s, const double *charge, double rcut);
+
 /* Neighbour-list skin s >= 0: pairs within r_c,ab + s are listed (paper section 4),
  * and the list is rebuilt once any particle has moved more than s/2 since the last
  * build (section 6).  Default 0.3. */
@@ -185,7 +196,7 @@ typedef struct {
   char gpu[64];          /* device architecture name (hipDeviceProp_t::gcnArchName) */
   int32_t compute_units; /* of that device */
   int32_t precision;     /* srmd_precision */
-  int32_t cutoff_method; /* srmd_cutoff */
+  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term */
   int32_t thermostat;    /* 0 NVE, 1 Nose-Hoover NVT */
   int32_t ntypes;
   int32_t reserved;

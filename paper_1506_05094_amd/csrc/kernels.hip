@@ -119,8 +119,14 @@ struct alignas(16) PairRow {
   float ushift, fc, rc, pad;     // U(rc), F(rc), rc
 };
 
+// Constants of the shifted-force Coulomb term of a type pair (kernel method 3).
+struct alignas(16) CoulRow {
+  float qq, rcc2, inv_rcc2, two_inv_rcc;  // q_a q_b, r_cc^2, 1 / r_cc^2, 2 / r_cc
+};
+
 struct SharedPairs {
   PairRow row[kMaxPairs];
+  CoulRow crow[kMaxPairs];
 };
 
 __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) {
@@ -136,6 +142,12 @@ __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) 
     r.rc = c.pt.rc[t];
     r.pad = 0.f;
     sp.row[t] = r;
+    CoulRow q;
+    q.qq = c.pt.qq[t];
+    q.rcc2 = c.pt.rcc2;
+    q.inv_rcc2 = c.pt.inv_rcc2;
+    q.two_inv_rcc = c.pt.two_inv_rcc;
+    sp.crow[t] = q;
   }
 }
 
@@ -163,7 +175,42 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
               mz = __builtin_rintf(ez * c.invL[2]);
   float dx = __builtin_fmaf(-mx, c.L[0], ex), dy = __builtin_fmaf(-my, c.L[1], ey), dz = __builtin_fmaf(-mz, c.L[2], ez);
   const float r2s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-  const PairRow &pr = sp.row[ti * ntypes + ptype(pj)];
+  const int pidx = ti * ntypes + ptype(pj);
+  const PairRow &pr = sp.row[pidx];
+  if (METHOD == 3) {
+    // shifted-force Lennard-Jones inside r_c,ab plus shifted-force Coulomb inside r_cc
+    // (paper section 9): q_a q_b (1/r - 1/r_cc + (r - r_cc)/r_cc^2), force
+    // q_a q_b (1/r^2 - 1/r_cc^2); each term has its own float32 in/out decision
+    const CoulRow &cr = sp.crow[pidx];
+    const bool in_lj = r2s < pr.rc2, in_c = r2s < cr.rcc2;
+    if (in_lj || in_c) {
+      dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
+      dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
+      dz = (float)(((double)pj.z - wi.z) - (double)mz * c.Ld[2]);
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      const float inv_r2 = __builtin_amdgcn_rcpf(r2);
+      const float inv_r = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * inv_r;
+      float fr = 0.f, e = 0.f;
+      if (in_lj) {
+        const float s2 = pr.sig2 * inv_r2;
+        const float s6 = s2 * s2 * s2;
+        const float s12 = s6 * s6;
+        fr = __builtin_fmaf(-pr.fc, inv_r, pr.eps24 * __builtin_fmaf(2.0f, s12, -s6) * inv_r2);
+        e = __builtin_fmaf(r - pr.rc, pr.fc, __builtin_fmaf(pr.eps4, s12 - s6, -pr.ushift));
+      }
+      if (in_c) {
+        fr = __builtin_fmaf(cr.qq * inv_r, inv_r2 - cr.inv_rcc2, fr);
+        e = __builtin_fmaf(cr.qq, __builtin_fmaf(r, cr.inv_rcc2, inv_r) - cr.two_inv_rcc, e);
+      }
+      fx = __builtin_fmaf(-fr, dx, fx);
+      fy = __builtin_fmaf(-fr, dy, fy);
+      fz = __builtin_fmaf(-fr, dz, fz);
+      u += e;
+      w = __builtin_fmaf(fr, r2, w);
+    }
+    return;
+  }
   if (r2s < pr.rc2) {
     dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
     dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
@@ -1869,7 +1916,8 @@ template <int TP, bool BIG>
 static const void *multi_fn(int method) {
   return method == 0 ? (const void *)k_multi<TP, 0, BIG>
          : method == 1 ? (const void *)k_multi<TP, 1, BIG>
-                       : (const void *)k_multi<TP, 2, BIG>;
+         : method == 2 ? (const void *)k_multi<TP, 2, BIG>
+                       : (const void *)k_multi<TP, 3, BIG>;
 }
 
 // The persistent kernel for (tp, method); the large-system form exists for tp <= 8.
@@ -1957,6 +2005,7 @@ static hipError_t launch_step_tp(int method, int prec, dim3 g, dim3 b, hipStream
   SRMD_STEP_CASE(0, 0) SRMD_STEP_CASE(0, 1) SRMD_STEP_CASE(0, 2)
   SRMD_STEP_CASE(1, 0) SRMD_STEP_CASE(1, 1) SRMD_STEP_CASE(1, 2)
   SRMD_STEP_CASE(2, 0) SRMD_STEP_CASE(2, 1) SRMD_STEP_CASE(2, 2)
+  SRMD_STEP_CASE(3, 0) SRMD_STEP_CASE(3, 1) SRMD_STEP_CASE(3, 2)
 #undef SRMD_STEP_CASE
   return hipErrorInvalidValue;
 }
@@ -1967,6 +2016,7 @@ static hipError_t launch_force_tp(int method, dim3 g, dim3 b, hipStream_t st, co
   if (method == 0) hipLaunchKernelGGL((k_force<TP, 0>), g, b, 0, st, c, p, cur);
   else if (method == 1) hipLaunchKernelGGL((k_force<TP, 1>), g, b, 0, st, c, p, cur);
   else if (method == 2) hipLaunchKernelGGL((k_force<TP, 2>), g, b, 0, st, c, p, cur);
+  else if (method == 3) hipLaunchKernelGGL((k_force<TP, 3>), g, b, 0, st, c, p, cur);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -69,6 +69,9 @@ struct srmd_system {
   double sigma[kMaxPairs] = {}, eps[kMaxPairs] = {}, rc[kMaxPairs] = {};
   bool pair_given[kMaxPairs] = {};
   int method = -1;
+  bool coulomb = false;                 // shifted-force Coulomb term on (srmd_set_coulomb_sf)
+  double charge[kMaxTypes] = {0, 0, 0, 0};
+  double rcc = 0.0;                     // its cutoff
   double skin = 0.3;
   // integrator
   bool integrator_set = false;
@@ -176,11 +179,15 @@ double lj_f(double r, double sig, double eps) {
 }
 
 double rc_max(const srmd_system *s) {
-  double m = 0.0;
+  double m = s->coulomb ? s->rcc : 0.0;
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
     if (s->pair_given[a]) m = std::max(m, s->rc[a]);
   return m;
 }
+
+// The method index the kernels are instantiated for: the Lennard-Jones cutoff
+// method, or 3 for shifted-force Lennard-Jones plus shifted-force Coulomb.
+int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->method; }
 
 bool all_pairs_given(const srmd_system *s) {
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
@@ -263,7 +270,7 @@ void resolve_persistent(srmd_system *s) {
   }
   const int threads = s->tp * s->ppb;
   const int units = step_blocks(s) * (threads / 64);
-  const int cap = multi_max_groups(s->tp, s->method, !s->c.small_sort, persist_lds(s));
+  const int cap = multi_max_groups(s->tp, kmethod(s), !s->c.small_sort, persist_lds(s));
   int want = preq > 0 ? preq : std::max(1, (units + 7) / 8);
   if (preq < 0) want = std::min(want, cap);
   if (want > cap || want < 1)
@@ -277,6 +284,8 @@ void resolve_persistent(srmd_system *s) {
 srmd_status prepare(srmd_system *s) {
   if (s->method < 0 || !all_pairs_given(s))
     return fail(s, SRMD_EINVAL, "pair potential not set for every type pair (srmd_set_pair_lj)");
+  if (s->coulomb && s->method != SRMD_CUT_SF)
+    return fail(s, SRMD_EUNSUPPORTED, "the Coulomb term runs with shifted-force Lennard-Jones (SRMD_CUT_SF) only");
   if (!s->dirty) return SRMD_OK;
   resolve_launch(s);
   SysConst &c = s->c;
@@ -337,8 +346,13 @@ srmd_status prepare(srmd_system *s) {
     c.mass[t] = s->mass[t];
     c.inv_mass[t] = (float)(1.0 / s->mass[t]);
   }
+  c.pt.rcc2 = s->coulomb ? (float)(s->rcc * s->rcc) : 0.0f;
+  c.pt.inv_rcc2 = s->coulomb ? (float)(1.0 / (s->rcc * s->rcc)) : 0.0f;
+  c.pt.two_inv_rcc = s->coulomb ? (float)(2.0 / s->rcc) : 0.0f;
   for (int a = 0; a < s->ntypes * s->ntypes; ++a) {
-    const double rs = s->rc[a] + s->skin;
+    // listed within the larger of the two cutoffs of the pair, plus the skin
+    const double rs = (s->coulomb ? std::max(s->rc[a], s->rcc) : s->rc[a]) + s->skin;
+    c.pt.qq[a] = s->coulomb ? (float)(s->charge[a / s->ntypes] * s->charge[a % s->ntypes]) : 0.0f;
     c.pt.cs2[a] = (float)(rs * rs);
     c.pt.rc2[a] = (float)(s->rc[a] * s->rc[a]);
     c.pt.sig2[a] = (float)(s->sigma[a] * s->sigma[a]);
@@ -388,7 +402,7 @@ srmd_status enqueue_steps(srmd_system *s, int count, int cur) {
   for (int k = 0; k < count; ++k) {
     const int cb = (cur + k) & 1;
     HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, cb));
-    HIPCHK(s, launch_step(s->tp, s->method, (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb));
+    HIPCHK(s, launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb));
     HIPCHK(s, launch_finish(0, step_blocks(s), cb ^ 1, s->stream, s->c, s->p));
   }
   return SRMD_OK;
@@ -524,7 +538,7 @@ srmd_status launch_persistent(srmd_system *s, int cnt) {
     s->desc_valid = true;
   }
   if (g > 1) HIPCHK(s, hipMemsetAsync(s->p.bar_flags, 0, sizeof(unsigned) * 2 * 256, s->stream));
-  HIPCHK(s, launch_multi(s->tp, s->method, !s->c.small_sort, g, persist_lds(s), s->stream, s->d_desc, s->d_jobs, s->d_job_off,
+  HIPCHK(s, launch_multi(s->tp, kmethod(s), !s->c.small_sort, g, persist_lds(s), s->stream, s->d_desc, s->d_jobs, s->d_job_off,
                          cnt, g > 1));
   s->cur ^= (cnt & 1);
   return SRMD_OK;
@@ -716,7 +730,7 @@ srmd_status batch_sync_desc(srmd_batch *b) {
     srmd_system *s = b->sys[r];
     srmd_status st = prepare(s);
     if (st != SRMD_OK) return bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
-    if (s->tp != b->tp || s->method != b->method)
+    if (s->tp != b->tp || kmethod(s) != b->method)
       return bfail(b, SRMD_EINVAL, "replicas must share the cutoff method and the threads per particle");
     const ReplicaDesc d = make_desc(s);
     if (std::memcmp(&d, &b->host_desc[r], sizeof(d)) != 0) {
@@ -1070,6 +1084,26 @@ srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigm
   return SRMD_OK;
 }
 
+srmd_status srmd_set_coulomb_sf(srmd_system *s, const double *charge, double rcut) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!charge) {
+    s->coulomb = false;
+    s->dirty = true;
+    return SRMD_OK;
+  }
+  if (!(rcut > 0) || !std::isfinite(rcut)) return fail(s, SRMD_EINVAL, "the Coulomb cutoff must be positive");
+  for (int t = 0; t < s->ntypes; ++t)
+    if (!std::isfinite(charge[t])) return fail(s, SRMD_EINVAL, "non-finite charge");
+  for (int k = 0; k < 3; ++k)
+    if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+  for (int t = 0; t < kMaxTypes; ++t) s->charge[t] = t < s->ntypes ? charge[t] : 0.0;
+  s->rcc = rcut;
+  s->coulomb = true;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
 srmd_status srmd_set_skin(srmd_system *s, double skin) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
   if (!(skin >= 0) || !std::isfinite(skin)) return fail(s, SRMD_EINVAL, "skin must be >= 0");
@@ -1189,7 +1223,7 @@ srmd_status srmd_compute_forces(srmd_system *s, srmd_thermo *out) {
     st = flush_host_sort(s);
     if (st != SRMD_OK) return st;
     HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, s->cur));
-    HIPCHK(s, launch_force(s->tp, s->method, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur));
+    HIPCHK(s, launch_force(s->tp, kmethod(s), step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur));
     HIPCHK(s, launch_finish(1, step_blocks(s), s->cur, s->stream, s->c, s->p));
     Control h;
     st = read_ctl(s, &h);
@@ -1457,7 +1491,7 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
       hipError_t e = launch_rebuild(s->stream, s->c, s->p, s->cur);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k], s->stream);
       if (e == hipSuccess)
-        e = launch_step(s->tp, s->method, (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur);
+        e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s->stream);
       if (e == hipSuccess) e = launch_finish(0, step_blocks(s), s->cur ^ 1, s->stream, s->c, s->p);
       if (e != hipSuccess) result = fail(s, SRMD_EHIP, std::string("profiled launch: ") + hipGetErrorString(e));
@@ -1885,7 +1919,7 @@ srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key) {
   std::memcpy(key->gpu, g.c_str(), std::min(g.size(), sizeof(key->gpu) - 1));
   key->compute_units = prop.multiProcessorCount;
   key->precision = (int32_t)s->prec;
-  key->cutoff_method = s->method;
+  key->cutoff_method = kmethod(s);
   key->thermostat = s->thermostat;
   key->ntypes = s->ntypes;
   const size_t n = (size_t)s->n;
@@ -2200,7 +2234,7 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
   b->sys.assign(systems, systems + count);
   b->stream = systems[0]->stream;
   b->tp = systems[0]->tp;
-  b->method = systems[0]->method;
+  b->method = kmethod(systems[0]);
   int nmax = 0;
   for (auto *s : b->sys) nmax = std::max(nmax, s->n);
   b->lds = batch_lds_bytes(nmax);

@@ -30,6 +30,10 @@ struct PairTable {
   float ushift[kMaxPairs]; // U(rc) for the shifted methods (0 for plain truncation)
   float fc[kMaxPairs];     // F(rc) = -U'(rc) for shifted force (0 otherwise)
   float rc[kMaxPairs];     // rc_ab
+  // shifted-force Coulomb term (kernel method 3 only): q_a q_b per pair, and of the
+  // one Coulomb cutoff r_cc: r_cc^2, 1 / r_cc^2 and 2 / r_cc
+  float qq[kMaxPairs];
+  float rcc2, inv_rcc2, two_inv_rcc;
 };
 
 // Everything a kernel needs besides pointers; passed by value.

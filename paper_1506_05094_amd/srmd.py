@@ -141,6 +141,7 @@ def load():
         "srmd_set_pair_lj": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                   ctypes.c_double, ctypes.c_int]),
         "srmd_set_skin": (st, [sysp, ctypes.c_double]),
+        "srmd_set_coulomb_sf": (st, [sysp, _dp, ctypes.c_double]),
         "srmd_set_integrator_nve": (st, [sysp, ctypes.c_double]),
         "srmd_set_integrator_nvt": (st, [sysp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
@@ -276,6 +277,17 @@ class System:
 
     def set_skin(self, skin):
         _check(load().srmd_set_skin(self._h, float(skin)), self._h)
+
+    def set_coulomb_sf(self, charges, rcut):
+        """Shifted-force Coulomb term (paper section 9): one charge per type, one cutoff;
+        charges=None removes it."""
+        if charges is None:
+            _check(load().srmd_set_coulomb_sf(self._h, None, 0.0), self._h)
+            return
+        q = np.ascontiguousarray(charges, dtype=np.float64)
+        if q.shape != (self.ntypes,):
+            raise ValueError("one charge per type")
+        _check(load().srmd_set_coulomb_sf(self._h, _ptr(q, _dp), float(rcut)), self._h)
 
     def set_integrator_nve(self, dt):
         _check(load().srmd_set_integrator_nve(self._h, float(dt)), self._h)
@@ -444,7 +456,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
             "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
-            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error"]
+            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf"]
 
 
 def _export_c_names():

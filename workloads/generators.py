@@ -280,3 +280,36 @@ def config3_states(count: int = 256, master_seed: int = 2026, n_lo: int = 500, n
 def config4_state() -> State:
     """LJ fluid, N = 32768, config 0 parameters, seed 4."""
     return lj_fcc_state(32768, LJ_RHO, LJ_T, 4)
+
+
+# ---- the molten salt of the Coulomb benchmark (paper section 9) ------------------------
+
+SALT_RHO = 0.3677
+SALT_T = 2.0
+SALT_RC_COUL = 6.0
+
+
+def salt_params(rc_lj: float = 2.5):
+    """Molten salt: identical Lennard-Jones parameters (sigma = epsilon = 1, cutoff rc_lj)
+    for both species; charges +1 and -1 (reduced units); Coulomb cutoff 6.0.
+    Returns (sigma, epsilon, rc, charges, rc_coulomb)."""
+    one = np.ones((2, 2))
+    return one.copy(), one.copy(), rc_lj * one, np.array([1.0, -1.0]), SALT_RC_COUL
+
+
+def molten_salt_state(n: int, seed: int, rho: float = SALT_RHO, T: float = SALT_T, min_dist: float = 0.8) -> State:
+    """Half cations (type 0), half anions (type 1), assigned by a seeded permutation
+    (n even: neutral), placed by random sequential insertion at least ``min_dist``
+    apart, unit masses, Maxwell-Boltzmann velocities at T."""
+    if n % 2:
+        raise ValueError("the salt needs an even particle count")
+    rng = np.random.default_rng(seed)
+    types = np.zeros(n, dtype=np.int32)
+    types[n // 2:] = 1
+    types = types[rng.permutation(n)]
+    L = _f32_side((n / rho) ** (1.0 / 3.0))
+    box = np.array([L, L, L])
+    pos = _random_insertion(n, L, types, np.full((2, 2), min_dist), rng)
+    vel = maxwell_boltzmann(n, T, np.ones(n), seed + 7919).astype(np.float32)
+    return State(pos=_wrap_f32(pos, box), vel=vel, types=types, box=box, mass=np.array([1.0, 1.0]), ntypes=2,
+                 seed=seed, recipe=f"molten_salt(N={n},rho={rho},T={T},seed={seed},dmin={min_dist})")
