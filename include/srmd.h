@@ -134,8 +134,11 @@ srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double
 
 /* Thread layout of the force kernel (paper section 4 table of code conventions):
  * tp threads per particle (power of two, 1..64) and ppb particles per block,
- * tp*ppb <= 1024 and a multiple of 64.  (0, 0) selects the built-in default for the
- * system size or the value found by srmd_autotune. */
+ * tp*ppb <= 1024 and a multiple of 64.  (0, 0) selects the value found by
+ * srmd_autotune, else the built-in default: the smallest power of two tp <= 32 with
+ * n * tp >= 32768 lanes (65536 in persistent mode) and tp >= E / 64 for E the mean
+ * particle count within max r_c + skin (long lists, e.g. with the Coulomb term),
+ * and ppb = 256 / tp. */
 srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
 
 /* Choose how a list rebuild runs (tuning; the resulting list is the same).

@@ -212,9 +212,16 @@ void launch_of(const srmd_system *s, int *tp_out, int *ppb_out) {
       tp = s->tp_tuned;
       ppb = s->ppb_tuned;
     } else {
+      // enough lanes to fill the device, and for long lists (the Coulomb term's
+      // several hundred entries) at most about 64 entries per lane; the expected
+      // length is the mean count inside r_c,max + s
       const bool persistent = s->persist_set ? s->persist_req != 0 : s->persist_tuned != 0;
       const int lanes = persistent ? 65536 : 32768;
-      tp = std::min(32, pow2_at_least(std::max(1, lanes / std::max(1, s->n))));
+      const double reach = rc_max(s) + s->skin;
+      const double V = (double)s->Lf[0] * (double)s->Lf[1] * (double)s->Lf[2];
+      const double expected = 4.0 / 3.0 * M_PI * reach * reach * reach * (double)s->n / V;
+      const int by_list = (int)std::min(64.0, expected / 64.0);
+      tp = std::min(32, pow2_at_least(std::max(1, std::max(lanes / std::max(1, s->n), by_list))));
       ppb = 0;
     }
   }
