@@ -119,3 +119,30 @@ def test_full_autotune_without_cache_nve_key_temperature():
         s.build_neighbor_list()
         got = s.neighbor_pairs()
     np.testing.assert_array_equal(got, _pairs_at(after["pos"], state.types, state.box, rc, t["skin"]))
+
+
+def test_full_autotune_salt_key_separates_charged_system(tmp_path):
+    """The molten salt tunes with its Coulomb method in the key; the same particles
+    without charges do not reuse that record."""
+    st = gen.molten_salt_state(2000, 31)
+    sig, eps, rc, q, rcc = gen.salt_params()
+    cache = str(tmp_path / "tuned.txt")
+    print("salt 2000: full autotune", flush=True)
+    with make_system(st, sig, eps, rc, "sf") as s:
+        s.set_coulomb_sf(q, rcc)
+        s.set_integrator_nvt(0.004, gen.SALT_T, 0.2)
+        key = s.tuning_key()
+        t = s.autotune_full(20, cache)
+        _check_choice(t)
+        assert key["cutoff_method"] == 3 and t["from_cache"] == 0
+        s.build_neighbor_list()
+        got = s.neighbor_pairs()
+        pos = s.get_state()["pos"]
+    cs2, _ = oracle.cut_tables(np.maximum(rc, rcc), t["skin"])
+    np.testing.assert_array_equal(got, oracle.pair_set(pos, st.types, st.box, cs2))
+    with make_system(st, sig, eps, rc, "sf") as s2:
+        s2.set_integrator_nvt(0.004, gen.SALT_T, 0.2)
+        assert s2.tuning_key()["cutoff_method"] == 2
+        t2 = s2.autotune_full(20, cache)
+        assert t2["from_cache"] == 0
+    assert len(open(cache).read().splitlines()) == 2

@@ -160,3 +160,37 @@ def test_large_salt_sampled_forces():
     assert force_error(F[sel], Fr) <= FORCE_TOL
     _, _, _, U, W = _oracle_forces(st.pos, st)
     assert rel(th["pe"], U) <= ENERGY_TOL and rel(th["virial"], W) <= ENERGY_TOL
+
+
+def test_large_salt_persistent_equals_chain():
+    """N = 20 000 runs the large-system persistent kernel (four-phase sort, lists in
+    device memory) with the Coulomb method: bitwise equal to the launch chains."""
+    print("salt 20000 persistent vs chain", flush=True)
+    st = gen.molten_salt_state(20000, 23)
+    out = []
+    for mode in (0, -1):
+        with _salt_system(st, launch=(8, 32)) as s:
+            s.set_integrator_nvt(0.004, gen.SALT_T, 0.2)
+            s.set_persistent(mode)
+            s.step(60)
+            assert (s.stats()["persistent_groups"] > 0) == (mode == -1)
+            out.append(s.get_state()["pos"])
+    np.testing.assert_array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("precision", ["f32_kahan", "f64pos"])
+def test_salt_trajectory_other_position_precisions(salt2000, precision):
+    """The Coulomb method in the compensated and float64-master position variants:
+    20 NVT steps within 1e-4 of the FP64 oracle."""
+    print(f"salt 2000 trajectory {precision}", flush=True)
+    st = salt2000
+    sig, eps, rc, q, rcc = gen.salt_params()
+    with make_system(st, sig, eps, rc, "sf", skin=SKIN, precision=precision) as s:
+        s.set_coulomb_sf(q, rcc)
+        s.set_integrator_nvt(0.004, gen.SALT_T, 0.2)
+        s.step(20)
+        got = s.get_state()["pos"]
+    ref = oracle.integrate(st.pos, st.vel, st.types, st.mass, st.box, sig, eps, rc, "sf", 0.004, 20, thermostat=True,
+                           T0=gen.SALT_T, tau=0.2, charges=q, rc_coul=rcc)
+    d = min_image(got.astype(np.float64) - ref["pos"], st.box)
+    assert np.abs(d).max() <= 1e-4
