@@ -28,6 +28,11 @@
  *    The potential energy of a particle is half its pair energies (paper, force
  *    kernel figure: compensation for double counting).
  *
+ *  - optionally, in place of 12-6 Lennard-Jones, the pair potential
+ *    U(r) = A (sigma/r)^m - B (sigma/r)^n with even integer exponents (paper section 2
+ *    lists generalised Lennard-Jones and inverse-power-law potentials among the
+ *    pair potentials: both are of this form), with the same three cutoff methods.
+ *
  *  - optionally, Coulomb interactions with a shifted-force cutoff (paper section
  *    9): between charges q_a, q_b (per type, reduced units in which the Coulomb
  *    constant is one) U(r) = q_a q_b (1/r - 1/r_cc + (r - r_cc)/r_cc^2) and
@@ -194,6 +199,47 @@ void oracle_pair(double r, double sig, double eps, double rc, int method, double
   }
 }
 
+/* ---- two-power pair potential ---------------------------------------------- */
+/* U(r) = A (sig/r)^m - B (sig/r)^n;  F(r) = -dU/dr = (m A (sig/r)^m - n B (sig/r)^n) / r */
+static void mie_uf(double r, double A, double B, int m, int n, double sig, double *u, double *f) {
+  double s = sig / r;
+  double sm = pow(s, (double)m), sn = pow(s, (double)n);
+  *u = A * sm - B * sn;
+  *f = ((double)m * A * sm - (double)n * B * sn) / r;
+}
+
+/* pair energy and radial force of the two-power potential under a cutoff method */
+void oracle_pair_mie(double r, double A, double B, int m, int n, double sig, double rc, int method, double *u,
+                     double *f) {
+  double ur, fr;
+  mie_uf(r, A, B, m, n, sig, &ur, &fr);
+  if (method == ORACLE_TRUNC) {
+    *u = ur;
+    *f = fr;
+    return;
+  }
+  double uc, fc;
+  mie_uf(rc, A, B, m, n, sig, &uc, &fc);
+  if (method == ORACLE_SP) {
+    *u = ur - uc;
+    *f = fr;
+  } else {
+    *u = ur - uc + (r - rc) * fc;
+    *f = fr - fc;
+  }
+}
+
+/* One pair's short-range term: Lennard-Jones, or the two-power potential when mie is
+ * given (per type pair ab: mie[4 ab .. 4 ab + 3] = A, B, m, n). */
+static void short_pair(const double *mie, int ab, double r, const double *sigma, const double *eps, const double *rc,
+                       int method, double *u, double *f) {
+  if (mie)
+    oracle_pair_mie(r, mie[4 * ab], mie[4 * ab + 1], (int)mie[4 * ab + 2], (int)mie[4 * ab + 3], sigma[ab], rc[ab],
+                    method, u, f);
+  else
+    oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, u, f);
+}
+
 /* ---- Coulomb with a shifted-force cutoff (paper section 9) ---------------- */
 /* The plain Coulomb pair force qq / r^2 with its value at r_cc subtracted, and
  * the potential that integrates it back from r_cc (zero at r_cc):
@@ -208,8 +254,8 @@ void oracle_coulomb_sf(double r, double qq, double rcc, double *u, double *f) {
  *  Outputs (length nsel or n): F[3*k..], pe[k] = 1/2 sum_j u_ij,
  *  w[k] = 1/2 * 1/3 sum_j (r_i - r_j) . F_ij.   Totals (over the selection):
  *  totals[0] = sum pe, totals[1] = sum w.  In/out decision: r2_f32 < rc2_f32. */
-void oracle_forces_f32_q(int n, const float *pos, const int *type, const double *box, int ntypes,
-                         const double *sigma, const double *eps, const double *rc, int method,
+void oracle_forces_f32_g(int n, const float *pos, const int *type, const double *box, int ntypes,
+                         const double *sigma, const double *eps, const double *rc, int method, const double *mie,
                          const double *charge, double rcc, int nsel, const int *sel, double *F, double *pe,
                          double *w, double *totals) {
   float L32[3], invL[3];
@@ -236,7 +282,7 @@ void oracle_forces_f32_q(int n, const float *pos, const int *type, const double 
       }
       double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       double u = 0.0, f = 0.0;
-      if (in_lj) oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      if (in_lj) short_pair(mie, ab, r, sigma, eps, rc, method, &u, &f);
       if (in_c) {
         double uc, fc;
         oracle_coulomb_sf(r, charge[type[i]] * charge[type[j]], rcc, &uc, &fc);
@@ -265,18 +311,28 @@ void oracle_forces_f32_q(int n, const float *pos, const int *type, const double 
   free(rc2);
 }
 
+/* Lennard-Jones with the optional Coulomb term. */
+void oracle_forces_f32_q(int n, const float *pos, const int *type, const double *box, int ntypes,
+                         const double *sigma, const double *eps, const double *rc, int method,
+                         const double *charge, double rcc, int nsel, const int *sel, double *F, double *pe,
+                         double *w, double *totals) {
+  oracle_forces_f32_g(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, charge, rcc, nsel, sel, F, pe, w,
+                      totals);
+}
+
 /* The Lennard-Jones-only form (no charges). */
 void oracle_forces_f32(int n, const float *pos, const int *type, const double *box, int ntypes,
                        const double *sigma, const double *eps, const double *rc, int method, int nsel,
                        const int *sel, double *F, double *pe, double *w, double *totals) {
-  oracle_forces_f32_q(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, 0.0, nsel, sel, F, pe, w, totals);
+  oracle_forces_f32_g(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, NULL, 0.0, nsel, sel, F, pe, w,
+                      totals);
 }
 
 /* Forces on double-precision positions, in/out decision r^2 < rc^2 in FP64
  * (and r^2 < r_cc^2 for the Coulomb term when charge != NULL).
  * Used by the reference integrator. */
-void oracle_forces_f64_q(int n, const double *pos, const int *type, const double *box, int ntypes,
-                         const double *sigma, const double *eps, const double *rc, int method,
+void oracle_forces_f64_g(int n, const double *pos, const int *type, const double *box, int ntypes,
+                         const double *sigma, const double *eps, const double *rc, int method, const double *mie,
                          const double *charge, double rcc, double *F, double *pe, double *w, double *totals) {
 #pragma omp parallel for schedule(dynamic, 8)
   for (int i = 0; i < n; ++i) {
@@ -294,7 +350,7 @@ void oracle_forces_f64_q(int n, const double *pos, const int *type, const double
       if (!in_lj && !in_c) continue;
       double r = sqrt(r2);
       double u = 0.0, f = 0.0;
-      if (in_lj) oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, &u, &f);
+      if (in_lj) short_pair(mie, ab, r, sigma, eps, rc, method, &u, &f);
       if (in_c) {
         double uc, fc;
         oracle_coulomb_sf(r, charge[type[i]] * charge[type[j]], rcc, &uc, &fc);
@@ -322,10 +378,16 @@ void oracle_forces_f64_q(int n, const double *pos, const int *type, const double
   totals[1] = nsum_value(&tw);
 }
 
+void oracle_forces_f64_q(int n, const double *pos, const int *type, const double *box, int ntypes,
+                         const double *sigma, const double *eps, const double *rc, int method,
+                         const double *charge, double rcc, double *F, double *pe, double *w, double *totals) {
+  oracle_forces_f64_g(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, charge, rcc, F, pe, w, totals);
+}
+
 void oracle_forces_f64(int n, const double *pos, const int *type, const double *box, int ntypes,
                        const double *sigma, const double *eps, const double *rc, int method, double *F,
                        double *pe, double *w, double *totals) {
-  oracle_forces_f64_q(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, 0.0, F, pe, w, totals);
+  oracle_forces_f64_g(n, pos, type, box, ntypes, sigma, eps, rc, method, NULL, NULL, 0.0, F, pe, w, totals);
 }
 
 /* Kinetic energy 1/2 sum m v^2 (compensated). */
@@ -376,10 +438,10 @@ int oracle_rebuild_needed(int n, const float *pos, const float *pos0, const doub
  *   P^n = (2 KE / 3 + W) / V, xi^n, I^n, H^n = KE + PE + g T0 (tau^2 xi^2 / 2 + I), KE(v^{n+1/2}).
  * inv_tau2 = 1/tau^2 (0 means no coupling).  image counts crossings of the box.
  */
-int oracle_integrate_q(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
+int oracle_integrate_g(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
                        const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
-                       int method, const double *charge, double rcc, double dt, int thermostat, double T0,
-                       double inv_tau2, double *xi, double *xi_int, int nsteps, double *thermo) {
+                       int method, const double *mie, const double *charge, double rcc, double dt, int thermostat,
+                       double T0, double inv_tau2, double *xi, double *xi_int, int nsteps, double *thermo) {
   double *F = (double *)malloc(sizeof(double) * 3 * (size_t)n);
   double *pe = (double *)malloc(sizeof(double) * (size_t)n);
   double *w = (double *)malloc(sizeof(double) * (size_t)n);
@@ -390,7 +452,7 @@ int oracle_integrate_q(int n, double *pos, double *vel, int *image, const int *t
   double V = box[0] * box[1] * box[2];
   for (int step = 0; step < nsteps; ++step) {
     double tot[2];
-    oracle_forces_f64_q(n, pos, type, box, ntypes, sigma, eps, rc, method, charge, rcc, F, pe, w, tot);
+    oracle_forces_f64_g(n, pos, type, box, ntypes, sigma, eps, rc, method, mie, charge, rcc, F, pe, w, tot);
     double x = thermostat ? *xi : 0.0;
     double a = 1.0 - x * dt / 2.0, b = 1.0 + x * dt / 2.0;
     for (int i = 0; i < n; ++i) {
@@ -446,11 +508,19 @@ int oracle_integrate_q(int n, double *pos, double *vel, int *image, const int *t
   return 0;
 }
 
+int oracle_integrate_q(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
+                       const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
+                       int method, const double *charge, double rcc, double dt, int thermostat, double T0,
+                       double inv_tau2, double *xi, double *xi_int, int nsteps, double *thermo) {
+  return oracle_integrate_g(n, pos, vel, image, type, mass, box, ntypes, sigma, eps, rc, method, NULL, charge, rcc,
+                            dt, thermostat, T0, inv_tau2, xi, xi_int, nsteps, thermo);
+}
+
 /* The Lennard-Jones-only form (no charges). */
 int oracle_integrate(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
                      const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
                      int method, double dt, int thermostat, double T0, double inv_tau2, double *xi,
                      double *xi_int, int nsteps, double *thermo) {
-  return oracle_integrate_q(n, pos, vel, image, type, mass, box, ntypes, sigma, eps, rc, method, NULL, 0.0, dt,
-                            thermostat, T0, inv_tau2, xi, xi_int, nsteps, thermo);
+  return oracle_integrate_g(n, pos, vel, image, type, mass, box, ntypes, sigma, eps, rc, method, NULL, NULL, 0.0,
+                            dt, thermostat, T0, inv_tau2, xi, xi_int, nsteps, thermo);
 }

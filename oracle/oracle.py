@@ -20,7 +20,8 @@ METHODS = {"trunc": TRUNC, "sp": SP, "sf": SF}
 
 __all__ = [
     "build", "load", "TRUNC", "SP", "SF", "METHODS", "cut_tables", "pair_set", "neighbors_of",
-    "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads", "coulomb_sf",
+    "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads",
+    "coulomb_sf", "pair_mie",
 ]
 
 
@@ -67,16 +68,19 @@ def load():
     lib.oracle_forces_f64.restype = None
     lib.oracle_coulomb_sf.argtypes = [ctypes.c_double] * 3 + [_dp, _dp]
     lib.oracle_coulomb_sf.restype = None
-    lib.oracle_forces_f32_q.argtypes = [ctypes.c_int, _fp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
-                                        _dp, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp, _dp, _dp]
-    lib.oracle_forces_f32_q.restype = None
-    lib.oracle_forces_f64_q.argtypes = [ctypes.c_int, _dp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
-                                        _dp, ctypes.c_double, _dp, _dp, _dp, _dp]
-    lib.oracle_forces_f64_q.restype = None
-    lib.oracle_integrate_q.argtypes = [ctypes.c_int, _dp, _dp, _ip, _ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp,
-                                       ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+    lib.oracle_pair_mie.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
+    lib.oracle_pair_mie.restype = None
+    lib.oracle_forces_f32_g.argtypes = [ctypes.c_int, _fp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
+                                        _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp, _dp, _dp]
+    lib.oracle_forces_f32_g.restype = None
+    lib.oracle_forces_f64_g.argtypes = [ctypes.c_int, _dp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
+                                        _dp, _dp, ctypes.c_double, _dp, _dp, _dp, _dp]
+    lib.oracle_forces_f64_g.restype = None
+    lib.oracle_integrate_g.argtypes = [ctypes.c_int, _dp, _dp, _ip, _ip, _dp, _dp, ctypes.c_int, _dp, _dp, _dp,
+                                       ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                        ctypes.c_double, ctypes.c_double, _dp, _dp, ctypes.c_int, _dp]
-    lib.oracle_integrate_q.restype = ctypes.c_int
+    lib.oracle_integrate_g.restype = ctypes.c_int
     lib.oracle_kinetic.argtypes = [ctypes.c_int, _dp, _ip, _dp]
     lib.oracle_kinetic.restype = ctypes.c_double
     lib.oracle_max_disp2.argtypes = [ctypes.c_int, _fp, _fp, _dp]
@@ -167,6 +171,23 @@ def coulomb_sf(r, qq, rcc):
     return u.value, f.value
 
 
+def pair_mie(r, A, B, m, n, sigma, rc, method):
+    """(u, f) of one pair of the two-power potential A (sigma/r)^m - B (sigma/r)^n."""
+    u = ctypes.c_double()
+    f = ctypes.c_double()
+    load().oracle_pair_mie(float(r), float(A), float(B), int(m), int(n), float(sigma), float(rc), _method(method),
+                           ctypes.byref(u), ctypes.byref(f))
+    return u.value, f.value
+
+
+def _mie(mie, ntypes):
+    """Pack (A, B, m, n), each ntypes x ntypes, as 4 doubles per type pair."""
+    if mie is None:
+        return None
+    parts = [np.asarray(x, np.float64).reshape(ntypes, ntypes) for x in mie]
+    return np.ascontiguousarray(np.stack(parts, -1).reshape(-1))
+
+
 def _charges(charges, ntypes):
     if charges is None:
         return None
@@ -176,9 +197,11 @@ def _charges(charges, ntypes):
     return q
 
 
-def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, rc_coul=0.0):
+def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, rc_coul=0.0, mie=None):
     """Forces (k, 3), per-particle PE (k,), per-particle virial (k,), total PE, total W on float32 positions.
-    With charges (one per type), the shifted-force Coulomb term with cutoff rc_coul is added."""
+    With charges (one per type), the shifted-force Coulomb term with cutoff rc_coul is added.
+    With mie = (A, B, m, n) (each ntypes x ntypes), the two-power potential replaces
+    Lennard-Jones (eps is then unused)."""
     pos = _c(pos, np.float32)
     types = _c(types, np.int32)
     box = _c(box, np.float64)
@@ -198,13 +221,14 @@ def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, 
     w = np.zeros(k)
     tot = np.zeros(2)
     q = _charges(charges, sigma.shape[0])
-    load().oracle_forces_f32_q(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
-                               _method(method), None if q is None else _p(q), float(rc_coul), k, selp, _p(F),
-                               _p(pe), _p(w), _p(tot))
+    g = _mie(mie, sigma.shape[0])
+    load().oracle_forces_f32_g(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
+                               _method(method), None if g is None else _p(g), None if q is None else _p(q),
+                               float(rc_coul), k, selp, _p(F), _p(pe), _p(w), _p(tot))
     return F, pe, w, float(tot[0]), float(tot[1])
 
 
-def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.0):
+def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.0, mie=None):
     pos = _c(pos, np.float64)
     types = _c(types, np.int32)
     box = _c(box, np.float64)
@@ -217,9 +241,10 @@ def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.
     w = np.zeros(n)
     tot = np.zeros(2)
     q = _charges(charges, sigma.shape[0])
-    load().oracle_forces_f64_q(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
-                               _method(method), None if q is None else _p(q), float(rc_coul), _p(F), _p(pe),
-                               _p(w), _p(tot))
+    g = _mie(mie, sigma.shape[0])
+    load().oracle_forces_f64_g(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
+                               _method(method), None if g is None else _p(g), None if q is None else _p(q),
+                               float(rc_coul), _p(F), _p(pe), _p(w), _p(tot))
     return F, pe, w, float(tot[0]), float(tot[1])
 
 
@@ -248,7 +273,7 @@ THERMO_FIELDS = ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_inte
 
 
 def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, thermostat=False, T0=1.0,
-              tau=None, xi=0.0, xi_int=0.0, image=None, charges=None, rc_coul=0.0):
+              tau=None, xi=0.0, xi_int=0.0, image=None, charges=None, rc_coul=0.0, mie=None):
     """Run nsteps of leapfrog (NVE) or Nose-Hoover leapfrog (NVT) in FP64.
 
     Returns dict(pos, vel, image, xi, xi_int, thermo) with thermo an (nsteps, 9) array whose
@@ -269,9 +294,10 @@ def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, th
     xi_i = ctypes.c_double(xi_int)
     thermo = np.zeros((nsteps, 9))
     q = _charges(charges, sigma.shape[0])
-    rc_ = load().oracle_integrate_q(n, _p(pos), _p(vel), _p(image), _p(types), _p(mass), _p(box), sigma.shape[0],
-                                    _p(sigma), _p(eps), _p(rc), _method(method), None if q is None else _p(q),
-                                    float(rc_coul), float(dt), int(bool(thermostat)), float(T0), float(inv_tau2),
+    g = _mie(mie, sigma.shape[0])
+    rc_ = load().oracle_integrate_g(n, _p(pos), _p(vel), _p(image), _p(types), _p(mass), _p(box), sigma.shape[0],
+                                    _p(sigma), _p(eps), _p(rc), _method(method), None if g is None else _p(g),
+                                    None if q is None else _p(q), float(rc_coul), float(dt), int(bool(thermostat)), float(T0), float(inv_tau2),
                                     ctypes.byref(xi_c), ctypes.byref(xi_i), int(nsteps), _p(thermo))
     if rc_ != 0:
         raise MemoryError("oracle_integrate failed")
