@@ -109,6 +109,18 @@ srmd_status srmd_set_allocator(void *(*alloc)(size_t bytes, void *ctx), void (*f
 srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigma, double epsilon, double rcut,
                              srmd_cutoff method);
 
+/* Two-power pair potential between types ti and tj (symmetric), in place of
+ * Lennard-Jones (paper section 2 lists generalised Lennard-Jones and inverse power
+ * laws among the pair potentials; both have this form):
+ *   U(r) = A (sigma/r)^m - B (sigma/r)^n  for r < rcut,
+ * A, B >= 0, even exponents 2 <= n < m <= 48 (B = 0: an inverse power law of
+ * exponent m; A = eps n/(m-n), B = eps m/(m-n): generalised Lennard-Jones), modified
+ * by the cutoff method as srmd_set_pair_lj.  All type pairs of a system use one
+ * potential and one method (mixing with srmd_set_pair_lj: SRMD_EINVAL).  The
+ * Coulomb term does not combine with it (SRMD_EUNSUPPORTED at the next step). */
+srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, double B, int32_t m, int32_t n,
+                              double sigma, double rcut, srmd_cutoff method);
+
 /* Coulomb interactions with a shifted-force cutoff (paper section 9, the molten
  * salt benchmark): charge[t] per type (host array of ntypes doubles, reduced units
  * in which the Coulomb constant is one), one cutoff rcut > 0 for every type pair.
@@ -199,7 +211,7 @@ typedef struct {
   char gpu[64];          /* device architecture name (hipDeviceProp_t::gcnArchName) */
   int32_t compute_units; /* of that device */
   int32_t precision;     /* srmd_precision */
-  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term */
+  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term, 4 two-power potential */
   int32_t thermostat;    /* 0 NVE, 1 Nose-Hoover NVT */
   int32_t ntypes;
   int32_t reserved;

@@ -124,9 +124,17 @@ struct alignas(16) CoulRow {
   float qq, rcc2, inv_rcc2, two_inv_rcc;  // q_a q_b, r_cc^2, 1 / r_cc^2, 2 / r_cc
 };
 
+// Constants of the two-power potential of a type pair (kernel method 4): B, n B,
+// and the half exponents m/2, n/2 (A and m A are in the PairRow's eps4 and eps24).
+struct alignas(16) MieRow {
+  float b, nb;
+  int hm, hn;
+};
+
 struct SharedPairs {
   PairRow row[kMaxPairs];
   CoulRow crow[kMaxPairs];
+  MieRow mrow[kMaxPairs];
 };
 
 __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) {
@@ -148,6 +156,12 @@ __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) 
     q.inv_rcc2 = c.pt.inv_rcc2;
     q.two_inv_rcc = c.pt.two_inv_rcc;
     sp.crow[t] = q;
+    MieRow g;
+    g.b = c.pt.mie_b[t];
+    g.nb = c.pt.mie_nb[t];
+    g.hm = c.pt.mie_hm[t];
+    g.hn = c.pt.mie_hn[t];
+    sp.mrow[t] = g;
   }
 }
 
@@ -166,6 +180,17 @@ __device__ __forceinline__ Wide widen(const float4 p) { return Wide{(double)p.x,
 // in float32 first would cost about ulp(L/2) of absolute accuracy.
 // Accumulates the force on i (-fr * d, with fr = F(r)/r and d = r_j - r_i), the
 // pair energy u and fr * r^2 (= r . F) for the virial.
+// x^h for 0 <= h < 32 by binary exponentiation (five squarings, fixed order).
+__device__ __forceinline__ float pow_int(float x, int h) {
+  float r = 1.0f;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    if (h & (1 << k)) r *= x;
+    x *= x;
+  }
+  return r;
+}
+
 template <int METHOD>
 __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const float4 pj, int ti, int ntypes,
                                          const SharedPairs &sp, const SysConst &c, float &fx, float &fy, float &fz,
@@ -177,6 +202,32 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
   const float r2s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
   const int pidx = ti * ntypes + ptype(pj);
   const PairRow &pr = sp.row[pidx];
+  if (METHOD == 4) {
+    // two-power potential A s^m - B s^n, s = sigma/r, with the cutoff method carried
+    // by U(rc) (zero when truncated) and F(rc) (nonzero for shifted force only)
+    if (r2s < pr.rc2) {
+      dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
+      dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
+      dz = (float)(((double)pj.z - wi.z) - (double)mz * c.Ld[2]);
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      const float inv_r2 = __builtin_amdgcn_rcpf(r2);
+      const MieRow &mr = sp.mrow[pidx];
+      const float s2 = pr.sig2 * inv_r2;
+      const float sm = pow_int(s2, mr.hm), sn = pow_int(s2, mr.hn);
+      float fr = (pr.eps24 * sm - mr.nb * sn) * inv_r2;
+      float e = pr.eps4 * sm - mr.b * sn - pr.ushift;
+      const float inv_r = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * inv_r;
+      fr = __builtin_fmaf(-pr.fc, inv_r, fr);
+      e = __builtin_fmaf(r - pr.rc, pr.fc, e);
+      fx = __builtin_fmaf(-fr, dx, fx);
+      fy = __builtin_fmaf(-fr, dy, fy);
+      fz = __builtin_fmaf(-fr, dz, fz);
+      u += e;
+      w = __builtin_fmaf(fr, r2, w);
+    }
+    return;
+  }
   if (METHOD == 3) {
     // shifted-force Lennard-Jones inside r_c,ab plus shifted-force Coulomb inside r_cc
     // (paper section 9): q_a q_b (1/r - 1/r_cc + (r - r_cc)/r_cc^2), force
@@ -1917,7 +1968,8 @@ static const void *multi_fn(int method) {
   return method == 0 ? (const void *)k_multi<TP, 0, BIG>
          : method == 1 ? (const void *)k_multi<TP, 1, BIG>
          : method == 2 ? (const void *)k_multi<TP, 2, BIG>
-                       : (const void *)k_multi<TP, 3, BIG>;
+         : method == 3 ? (const void *)k_multi<TP, 3, BIG>
+                       : (const void *)k_multi<TP, 4, BIG>;
 }
 
 // The persistent kernel for (tp, method); the large-system form exists for tp <= 8.
@@ -2006,6 +2058,7 @@ static hipError_t launch_step_tp(int method, int prec, dim3 g, dim3 b, hipStream
   SRMD_STEP_CASE(1, 0) SRMD_STEP_CASE(1, 1) SRMD_STEP_CASE(1, 2)
   SRMD_STEP_CASE(2, 0) SRMD_STEP_CASE(2, 1) SRMD_STEP_CASE(2, 2)
   SRMD_STEP_CASE(3, 0) SRMD_STEP_CASE(3, 1) SRMD_STEP_CASE(3, 2)
+  SRMD_STEP_CASE(4, 0) SRMD_STEP_CASE(4, 1) SRMD_STEP_CASE(4, 2)
 #undef SRMD_STEP_CASE
   return hipErrorInvalidValue;
 }
@@ -2017,6 +2070,7 @@ static hipError_t launch_force_tp(int method, dim3 g, dim3 b, hipStream_t st, co
   else if (method == 1) hipLaunchKernelGGL((k_force<TP, 1>), g, b, 0, st, c, p, cur);
   else if (method == 2) hipLaunchKernelGGL((k_force<TP, 2>), g, b, 0, st, c, p, cur);
   else if (method == 3) hipLaunchKernelGGL((k_force<TP, 3>), g, b, 0, st, c, p, cur);
+  else if (method == 4) hipLaunchKernelGGL((k_force<TP, 4>), g, b, 0, st, c, p, cur);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

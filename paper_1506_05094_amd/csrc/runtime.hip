@@ -69,6 +69,9 @@ struct srmd_system {
   double sigma[kMaxPairs] = {}, eps[kMaxPairs] = {}, rc[kMaxPairs] = {};
   bool pair_given[kMaxPairs] = {};
   int method = -1;
+  int pot = -1;                         // 0 Lennard-Jones, 1 two-power (srmd_set_pair_mie); -1 none yet
+  double mie_a[kMaxPairs] = {}, mie_b[kMaxPairs] = {};
+  int mie_m[kMaxPairs] = {}, mie_n[kMaxPairs] = {};
   bool coulomb = false;                 // shifted-force Coulomb term on (srmd_set_coulomb_sf)
   double charge[kMaxTypes] = {0, 0, 0, 0};
   double rcc = 0.0;                     // its cutoff
@@ -172,6 +175,17 @@ double lj_u(double r, double sig, double eps) {
   return 4.0 * eps * (sr6 * sr6 - sr6);
 }
 
+// A s^m - B s^n with s = sig / r, and its force -dU/dr
+double mie_u(double r, double A, double B, int m, int n, double sig) {
+  const double s = sig / r;
+  return A * std::pow(s, m) - B * std::pow(s, n);
+}
+
+double mie_f(double r, double A, double B, int m, int n, double sig) {
+  const double s = sig / r;
+  return (m * A * std::pow(s, m) - n * B * std::pow(s, n)) / r;
+}
+
 double lj_f(double r, double sig, double eps) {
   const double sr = sig / r;
   const double sr6 = sr * sr * sr * sr * sr * sr;
@@ -186,8 +200,9 @@ double rc_max(const srmd_system *s) {
 }
 
 // The method index the kernels are instantiated for: the Lennard-Jones cutoff
-// method, or 3 for shifted-force Lennard-Jones plus shifted-force Coulomb.
-int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->method; }
+// method, 3 for shifted-force Lennard-Jones plus shifted-force Coulomb, 4 for the
+// two-power potential (any cutoff method).
+int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->pot == 1 ? 4 : s->method; }
 
 bool all_pairs_given(const srmd_system *s) {
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
@@ -291,7 +306,7 @@ void resolve_persistent(srmd_system *s) {
 srmd_status prepare(srmd_system *s) {
   if (s->method < 0 || !all_pairs_given(s))
     return fail(s, SRMD_EINVAL, "pair potential not set for every type pair (srmd_set_pair_lj)");
-  if (s->coulomb && s->method != SRMD_CUT_SF)
+  if (s->coulomb && (s->method != SRMD_CUT_SF || s->pot != 0))
     return fail(s, SRMD_EUNSUPPORTED, "the Coulomb term runs with shifted-force Lennard-Jones (SRMD_CUT_SF) only");
   if (!s->dirty) return SRMD_OK;
   resolve_launch(s);
@@ -368,6 +383,18 @@ srmd_status prepare(srmd_system *s) {
     c.pt.rc[a] = (float)s->rc[a];
     c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)lj_u(s->rc[a], s->sigma[a], s->eps[a]);
     c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)lj_f(s->rc[a], s->sigma[a], s->eps[a]) : 0.0f;
+    if (s->pot == 1) {
+      const double A = s->mie_a[a], B = s->mie_b[a];
+      const int m = s->mie_m[a], n = s->mie_n[a];
+      c.pt.eps4[a] = (float)A;
+      c.pt.eps24[a] = (float)(m * A);
+      c.pt.mie_b[a] = (float)B;
+      c.pt.mie_nb[a] = (float)(n * B);
+      c.pt.mie_hm[a] = m / 2;
+      c.pt.mie_hn[a] = n / 2;
+      c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)mie_u(s->rc[a], A, B, m, n, s->sigma[a]);
+      c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)mie_f(s->rc[a], A, B, m, n, s->sigma[a]) : 0.0f;
+    }
   }
   // storage that depends on the layout
   const long long need_nbl = (long long)nmax * c.nvp;
@@ -1076,15 +1103,51 @@ srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigm
     return fail(s, SRMD_EINVAL, "unknown cutoff method");
   if (s->method >= 0 && s->method != (int)method)
     return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
+  if (s->pot == 1) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (two-power set before)");
   for (int k = 0; k < 3; ++k)
     if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
       return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
   s->method = (int)method;
+  s->pot = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const int a = pass ? pair_index(s, tj, ti) : pair_index(s, ti, tj);
     s->sigma[a] = sigma;
     s->eps[a] = epsilon;
     s->rc[a] = rcut;
+    s->pair_given[a] = true;
+  }
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, double B, int32_t m, int32_t n,
+                              double sigma, double rcut, srmd_cutoff method) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (ti < 0 || tj < 0 || ti >= s->ntypes || tj >= s->ntypes) return fail(s, SRMD_EINVAL, "type index out of range");
+  if (!(A >= 0) || !(B >= 0) || !std::isfinite(A) || !std::isfinite(B) || !(sigma > 0) || !std::isfinite(sigma) ||
+      !(rcut > 0) || !std::isfinite(rcut))
+    return fail(s, SRMD_EINVAL, "A, B must be non-negative and sigma, rcut positive");
+  if (m % 2 || n % 2 || n < 2 || m <= n || m > 48)
+    return fail(s, SRMD_EINVAL, "exponents must be even with 2 <= n < m <= 48");
+  if (method != SRMD_CUT_TRUNC && method != SRMD_CUT_SP && method != SRMD_CUT_SF)
+    return fail(s, SRMD_EINVAL, "unknown cutoff method");
+  if (s->method >= 0 && s->method != (int)method)
+    return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
+  if (s->pot == 0) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (Lennard-Jones set before)");
+  for (int k = 0; k < 3; ++k)
+    if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+  s->method = (int)method;
+  s->pot = 1;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int a = pass ? pair_index(s, tj, ti) : pair_index(s, ti, tj);
+    s->sigma[a] = sigma;
+    s->eps[a] = 0.0;
+    s->rc[a] = rcut;
+    s->mie_a[a] = A;
+    s->mie_b[a] = B;
+    s->mie_m[a] = m;
+    s->mie_n[a] = n;
     s->pair_given[a] = true;
   }
   s->dirty = true;

@@ -34,6 +34,10 @@ struct PairTable {
   // one Coulomb cutoff r_cc: r_cc^2, 1 / r_cc^2 and 2 / r_cc
   float qq[kMaxPairs];
   float rcc2, inv_rcc2, two_inv_rcc;
+  // two-power potential A (sigma/r)^m - B (sigma/r)^n (kernel method 4; A and m A
+  // travel in eps4 and eps24): B, n B and the half exponents m/2, n/2
+  float mie_b[kMaxPairs], mie_nb[kMaxPairs];
+  int mie_hm[kMaxPairs], mie_hn[kMaxPairs];
 };
 
 // Everything a kernel needs besides pointers; passed by value.

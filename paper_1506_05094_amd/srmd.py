@@ -142,6 +142,8 @@ def load():
                                   ctypes.c_double, ctypes.c_int]),
         "srmd_set_skin": (st, [sysp, ctypes.c_double]),
         "srmd_set_coulomb_sf": (st, [sysp, _dp, ctypes.c_double]),
+        "srmd_set_pair_mie": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
         "srmd_set_integrator_nve": (st, [sysp, ctypes.c_double]),
         "srmd_set_integrator_nvt": (st, [sysp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
@@ -277,6 +279,17 @@ class System:
 
     def set_skin(self, skin):
         _check(load().srmd_set_skin(self._h, float(skin)), self._h)
+
+    def set_pairs_mie(self, A, B, m, n, sigma, rc, method):
+        """Two-power potential A (sigma/r)^m - B (sigma/r)^n for every type pair (arrays
+        ntypes x ntypes, symmetric) with one cutoff method."""
+        lib = load()
+        mth = CUTOFF[method] if isinstance(method, str) else int(method)
+        A, B, m, n, sigma, rc = (np.asarray(x).reshape(self.ntypes, self.ntypes) for x in (A, B, m, n, sigma, rc))
+        for a in range(self.ntypes):
+            for b in range(a, self.ntypes):
+                _check(lib.srmd_set_pair_mie(self._h, a, b, float(A[a, b]), float(B[a, b]), int(m[a, b]),
+                                             int(n[a, b]), float(sigma[a, b]), float(rc[a, b]), mth), self._h)
 
     def set_coulomb_sf(self, charges, rcut):
         """Shifted-force Coulomb term (paper section 9): one charge per type, one cutoff;
@@ -456,7 +469,8 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
             "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
-            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf"]
+            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf",
+            "srmd_set_pair_mie"]
 
 
 def _export_c_names():
