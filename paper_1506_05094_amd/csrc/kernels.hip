@@ -398,8 +398,10 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v)
 // in the first thread of each group.  Every thread of the block must call it.
 // With group = blockDim.x this is the block-wide reduction; the batched kernel
 // uses groups to reproduce the blocks of the single-system kernels exactly.
-__device__ void group_reduce(BlockPartial &v, BlockPartial *s_waves, int group) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wpg = group >> 6;
+// used: the group's waves that can hold data (the rest hold zero partials, whose fold
+// changes nothing: no partial is -0.0, since every sum starts from +0.0)
+__device__ void group_reduce(BlockPartial &v, BlockPartial *s_waves, int group, int used = 64) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, wpg = min(group >> 6, used);
   v.pe = wave_sum(v.pe);
   v.w = wave_sum(v.w);
   v.ke_half = wave_sum(v.ke_half);
@@ -1512,7 +1514,8 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
     a.t0 = q.t0 < a.t0 ? q.t0 : a.t0;
     a.t1 = q.t1 > a.t1 ? q.t1 : a.t1;
   }
-  block_reduce(a, s_waves);
+  // threads at or past G hold zero partials: only the first (G + 63) / 64 waves are folded
+  group_reduce(a, s_waves, (int)blockDim.x, (G + 63) / 64);
   if (threadIdx.x == 0) {
     Control *ctl = p.ctl;
     int rebuild = 0;
@@ -1933,8 +1936,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       }
       __syncthreads();
       if (tid == 0) {
+        // the waves of k_finish that hold data (as its group_reduce folds them)
         BlockPartial a = s_waves[0];
-        for (int q = 1; q < 16; ++q) fold(a, s_waves[q]);
+        const int used = min(16, (G + 63) / 64);
+        for (int q = 1; q < used; ++q) fold(a, s_waves[q]);
         a.t0 = 0ull;
         a.t1 = 0ull;
         if (J.w == 0) finish_step(c, p, a, cv);  // the one writer of the control block
