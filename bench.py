@@ -5,14 +5,17 @@ Default workload: Kob-Andersen 80:20 binary Lennard-Jones mixture, N = 4096,
 density 1.2, Nose-Hoover NVT at T = 0.45 (tau = 0.2), dt = 0.005, shifted-force
 cutoff 2.5 sigma_ab, skin 0.3, float32 positions and forces with float64
 reductions.  Seeded random non-overlapping start, relaxed by an untimed
-2000-step NVT run at dt = 0.001, then W untimed and K timed steps at dt = 0.005.
-A step is one pass of the whole hot path: displacement check, list rebuild when
-due (cell binning, counting sort, reorder, cell-stencil list), pair forces,
-integrator and thermostat.
+2000-step NVT run at dt = 0.001 and untimed NVT steps at dt = 0.005 until the
+temperature is within 3 % of T0, then W untimed and K timed steps (one
+srmd_step call).  A step is one pass of the whole hot path: displacement check,
+list rebuild when due (cell binning, counting sort, reorder, cell-stencil list),
+pair forces, integrator and thermostat.
 
 Prints one JSON line with particle-steps/s (whole job), the roofline position of
-the dominant kernel (the fused force + integrator kernel) and the CPU oracle's
-rate on the host cores.
+the dominant kernel (per step: algorithmic bytes and FLOPs against HBM and FP32
+peaks, from kernel durations taken in a separate untimed pass), the CPU oracle's
+rate on the host cores and on one core, and the batched-replica comparison of
+256 Kob-Andersen replicas against one system per launch.
 """
 import argparse
 import json
@@ -62,21 +65,48 @@ def workload(name, n, skin):
     raise SystemExit(f"unknown workload {name}")
 
 
-def step_kernel_bytes(n, list_entries):
-    """Algorithmic bytes of one fused step-kernel launch.
-
-    Per particle: list length (4) + list entries (4 each) + position (16; the
-    spatially sorted position array is counted once, it serves every neighbour read)
-    + velocity (16) + image/id (16) + last-build position (16) read, and position,
-    velocity, image/id and force (4 x 16) written: 132 B + 4 B per list entry.
-    """
-    return 132.0 * n + 4.0 * list_entries
+FP32_PEAK_TFLOPS = 157.3
 
 
-def hbm_traffic(workload_name, n, mode, tp, ppb, skin):
-    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE passes (profiles/traffic.json), or None when they were
-    taken with another kernel source or another workload / launch shape."""
+def path_bytes_per_particle_step(list_len, steps_per_rebuild, whole_path):
+    """Algorithmic bytes per particle-step: force kernel 4 per list entry + 40 (list
+    length, own position, force and energy out, virial), integrator 96 (position,
+    velocity, force and last-build position in; position and velocity out), and for
+    the whole path (the persistent kernel) the rebuild's 170 + 4 per list entry
+    amortised over the steps between rebuilds.  The neighbours' positions count once:
+    the spatially sorted position array serves every neighbour read."""
+    b = 4.0 * list_len + 40.0 + 96.0
+    if whole_path:
+        b += (170.0 + 4.0 * list_len) / max(steps_per_rebuild, 1.0)
+    return b
+
+
+def flops_per_particle_step(list_len, in_range, method):
+    """Algorithmic FP32 FLOPs per particle-step (FMA = 2, rcp / rsq = 1): 20 per list
+    entry (difference, minimum image, r^2) and per in-range pair 21 (shifted
+    potential) or 27 (shifted force)."""
+    return 20.0 * list_len + (27.0 if method == "sf" else 21.0) * in_range
+
+
+def in_range_pairs_per_particle(pos, types, box, rc):
+    """Mean count of partners within r_c,ab (float64 distances of the final state)."""
+    from scipy.spatial import cKDTree
+
+    p = np.mod(pos.astype(np.float64) + box / 2, box)
+    tree = cKDTree(p, boxsize=box)
+    pr = tree.query_pairs(float(np.max(rc)), output_type="ndarray")
+    d = p[pr[:, 0]] - p[pr[:, 1]]
+    d -= box * np.rint(d / box)
+    r = np.sqrt((d * d).sum(1))
+    keep = r < rc[types[pr[:, 0]], types[pr[:, 1]]]
+    return 2.0 * keep.sum() / len(pos)
+
+
+def hbm_traffic_per_step(workload_name, n, mode, tp, ppb, skin):
+    """HBM bytes per step of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (profiles/traffic.json; per dispatch, divided by
+    the steps of that dispatch), or None when they were taken with another kernel
+    source or another workload / launch shape."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -92,12 +122,24 @@ def hbm_traffic(workload_name, n, mode, tp, ppb, skin):
         return None
     for e in table.get("entries", []):
         if (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"]) == (workload_name, n, mode, tp, ppb, skin):
-            return 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
+            per_dispatch = 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
+            return per_dispatch / e["steps_per_launch"]
+    return None
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
     return None
 
 
 def cpu_baseline(state, params, method, integ, budget_s=12.0):
-    """The oracle (FP64, O(N^2), OpenMP over particles) on the host cores."""
+    """The oracle (FP64, O(N^2), OpenMP over particles) on every host core, and on one."""
     import oracle
 
     sig, eps, rc = params[:3]
@@ -106,27 +148,46 @@ def cpu_baseline(state, params, method, integ, budget_s=12.0):
         kw = dict(charges=params[3], rc_coul=params[4])
     if integ[0] == "nvt":
         kw.update(thermostat=True, T0=integ[2], tau=integ[3])
-    t0 = time.perf_counter()
-    oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1], 1, **kw)
-    t1 = time.perf_counter() - t0
-    steps = int(max(1, min(2000, budget_s / max(t1, 1e-6))))
-    t0 = time.perf_counter()
-    oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1], steps,
-                     **kw)
-    dt = time.perf_counter() - t0
-    return {"value": state.n * steps / dt, "unit": "particle-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+
+    def rate(budget):
+        t0 = time.perf_counter()
+        oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1], 1,
+                         **kw)
+        t1 = time.perf_counter() - t0
+        steps = int(max(1, min(2000, budget / max(t1, 1e-6))))
+        t0 = time.perf_counter()
+        oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, integ[1],
+                         steps, **kw)
+        dt = time.perf_counter() - t0
+        return state.n * steps / dt, steps, dt
+
+    cores = oracle.num_threads()
+    v_all, steps, dt = rate(budget_s)
+    oracle.set_num_threads(1)
+    try:
+        v_one, steps1, dt1 = rate(budget_s / 3)
+    finally:
+        oracle.set_num_threads(cores)
+    return {"value": v_all, "unit": "particle-steps/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "value_one_core": v_one,
             "sample": f"{steps} oracle steps of the same system (N={state.n}, O(N^2) FP64 forces) from the seeded "
-                      f"start, {dt:.1f} s wall"}
+                      f"start on {cores} threads, {dt:.1f} s wall; {steps1} steps on one thread, {dt1:.1f} s wall"}
 
 
-def run_replicas(args):
-    """Batched Kob-Andersen replicas: one persistent launch vs one launch chain per system."""
+def replica_comparison(args, steps=None, base_steps=None):
+    """Config 3: 256 Kob-Andersen replicas (N ~ U[500, 8000], T ~ U[0.4, 1.0], NVT dt
+    0.005) advanced by one persistent launch per 500 steps, against the same systems
+    advanced one system per launch in three forms: the batch's launch shape with
+    launch chains (a replica then follows its batched trajectory bit for bit, so the
+    energy drift is equal by construction), each system's default shape with launch
+    chains, and the default shape with the persistent kernel.  Returns a dict."""
     import torch
 
     from paper_1506_05094_amd import srmd
     from workloads import generators as gen
 
+    steps = steps or args.replica_steps
+    base_steps = base_steps or args.baseline_steps
     t0 = time.perf_counter()
     states = gen.ka_replica_states(args.replicas, workers=min(16, os.cpu_count() or 1))
     log(f"generated {len(states)} replicas (N = {sum(s.n for s in states)}) in {time.perf_counter() - t0:.1f} s")
@@ -134,7 +195,6 @@ def run_replicas(args):
     temps = [T for (_, T, _) in gen.config3_states(args.replicas)]
     stream = torch.cuda.current_stream().cuda_stream
     # t_p = 1, 256 particles per block: the fastest batch layout measured on MI355X
-    # (t_p = 1 / 2 / 4 / 8: 1.37 / 1.31 / 1.26 / 1.05e9 particle-steps/s)
     tp, ppb = args.tp or 1, args.ppb or max(1, 256 // (args.tp or 1))
     systems = []
     for st, T in zip(states, temps):
@@ -143,23 +203,30 @@ def run_replicas(args):
         s.set_integrator_nvt(0.001, T, 0.2)
         systems.append(s)
     ntot = sum(s.n for s in systems)
+    nr = np.array([s.n for s in systems])
+    every = max(1, steps // 50)
+
+    def drift(trace, k):
+        h = trace["h_conserved"] / nr[:, None]
+        x = np.arange(h.shape[1]) * k
+        d = np.array([np.polyfit(x, h[r], 1)[0] for r in range(h.shape[0])])
+        return {"median_abs": float(np.median(np.abs(d))), "max_abs": float(np.max(np.abs(d)))}
+
     batch = srmd.Batch(systems)
     batch.step(2000)  # relax the random insertion (untimed)
     for s, T in zip(systems, temps):
         s.set_integrator_nvt(0.005, T, 0.2)
-    batch.step(args.warmup)
+    batch.step(max(args.warmup, 200))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    trace = batch.step(args.steps, thermo_every=max(1, args.steps // 50))
+    trace = batch.step(steps, thermo_every=every)
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t0
-    value_b = ntot * args.steps / wall_b
-    log(f"batched: {args.steps} steps of {len(systems)} replicas in {wall_b:.3f} s -> {value_b:.4e} particle-steps/s")
-    # baselines: the same systems advanced one at a time (one system per launch), in
-    # three forms: the batch's launch shape with launch chains, each system's default
-    # launch shape with launch chains, and the default shape with the persistent kernel
-    # (500 steps per launch); the best of them is the denominator
-    base_steps = min(args.steps, args.baseline_steps)
+    value_b = ntot * steps / wall_b
+    batch.close()
+    log(f"batched: {steps} steps of {len(systems)} replicas in {wall_b:.3f} s -> {value_b:.4e} particle-steps/s")
+    base_steps = min(steps, base_steps)
+    base_every = max(1, base_steps // 20)
     baselines = {}
     for name, shape, mode in (("chain_same_shape", (tp, ppb), 0), ("chain_default_shape", (0, 0), 0),
                               ("persistent_default_shape", (0, 0), -1)):
@@ -169,35 +236,44 @@ def run_replicas(args):
             s.step(base_steps)  # list rebuilt for the new layout, graphs of these lengths captured (untimed)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for s in systems:
-            s.step(base_steps)
+        tr = [s.step(base_steps, thermo_every=base_every) for s in systems]
         torch.cuda.synchronize()
         wall_s = time.perf_counter() - t0
-        baselines[name] = {"value": ntot * base_steps / wall_s, "steps": base_steps, "wall_s": wall_s}
+        tr = np.stack(tr)
+        baselines[name] = {"value": ntot * base_steps / wall_s, "steps": base_steps, "wall_s": wall_s,
+                           "h_drift_per_particle_per_step": drift(tr, base_every)}
         log(f"one system per launch ({name}): {base_steps} steps each in {wall_s:.3f} s -> "
             f"{baselines[name]['value']:.4e} particle-steps/s; batched / this = "
             f"{value_b / baselines[name]['value']:.2f}")
-    best = max(baselines.values(), key=lambda b: b["value"])
-    value_s = best["value"]
-    h = trace["h_conserved"] / np.array([s.n for s in systems])[:, None]
-    steps_axis = np.arange(h.shape[1])
-    drift = np.array([np.polyfit(steps_axis, h[r], 1)[0] for r in range(h.shape[0])]) / max(1, args.steps // 50)
-    batch.close()
     for s in systems:
         s.close()
+    best = max(baselines.values(), key=lambda b: b["value"])
+    return {
+        "workload": f"{len(systems)} Kob-Andersen replicas, N ~ U[500, 8000], T ~ U[0.4, 1.0], NVT dt 0.005, "
+                    "one persistent launch per 500 steps",
+        "n_total": ntot, "tp": tp, "ppb": ppb, "steps": steps, "value": value_b, "unit": "particle-steps/s",
+        "wall_s": wall_b, "one_launch_per_system": baselines,
+        "batched_over_single_same_shape": value_b / baselines["chain_same_shape"]["value"],
+        "batched_over_single_best": value_b / best["value"],
+        "note": "same shape: each replica follows its single-system trajectory bit for bit, so the energy drift is "
+                "equal by construction; best: the fastest one-system-per-launch form (other launch shape, drift "
+                "reported beside it)",
+        "h_drift_per_particle_per_step": drift(trace, every),
+    }
+
+
+def run_replicas(args):
+    """Batched Kob-Andersen replicas: one persistent launch vs one launch chain per system."""
+    r = replica_comparison(args, steps=args.steps)
     out = {
-        "metric": METRIC, "value": value_b, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall_b / args.steps * 1e3, "higher_is_better": True,
+        "metric": METRIC, "value": r["value"], "unit": "particle-steps/s", "n_gpus": 1, "steps": r["steps"],
+        "warmup": args.warmup, "ms_per_step": r["wall_s"] / r["steps"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{len(systems)} Kob-Andersen replicas, N ~ U[500, 8000], T ~ U[0.4, 1.0], NVT "
-                               "dt 0.005, one persistent launch", "n_total": ntot, "tp": tp, "ppb": ppb},
-        "one_launch_per_system": baselines,
-        "batched_over_single": value_b / value_s,
-        "batched_over_single_note": "denominator: the fastest one-system-per-launch form; at the batch's launch "
-                                    "shape a replica follows its single-system trajectory bit for bit, so the "
-                                    "energy drift is equal by construction",
-        "h_drift_per_particle_per_step": {"median_abs": float(np.median(np.abs(drift))),
-                                          "max_abs": float(np.max(np.abs(drift)))},
+        "config": {"workload": r["workload"], "n_total": r["n_total"], "tp": r["tp"], "ppb": r["ppb"]},
+        "one_launch_per_system": r["one_launch_per_system"],
+        "batched_over_single_same_shape": r["batched_over_single_same_shape"],
+        "batched_over_single_best": r["batched_over_single_best"], "note": r["note"],
+        "h_drift_per_particle_per_step": r["h_drift_per_particle_per_step"],
     }
     print(json.dumps(out), flush=True)
 
@@ -308,8 +384,8 @@ def main():
     ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
     ap.add_argument("--tune", action="store_true",
                     help="run the autotuner (untimed) after the relaxation; the tuned layout and mode are timed")
-    ap.add_argument("--skin", type=float, default=0.5,
-                    help="neighbour-list skin of the ka4096 and lj workloads (default: the paper's default, 0.5)")
+    ap.add_argument("--skin", type=float, default=0.3,
+                    help="neighbour-list skin of the ka4096, lj and salt workloads (default 0.3)")
     ap.add_argument("--tune-full", action="store_true",
                     help="as --tune (and for the size sweep) with the full autotuner: skin optimisation, every "
                          "list method within 20 %% of the fastest, and the tuned-parameter file of --tune-cache")
@@ -317,7 +393,10 @@ def main():
     ap.add_argument("--sizes", default="1000,4000,16000,64000,256000,1024000", help="N values of the size sweep")
     ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial (size sweep, --tune)")
     ap.add_argument("--replicas", type=int, default=256)
-    ap.add_argument("--baseline-steps", type=int, default=1000)
+    ap.add_argument("--baseline-steps", type=int, default=200,
+                    help="steps per system of each one-system-per-launch form in the replica comparison")
+    ap.add_argument("--replica-steps", type=int, default=1000,
+                    help="batched steps of the replica comparison in the default line (0: leave it out)")
     ap.add_argument("--n", type=int, default=864, help="particles for --workload lj (salt: 2000 unless given)")
     ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
     ap.add_argument("--ppb", type=int, default=0)
@@ -325,7 +404,8 @@ def main():
                     help="persistent: 500 steps per launch of one kernel (systems up to 8192 particles here); "
                          "chain: graph-captured launch chains")
     ap.add_argument("--groups", type=int, default=-1, help="workgroups of the persistent kernel (-1: automatic)")
-    ap.add_argument("--profile-steps", type=int, default=1000)
+    ap.add_argument("--profile-steps", type=int, default=1000,
+                    help="steps of the untimed pass that times the dominant kernel's launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB between two device buffers three times (a plain copy of known "
@@ -376,6 +456,11 @@ def main():
         s.set_integrator_nvt(0.001, integ[2], integ[3])
         s.step(2000)  # relax the random insertion (untimed)
         s.set_integrator_nvt(integ[1], integ[2], integ[3])
+        # untimed: bring the temperature to T0 whatever --warmup is
+        for _ in range(40):
+            tr = s.step(500, thermo_every=10)
+            if abs(np.mean(tr["temperature"][-10:]) / integ[2] - 1.0) < 0.03:
+                break
     else:
         s.set_integrator_nve(integ[1])
     tuned = None
@@ -383,7 +468,7 @@ def main():
         # untimed: the full autotuner picks layout, list builder, mode and skin
         tuned = s.autotune_full(args.tune_steps, args.tune_cache)
         log(f"autotune_full: {tuned}")
-        desc["skin"] = tuned["skin"]
+        desc["skin_tuned"] = tuned["skin"]
         persistent = s.stats()["persistent_groups"] > 0
     elif args.tune:
         # untimed: the autotuner picks layout, list builder and mode from this state
@@ -393,12 +478,7 @@ def main():
     torch.cuda.synchronize()
     st0 = s.stats()
     t0 = time.perf_counter()
-    if persistent:
-        # the timed steps themselves, with a HIP event pair around every launch of
-        # the persistent kernel (500 steps per launch) on the system's stream
-        ev_ms, dev_ms, launches = s.profile_step_kernel(args.steps)
-    else:
-        s.step(args.steps)
+    s.step(args.steps)  # the product call: every timed step in one srmd_step
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st1 = s.stats()
@@ -408,38 +488,56 @@ def main():
     log(f"timed {args.steps} steps in {wall:.4f} s: {value:.4e} particle-steps/s, {args.steps / wall:.1f} steps/s, "
         f"rebuilds {st1['n_rebuilds'] - st0['n_rebuilds']}, tp {st1['tp']} ppb {st1['ppb']}, "
         f"groups {st1['persistent_groups']}, T {th['temperature']:.4f}")
-    if persistent:
-        steps_per_launch = args.steps / launches
-    else:
-        # launch chains: the fused step kernel timed per launch in a profiled pass
-        ev_ms, dev_ms, launches = s.profile_step_kernel(args.profile_steps)
-        steps_per_launch = 1
-    # entries of a list built at the final positions (the counter of the last build
-    # reads 0 when the run ended on a step that scheduled a rebuild)
-    s.build_neighbor_list()
+    # untimed: the dominant kernel's launches timed one by one with HIP events on the
+    # system's stream (persistent: launches of 500 steps; chains: the step kernel)
+    prof_steps = max(args.profile_steps, 1000 if persistent else 200)
+    ev_ms, dev_ms, launches = s.profile_step_kernel(prof_steps)
     st2 = s.stats()
-    avg_s = ev_ms / 1e3 / launches
-    dev_avg_s = dev_ms / 1e3 / launches
-    bytes_launch = step_kernel_bytes(n, st2["list_entries"]) * steps_per_launch
-    achieved = bytes_launch / avg_s / 1e9
-    log(f"dominant kernel: {launches} launches of {steps_per_launch:g} steps, event avg {avg_s * 1e6:.2f} us "
-        f"({avg_s * 1e6 / steps_per_launch:.3f} us/step), device-clock avg {dev_avg_s * 1e6:.2f} us, "
-        f"{bytes_launch / 1e6:.3f} MB algorithmic per launch -> {achieved:.1f} GB/s")
+    steps_per_launch = prof_steps / launches if persistent else 1.0
+    # list length of a list built at the final positions (the counter of the last
+    # build reads 0 when the run ended on a step that scheduled a rebuild), and the
+    # measured steps per rebuild over the timed and profiled steps
+    fin = s.get_state()
+    s.build_neighbor_list()
+    list_len = s.stats()["list_entries"] / n
+    rebuilds = st2["n_rebuilds"] - st0["n_rebuilds"]
+    steps_per_rebuild = (args.steps + prof_steps) / max(rebuilds, 1)
+    # the Coulomb term's cutoff widens the pairs whose force is evaluated (molten salt)
+    rc_eval = np.maximum(rc, params[4]) if len(params) == 5 else rc
+    in_range = in_range_pairs_per_particle(fin["pos"], state.types, state.box, rc_eval)
+    step_s = ev_ms / 1e3 / launches / steps_per_launch  # dominant kernel, per step
+    bytes_step = n * path_bytes_per_particle_step(list_len, steps_per_rebuild, persistent)
+    flops_step = n * flops_per_particle_step(list_len, in_range, method)
+    hbm_gbs = bytes_step / step_s / 1e9
+    tflops = flops_step / step_s / 1e12
+    hbm_frac, fp32_frac = hbm_gbs / HBM_PEAK_GBS, tflops / FP32_PEAK_TFLOPS
     kname = ("k_multi (persistent: list build, sort, pair force, integrator, reductions)" if persistent
              else "k_step (fused pair force + integrator)")
-    traffic = hbm_traffic(desc["workload"], n, "persistent" if persistent else "chain", st1["tp"], st1["ppb"],
-                          desc["skin"])
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-                "traffic_note": "HBM bytes per launch (FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000, copy-calibrated)",
-                "kernel": kname, "steps_per_launch": steps_per_launch, "avg_us_events": round(avg_s * 1e6, 3),
-                "avg_us_device_clock": round(dev_avg_s * 1e6, 3), "bytes_per_launch": bytes_launch,
-                "list_entries_per_particle": round(st2["list_entries"] / n, 2)}
+    traffic = hbm_traffic_per_step(desc["workload"], n, "persistent" if persistent else "chain", st1["tp"],
+                                   st1["ppb"], desc["skin"])
+    # the arithmetic intensity sits below the FP32 ridge (157.3 / 8 = 19.7 FLOP/B), so
+    # the roofline bound is HBM; when both fractions are far below one the kernel is
+    # held by latency and synchronisation instead (small systems, paper section 3)
+    bound = "hbm" if max(hbm_frac, fp32_frac) >= 0.1 else "latency"
+    log(f"dominant kernel: {launches} launches of {steps_per_launch:g} steps, {step_s * 1e6:.3f} us/step; "
+        f"{bytes_step / 1e6:.3f} MB and {flops_step / 1e6:.2f} MFLOP algorithmic per step -> {hbm_gbs:.1f} GB/s "
+        f"({hbm_frac:.4f} of HBM), {tflops:.3f} TFLOP/s ({fp32_frac:.4f} of FP32); list {list_len:.1f}, "
+        f"in range {in_range:.1f}, steps per rebuild {steps_per_rebuild:.1f}")
+    roofline = {"bound": bound, "achieved": round(hbm_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(hbm_frac, 5), "traffic": traffic,
+                "traffic_note": "HBM bytes per step of the dominant kernel (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE, "
+                                "copy-calibrated), null when the counters belong to other kernel source or shape",
+                "bytes_per_step": bytes_step, "units": "per step (algorithmic bytes and FLOPs / kernel time per step)",
+                "fp32": {"achieved": round(tflops, 4), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(fp32_frac, 5), "flops_per_step": flops_step},
+                "kernel": kname, "steps_per_launch": steps_per_launch, "us_per_step": round(step_s * 1e6, 3),
+                "profiled_steps": prof_steps, "list_entries_per_particle": round(list_len, 2),
+                "in_range_per_particle": round(in_range, 2), "steps_per_rebuild": round(steps_per_rebuild, 2)}
+    s.close()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(state, params, method, integ)
         log(f"cpu baseline: {cpu}")
-    s.close()
     out = {
         "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -448,8 +546,11 @@ def main():
                        groups=st1["persistent_groups"]),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],
+        "final_temperature": th["temperature"],
         "roofline": roofline, "cpu_baseline": cpu,
     }
+    if args.workload == "ka4096" and args.replica_steps > 0:
+        out["batched_replicas"] = replica_comparison(args)
     print(json.dumps(out), flush=True)
 
 

@@ -220,6 +220,12 @@ typedef struct {
   double temperature;    /* T0 under NVT; under NVE the kinetic temperature 2 KE / (3N - 3) of the state */
   double dt;
   double sigma[16], epsilon[16], rcut[16];
+  int32_t potential;        /* 0 12-6 Lennard-Jones, 1 the two-power potential */
+  int32_t reserved2;
+  double pot_param[16][4];  /* per type pair, the potential's parameters besides sigma and rcut
+                               (two-power: A, B, m, n); zero for Lennard-Jones */
+  double charge[4];         /* Coulomb charges per type (zero without the Coulomb term) */
+  double rc_coulomb;        /* Coulomb cutoff (zero without the term) */
 } srmd_tuning_key;
 
 /* Parameters chosen by srmd_autotune_full (or read back from its cache file). */
@@ -240,8 +246,9 @@ srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key);
 
 /* Look key up in the tuned-parameter file at path (host code only, no GPU call).
  * A record matches when the GPU name, compute units, precision, cutoff method,
- * integrator, type count and particle counts are equal, dt, density and every
- * pair parameter agree to 1e-6 relative, and the temperature to 2 % relative;
+ * potential, integrator, type count and particle counts are equal, dt, density,
+ * every pair parameter, charge and the Coulomb cutoff agree to 1e-6 relative, and
+ * the temperature to 2 % relative;
  * the last matching record wins.  *found = 1 and *out filled on a match, else
  * *found = 0.  A missing file is no match; unreadable or malformed lines are
  * skipped.  SRMD_EINVAL for NULL arguments. */
@@ -293,9 +300,43 @@ srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd
  * widened). force holds the forces of the last force evaluation. */
 srmd_status srmd_get_state(srmd_system *s, float *pos, float *vel, int32_t *image, float *force, double *pos64);
 
+/* Per-particle terms of the pair sums, in original particle order; either pointer
+ * may be NULL.  pe: float32 n, half the pair energies of each particle (the force
+ * kernel figure of paper section 5 halves them against double counting), from the
+ * last force evaluation (srmd_compute_forces or a time step).  virial: float32 n,
+ * 1/6 sum_j r_ij . F_ij of each particle (its share of W = 1/3 sum over pairs of
+ * r_ij . F_ij, paper section 2 "energy, pressure"), from the last srmd_compute_forces
+ * call only (time steps do not store it; zero before the first call).  Both sum, in
+ * float64, to the pe and virial of that evaluation's record up to summation order. */
+srmd_status srmd_get_particle_terms(srmd_system *s, float *pe, float *virial);
+
 /* Overwrite positions and/or velocities (original order, float32 n*3, either NULL to
- * keep), image counters are reset when pos is given.  Forces a rebuild. */
+ * keep), image counters are reset when pos is given.  Forces a rebuild and clears
+ * the sticky error bits of the replaced state. */
 srmd_status srmd_set_state(srmd_system *s, const float *pos, const float *vel);
+
+/* Full-state checkpoint (the paper's autotuner, appendix, starts every trial from a
+ * stored configuration; this is that store, exported).  srmd_save_state writes the
+ * whole dynamic state into buf (caller-owned, host memory): positions, velocities,
+ * image counters and particle ids, last-build positions, last forces, the float64
+ * or compensation residuals of the precision variants, the neighbour list in use
+ * with its lengths, the step counter, rebuild count, Nose-Hoover friction and its
+ * time integral, and the last thermodynamic record, all in the device's spatially
+ * sorted order.  *needed receives the size in bytes; with buf NULL only *needed is
+ * written; bytes < *needed fails with SRMD_EINVAL.  Synchronises the stream.
+ * The blob is an opaque host-order byte string for this library build. */
+srmd_status srmd_save_state(srmd_system *s, void *buf, size_t bytes, size_t *needed);
+
+/* Load a blob written by srmd_save_state into s, which must have the same particle
+ * count, type count, precision and float32 box (SRMD_EINVAL otherwise, and on a
+ * blob whose size, types or particle ids are inconsistent; s is then unchanged).
+ * When s has the same list layout as the saving system (threads per particle, list
+ * capacity, cell grid, list builder and list radii), the stored list is restored
+ * and steps continue the saved trajectory bit for bit, also across the launch
+ * chain, the persistent kernel and batches; otherwise the list is rebuilt before
+ * the next force evaluation (the same physics, other summation order).  The
+ * integrator and pair potential are those set on s.  Sticky error bits clear. */
+srmd_status srmd_load_state(srmd_system *s, const void *buf, size_t bytes);
 
 /* The neighbour list as (id_i, id_j) pairs in original ids, lexicographically sorted.
  * pairs holds 2*cap int32; *count receives the total number of pairs (the call fails

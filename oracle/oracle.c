@@ -76,6 +76,15 @@ int oracle_num_threads(void) {
 #endif
 }
 
+/* set the thread count of later OpenMP loops (k >= 1); results do not depend on it */
+void oracle_set_num_threads(int k) {
+#ifdef _OPENMP
+  if (k >= 1) omp_set_num_threads(k);
+#else
+  (void)k;
+#endif
+}
+
 /* ---- compensated (Neumaier) summation ------------------------------------ */
 typedef struct {
   double s, c;

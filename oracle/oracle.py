@@ -21,7 +21,7 @@ METHODS = {"trunc": TRUNC, "sp": SP, "sf": SF}
 __all__ = [
     "build", "load", "TRUNC", "SP", "SF", "METHODS", "cut_tables", "pair_set", "neighbors_of",
     "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads",
-    "coulomb_sf", "pair_mie",
+    "coulomb_sf", "pair_mie", "set_num_threads",
 ]
 
 
@@ -93,6 +93,8 @@ def load():
     lib.oracle_integrate.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -307,3 +309,8 @@ def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, th
 def num_threads():
     """Threads the oracle's OpenMP loops use."""
     return int(load().oracle_num_threads())
+
+
+def set_num_threads(k):
+    """Threads of the oracle's later OpenMP loops (results do not depend on it)."""
+    load().oracle_set_num_threads(int(k))

@@ -64,9 +64,13 @@ __device__ __forceinline__ float dist2(const float4 a, const float4 b, const Sys
 
 __device__ __forceinline__ int ptype(const float4 r) { return __float_as_int(r.w); }
 
+// Cell coordinate along one axis, clamped to [0, nc - 1] in float32 before the
+// conversion: x + L/2 can round to L, and a non-finite coordinate (a blown-up run,
+// reported through the error word) lands in cell 0 (fmaxf returns the non-NaN
+// operand), so no input can produce a cell index outside the grid.
 __device__ __forceinline__ int cell_coord(float x, float halfL, float scale, int nc) {
-  const int k = (int)floorf((x + halfL) * scale);
-  return min(max(k, 0), nc - 1);
+  const float f = fminf(fmaxf(floorf((x + halfL) * scale), 0.0f), (float)(nc - 1));
+  return (int)f;
 }
 
 __device__ __forceinline__ void cell_coords(const float4 r, const SysConst &c, int &cx, int &cy, int &cz) {
@@ -1260,6 +1264,7 @@ __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) 
   BlockPartial v = zero_partial();
   if (active && t == 0) {
     p.force[i] = make_float4(fx, fy, fz, 0.5f * u);
+    p.wpart[i] = (float)((double)w / 6.0);
     v.pe = 0.5 * (double)u;
     v.w = (double)w / 6.0;
     const double dvx = vo.x, dvy = vo.y, dvz = vo.z;
@@ -2049,7 +2054,44 @@ int batch_max_particles() { return kSmallN; }
 // Dynamic LDS of the large-system persistent kernel: the list build's candidate windows.
 size_t big_lds_bytes() { return 4 * (size_t)(kBatchWaves * kWaveCand); }
 
+// ---------------------------------------------------------------- start of a stepping call
+
+// One launch at the start of srmd_step: the call's trace settings go into the
+// control block, and the dynamic state the call starts from (positions, velocities,
+// last-build positions, images and ids, precision residuals and the control block
+// itself) is copied into the replay snapshot.
+__global__ __launch_bounds__(256) void k_call_begin(SysConst c, SysPtrs p, Snapshot snap, int cur, int thermo_every,
+                                                    long long trace_cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    Control k = *p.ctl;
+    k.thermo_every = thermo_every;
+    k.trace_cap = trace_cap;
+    k.n_records = 0;
+    *p.ctl = k;
+    *snap.ctl = k;
+  }
+  if (i < c.n) {
+    snap.pos[i] = p.pos[cur][i];
+    snap.vel[i] = p.vel[i];
+    snap.last[i] = p.last[i];
+    snap.img[i] = p.img[i];
+    if (snap.kahan) snap.kahan[i] = p.kahan[i];
+    if (snap.pos64) {
+      snap.pos64[3 * i] = p.pos64[3 * i];
+      snap.pos64[3 * i + 1] = p.pos64[3 * i + 1];
+      snap.pos64[3 * i + 2] = p.pos64[3 * i + 2];
+    }
+  }
+}
+
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_call_begin(hipStream_t st, const SysConst &c, const SysPtrs &p, const Snapshot &snap, int cur,
+                             int thermo_every, long long trace_cap) {
+  hipLaunchKernelGGL(k_call_begin, dim3((c.n + 255) / 256), dim3(256), 0, st, c, p, snap, cur, thermo_every, trace_cap);
+  return hipGetLastError();
+}
 
 template <int TP>
 static hipError_t launch_step_tp(int method, int prec, dim3 g, dim3 b, hipStream_t st, const SysConst &c,

@@ -23,6 +23,8 @@ hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t
 hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
 hipError_t launch_finish(int mode, int G, int next, hipStream_t st, const SysConst &c, const SysPtrs &p);
 hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
+hipError_t launch_call_begin(hipStream_t st, const SysConst &c, const SysPtrs &p, const Snapshot &snap, int cur,
+                             int thermo_every, long long trace_cap);
 bool small_sort_fits(int n, int ncell);
 size_t batch_lds_bytes(int n_max_particles);
 int batch_max_particles();
@@ -107,10 +109,8 @@ struct srmd_system {
   int part_alloc = 0;
   std::vector<DevBuf> bufs;
   // snapshot for list-overflow replay
-  float4 *snap_pos = nullptr, *snap_vel = nullptr, *snap_last = nullptr, *snap_kahan = nullptr;
-  int4 *snap_img = nullptr;
-  double *snap_pos64 = nullptr;
-  Control *snap_ctl = nullptr;
+  Snapshot snap{};
+  Control *h_ctl = nullptr;  // pinned host copy of the control block, read back once per call
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   std::string err;
 };
@@ -301,14 +301,9 @@ void resolve_persistent(srmd_system *s) {
     s->persist_groups = want;
 }
 
-// Rebuild the kernel constants, the cell grid and the list storage after any change
-// of parameters or launch shape.
-srmd_status prepare(srmd_system *s) {
-  if (s->method < 0 || !all_pairs_given(s))
-    return fail(s, SRMD_EINVAL, "pair potential not set for every type pair (srmd_set_pair_lj)");
-  if (s->coulomb && (s->method != SRMD_CUT_SF || s->pot != 0))
-    return fail(s, SRMD_EUNSUPPORTED, "the Coulomb term runs with shifted-force Lennard-Jones (SRMD_CUT_SF) only");
-  if (!s->dirty) return SRMD_OK;
+// The kernel constants of s: launch shape, cell grid, list capacity and the
+// per-type-pair tables (host only; no device memory is touched).
+srmd_status fill_const(srmd_system *s) {
   resolve_launch(s);
   SysConst &c = s->c;
   std::memset(&c, 0, sizeof(c));
@@ -396,6 +391,21 @@ srmd_status prepare(srmd_system *s) {
       c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)mie_f(s->rc[a], A, B, m, n, s->sigma[a]) : 0.0f;
     }
   }
+  return SRMD_OK;
+}
+
+// Rebuild the kernel constants, the cell grid and the list storage after any change
+// of parameters or launch shape.
+srmd_status prepare(srmd_system *s) {
+  if (s->method < 0 || !all_pairs_given(s))
+    return fail(s, SRMD_EINVAL, "pair potential not set for every type pair (srmd_set_pair_lj)");
+  if (s->coulomb && (s->method != SRMD_CUT_SF || s->pot != 0))
+    return fail(s, SRMD_EUNSUPPORTED, "the Coulomb term runs with shifted-force Lennard-Jones (SRMD_CUT_SF) only");
+  if (!s->dirty) return SRMD_OK;
+  srmd_status st0 = fill_const(s);
+  if (st0 != SRMD_OK) return st0;
+  SysConst &c = s->c;
+  const int nmax = s->n_max;
   // storage that depends on the layout
   const long long need_nbl = (long long)nmax * c.nvp;
   if (need_nbl > s->nbl_alloc) {
@@ -470,33 +480,40 @@ srmd_status get_graph(srmd_system *s, int count, int cur, hipGraphExec_t *out) {
 }
 
 srmd_status alloc_snapshot(srmd_system *s) {
-  if (s->snap_pos) return SRMD_OK;
+  if (s->snap.pos) return SRMD_OK;
   const size_t n = (size_t)s->n;
-  s->snap_pos = (float4 *)dev_alloc(s, sizeof(float4) * n);
-  s->snap_vel = (float4 *)dev_alloc(s, sizeof(float4) * n);
-  s->snap_last = (float4 *)dev_alloc(s, sizeof(float4) * n);
-  s->snap_img = (int4 *)dev_alloc(s, sizeof(int4) * n);
-  s->snap_ctl = (Control *)dev_alloc(s, sizeof(Control));
-  if (s->prec == SRMD_PREC_F64POS) s->snap_pos64 = (double *)dev_alloc(s, sizeof(double) * 3 * n);
-  if (s->prec == SRMD_PREC_F32_KAHAN) s->snap_kahan = (float4 *)dev_alloc(s, sizeof(float4) * n);
-  if (!s->snap_pos || !s->snap_vel || !s->snap_last || !s->snap_img || !s->snap_ctl)
+  Snapshot &q = s->snap;
+  q.pos = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  q.vel = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  q.last = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  q.img = (int4 *)dev_alloc(s, sizeof(int4) * n);
+  q.ctl = (Control *)dev_alloc(s, sizeof(Control));
+  if (s->prec == SRMD_PREC_F64POS) q.pos64 = (double *)dev_alloc(s, sizeof(double) * 3 * n);
+  if (s->prec == SRMD_PREC_F32_KAHAN) q.kahan = (float4 *)dev_alloc(s, sizeof(float4) * n);
+  if (!q.pos || !q.vel || !q.last || !q.img || !q.ctl || (s->p.pos64 && !q.pos64) || (s->p.kahan && !q.kahan)) {
+    for (void *b : {(void *)q.pos, (void *)q.vel, (void *)q.last, (void *)q.img, (void *)q.ctl, (void *)q.pos64,
+                    (void *)q.kahan})
+      dev_free(s, b);
+    q = Snapshot{};
     return fail(s, SRMD_ENOMEM, "snapshot allocation failed");
+  }
   return SRMD_OK;
 }
 
-srmd_status snapshot(srmd_system *s, bool restore) {
+// Put the call-start snapshot back (after a list overflow).
+srmd_status restore_snapshot(srmd_system *s) {
   const size_t n = (size_t)s->n;
-  auto cp = [&](void *a, void *b, size_t bytes) {
-    return restore ? hipMemcpyAsync(a, b, bytes, hipMemcpyDeviceToDevice, s->stream)
-                   : hipMemcpyAsync(b, a, bytes, hipMemcpyDeviceToDevice, s->stream);
+  const Snapshot &q = s->snap;
+  auto cp = [&](void *dst, const void *src, size_t bytes) {
+    return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->stream);
   };
-  HIPCHK(s, cp(s->p.pos[s->cur], s->snap_pos, sizeof(float4) * n));
-  HIPCHK(s, cp(s->p.vel, s->snap_vel, sizeof(float4) * n));
-  HIPCHK(s, cp(s->p.last, s->snap_last, sizeof(float4) * n));
-  HIPCHK(s, cp(s->p.img, s->snap_img, sizeof(int4) * n));
-  HIPCHK(s, cp(s->p.ctl, s->snap_ctl, sizeof(Control)));
-  if (s->p.pos64) HIPCHK(s, cp(s->p.pos64, s->snap_pos64, sizeof(double) * 3 * n));
-  if (s->p.kahan) HIPCHK(s, cp(s->p.kahan, s->snap_kahan, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.pos[s->cur], q.pos, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.vel, q.vel, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.last, q.last, sizeof(float4) * n));
+  HIPCHK(s, cp(s->p.img, q.img, sizeof(int4) * n));
+  HIPCHK(s, cp(s->p.ctl, q.ctl, sizeof(Control)));
+  if (s->p.pos64) HIPCHK(s, cp(s->p.pos64, q.pos64, sizeof(double) * 3 * n));
+  if (s->p.kahan) HIPCHK(s, cp(s->p.kahan, q.kahan, sizeof(float4) * n));
   return SRMD_OK;
 }
 
@@ -907,7 +924,7 @@ srmd_status batch_plan(srmd_batch *b, int W) {
 // capacity (paper section 4); the next run rebuilds the list.
 srmd_status restore_and_regrow(srmd_system *s, int cur0) {
   s->cur = cur0;
-  srmd_status st = snapshot(s, true);
+  srmd_status st = restore_snapshot(s);
   if (st != SRMD_OK) return st;
   Control r;
   st = read_ctl(s, &r);
@@ -924,22 +941,14 @@ srmd_status restore_and_regrow(srmd_system *s, int cur0) {
 // Trace settings live in the control block so the captured graphs stay valid.
 srmd_status run_with_replay(srmd_system *s, long long nsteps, int32_t thermo_every, long long cap) {
   for (int attempt = 0; attempt < 8; ++attempt) {
-    Control hc;
-    srmd_status st = read_ctl(s, &hc);
-    if (st != SRMD_OK) return st;
-    hc.thermo_every = thermo_every;
-    hc.trace_cap = cap;
-    hc.n_records = 0;
-    st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
-    if (st != SRMD_OK) return st;
     const int cur0 = s->cur;
-    st = snapshot(s, false);
+    HIPCHK(s, launch_call_begin(s->stream, s->c, s->p, s->snap, s->cur, thermo_every, cap));
+    srmd_status st = run_steps(s, nsteps);
     if (st != SRMD_OK) return st;
-    st = run_steps(s, nsteps);
-    if (st != SRMD_OK) return st;
-    Control h;
-    st = read_ctl(s, &h);
-    if (st != SRMD_OK) return st;
+    // the one host round trip of the call: the control block's sticky error word
+    HIPCHK(s, hipMemcpyAsync(s->h_ctl, s->p.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(s, hipStreamSynchronize(s->stream));
+    Control h = *s->h_ctl;
     st = check_barrier(s, &h);
     if (st != SRMD_OK) return st;
     if (h.error & 2) {
@@ -956,11 +965,9 @@ srmd_status run_with_replay(srmd_system *s, long long nsteps, int32_t thermo_eve
 // Copy the records of the last run's device trace into trace (cap entries at most).
 srmd_status download_trace(srmd_system *s, long long cap, srmd_thermo *trace) {
   if (cap <= 0) return SRMD_OK;
-  Control h;
-  srmd_status st = read_ctl(s, &h);
-  if (st != SRMD_OK) return st;
-  if (h.n_records <= 0) return SRMD_OK;
-  std::vector<Thermo> tmp((size_t)std::min<long long>(h.n_records, cap));
+  const long long nrec = s->h_ctl->n_records;  // read back at the end of the run
+  if (nrec <= 0) return SRMD_OK;
+  std::vector<Thermo> tmp((size_t)std::min<long long>(nrec, cap));
   HIPCHK(s, hipMemcpyAsync(tmp.data(), s->p.trace, sizeof(Thermo) * tmp.size(), hipMemcpyDeviceToHost, s->stream));
   HIPCHK(s, hipStreamSynchronize(s->stream));
   for (size_t k = 0; k < tmp.size(); ++k) to_public(tmp[k], &trace[k]);
@@ -1022,6 +1029,11 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
     }
     s->own_stream = true;
   }
+  if (hipHostMalloc((void **)&s->h_ctl, sizeof(Control), hipHostMallocDefault) != hipSuccess) {
+    s->h_ctl = nullptr;
+    srmd_destroy(s);
+    return fail(nullptr, SRMD_ENOMEM, "pinned host allocation failed");
+  }
   const size_t N = (size_t)n;
   bool ok = true;
   auto A = [&](size_t bytes) {
@@ -1034,6 +1046,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   s->p.vel = (float4 *)A(sizeof(float4) * N);
   s->p.img = (int4 *)A(sizeof(int4) * N);
   s->p.force = (float4 *)A(sizeof(float4) * N);
+  s->p.wpart = (float *)A(sizeof(float) * N);
   s->p.last = (float4 *)A(sizeof(float4) * N);
   s->p.nnb = (int *)A(sizeof(int) * N);
   s->p.cell_of = (unsigned *)A(sizeof(unsigned) * N);
@@ -1066,6 +1079,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   if (hipMemcpyAsync(s->p.ctl, &hc, sizeof(hc), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipMemcpyAsync(s->p.thermo, &ht, sizeof(ht), hipMemcpyHostToDevice, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.force, 0, sizeof(float4) * N, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.wpart, 0, sizeof(float) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.tile_count, 0, sizeof(unsigned) * kScanMaxTiles, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.t_pos, 0, sizeof(float4) * N, s->stream) != hipSuccess) {
@@ -1088,6 +1102,7 @@ srmd_status srmd_destroy(srmd_system *s) {
   drop_graphs(s);
   while (!s->bufs.empty()) dev_free(s, s->bufs.back().ptr);
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  if (s->h_ctl) (void)hipHostFree(s->h_ctl);
   delete s;
   return SRMD_OK;
 }
@@ -1377,6 +1392,25 @@ srmd_status srmd_get_state(srmd_system *s, float *pos, float *vel, int32_t *imag
   return SRMD_OK;
 }
 
+srmd_status srmd_get_particle_terms(srmd_system *s, float *pe, float *virial) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  const size_t n = (size_t)s->n;
+  std::vector<int4> hi(n);
+  std::vector<float4> hf(n);
+  std::vector<float> hw(n);
+  HIPCHK(s, hipMemcpyAsync(hi.data(), s->p.img, sizeof(int4) * n, hipMemcpyDeviceToHost, s->stream));
+  if (pe) HIPCHK(s, hipMemcpyAsync(hf.data(), s->p.force, sizeof(float4) * n, hipMemcpyDeviceToHost, s->stream));
+  if (virial) HIPCHK(s, hipMemcpyAsync(hw.data(), s->p.wpart, sizeof(float) * n, hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  for (size_t k = 0; k < n; ++k) {
+    const int id = hi[k].w;
+    if (id < 0 || (size_t)id >= n) return fail(s, SRMD_ESTATE, "corrupt particle id on the device");
+    if (pe) pe[id] = hf[k].w;
+    if (virial) virial[id] = hw[k];
+  }
+  return SRMD_OK;
+}
+
 srmd_status srmd_set_state(srmd_system *s, const float *pos, const float *vel) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
   const size_t n = (size_t)s->n;
@@ -1414,7 +1448,184 @@ srmd_status srmd_set_state(srmd_system *s, const float *pos, const float *vel) {
   }
   srmd_status st = upload_state(s, P.data(), Vv.data(), T.data());
   if (st != SRMD_OK) return st;
+  st = set_ctl_int(s, offsetof(Control, error), 0);  // errors of the replaced state do not carry over
+  if (st != SRMD_OK) return st;
   return request_rebuild(s);
+}
+
+// ---------------------------------------------------------------------------
+// Full-state checkpoint.  The blob holds the device state in its device (spatially
+// sorted) order, so that a loaded system continues the saved trajectory bit for
+// bit: positions (type bits included), velocities, images and ids, last-build
+// positions, last forces, the precision residuals, the neighbour list and its
+// lengths, the control block (step, rebuilds, Nose-Hoover friction and its
+// integral) and the last thermodynamic record.  The list is restored only into the
+// same list layout; otherwise the loaded state rebuilds it before the next force
+// evaluation.
+
+namespace {
+
+constexpr char kStateMagic[8] = {'S', 'R', 'M', 'D', 'S', 'T', 'v', '1'};
+
+// What a stored list depends on besides the particle order: the list geometry and
+// the per-type-pair list radii.
+struct ListLayout {
+  int tp, n_max, nvp, ncell, nc[3], full_axis, small_sort, list_kind;
+  float cs2[kMaxPairs];
+};
+
+struct StateHeader {
+  char magic[8];
+  int32_t n, ntypes, prec, cur_unused;
+  float L[3];
+  int32_t sort_state;   // 0 none pending; 1 rebuild requested, sort not yet run; 2 sort already run
+  int64_t list_rows;    // rows of tp entries per particle stored (0: no list)
+  ListLayout layout;
+  Control ctl;
+  Thermo thermo;
+};
+
+ListLayout layout_of(const srmd_system *s) {
+  ListLayout l;
+  std::memset(&l, 0, sizeof(l));
+  l.tp = s->c.tp;
+  l.n_max = s->c.n_max;
+  l.nvp = s->c.nvp;
+  l.ncell = s->c.ncell;
+  for (int k = 0; k < 3; ++k) l.nc[k] = s->c.nc[k];
+  l.full_axis = s->c.full_axis;
+  l.small_sort = s->c.small_sort;
+  l.list_kind = s->c.list_kind;
+  for (int a = 0; a < kMaxPairs; ++a) l.cs2[a] = s->c.pt.cs2[a];
+  return l;
+}
+
+size_t state_bytes(const srmd_system *s, long long rows) {
+  const size_t n = (size_t)s->n;
+  size_t b = sizeof(StateHeader) + n * (5 * sizeof(float4) + sizeof(int));
+  if (s->p.pos64) b += 3 * n * sizeof(double);
+  if (s->p.kahan) b += n * sizeof(float4);
+  b += (size_t)rows * (size_t)s->c.nvp * (size_t)s->c.tp * sizeof(int);
+  return b;
+}
+
+}  // namespace
+
+srmd_status srmd_save_state(srmd_system *s, void *buf, size_t bytes, size_t *needed) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!needed) return fail(s, SRMD_EINVAL, "needed is NULL");
+  srmd_status st = prepare(s);  // a pending parameter change requests its rebuild first
+  if (st != SRMD_OK) return st;
+  StateHeader h;
+  std::memset(&h, 0, sizeof(h));
+  HIPCHK(s, hipMemcpyAsync(&h.ctl, s->p.ctl, sizeof(Control), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipMemcpyAsync(&h.thermo, s->p.thermo, sizeof(Thermo), hipMemcpyDeviceToHost, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  // the list is stored when it is the one the next force evaluation uses
+  const long long rows = h.ctl.rebuild ? 0 : (h.ctl.max_nbrs + s->c.tp - 1) / s->c.tp;
+  *needed = state_bytes(s, rows);
+  if (!buf) return SRMD_OK;
+  if (bytes < *needed) return fail(s, SRMD_EINVAL, "state buffer too small");
+  std::memcpy(h.magic, kStateMagic, 8);
+  h.n = s->n;
+  h.ntypes = s->ntypes;
+  h.prec = (int32_t)s->prec;
+  for (int k = 0; k < 3; ++k) h.L[k] = s->Lf[k];
+  h.sort_state = !h.ctl.rebuild ? 0 : (s->c.small_sort && !s->sort_pending) ? 2 : 1;
+  h.list_rows = rows;
+  h.layout = layout_of(s);
+  const size_t n = (size_t)s->n;
+  char *q = (char *)buf;
+  std::memcpy(q, &h, sizeof(h));
+  q += sizeof(h);
+  auto d2h = [&](const void *src, size_t b) {
+    hipError_t e = hipMemcpyAsync(q, src, b, hipMemcpyDeviceToHost, s->stream);
+    q += b;
+    return e;
+  };
+  HIPCHK(s, d2h(s->p.pos[s->cur], sizeof(float4) * n));
+  HIPCHK(s, d2h(s->p.vel, sizeof(float4) * n));
+  HIPCHK(s, d2h(s->p.img, sizeof(int4) * n));
+  HIPCHK(s, d2h(s->p.last, sizeof(float4) * n));
+  HIPCHK(s, d2h(s->p.force, sizeof(float4) * n));
+  HIPCHK(s, d2h(s->p.nnb, sizeof(int) * n));
+  if (s->p.pos64) HIPCHK(s, d2h(s->p.pos64, 3 * sizeof(double) * n));
+  if (s->p.kahan) HIPCHK(s, d2h(s->p.kahan, sizeof(float4) * n));
+  if (rows > 0) HIPCHK(s, d2h(s->p.nbl, (size_t)rows * (size_t)s->c.nvp * (size_t)s->c.tp * sizeof(int)));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
+}
+
+srmd_status srmd_load_state(srmd_system *s, const void *buf, size_t bytes) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (!buf || bytes < sizeof(StateHeader)) return fail(s, SRMD_EINVAL, "state buffer too small");
+  StateHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  if (std::memcmp(h.magic, kStateMagic, 8) != 0) return fail(s, SRMD_EINVAL, "not a saved srmd state");
+  if (h.n != s->n || h.ntypes != s->ntypes || h.prec != (int32_t)s->prec)
+    return fail(s, SRMD_EINVAL, "saved state has another particle count, type count or precision");
+  for (int k = 0; k < 3; ++k)
+    if (h.L[k] != s->Lf[k]) return fail(s, SRMD_EINVAL, "saved state has another box");
+  if (h.list_rows < 0 || h.list_rows > h.layout.n_max || h.layout.tp < 1 || h.layout.nvp < h.n)
+    return fail(s, SRMD_EINVAL, "corrupt saved state header");
+  srmd_status st = prepare(s);
+  if (st != SRMD_OK) return st;
+  const size_t n = (size_t)s->n;
+  size_t need = sizeof(StateHeader) + n * (5 * sizeof(float4) + sizeof(int));
+  if (s->p.pos64) need += 3 * n * sizeof(double);
+  if (s->p.kahan) need += n * sizeof(float4);
+  const size_t list_b = (size_t)h.list_rows * (size_t)h.layout.nvp * (size_t)h.layout.tp * sizeof(int);
+  if (bytes != need + list_b) return fail(s, SRMD_EINVAL, "state buffer size does not match its header");
+  // every particle id appears once and every type is in range
+  const char *q = (const char *)buf + sizeof(StateHeader);
+  {
+    const float4 *hp = (const float4 *)q;
+    const int4 *hi = (const int4 *)(q + 2 * sizeof(float4) * n);
+    std::vector<char> seen(n, 0);
+    for (size_t k = 0; k < n; ++k) {
+      int ty;
+      std::memcpy(&ty, &hp[k].w, 4);
+      const int id = hi[k].w;
+      if (ty < 0 || ty >= s->ntypes || id < 0 || (size_t)id >= n || seen[(size_t)id])
+        return fail(s, SRMD_EINVAL, "corrupt saved state (types or particle ids)");
+      seen[(size_t)id] = 1;
+    }
+  }
+  const ListLayout cur = layout_of(s);
+  const bool keep_list = std::memcmp(&cur, &h.layout, sizeof(ListLayout)) == 0 && h.sort_state == 0;
+  auto h2d = [&](void *dst, size_t b) {
+    hipError_t e = hipMemcpyAsync(dst, q, b, hipMemcpyHostToDevice, s->stream);
+    q += b;
+    return e;
+  };
+  HIPCHK(s, h2d(s->p.pos[s->cur], sizeof(float4) * n));
+  HIPCHK(s, h2d(s->p.vel, sizeof(float4) * n));
+  HIPCHK(s, h2d(s->p.img, sizeof(int4) * n));
+  HIPCHK(s, h2d(s->p.last, sizeof(float4) * n));
+  HIPCHK(s, h2d(s->p.force, sizeof(float4) * n));
+  if (keep_list) {
+    HIPCHK(s, h2d(s->p.nnb, sizeof(int) * n));
+  } else {
+    q += sizeof(int) * n;
+  }
+  if (s->p.pos64) HIPCHK(s, h2d(s->p.pos64, 3 * sizeof(double) * n));
+  if (s->p.kahan) HIPCHK(s, h2d(s->p.kahan, sizeof(float4) * n));
+  if (keep_list) HIPCHK(s, h2d(s->p.nbl, list_b));
+  Control c = h.ctl;
+  c.error = 0;
+  if (!keep_list) {
+    // the list is rebuilt (spatial sort first) before the next force evaluation; a
+    // sort the saved run already performed counts its rebuild once
+    if (h.sort_state == 2) c.n_rebuilds -= 1;
+    c.rebuild = 1;
+    s->sort_pending = true;
+  } else {
+    s->sort_pending = false;
+  }
+  HIPCHK(s, hipMemcpyAsync(s->p.ctl, &c, sizeof(Control), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipMemcpyAsync(s->p.thermo, &h.thermo, sizeof(Thermo), hipMemcpyHostToDevice, s->stream));
+  HIPCHK(s, hipStreamSynchronize(s->stream));
+  return SRMD_OK;
 }
 
 srmd_status srmd_get_neighbor_pairs(srmd_system *s, int32_t *pairs, int64_t cap, int64_t *count) {
@@ -1750,16 +1961,18 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
 
 // ---------------------------------------------------------------------------
 // Tuned-parameter file (paper appendix, step 8).  One text line per record:
-//   srmd-tuning-v1 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
+//   srmd-tuning-v2 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
 //   count=<c_0,...> dt=<x> temperature=<x> density=<x> sigma=<k*k values>
-//   epsilon=<k*k values> rcut=<k*k values> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x>
+//   epsilon=<k*k values> rcut=<k*k values> potential=<n> param=<4*k*k values>
+//   charge=<k values> rcc=<x> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x>
+// (records of another version are skipped)
 // Floating-point fields are printed with 17 significant digits, so they read back
 // to the same double.
 }  // extern "C"
 
 namespace {
 
-constexpr const char *kTuneTag = "srmd-tuning-v1";
+constexpr const char *kTuneTag = "srmd-tuning-v2";
 constexpr double kTuneRelTol = 1e-6;   // dt, density and pair parameters
 constexpr double kTuneTempTol = 0.02;  // temperature
 
@@ -1790,10 +2003,16 @@ bool key_match(const srmd_tuning_key &a, const srmd_tuning_key &b) {
   if (!rel_close(a.dt, b.dt, kTuneRelTol) || !rel_close(a.density, b.density, kTuneRelTol) ||
       !rel_close(a.temperature, b.temperature, kTuneTempTol))
     return false;
-  for (int q = 0; q < a.ntypes * a.ntypes; ++q)
+  for (int q = 0; q < a.ntypes * a.ntypes; ++q) {
     if (!rel_close(a.sigma[q], b.sigma[q], kTuneRelTol) || !rel_close(a.epsilon[q], b.epsilon[q], kTuneRelTol) ||
         !rel_close(a.rcut[q], b.rcut[q], kTuneRelTol))
       return false;
+    for (int r = 0; r < 4; ++r)
+      if (!rel_close(a.pot_param[q][r], b.pot_param[q][r], kTuneRelTol)) return false;
+  }
+  if (a.potential != b.potential || !rel_close(a.rc_coulomb, b.rc_coulomb, kTuneRelTol)) return false;
+  for (int t = 0; t < a.ntypes; ++t)
+    if (!rel_close(a.charge[t], b.charge[t], kTuneRelTol)) return false;
   return true;
 }
 
@@ -1830,6 +2049,10 @@ std::string tuning_line(const srmd_tuning_key &k, const srmd_tuning &t) {
   field("sigma", nums(k.sigma, k.ntypes * k.ntypes));
   field("epsilon", nums(k.epsilon, k.ntypes * k.ntypes));
   field("rcut", nums(k.rcut, k.ntypes * k.ntypes));
+  field("potential", std::to_string(k.potential));
+  field("param", nums(&k.pot_param[0][0], 4 * k.ntypes * k.ntypes));
+  field("charge", nums(k.charge, k.ntypes));
+  field("rcc", num(k.rc_coulomb));
   field("tp", std::to_string(t.tp));
   field("ppb", std::to_string(t.ppb));
   field("list", std::to_string(t.list_mode));
@@ -1915,6 +2138,14 @@ bool parse_tuning_line(const std::string &line, srmd_tuning_key *k, srmd_tuning 
   for (int a = 0; a < 3; ++a) {
     auto it = kv.find(arr_names[a]);
     if (it == kv.end() || !parse_list(it->second, nt * nt, arrs[a], nullptr)) return false;
+  }
+  {
+    auto pi = kv.find("param"), qi = kv.find("charge");
+    if (!one_int("potential", &v[0]) || v[0] < 0 || v[0] > 1 || pi == kv.end() || qi == kv.end() ||
+        !parse_list(pi->second, 4 * nt * nt, &k->pot_param[0][0], nullptr) ||
+        !parse_list(qi->second, nt, k->charge, nullptr) || !one_num("rcc", &k->rc_coulomb))
+      return false;
+    k->potential = (int32_t)v[0];
   }
   if (!one_int("tp", &v[0]) || !one_int("ppb", &v[1]) || !one_int("list", &v[2]) || !one_int("persistent", &v[3]) ||
       !one_num("skin", &t->skin))
@@ -2015,7 +2246,18 @@ srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key) {
       key->sigma[q] = s->sigma[pi];
       key->epsilon[q] = s->eps[pi];
       key->rcut[q] = s->rc[pi];
+      if (s->pot == 1) {
+        key->pot_param[q][0] = s->mie_a[pi];
+        key->pot_param[q][1] = s->mie_b[pi];
+        key->pot_param[q][2] = s->mie_m[pi];
+        key->pot_param[q][3] = s->mie_n[pi];
+      }
     }
+  key->potential = s->pot == 1 ? 1 : 0;
+  if (s->coulomb) {
+    for (int t = 0; t < s->ntypes; ++t) key->charge[t] = s->charge[t];
+    key->rc_coulomb = s->rcc;
+  }
   return SRMD_OK;
 }
 
@@ -2342,21 +2584,18 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
   }
   srmd_status st = batch_sync_desc(b);
   if (st != SRMD_OK) return st;
+  std::vector<hipStream_t> streams;
   for (auto *s : b->sys) {
-    Control hc;
-    st = read_ctl(s, &hc);
+    // trace settings and replay snapshot in one launch, then a host-requested
+    // rebuild's spatial sort, both on the system's stream before the batched launch
+    if (launch_call_begin(s->stream, s->c, s->p, s->snap, s->cur, thermo_every, cap) != hipSuccess)
+      return bfail(b, SRMD_EHIP, "replica call start failed");
+    st = flush_host_sort(s);
     if (st != SRMD_OK) return bfail(b, st, s->err);
-    hc.thermo_every = thermo_every;
-    hc.trace_cap = cap;
-    hc.n_records = 0;
-    st = h2d_sync(s, s->p.ctl, &hc, sizeof(Control));
-    if (st == SRMD_OK) st = snapshot(s, false);
-    // a host-requested rebuild needs its spatial sort before the batched launch
-    if (st == SRMD_OK) st = flush_host_sort(s);
-    if (st != SRMD_OK) return bfail(b, st, s->err);
+    if (std::find(streams.begin(), streams.end(), s->stream) == streams.end()) streams.push_back(s->stream);
   }
-  for (auto *s : b->sys)
-    if (hipStreamSynchronize(s->stream) != hipSuccess) return bfail(b, SRMD_EHIP, "replica stream sync failed");
+  for (hipStream_t q : streams)
+    if (hipStreamSynchronize(q) != hipSuccess) return bfail(b, SRMD_EHIP, "replica stream sync failed");
   hipError_t e = hipSuccess;
   for (size_t r = 0; r < b->sys.size() && e == hipSuccess; ++r)
     if (b->pieces[r] > 1) e = hipMemsetAsync(b->sys[r]->p.bar_flags, 0, sizeof(unsigned) * 2 * 256, b->stream);
@@ -2379,9 +2618,9 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
   srmd_status result = SRMD_OK;
   for (size_t r = 0; r < b->sys.size(); ++r) {
     srmd_system *s = b->sys[r];
-    Control h;
-    st = read_ctl(s, &h);
+    st = read_ctl(s, s->h_ctl);
     if (st != SRMD_OK) return bfail(b, st, s->err);
+    Control h = *s->h_ctl;
     st = check_barrier(s, &h);
     if (st != SRMD_OK) {
       if (result == SRMD_OK) result = bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);

@@ -115,6 +115,7 @@ struct SysPtrs {
   float4 *vel;      // velocities, .w unused
   int4 *img;        // image counters in .xyz, original particle id in .w
   float4 *force;    // last forces, per-particle potential energy in .w
+  float *wpart;     // per-particle virial 1/6 sum_j r_ij . F_ij of the last force-only evaluation
   float4 *last;     // positions at the last build
   double *pos64;    // float64 master positions (3 per particle) or nullptr
   float4 *kahan;    // Kahan residuals or nullptr
@@ -136,6 +137,15 @@ struct SysPtrs {
   Thermo *thermo;   // last record
   Thermo *trace;    // device trace (trace_cap records)
   unsigned *bar_flags;  // arrival words of the persistent kernel's grid barrier (2 x 256)
+};
+
+// The call-start copy of a system's dynamic state, put back when a list overflow
+// forces a replay of the call (pos64 and kahan only in their precision variants).
+struct Snapshot {
+  float4 *pos, *vel, *last, *kahan;
+  int4 *img;
+  double *pos64;
+  Control *ctl;
 };
 
 // One system of a persistent launch: its constants, its device arrays, the position

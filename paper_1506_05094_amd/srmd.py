@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 
 import numpy as np
 
@@ -47,16 +48,21 @@ class srmd_tuning_key(ctypes.Structure):
                 ("cutoff_method", ctypes.c_int32), ("thermostat", ctypes.c_int32), ("ntypes", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("count", ctypes.c_int64 * 4), ("density", ctypes.c_double),
                 ("temperature", ctypes.c_double), ("dt", ctypes.c_double), ("sigma", ctypes.c_double * 16),
-                ("epsilon", ctypes.c_double * 16), ("rcut", ctypes.c_double * 16)]
+                ("epsilon", ctypes.c_double * 16), ("rcut", ctypes.c_double * 16), ("potential", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32), ("pot_param", ctypes.c_double * 64), ("charge", ctypes.c_double * 4),
+                ("rc_coulomb", ctypes.c_double)]
 
     def as_dict(self):
         k = self.ntypes
         d = {name: getattr(self, name) for name in ("compute_units", "precision", "cutoff_method", "thermostat",
-                                                    "ntypes", "density", "temperature", "dt")}
+                                                    "ntypes", "density", "temperature", "dt", "potential",
+                                                    "rc_coulomb")}
         d["gpu"] = self.gpu.decode()
         d["count"] = list(self.count[:k])
         for name in ("sigma", "epsilon", "rcut"):
             d[name] = np.array(getattr(self, name)[:k * k]).reshape(k, k)
+        d["pot_param"] = np.array(self.pot_param[:4 * k * k]).reshape(k, k, 4)
+        d["charge"] = list(self.charge[:k])
         return d
 
     @classmethod
@@ -74,6 +80,15 @@ class srmd_tuning_key(ctypes.Structure):
             assert a.size == nt * nt
             for q, v in enumerate(a):
                 getattr(k, name)[q] = float(v)
+        k.potential = int(d.get("potential", 0))
+        k.rc_coulomb = float(d.get("rc_coulomb", 0.0))
+        if "pot_param" in d:
+            a = np.asarray(d["pot_param"], np.float64).reshape(-1)
+            assert a.size == 4 * nt * nt
+            for q, v in enumerate(a):
+                k.pot_param[q] = float(v)
+        for q, v in enumerate(d.get("charge", [])):
+            k.charge[q] = float(v)
         return k
 
 
@@ -167,6 +182,9 @@ def load():
         "srmd_compute_forces": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
         "srmd_step": (st, [sysp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
         "srmd_get_state": (st, [sysp, _fp, _fp, _ip, _fp, _dp]),
+        "srmd_get_particle_terms": (st, [sysp, _fp, _fp]),
+        "srmd_save_state": (st, [sysp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+        "srmd_load_state": (st, [sysp, _vp, ctypes.c_size_t]),
         "srmd_set_state": (st, [sysp, _fp, _fp]),
         "srmd_get_neighbor_pairs": (st, [sysp, _ip, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
         "srmd_get_thermo": (st, [sysp, ctypes.POINTER(srmd_thermo)]),
@@ -255,6 +273,10 @@ class System:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave the
+        # memory to the process exit instead of calling into the library
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -377,6 +399,28 @@ class System:
                                      _ptr(p64, _dp)), self._h)
         return dict(pos=pos, vel=vel, image=img, force=frc, pos64=p64)
 
+    def particle_terms(self):
+        """Per-particle potential energy (half the pair energies) and virial (1/6 sum of
+        r_ij . F_ij, from the last compute_forces call), original order."""
+        pe = np.zeros(self.n, np.float32)
+        w = np.zeros(self.n, np.float32)
+        _check(load().srmd_get_particle_terms(self._h, _ptr(pe, _fp), _ptr(w, _fp)), self._h)
+        return pe, w
+
+    def save_state(self):
+        """The full dynamic state as bytes (srmd_save_state)."""
+        lib = load()
+        need = ctypes.c_size_t()
+        _check(lib.srmd_save_state(self._h, None, 0, ctypes.byref(need)), self._h)
+        buf = ctypes.create_string_buffer(need.value)
+        _check(lib.srmd_save_state(self._h, buf, need.value, ctypes.byref(need)), self._h)
+        return buf.raw[:need.value]
+
+    def load_state(self, blob):
+        """Load bytes written by save_state (srmd_load_state)."""
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(load().srmd_load_state(self._h, buf, len(blob)), self._h)
+
     def set_state(self, pos=None, vel=None):
         pos = None if pos is None else _f32(pos).reshape(-1, 3)
         vel = None if vel is None else _f32(vel).reshape(-1, 3)
@@ -450,6 +494,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: leave the
+        # memory to the process exit instead of calling into the library
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -467,7 +515,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_autotune", "srmd_tuning_key_of", "srmd_tuning_cache_find", "srmd_tuning_cache_store",
             "srmd_autotune_full", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_set_rebuild_path", "srmd_set_persistent",
+            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
             "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf",
             "srmd_set_pair_mie"]

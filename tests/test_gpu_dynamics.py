@@ -314,15 +314,28 @@ def test_size_sweep_sampled_parity(n):
     with make_system(state, sig, eps, rc, "sp") as s:
         th = s.compute_forces()
         F = s.get_state()["force"]
+        upp, wpp = s.particle_terms()
         pairs = s.neighbor_pairs() if n <= 256000 else None
         stats = s.stats()
     rng = np.random.default_rng(n)
     sel = np.sort(rng.choice(n, 300, replace=False)).astype(np.int32)
     Fr, pe, w, _, _ = oracle.forces_f32(state.pos, state.types, state.box, sig, eps, rc, "sp", sel=sel)
     assert np.abs(F[sel] - Fr).max() <= FORCE_TOL * max(np.abs(Fr).max(), 1.0)
+    # per-particle potential energy and virial of the sampled particles
+    assert np.abs(upp[sel] - pe).max() <= FORCE_TOL * np.abs(pe).max()
+    assert np.abs(wpp[sel] - w).max() <= FORCE_TOL * np.abs(w).max()
+    # the float64 block reduction equals the float64 sum of the per-particle terms
+    # (every block partial folded once, whatever the block count: N = 1M runs 4000)
+    assert th["pe"] == pytest.approx(upp.astype(np.float64).sum(), rel=1e-12)
+    assert th["virial"] == pytest.approx(wpp.astype(np.float64).sum(), rel=1e-6)
     # whole-system properties at any size: momentum conservation, energy per particle
     assert np.abs(F.astype(np.float64).sum(0)).max() <= 1e-5 * np.sqrt(n) * np.abs(F).max()
     assert -7.0 < th["pe"] / n < -5.0
+    if n <= 64000:
+        # whole-system totals against the oracle's O(N^2) sum
+        _, _, _, U, W = oracle.forces_f32(state.pos, state.types, state.box, sig, eps, rc, "sp")
+        assert rel(th["pe"], U) <= ENERGY_TOL
+        assert rel(th["virial"], W) <= ENERGY_TOL
     if pairs is None:
         return
     cs2, _ = oracle.cut_tables(rc, 0.3)
@@ -332,6 +345,32 @@ def test_size_sweep_sampled_parity(n):
         ref = oracle.neighbors_of(state.pos, state.types, state.box, cs2, int(i))
         np.testing.assert_array_equal(pairs[starts[k]:ends[k], 1], ref)
     assert stats["list_entries"] == len(pairs)
+
+
+@pytest.mark.parametrize("mode", ["chain", "persistent"])
+def test_many_block_partials_folded_against_oracle(mode):
+    # 4000 block partials (more than the 1024 threads of the final reduction, so each
+    # thread folds several) in the force-only reduction and in the steps of both forms
+    n = 64000
+    state = gen.jitter_positions(gen.config2_state(n), 0.05, 3 * n)
+    sig, eps, rc = gen.lj_params()
+    tp, ppb = (4, 16) if mode == "chain" else (8, 8)
+    print(f"N={n} mode={mode} tp={tp} ppb={ppb}", flush=True)
+    _, _, _, U, W = oracle.forces_f32(state.pos, state.types, state.box, sig, eps, rc, "sp")
+    with make_system(state, sig, eps, rc, "sp", launch=(tp, ppb)) as s:
+        assert s.stats()["blocks"] == n * tp // (tp * ppb) > 1024
+        th = s.compute_forces()
+        assert rel(th["pe"], U) <= ENERGY_TOL
+        assert rel(th["virial"], W) <= ENERGY_TOL
+        if mode == "persistent":
+            s.set_persistent(-1)
+        s.set_integrator_nve(0.005)
+        tr = s.step(1, thermo_every=1)
+        upp, _ = s.particle_terms()
+    # the step's record at step 0 holds the energies of the starting positions
+    assert rel(tr["pe"][0], U) <= ENERGY_TOL
+    assert rel(tr["virial"][0], W) <= ENERGY_TOL
+    assert tr["pe"][0] == pytest.approx(upp.astype(np.float64).sum(), rel=1e-12)
 
 
 def test_size_sweep_steps_stay_finite_large():

@@ -175,3 +175,32 @@ def test_fewer_than_five_cells_per_axis():
     a = _trajectory_vs_oracle(st, gen.lj_params(), "sp", 30, launch=(8, 32))
     b = _trajectory_vs_oracle(st, gen.lj_params(), "sp", 30, launch=(8, 32), persistent=-1)
     np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("form", ["chain", "persistent", "force_only"])
+def test_non_finite_force_reports_estate(form):
+    """Two particles on one site (r = 0): the first force evaluation is not finite,
+    and the call returns SRMD_ESTATE.  Only these two particles turn non-finite
+    (NVE); the cell coordinate of a non-finite position is clamped into the grid, so
+    the later steps of the call index nothing outside the arrays."""
+    from paper_1506_05094_amd import srmd
+    state = gen.config0_state().copy()
+    state.pos[7] = state.pos[3]
+    sig, eps, rc = gen.lj_params()
+    print(f"form={form}", flush=True)
+    with make_system(state, sig, eps, rc, "sp") as s:
+        s.set_integrator_nve(0.005)
+        if form == "persistent":
+            s.set_persistent(-1)
+        with pytest.raises(srmd.SrmdError) as e:
+            if form == "force_only":
+                s.compute_forces()
+            else:
+                s.step(30)
+        assert e.value.status == srmd.SRMD_ESTATE
+        # the system stays usable: a finite state set from the host steps again
+        s.set_state(pos=gen.config0_state().pos, vel=gen.config0_state().vel)
+        if form == "persistent":
+            s.set_persistent(0)
+        s.step(5)
+        assert np.isfinite(s.get_state()["pos"]).all()

@@ -121,3 +121,42 @@ def test_short_trajectory_nvt():
     assert np.abs(d).max() <= 1e-4
     np.testing.assert_allclose(tr["xi"], ref["thermo"][:, 5], rtol=1e-4, atol=1e-6)
     np.testing.assert_allclose(tr["pe"], ref["thermo"][:, 0], rtol=1e-5)
+
+
+@pytest.mark.parametrize("name", ["lj864_jitter", "ka4096_random"])
+def test_thermo_record_against_oracle(name):
+    """Every field of the thermodynamic record (paper section 2: energy, pressure)
+    against the oracle.  Kinetic energies of identical velocities agree to 1e-12
+    (float64 on both sides, only the summation order differs); the fields that
+    depend on the first step's forces (through v(1/2)) to the force tolerance."""
+    state, (sig, eps, rc), method = CASES[name]
+    nvt = name.startswith("ka")
+    print(f"case {name}", flush=True)
+    with make_system(state, sig, eps, rc, method) as s:
+        th = s.compute_forces()
+        if nvt:
+            s.set_integrator_nvt(0.005, 0.45, 0.2)
+        else:
+            s.set_integrator_nve(0.005)
+        tr = s.step(1, thermo_every=1)
+        v_half = s.get_state()["vel"].astype(np.float64)
+    kw = dict(thermostat=True, T0=0.45, tau=0.2) if nvt else {}
+    ref = oracle.integrate(state.pos, state.vel, state.types, state.mass, state.box, sig, eps, rc, method, 0.005,
+                           1, **kw)["thermo"][0]
+    pe, ke, w, T, P, xi, xi_int, h, ke_half = ref
+    v0 = state.vel.astype(np.float64)
+    # force-only record: the kinetic energy of the stored velocities v(-1/2)
+    assert rel(th["ke"], oracle.kinetic(v0, state.types, state.mass)) <= 1e-12
+    assert rel(th["pe"], pe) <= ENERGY_TOL and rel(th["virial"], w) <= ENERGY_TOL
+    r = tr[0]
+    # identical velocities: v(1/2) as the device holds it, v(0) = (v(-1/2) + v(1/2)) / 2
+    assert rel(r["ke_half"], oracle.kinetic(v_half, state.types, state.mass)) <= 1e-12
+    assert rel(r["ke"], oracle.kinetic(0.5 * (v0 + v_half), state.types, state.mass)) <= 1e-12
+    # the record against the oracle's own step (its v(1/2) from float64 forces)
+    assert rel(r["pe"], pe) <= ENERGY_TOL and rel(r["virial"], w) <= ENERGY_TOL
+    assert rel(r["ke"], ke) <= 1e-5 and rel(r["ke_half"], ke_half) <= 1e-5
+    assert rel(r["temperature"], T) <= 1e-5
+    assert rel(r["pressure"], P) <= 1e-5
+    assert rel(r["h_conserved"], h) <= 1e-5
+    assert r["xi"] == xi == 0.0 and r["xi_integral"] == xi_int == 0.0
+    assert r["step"] == 0

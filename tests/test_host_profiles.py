@@ -1,6 +1,6 @@
-"""CPU checks of the committed measurement records: the HBM-traffic table that
-bench.py reports from belongs to the current kernel source, every entry names a
-profile summary that exists, and bench.py's lookup finds the default workload."""
+"""CPU checks of the committed measurement records: bench.py reports HBM traffic
+only from counters of the current kernel source and the same launch shape, every
+table entry names a profile summary that exists, and the algorithmic work counts."""
 import hashlib
 import json
 import os
@@ -13,10 +13,26 @@ def _table():
         return json.load(f)
 
 
-def test_traffic_table_matches_kernel_source():
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    return bench
+
+
+def test_traffic_is_reported_only_for_the_profiled_kernel_source():
     with open(os.path.join(ROOT, "paper_1506_05094_amd", "csrc", "kernels.hip"), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
-    assert _table()["kernels_hip_sha256"] == digest, "kernels.hip changed since the counter passes: re-profile"
+    bench = _bench()
+    current = _table()["kernels_hip_sha256"] == digest
+    for e in _table()["entries"]:
+        t = bench.hbm_traffic_per_step(e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"])
+        if current:
+            per_dispatch = 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
+            assert t == per_dispatch / e["steps_per_launch"]
+        else:
+            assert t is None  # counters of other kernel source are never reported
 
 
 def test_every_entry_names_an_existing_summary():
@@ -28,11 +44,17 @@ def test_every_entry_names_an_existing_summary():
         assert e["fetch_kib"] > 0 and e["write_kib"] > 0
 
 
-def test_bench_lookup_finds_the_default_workload():
-    import importlib.util
-    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
-    bench = importlib.util.module_from_spec(spec)
-    spec.loader.exec_module(bench)
-    t = bench.hbm_traffic("Kob-Andersen 80:20 NVT", 4096, "persistent", 16, 16, 0.5)
-    assert t is not None and 5e8 < t < 7e8
-    assert bench.hbm_traffic("Kob-Andersen 80:20 NVT", 4096, "persistent", 16, 16, 0.3) is None
+def test_bench_lookup_needs_the_same_shape():
+    bench = _bench()
+    for e in _table()["entries"]:
+        assert bench.hbm_traffic_per_step(e["workload"], e["n"], e["mode"], e["tp"] * 2, e["ppb"], e["skin"]) is None
+        assert bench.hbm_traffic_per_step(e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"] + 0.1) is None
+
+
+def test_bench_work_counts():
+    bench = _bench()
+    # force 4 per entry + 40, integrator 96; the whole path adds (170 + 4 L) / k
+    assert bench.path_bytes_per_particle_step(100.0, 20.0, False) == 536.0
+    assert bench.path_bytes_per_particle_step(100.0, 20.0, True) == 536.0 + 570.0 / 20.0
+    assert bench.flops_per_particle_step(100.0, 60.0, "sf") == 2000.0 + 27 * 60.0
+    assert bench.flops_per_particle_step(100.0, 60.0, "sp") == 2000.0 + 21 * 60.0

@@ -47,7 +47,7 @@ def test_round_trip_is_exact(srmd, tmp_path):
     assert got["skin"] == 0.3 + 1e-13  # 17 significant digits read back to the same double
     assert got["baseline_ms_per_step"] == 0.0 and got["tuned_ms_per_step"] == 0.0
     line = open(path).read()
-    assert line.startswith("srmd-tuning-v1 ") and line.count("\n") == 1 and "count=3277,819" in line
+    assert line.startswith("srmd-tuning-v2 ") and line.count("\n") == 1 and "count=3277,819" in line
 
 
 @pytest.mark.parametrize("field,value,match", [
@@ -86,6 +86,38 @@ def test_pair_parameters_must_agree(srmd, tmp_path, name):
     assert srmd.tuning_cache_find(path, k) is None
 
 
+def _mie_salt_key():
+    k = _key()
+    k["cutoff_method"] = 4
+    k["potential"] = 1
+    k["pot_param"] = [[[2.0, 4.0, 12, 6], [1.5, 3.0, 12, 6]], [[1.5, 3.0, 12, 6], [0.5, 1.0, 12, 6]]]
+    return k
+
+
+@pytest.mark.parametrize("change", ["A", "B", "m", "n", "potential"])
+def test_potential_parameters_must_agree(srmd, tmp_path, change):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _mie_salt_key(), _tuning())
+    assert srmd.tuning_cache_find(path, _mie_salt_key()) is not None
+    k = _mie_salt_key()
+    if change == "potential":
+        k["potential"] = 0
+    else:
+        r = "ABmn".index(change)
+        k["pot_param"][0][1][r] = k["pot_param"][1][0][r] = k["pot_param"][0][1][r] + 2
+    assert srmd.tuning_cache_find(path, k) is None
+
+
+def test_coulomb_parameters_must_agree(srmd, tmp_path):
+    path = str(tmp_path / "tuned.txt")
+    k = {**_key(), "cutoff_method": 3, "charge": [1.0, -1.0], "rc_coulomb": 6.0}
+    srmd.tuning_cache_store(path, k, _tuning())
+    assert srmd.tuning_cache_find(path, k) is not None
+    assert srmd.tuning_cache_find(path, {**k, "charge": [2.0, -2.0]}) is None
+    assert srmd.tuning_cache_find(path, {**k, "rc_coulomb": 5.0}) is None
+    assert srmd.tuning_cache_find(path, {**k, "rc_coulomb": 6.0 * (1 + 1e-7)}) is not None
+
+
 def test_other_type_count_is_no_match(srmd, tmp_path):
     path = str(tmp_path / "tuned.txt")
     srmd.tuning_cache_store(path, _key(), _tuning())
@@ -113,7 +145,7 @@ def test_damaged_lines_are_skipped(srmd, tmp_path):
     bad = [
         "garbage",
         "",
-        good.replace("srmd-tuning-v1", "srmd-tuning-v0"),
+        good.replace("srmd-tuning-v2", "srmd-tuning-v1"),  # older record format
         good.replace(" tp=4", " tp=3"),              # not a power of two
         good.replace(" ppb=64", " ppb=40"),          # tp * ppb not a multiple of 64
         good.replace(" list=1", " list=7"),
@@ -156,5 +188,6 @@ def test_invalid_arguments(srmd, tmp_path):
 
 
 def test_struct_layouts(srmd):
-    assert ctypes.sizeof(srmd.srmd_tuning_key) == 64 + 6 * 4 + 4 * 8 + 3 * 8 + 3 * 16 * 8
+    assert ctypes.sizeof(srmd.srmd_tuning_key) == (64 + 6 * 4 + 4 * 8 + 3 * 8 + 3 * 16 * 8 + 2 * 4 + 64 * 8
+                                                   + 4 * 8 + 8)
     assert ctypes.sizeof(srmd.srmd_tuning) == 4 * 4 + 3 * 8 + 2 * 4

@@ -180,6 +180,82 @@ def test_fcc_lattice_sums(oracle_lib, method, pe_survey, w_survey):
     assert len(shells) == 54
 
 
+# ---------------------------------------------------------------- pressure and thermo record
+
+def test_pressure_of_an_ideal_gas(oracle_lib):
+    # No pair inside the cutoff: the virial vanishes and the pressure is the ideal-gas
+    # value N k T_kin / V with the kinetic temperature m <v^2> / (3 k) of equipartition
+    # (every particle, no momentum constraint).  Free flight keeps v(n) = v(n +- 1/2).
+    rng = np.random.default_rng(12)
+    n = 8
+    box = np.array([30.0, 24.0, 18.0])
+    pos = rng.uniform(-9.0, 9.0, (n, 3)) * np.array([1.0, 0.8, 0.6])
+    vel = rng.normal(0.0, 1.3, (n, 3))
+    types = np.array([0, 1] * 4, np.int32)
+    mass = np.array([1.0, 2.5])
+    one = np.ones((2, 2))
+    out = oracle.integrate(pos, vel, types, mass, box, one, one, one * 1e-3, "sp", 1e-3, 3)
+    m = mass[types][:, None]
+    t_kin = (m * vel * vel).sum() / (3 * n)
+    p_ideal = n * t_kin / np.prod(box)
+    np.testing.assert_allclose(out["thermo"][:, 4], p_ideal, rtol=1e-13)
+    np.testing.assert_array_equal(out["thermo"][:, 2], 0.0)
+    # the thermodynamic temperature counts 3N - 3 degrees of freedom (momentum fixed)
+    np.testing.assert_allclose(out["thermo"][:, 3], t_kin * 3 * n / (3 * n - 3), rtol=1e-13)
+
+
+@pytest.mark.parametrize("method", ["sp", "sf"])
+def test_static_pressure_is_minus_energy_volume_derivative(oracle_lib, method):
+    # At rest (T = 0) the pressure is -dU/dV under a uniform dilation of the
+    # configuration.  For the perfect config-0 FCC lattice the derivative is taken from
+    # independently enumerated lattice sums (U/N as a function of the lattice constant).
+    s = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    a = s.box[0] / 6
+
+    def u_per_particle(lat):
+        return 0.5 * sum(oracle.pair(r, 1.0, 1.0, 2.5, method)[0] for r in _fcc_shells(lat, 2.5))
+
+    h = 1e-6
+    # V/N = a^3 / 4, so dV/da per particle = 3 a^2 / 4
+    dudv = (u_per_particle(a * (1 + h)) - u_per_particle(a * (1 - h))) / (2 * h * a) / (0.75 * a * a)
+    out = oracle.integrate(s.pos, np.zeros_like(s.pos, dtype=np.float64), s.types, s.mass, s.box, sig, eps,
+                           rc, method, 0.005, 1)
+    assert out["thermo"][0, 4] == pytest.approx(-dudv, rel=1e-5)
+    if method == "sp":
+        assert out["thermo"][0, 4] == pytest.approx(-6.235317, abs=5e-6)  # shell-sum value of the survey
+
+
+def test_pressure_adds_kinetic_and_virial_terms(oracle_lib):
+    # Lattice with velocities: P(T) - P(T = 0) is the kinetic part 2 KE / (3V) of the
+    # same record (the lattice does not move in the first step's force evaluation).
+    s = gen.config0_state()
+    sig, eps, rc = gen.lj_params()
+    v = gen.maxwell_boltzmann(s.n, 0.722, np.ones(s.n), 6)
+    hot = oracle.integrate(s.pos, v, s.types, s.mass, s.box, sig, eps, rc, "sp", 0.005, 1)
+    cold = oracle.integrate(s.pos, np.zeros_like(v), s.types, s.mass, s.box, sig, eps, rc, "sp", 0.005, 1)
+    ke = hot["thermo"][0, 1]
+    assert hot["thermo"][0, 2] == cold["thermo"][0, 2]  # same positions, same virial
+    assert hot["thermo"][0, 4] - cold["thermo"][0, 4] == pytest.approx(2 * ke / (3 * np.prod(s.box)), rel=1e-10)
+    # the record's KE is that of v(0) = (v(-1/2) + v(1/2)) / 2; on the lattice F = 0, so v(0) = v(-1/2)
+    assert ke == pytest.approx(0.5 * (v * v).sum(), rel=1e-9)
+
+
+def test_conserved_energy_record(oracle_lib):
+    # NVE: H is KE + PE of the record; under Nose-Hoover it adds the thermostat's
+    # g T0 (tau^2 xi^2 / 2 + integral of xi) and stays constant along the run
+    s = gen.lj_fcc_state(108, 0.8442, 1.5, 23)
+    sig, eps, rc = gen.lj_params()
+    pos, vel = s.pos.astype(np.float64), s.vel.astype(np.float64)
+    nve = oracle.integrate(pos, vel, s.types, s.mass, s.box, sig, eps, rc, "sf", 0.002, 5)["thermo"]
+    np.testing.assert_array_equal(nve[:, 7], nve[:, 1] + nve[:, 0])
+    nvt = oracle.integrate(pos, vel, s.types, s.mass, s.box, sig, eps, rc, "sf", 0.002, 600, thermostat=True,
+                           T0=0.5, tau=0.1)["thermo"]
+    e = nvt[:, 0] + nvt[:, 1]
+    assert np.ptp(e) > 0.2 * s.n                              # the thermostat removes energy
+    assert np.ptp(nvt[:, 7]) < 1e-3 * np.ptp(e)               # but H stays put
+
+
 # ---------------------------------------------------------------- pair sets
 
 def test_fcc_pair_counts(oracle_lib):
