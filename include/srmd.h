@@ -373,6 +373,39 @@ srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out);
 srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *kernel_ms, double *device_ms,
                                      int64_t *launches);
 
+/* ---- Force evaluation without allocation ---------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the force evaluation of
+ * srmd_compute_forces for a 12-6 Lennard-Jones configuration given in device
+ * memory, with every intermediate array (sorted copies, cell starts, neighbour list,
+ * block partials) in one static device array of 16 MiB per GPU instead of
+ * library-allocated buffers.  Limits: 2..8192 particles, at most 8192 cells of side
+ * >= (rcut + skin) / 2, and a neighbour list that fits the array (SRMD_EUNSUPPORTED
+ * otherwise, before any work is enqueued).  Everything is enqueued on hip_stream
+ * (NULL: the null stream) without a host synchronisation, hipMalloc, hipFree or
+ * hipMemset, so the call can be captured into a HIP graph.  All calls on one GPU
+ * share its array: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller; every call clears what it
+ * reads before using it. */
+typedef struct {
+  int32_t n, ntypes;        /* particles (2..8192) and types (1..4) */
+  int32_t method;           /* srmd_cutoff, for every type pair */
+  int32_t reserved;
+  double box[3];            /* orthorhombic box sides */
+  double skin;              /* list skin >= 0 (pairs within rcut + skin are listed) */
+  double sigma[16], epsilon[16], rcut[16];  /* row-major ntypes x ntypes, symmetric */
+} srmd_lj_config;
+
+/* d_pos: device float32 n*3 (x, y, z per particle; wrapped into [-L/2, L/2) as
+ * srmd_create wraps them); d_type: device int32 n.  Outputs, device memory:
+ * d_force float32 n*3 in the input particle order, d_energy float64 [2] = potential
+ * energy and virial W, d_status int32 [1] = 0 or error bits (1 non-finite force,
+ * 2 neighbour list longer than the array holds, 4 a type out of range, taken as
+ * type 0).  The results equal those of srmd_compute_forces on a system created
+ * from the same positions, types and parameters at its default launch shape. */
+srmd_status srmd_compute_forces_noalloc(const srmd_lj_config *cfg, const float *d_pos, const int32_t *d_type,
+                                        float *d_force, double *d_energy, int32_t *d_status, void *hip_stream);
+
 /* Message of the last failure on s (or of the calling thread when s is NULL). */
 const char *srmd_last_error(const srmd_system *s);
 

@@ -2085,7 +2085,79 @@ __global__ __launch_bounds__(256) void k_call_begin(SysConst c, SysPtrs p, Snaps
   }
 }
 
+// ---------------------------------------------------------------- stateless force evaluation
+
+// Set-up of a stateless force evaluation in caller-provided scratch: the control
+// block cleared with a rebuild requested, and the caller's positions (x, y, z per
+// particle, wrapped into [-L/2, L/2) as srmd_create wraps them) and types stored in
+// original order with zero velocities, zero images and identity ids; *status
+// cleared.  A type out of range is stored as 0 with its image x counter set to 1
+// (reported by k_direct_out), so that no table lookup leaves the pair tables.
+__global__ __launch_bounds__(256) void k_direct_init(SysConst c, SysPtrs p, const float *__restrict__ xyz,
+                                                     const int *__restrict__ type, int *status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    Control k;
+    int *w = reinterpret_cast<int *>(&k);
+    for (int q = 0; q < (int)(sizeof(Control) / sizeof(int)); ++q) w[q] = 0;
+    k.rebuild = 1;
+    *p.ctl = k;
+    *status = 0;
+  }
+  if (i >= c.n) return;
+  float r[3];
+  for (int d = 0; d < 3; ++d) {
+    const double x = (double)xyz[3 * i + d], L = c.Ld[d];
+    float f = (float)(x - L * floor(x / L + 0.5));
+    if (f >= c.halfL[d]) f -= c.L[d];
+    if (f < -c.halfL[d]) f += c.L[d];
+    r[d] = f;
+  }
+  int ty = type[i];
+  const int bad = (ty < 0 || ty >= c.ntypes) ? 1 : 0;
+  if (bad) ty = 0;
+  p.pos[0][i] = make_float4(r[0], r[1], r[2], __int_as_float(ty));
+  p.vel[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  p.img[i] = make_int4(bad, 0, 0, i);
+}
+
+// End of a stateless force evaluation: forces in original particle order, the
+// float64 potential energy and virial, and into *status the control block's error
+// bits (bit 0 non-finite force, bit 1 list capacity exceeded) and bit 2 for a type
+// out of range.
+__global__ __launch_bounds__(256) void k_direct_out(SysConst c, SysPtrs p, float *__restrict__ force,
+                                                    double *__restrict__ energy, int *status) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    energy[0] = p.thermo->pe;
+    energy[1] = p.thermo->virial;
+    const int e = p.ctl->error & 3;
+    if (e) atomicOr(status, e);
+  }
+  if (t >= c.n) return;
+  const int4 im = p.img[t];
+  if (im.x != 0) atomicOr(status, 4);
+  const int id = im.w;
+  if (id < 0 || id >= c.n) return;
+  const float4 f = p.force[t];
+  force[3 * id] = f.x;
+  force[3 * id + 1] = f.y;
+  force[3 * id + 2] = f.z;
+}
+
 // ---------------------------------------------------------------- launchers
+
+hipError_t launch_direct_init(hipStream_t st, const SysConst &c, const SysPtrs &p, const float *xyz, const int *type,
+                              int *status) {
+  hipLaunchKernelGGL(k_direct_init, dim3((c.n + 255) / 256), dim3(256), 0, st, c, p, xyz, type, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_direct_out(hipStream_t st, const SysConst &c, const SysPtrs &p, float *force, double *energy,
+                             int *status) {
+  hipLaunchKernelGGL(k_direct_out, dim3((c.n + 255) / 256), dim3(256), 0, st, c, p, force, energy, status);
+  return hipGetLastError();
+}
 
 hipError_t launch_call_begin(hipStream_t st, const SysConst &c, const SysPtrs &p, const Snapshot &snap, int cur,
                              int thermo_every, long long trace_cap) {

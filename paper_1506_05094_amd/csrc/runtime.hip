@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -25,6 +26,10 @@ hipError_t launch_finish(int mode, int G, int next, hipStream_t st, const SysCon
 hipError_t launch_host_sort(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
 hipError_t launch_call_begin(hipStream_t st, const SysConst &c, const SysPtrs &p, const Snapshot &snap, int cur,
                              int thermo_every, long long trace_cap);
+hipError_t launch_direct_init(hipStream_t st, const SysConst &c, const SysPtrs &p, const float *xyz, const int *type,
+                              int *status);
+hipError_t launch_direct_out(hipStream_t st, const SysConst &c, const SysPtrs &p, float *force, double *energy,
+                             int *status);
 bool small_sort_fits(int n, int ncell);
 size_t batch_lds_bytes(int n_max_particles);
 int batch_max_particles();
@@ -2652,3 +2657,141 @@ srmd_status srmd_batch_destroy(srmd_batch *b) {
 const char *srmd_batch_last_error(const srmd_batch *b) { return b ? b->err.c_str() : g_thread_error.c_str(); }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Stateless force evaluation that allocates nothing: every intermediate array of
+// the force path (sorted copies, cell starts, neighbour list, block partials,
+// control block and record) lives in one static device array per GPU.
+
+namespace {
+
+constexpr size_t kDirectScratchBytes = (size_t)16 << 20;  // 16 MiB per GPU
+constexpr int kDirectMaxDevices = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kDirectScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kDirectMaxDevices] = {};
+
+// Device address of this GPU's scratch array, looked up once per device with that
+// device current (the array's host-side name is not a device address).
+srmd_status direct_scratch(void **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, SRMD_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kDirectMaxDevices) return fail(nullptr, SRMD_EUNSUPPORTED, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(nullptr, SRMD_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SRMD_OK;
+}
+
+// Consecutive 256-byte aligned pieces of the scratch array (host arithmetic only).
+struct Carve {
+  char *base;
+  size_t off;
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T *q = reinterpret_cast<T *>(base + off);
+    off += sizeof(T) * count;
+    return q;
+  }
+};
+
+}  // namespace
+
+extern "C" srmd_status srmd_compute_forces_noalloc(const srmd_lj_config *cfg, const float *d_pos,
+                                                   const int32_t *d_type, float *d_force, double *d_energy,
+                                                   int32_t *d_status, void *hip_stream) {
+  if (!cfg || !d_pos || !d_type || !d_force || !d_energy || !d_status)
+    return fail(nullptr, SRMD_EINVAL, "cfg and every device pointer are required");
+  const int n = cfg->n, nt = cfg->ntypes;
+  if (n < 2) return fail(nullptr, SRMD_EINVAL, "need at least 2 particles");
+  if (nt < 1 || nt > kMaxTypes) return fail(nullptr, SRMD_EINVAL, "ntypes must be in 1..4");
+  if (cfg->method < SRMD_CUT_TRUNC || cfg->method > SRMD_CUT_SF) return fail(nullptr, SRMD_EINVAL, "unknown cutoff method");
+  if (!(cfg->skin >= 0) || !std::isfinite(cfg->skin)) return fail(nullptr, SRMD_EINVAL, "skin must be >= 0");
+  // the system the force path would build for these parameters (host only)
+  srmd_system t;
+  t.n = n;
+  t.ntypes = nt;
+  for (int k = 0; k < 3; ++k) {
+    if (!(cfg->box[k] > 0) || !std::isfinite(cfg->box[k]) || !std::isfinite((float)cfg->box[k]))
+      return fail(nullptr, SRMD_EINVAL, "box sides must be positive and finite");
+    t.Lf[k] = (float)cfg->box[k];
+  }
+  for (int a = 0; a < nt; ++a)
+    for (int b = 0; b < nt; ++b) {
+      const int q = a * nt + b, r = b * nt + a;
+      const double sg = cfg->sigma[q], ep = cfg->epsilon[q], rc = cfg->rcut[q];
+      if (!(sg > 0) || !(ep >= 0) || !(rc > 0) || !std::isfinite(sg) || !std::isfinite(ep) || !std::isfinite(rc))
+        return fail(nullptr, SRMD_EINVAL, "sigma, rcut > 0 and epsilon >= 0 must be finite");
+      if (sg != cfg->sigma[r] || ep != cfg->epsilon[r] || rc != cfg->rcut[r])
+        return fail(nullptr, SRMD_EINVAL, "pair parameters must be symmetric");
+      t.sigma[q] = sg;
+      t.eps[q] = ep;
+      t.rc[q] = rc;
+      t.pair_given[q] = true;
+    }
+  t.method = cfg->method;
+  t.pot = 0;
+  t.skin = cfg->skin;
+  if (fill_const(&t) != SRMD_OK) return fail(nullptr, SRMD_EINVAL, t.err);
+  SysConst c = t.c;
+  if (!c.small_sort)
+    return fail(nullptr, SRMD_EUNSUPPORTED, "the allocation-free force path takes at most 8192 particles and 8192 cells");
+  void *base = nullptr;
+  srmd_status st = direct_scratch(&base);
+  if (st != SRMD_OK) return st;
+  const size_t N = (size_t)n;
+  const int threads = t.tp * t.ppb;
+  const int blocks = step_blocks(&t);
+  SysPtrs p{};
+  Carve cv{(char *)base, 0};
+  p.pos[0] = cv.take<float4>(N);
+  p.pos[1] = cv.take<float4>(N);
+  p.vel = cv.take<float4>(N);
+  p.img = cv.take<int4>(N);
+  p.force = cv.take<float4>(N);
+  p.wpart = cv.take<float>(N);
+  p.last = cv.take<float4>(N);
+  p.nnb = cv.take<int>(N);
+  p.t_pos = cv.take<float4>(N);
+  p.t_vel = cv.take<float4>(N);
+  p.t_img = cv.take<int4>(N);
+  p.cell_start = cv.take<unsigned>((size_t)c.ncell + 1);
+  p.part = cv.take<BlockPartial>((size_t)blocks);
+  p.ctl = cv.take<Control>(1);
+  p.thermo = cv.take<Thermo>(1);
+  // the list takes what is left, as many rows as fit (at most one per particle)
+  const size_t used = (cv.off + 255) & ~(size_t)255;
+  if (used >= kDirectScratchBytes) return fail(nullptr, SRMD_EUNSUPPORTED, "system too large for the scratch array");
+  const long long rows_fit = (long long)((kDirectScratchBytes - used) / (sizeof(int) * (size_t)c.nvp)) / 64 * 64;
+  const long long rows = std::min<long long>(rows_fit, (long long)c.nvp);
+  if (rows < c.n_max)
+    return fail(nullptr, SRMD_EUNSUPPORTED, "the neighbour list of this system does not fit the scratch array");
+  c.n_max = (int)rows;
+  p.nbl = cv.take<int>((size_t)rows * (size_t)c.nvp);
+  if (cv.off > kDirectScratchBytes) return fail(nullptr, SRMD_EUNSUPPORTED, "system too large for the scratch array");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  auto chk = [&](hipError_t e, const char *what) {
+    return e == hipSuccess ? SRMD_OK : fail(nullptr, SRMD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  if ((st = chk(launch_direct_init(stream, c, p, d_pos, d_type, d_status), "set-up kernel")) != SRMD_OK) return st;
+  if ((st = chk(launch_host_sort(stream, c, p, 0), "spatial sort")) != SRMD_OK) return st;
+  if ((st = chk(launch_rebuild(stream, c, p, 0), "list build")) != SRMD_OK) return st;
+  if ((st = chk(launch_force(t.tp, (int)t.method, blocks, threads, stream, c, p, 0), "force kernel")) != SRMD_OK)
+    return st;
+  if ((st = chk(launch_finish(1, blocks, 0, stream, c, p), "reduction")) != SRMD_OK) return st;
+  return chk(launch_direct_out(stream, c, p, d_force, d_energy, d_status), "output kernel");
+}

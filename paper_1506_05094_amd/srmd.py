@@ -92,6 +92,12 @@ class srmd_tuning_key(ctypes.Structure):
         return k
 
 
+class srmd_lj_config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("ntypes", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("box", ctypes.c_double * 3), ("skin", ctypes.c_double),
+                ("sigma", ctypes.c_double * 16), ("epsilon", ctypes.c_double * 16), ("rcut", ctypes.c_double * 16)]
+
+
 class srmd_tuning(ctypes.Structure):
     _fields_ = [("tp", ctypes.c_int32), ("ppb", ctypes.c_int32), ("list_mode", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("skin", ctypes.c_double),
@@ -183,6 +189,7 @@ def load():
         "srmd_step": (st, [sysp, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
         "srmd_get_state": (st, [sysp, _fp, _fp, _ip, _fp, _dp]),
         "srmd_get_particle_terms": (st, [sysp, _fp, _fp]),
+        "srmd_compute_forces_noalloc": (st, [ctypes.POINTER(srmd_lj_config), _vp, _vp, _vp, _vp, _vp, _vp]),
         "srmd_save_state": (st, [sysp, _vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
         "srmd_load_state": (st, [sysp, _vp, ctypes.c_size_t]),
         "srmd_set_state": (st, [sysp, _fp, _fp]),
@@ -515,7 +522,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_autotune", "srmd_tuning_key_of", "srmd_tuning_cache_find", "srmd_tuning_cache_store",
             "srmd_autotune_full", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent",
+            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_compute_forces_noalloc", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
             "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf",
             "srmd_set_pair_mie"]
@@ -552,6 +559,27 @@ def tuning_cache_store(path, key, tuning):
     k = srmd_tuning_key.from_dict(key)
     t = srmd_tuning.from_dict(tuning)
     _check(load().srmd_tuning_cache_store(os.fsencode(path), ctypes.byref(k), ctypes.byref(t)))
+
+
+def lj_config(n, box, sigma, eps, rc, method, skin=0.3):
+    """srmd_lj_config of a Lennard-Jones configuration (pair arrays ntypes x ntypes)."""
+    sigma, eps, rc = (np.asarray(x, np.float64) for x in (sigma, eps, rc))
+    nt = sigma.shape[0]
+    cfg = srmd_lj_config()
+    cfg.n, cfg.ntypes = int(n), nt
+    cfg.method = CUTOFF[method] if isinstance(method, str) else int(method)
+    for k in range(3):
+        cfg.box[k] = float(box[k])
+    cfg.skin = float(skin)
+    for q, (a, b, c) in enumerate(zip(sigma.reshape(-1), eps.reshape(-1), rc.reshape(-1))):
+        cfg.sigma[q], cfg.epsilon[q], cfg.rcut[q] = float(a), float(b), float(c)
+    return cfg
+
+
+def compute_forces_noalloc(cfg, d_pos, d_type, d_force, d_energy, d_status, stream=None):
+    """srmd_compute_forces_noalloc on device pointers (ints); enqueued only, no sync."""
+    _check(load().srmd_compute_forces_noalloc(ctypes.byref(cfg), _vp(d_pos), _vp(d_type), _vp(d_force),
+                                              _vp(d_energy), _vp(d_status), None if stream is None else _vp(stream)))
 
 
 def system_from_state(state, sigma, eps, rc, method, skin=0.3, precision="f32", stream=None):
