@@ -121,6 +121,40 @@ srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigm
 srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, double B, int32_t m, int32_t n,
                               double sigma, double rcut, srmd_cutoff method);
 
+/* Further pair potentials among those paper section 2 lists by name; the library
+ * takes their textbook forms (x = r / sigma):
+ *   SRMD_POT_YUKAWA         U = eps (sigma/r) exp(-kappa (r - sigma)),  params {eps, kappa},
+ *                           kappa >= 0, kappa sigma <= 60 (screened Coulomb);
+ *   SRMD_POT_BUCKINGHAM     U = A exp(-r/rho) - C / r^6,  params {A, rho, C}, A, C >= 0,
+ *                           rho > 0 (sigma unused but must be positive);
+ *   SRMD_POT_GAUSSIAN_CORE  U = eps exp(-x^2),  params {eps};
+ *   SRMD_POT_DZUGUTOV       U = eps [5.82 (x^-16 - 1.28) exp(1.1/(x - 1.87)) for x < 1.87
+ *                           + 1.28 exp(0.27/(x - 1.94)) for x < 1.94],  params {eps}
+ *                           (smoothly zero from 1.94 sigma on: rcut = 1.94 sigma is natural);
+ *   SRMD_POT_GIRIFALCO      U = -alpha [1/(x(x-1)^3) + 1/(x(x+1)^3) - 2/x^4]
+ *                           + beta [1/(x(x-1)^9) + 1/(x(x+1)^9) - 2/x^10],  params {alpha, beta},
+ *                           sigma = the sphere diameter, rcut > sigma.
+ * Unused params entries are ignored.  Pair forces are evaluated in float32 on the
+ * device (exp from the device library); energy sums in float64. */
+typedef enum {
+  SRMD_POT_YUKAWA = 2,
+  SRMD_POT_BUCKINGHAM = 3,
+  SRMD_POT_GAUSSIAN_CORE = 4,
+  SRMD_POT_DZUGUTOV = 5,
+  SRMD_POT_GIRIFALCO = 6
+} srmd_potential;
+
+/* One of the further potentials between types ti and tj (symmetric) in place of
+ * Lennard-Jones: params holds 4 doubles (host; see srmd_potential), modified by the
+ * cutoff method as srmd_set_pair_lj (paper section 2 cutoff methods: the shifts use
+ * the potential's own U(rcut) and F(rcut)).  All type pairs of a system use one
+ * potential kind and one method (mixing kinds, or with srmd_set_pair_lj /
+ * srmd_set_pair_mie: SRMD_EINVAL).  The Coulomb term does not combine with it
+ * (SRMD_EUNSUPPORTED at the next step).  rcut + skin must stay below half of every
+ * box side. */
+srmd_status srmd_set_pair_potential(srmd_system *s, int32_t ti, int32_t tj, srmd_potential kind,
+                                    const double *params, double sigma, double rcut, srmd_cutoff method);
+
 /* Coulomb interactions with a shifted-force cutoff (paper section 9, the molten
  * salt benchmark): charge[t] per type (host array of ntypes doubles, reduced units
  * in which the Coulomb constant is one), one cutoff rcut > 0 for every type pair.
@@ -211,7 +245,8 @@ typedef struct {
   char gpu[64];          /* device architecture name (hipDeviceProp_t::gcnArchName) */
   int32_t compute_units; /* of that device */
   int32_t precision;     /* srmd_precision */
-  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term, 4 two-power potential */
+  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term, 4 two-power potential,
+                            5 an srmd_potential (its kind in potential) */
   int32_t thermostat;    /* 0 NVE, 1 Nose-Hoover NVT */
   int32_t ntypes;
   int32_t reserved;
@@ -220,10 +255,11 @@ typedef struct {
   double temperature;    /* T0 under NVT; under NVE the kinetic temperature 2 KE / (3N - 3) of the state */
   double dt;
   double sigma[16], epsilon[16], rcut[16];
-  int32_t potential;        /* 0 12-6 Lennard-Jones, 1 the two-power potential */
+  int32_t potential;        /* 0 12-6 Lennard-Jones, 1 the two-power potential, 2..6 srmd_potential */
   int32_t reserved2;
   double pot_param[16][4];  /* per type pair, the potential's parameters besides sigma and rcut
-                               (two-power: A, B, m, n); zero for Lennard-Jones */
+                               (two-power: A, B, m, n; srmd_potential: its params); zero for
+                               Lennard-Jones */
   double charge[4];         /* Coulomb charges per type (zero without the Coulomb term) */
   double rc_coulomb;        /* Coulomb cutoff (zero without the term) */
 } srmd_tuning_key;

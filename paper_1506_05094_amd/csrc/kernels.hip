@@ -135,10 +135,16 @@ struct alignas(16) MieRow {
   int hm, hn;
 };
 
+// Constants of a further potential of a type pair (kernel method 5).
+struct alignas(16) GenRow {
+  float g0, g1, g2, g3;
+};
+
 struct SharedPairs {
   PairRow row[kMaxPairs];
   CoulRow crow[kMaxPairs];
   MieRow mrow[kMaxPairs];
+  GenRow grow[kMaxPairs];
 };
 
 __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) {
@@ -166,6 +172,7 @@ __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) 
     g.hm = c.pt.mie_hm[t];
     g.hn = c.pt.mie_hn[t];
     sp.mrow[t] = g;
+    sp.grow[t] = GenRow{c.pt.gen[t][0], c.pt.gen[t][1], c.pt.gen[t][2], c.pt.gen[t][3]};
   }
 }
 
@@ -193,6 +200,67 @@ __device__ __forceinline__ float pow_int(float x, int h) {
     x *= x;
   }
   return r;
+}
+
+// Energy u and force over distance fr = F(r)/r (F = -dU/dr, positive repulsive) of
+// the further pair potentials of paper section 2 (the paper names them only; these
+// are the textbook forms), in float32 from the pair's constants g (kind uniform over
+// the system):
+//  2 Yukawa        U = eps (sig/r) exp(-kappa (r - sig)) = g0 exp(-g1 r) / r
+//                  (g0 = eps sig exp(kappa sig), g1 = kappa)
+//  3 Buckingham    U = A exp(-r/rho) - C / r^6               (g0 = A, g1 = 1/rho, g2 = C)
+//  4 Gaussian core U = eps exp(-(r/sig)^2)                    (g0 = eps, g1 = 1/sig^2)
+//  5 Dzugutov      U = eps [5.82 (x^-16 - 1.28) exp(1.1 / (x - 1.87)) (x < 1.87)
+//                         + 1.28 exp(0.27 / (x - 1.94)) (x < 1.94)],  x = r/sig
+//                                                            (g0 = eps, g1 = 1/sig)
+//  6 Girifalco     U = -alpha [1/(s(s-1)^3) + 1/(s(s+1)^3) - 2/s^4]
+//                      + beta [1/(s(s-1)^9) + 1/(s(s+1)^9) - 2/s^10],  s = r/d
+//                                                            (g0 = alpha, g1 = beta, g2 = 1/d)
+__device__ __forceinline__ void pair_further(int kind, const GenRow &g, float r, float inv_r, float &u, float &fr) {
+  const float inv_r2 = inv_r * inv_r;
+  if (kind == 2) {
+    u = g.g0 * expf(-g.g1 * r) * inv_r;
+    fr = u * __builtin_fmaf(g.g1, r, 1.0f) * inv_r2;
+  } else if (kind == 3) {
+    const float e = g.g0 * expf(-g.g1 * r);
+    const float d6 = g.g2 * inv_r2 * inv_r2 * inv_r2;
+    u = e - d6;
+    fr = (e * g.g1 * inv_r - 6.0f * d6 * inv_r2);
+  } else if (kind == 4) {
+    const float e = g.g0 * expf(-r * r * g.g1);
+    u = e;
+    fr = 2.0f * g.g1 * e;
+  } else if (kind == 5) {
+    const float x = r * g.g1;
+    float uu = 0.0f, du = 0.0f;
+    if (x < 1.87f) {
+      const float q = 1.0f / (x - 1.87f);
+      const float e = expf(1.1f * q);
+      const float ix2 = 1.0f / (x * x);
+      const float xm = pow_int(ix2, 8);
+      uu = 5.82f * (xm - 1.28f) * e;
+      du = 5.82f * e * (-16.0f * xm / x - (xm - 1.28f) * 1.1f * q * q);
+    }
+    if (x < 1.94f) {
+      const float q = 1.0f / (x - 1.94f);
+      const float e = 1.28f * expf(0.27f * q);
+      uu += e;
+      du -= e * 0.27f * q * q;
+    }
+    u = g.g0 * uu;
+    fr = -g.g0 * du * g.g1 * inv_r;
+  } else {
+    const float s = r * g.g2, is = 1.0f / s;
+    const float ia = 1.0f / (s - 1.0f), ib = 1.0f / (s + 1.0f);
+    const float ia3 = ia * ia * ia, ib3 = ib * ib * ib, ia9 = ia3 * ia3 * ia3, ib9 = ib3 * ib3 * ib3;
+    const float is4 = is * is * is * is, is10 = is4 * is4 * is * is;
+    const float att = is * (ia3 + ib3) - 2.0f * is4;
+    const float rep = is * (ia9 + ib9) - 2.0f * is10;
+    const float datt = -is * is * (ia3 + ib3) - 3.0f * is * (ia3 * ia + ib3 * ib) + 8.0f * is4 * is;
+    const float drep = -is * is * (ia9 + ib9) - 9.0f * is * (ia9 * ia + ib9 * ib) + 20.0f * is10 * is;
+    u = -g.g0 * att + g.g1 * rep;
+    fr = (g.g0 * datt - g.g1 * drep) * g.g2 * inv_r;
+  }
 }
 
 template <int METHOD>
@@ -224,6 +292,27 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
       const float r = r2 * inv_r;
       fr = __builtin_fmaf(-pr.fc, inv_r, fr);
       e = __builtin_fmaf(r - pr.rc, pr.fc, e);
+      fx = __builtin_fmaf(-fr, dx, fx);
+      fy = __builtin_fmaf(-fr, dy, fy);
+      fz = __builtin_fmaf(-fr, dz, fz);
+      u += e;
+      w = __builtin_fmaf(fr, r2, w);
+    }
+    return;
+  }
+  if (METHOD == 5) {
+    // a further potential of paper section 2, cutoff method by U(rc) and F(rc)
+    if (r2s < pr.rc2) {
+      dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
+      dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
+      dz = (float)(((double)pj.z - wi.z) - (double)mz * c.Ld[2]);
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      const float inv_r = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * inv_r;
+      float e, fr;
+      pair_further(c.pot_kind, sp.grow[pidx], r, inv_r, e, fr);
+      fr = __builtin_fmaf(-pr.fc, inv_r, fr);
+      e = __builtin_fmaf(r - pr.rc, pr.fc, e - pr.ushift);
       fx = __builtin_fmaf(-fr, dx, fx);
       fy = __builtin_fmaf(-fr, dy, fy);
       fz = __builtin_fmaf(-fr, dz, fz);
@@ -1979,7 +2068,8 @@ static const void *multi_fn(int method) {
          : method == 1 ? (const void *)k_multi<TP, 1, BIG>
          : method == 2 ? (const void *)k_multi<TP, 2, BIG>
          : method == 3 ? (const void *)k_multi<TP, 3, BIG>
-                       : (const void *)k_multi<TP, 4, BIG>;
+         : method == 4 ? (const void *)k_multi<TP, 4, BIG>
+                       : (const void *)k_multi<TP, 5, BIG>;
 }
 
 // The persistent kernel for (tp, method); the large-system form exists for tp <= 8.
@@ -2106,6 +2196,7 @@ static hipError_t launch_step_tp(int method, int prec, dim3 g, dim3 b, hipStream
   SRMD_STEP_CASE(2, 0) SRMD_STEP_CASE(2, 1) SRMD_STEP_CASE(2, 2)
   SRMD_STEP_CASE(3, 0) SRMD_STEP_CASE(3, 1) SRMD_STEP_CASE(3, 2)
   SRMD_STEP_CASE(4, 0) SRMD_STEP_CASE(4, 1) SRMD_STEP_CASE(4, 2)
+  SRMD_STEP_CASE(5, 0) SRMD_STEP_CASE(5, 1) SRMD_STEP_CASE(5, 2)
 #undef SRMD_STEP_CASE
   return hipErrorInvalidValue;
 }
@@ -2118,6 +2209,7 @@ static hipError_t launch_force_tp(int method, dim3 g, dim3 b, hipStream_t st, co
   else if (method == 2) hipLaunchKernelGGL((k_force<TP, 2>), g, b, 0, st, c, p, cur);
   else if (method == 3) hipLaunchKernelGGL((k_force<TP, 3>), g, b, 0, st, c, p, cur);
   else if (method == 4) hipLaunchKernelGGL((k_force<TP, 4>), g, b, 0, st, c, p, cur);
+  else if (method == 5) hipLaunchKernelGGL((k_force<TP, 5>), g, b, 0, st, c, p, cur);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

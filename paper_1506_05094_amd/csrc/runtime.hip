@@ -71,9 +71,11 @@ struct srmd_system {
   double sigma[kMaxPairs] = {}, eps[kMaxPairs] = {}, rc[kMaxPairs] = {};
   bool pair_given[kMaxPairs] = {};
   int method = -1;
-  int pot = -1;                         // 0 Lennard-Jones, 1 two-power (srmd_set_pair_mie); -1 none yet
+  int pot = -1;                         // 0 Lennard-Jones, 1 two-power (srmd_set_pair_mie), 2..6 the further
+                                        // potentials (srmd_set_pair_potential); -1 none yet
   double mie_a[kMaxPairs] = {}, mie_b[kMaxPairs] = {};
   int mie_m[kMaxPairs] = {}, mie_n[kMaxPairs] = {};
+  double gen_p[kMaxPairs][4] = {};      // parameters of a further potential
   bool coulomb = false;                 // shifted-force Coulomb term on (srmd_set_coulomb_sf)
   double charge[kMaxTypes] = {0, 0, 0, 0};
   double rcc = 0.0;                     // its cutoff
@@ -192,6 +194,51 @@ double lj_f(double r, double sig, double eps) {
   return 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r;
 }
 
+// Energy and force -dU/dr of a further potential (kinds 2..6, srmd_set_pair_potential)
+// in float64, for its values at the cutoff.
+void further_uf(int kind, const double *p, double sig, double r, double *u, double *f) {
+  if (kind == 2) {  // Yukawa
+    const double e = std::exp(-p[1] * (r - sig));
+    *u = p[0] * sig / r * e;
+    *f = *u * (1.0 + p[1] * r) / r;
+  } else if (kind == 3) {  // Buckingham
+    const double e = p[0] * std::exp(-r / p[1]), d6 = p[2] / std::pow(r, 6);
+    *u = e - d6;
+    *f = e / p[1] - 6.0 * d6 / r;
+  } else if (kind == 4) {  // Gaussian core
+    const double e = p[0] * std::exp(-(r / sig) * (r / sig));
+    *u = e;
+    *f = 2.0 * r / (sig * sig) * e;
+  } else if (kind == 5) {  // Dzugutov
+    const double x = r / sig;
+    double uu = 0.0, du = 0.0;
+    if (x < 1.87) {
+      const double q = 1.0 / (x - 1.87), e = std::exp(1.1 * q), xm = std::pow(x, -16.0);
+      uu += 5.82 * (xm - 1.28) * e;
+      du += 5.82 * e * (-16.0 * xm / x - (xm - 1.28) * 1.1 * q * q);
+    }
+    if (x < 1.94) {
+      const double q = 1.0 / (x - 1.94), e = 1.28 * std::exp(0.27 * q);
+      uu += e;
+      du -= e * 0.27 * q * q;
+    }
+    *u = p[0] * uu;
+    *f = -p[0] * du / sig;
+  } else {  // Girifalco
+    const double x = r / sig, a = x - 1.0, b = x + 1.0;
+    auto br = [&](int k, double *v, double *dv) {
+      const double ak = std::pow(a, k), bk = std::pow(b, k), xk = std::pow(x, k + 1);
+      *v = 1.0 / (x * ak) + 1.0 / (x * bk) - 2.0 / xk;
+      *dv = -1.0 / (x * x * ak) - k / (x * ak * a) - 1.0 / (x * x * bk) - k / (x * bk * b) + 2.0 * (k + 1) / (xk * x);
+    };
+    double at, dat, rp, drp;
+    br(3, &at, &dat);
+    br(9, &rp, &drp);
+    *u = -p[0] * at + p[1] * rp;
+    *f = (p[0] * dat - p[1] * drp) / sig;
+  }
+}
+
 double rc_max(const srmd_system *s) {
   double m = s->coulomb ? s->rcc : 0.0;
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
@@ -202,7 +249,7 @@ double rc_max(const srmd_system *s) {
 // The method index the kernels are instantiated for: the Lennard-Jones cutoff
 // method, 3 for shifted-force Lennard-Jones plus shifted-force Coulomb, 4 for the
 // two-power potential (any cutoff method).
-int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->pot == 1 ? 4 : s->method; }
+int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->pot == 1 ? 4 : s->pot >= 2 ? 5 : s->method; }
 
 bool all_pairs_given(const srmd_system *s) {
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
@@ -341,6 +388,7 @@ srmd_status fill_const(srmd_system *s) {
     return fail(s, SRMD_EINVAL, "the all-pairs list build takes systems of at most 8192 particles and 8192 cells "
                                 "with the one-workgroup sort mode");
   c.list_blocks = std::max(1, std::min((s->n + 255) / 256, 2048));
+  c.pot_kind = s->pot >= 2 ? s->pot : 0;
   // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
   const double rho = s->n / V;
   int nmax = (int)std::ceil(1.5 * 4.0 / 3.0 * M_PI * reach * reach * reach * rho + 32.0);
@@ -389,6 +437,33 @@ srmd_status fill_const(srmd_system *s) {
       c.pt.mie_hn[a] = n / 2;
       c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)mie_u(s->rc[a], A, B, m, n, s->sigma[a]);
       c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)mie_f(s->rc[a], A, B, m, n, s->sigma[a]) : 0.0f;
+    }
+    if (s->pot >= 2) {
+      const double *q = s->gen_p[a], sg = s->sigma[a];
+      double uc, fcut;
+      further_uf(s->pot, q, sg, s->rc[a], &uc, &fcut);
+      c.pt.eps4[a] = c.pt.eps24[a] = 0.0f;
+      c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)uc;
+      c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)fcut : 0.0f;
+      float *g = c.pt.gen[a];
+      if (s->pot == 2) {
+        g[0] = (float)(q[0] * sg * std::exp(q[1] * sg));
+        g[1] = (float)q[1];
+      } else if (s->pot == 3) {
+        g[0] = (float)q[0];
+        g[1] = (float)(1.0 / q[1]);
+        g[2] = (float)q[2];
+      } else if (s->pot == 4) {
+        g[0] = (float)q[0];
+        g[1] = (float)(1.0 / (sg * sg));
+      } else if (s->pot == 5) {
+        g[0] = (float)q[0];
+        g[1] = (float)(1.0 / sg);
+      } else {
+        g[0] = (float)q[0];
+        g[1] = (float)q[1];
+        g[2] = (float)(1.0 / sg);
+      }
     }
   }
   return SRMD_OK;
@@ -1118,7 +1193,7 @@ srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigm
     return fail(s, SRMD_EINVAL, "unknown cutoff method");
   if (s->method >= 0 && s->method != (int)method)
     return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
-  if (s->pot == 1) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (two-power set before)");
+  if (s->pot >= 1) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (another one set before)");
   for (int k = 0; k < 3; ++k)
     if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
       return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
@@ -1148,7 +1223,7 @@ srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, 
     return fail(s, SRMD_EINVAL, "unknown cutoff method");
   if (s->method >= 0 && s->method != (int)method)
     return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
-  if (s->pot == 0) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (Lennard-Jones set before)");
+  if (s->pot == 0 || s->pot >= 2) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (another one set before)");
   for (int k = 0; k < 3; ++k)
     if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
       return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
@@ -1163,6 +1238,46 @@ srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, 
     s->mie_b[a] = B;
     s->mie_m[a] = m;
     s->mie_n[a] = n;
+    s->pair_given[a] = true;
+  }
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_pair_potential(srmd_system *s, int32_t ti, int32_t tj, srmd_potential kind,
+                                    const double *params, double sigma, double rcut, srmd_cutoff method) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (ti < 0 || tj < 0 || ti >= s->ntypes || tj >= s->ntypes) return fail(s, SRMD_EINVAL, "type index out of range");
+  const int k = (int)kind;
+  if (k < SRMD_POT_YUKAWA || k > SRMD_POT_GIRIFALCO) return fail(s, SRMD_EINVAL, "unknown potential kind");
+  if (!params) return fail(s, SRMD_EINVAL, "params is NULL");
+  if (!(sigma > 0) || !std::isfinite(sigma) || !(rcut > 0) || !std::isfinite(rcut))
+    return fail(s, SRMD_EINVAL, "sigma and rcut must be positive");
+  double p[4] = {params[0], params[1], params[2], params[3]};
+  for (double v : p)
+    if (!std::isfinite(v)) return fail(s, SRMD_EINVAL, "parameters must be finite");
+  if (k == SRMD_POT_YUKAWA && !(p[1] >= 0 && p[1] * sigma <= 60.0))
+    return fail(s, SRMD_EINVAL, "Yukawa: kappa >= 0 and kappa sigma <= 60");
+  if (k == SRMD_POT_BUCKINGHAM && !(p[0] >= 0 && p[1] > 0 && p[2] >= 0))
+    return fail(s, SRMD_EINVAL, "Buckingham: A >= 0, rho > 0, C >= 0");
+  if (k == SRMD_POT_GIRIFALCO && !(rcut > sigma))
+    return fail(s, SRMD_EINVAL, "Girifalco: rcut must exceed the diameter sigma");
+  if (method != SRMD_CUT_TRUNC && method != SRMD_CUT_SP && method != SRMD_CUT_SF)
+    return fail(s, SRMD_EINVAL, "unknown cutoff method");
+  if (s->method >= 0 && s->method != (int)method)
+    return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
+  if (s->pot >= 0 && s->pot != k) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential");
+  for (int q = 0; q < 3; ++q)
+    if (!(rcut + s->skin < 0.5 * (double)s->Lf[q]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+  s->method = (int)method;
+  s->pot = k;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int a = pass ? pair_index(s, tj, ti) : pair_index(s, ti, tj);
+    s->sigma[a] = sigma;
+    s->eps[a] = 0.0;
+    s->rc[a] = rcut;
+    for (int q = 0; q < 4; ++q) s->gen_p[a][q] = p[q];
     s->pair_given[a] = true;
   }
   s->dirty = true;
@@ -2141,7 +2256,7 @@ bool parse_tuning_line(const std::string &line, srmd_tuning_key *k, srmd_tuning 
   }
   {
     auto pi = kv.find("param"), qi = kv.find("charge");
-    if (!one_int("potential", &v[0]) || v[0] < 0 || v[0] > 1 || pi == kv.end() || qi == kv.end() ||
+    if (!one_int("potential", &v[0]) || v[0] < 0 || v[0] > 6 || pi == kv.end() || qi == kv.end() ||
         !parse_list(pi->second, 4 * nt * nt, &k->pot_param[0][0], nullptr) ||
         !parse_list(qi->second, nt, k->charge, nullptr) || !one_num("rcc", &k->rc_coulomb))
       return false;
@@ -2251,9 +2366,11 @@ srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key) {
         key->pot_param[q][1] = s->mie_b[pi];
         key->pot_param[q][2] = s->mie_m[pi];
         key->pot_param[q][3] = s->mie_n[pi];
+      } else if (s->pot >= 2) {
+        for (int r = 0; r < 4; ++r) key->pot_param[q][r] = s->gen_p[pi][r];
       }
     }
-  key->potential = s->pot == 1 ? 1 : 0;
+  key->potential = s->pot >= 1 ? s->pot : 0;
   if (s->coulomb) {
     for (int t = 0; t < s->ntypes; ++t) key->charge[t] = s->charge[t];
     key->rc_coulomb = s->rcc;

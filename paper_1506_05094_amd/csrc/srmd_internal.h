@@ -38,6 +38,9 @@ struct PairTable {
   // travel in eps4 and eps24): B, n B and the half exponents m/2, n/2
   float mie_b[kMaxPairs], mie_nb[kMaxPairs];
   int mie_hm[kMaxPairs], mie_hn[kMaxPairs];
+  // further potentials (kernel method 5, kind in SysConst::pot_kind): four float32
+  // constants per pair derived from the parameters (see pair_further)
+  float gen[kMaxPairs][4];
 };
 
 // Everything a kernel needs besides pointers; passed by value.
@@ -67,7 +70,7 @@ struct SysConst {
   int small_sort;    // 1: the spatial sort runs in one workgroup (small systems)
   int list_kind;     // list builder of the launch chain: 1 wave per particle, 2 thread per particle, 3 wave per cell
   int list_blocks;   // grid of the thread-per-particle list build and the sort kernels
-  int pad1;
+  int pot_kind;      // kernel method 5: 2 Yukawa, 3 Buckingham, 4 Gaussian core, 5 Dzugutov, 6 Girifalco
   float inv_mass[kMaxTypes];
   double mass[kMaxTypes];
   PairTable pt;

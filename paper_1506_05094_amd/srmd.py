@@ -20,6 +20,7 @@ SRMD_OK, SRMD_EINVAL, SRMD_ENOMEM, SRMD_EHIP, SRMD_ESTATE, SRMD_EUNSUPPORTED = 0
 SRMD_CUT_TRUNC, SRMD_CUT_SP, SRMD_CUT_SF = 0, 1, 2
 SRMD_PREC_F32, SRMD_PREC_F32_KAHAN, SRMD_PREC_F64POS = 0, 1, 2
 CUTOFF = {"trunc": SRMD_CUT_TRUNC, "sp": SRMD_CUT_SP, "sf": SRMD_CUT_SF}
+POTENTIALS = {"yukawa": 2, "buckingham": 3, "gaussian": 4, "dzugutov": 5, "girifalco": 6}
 PRECISION = {"f32": SRMD_PREC_F32, "f32_kahan": SRMD_PREC_F32_KAHAN, "f64pos": SRMD_PREC_F64POS}
 
 
@@ -159,6 +160,8 @@ def load():
         "srmd_set_coulomb_sf": (st, [sysp, _dp, ctypes.c_double]),
         "srmd_set_pair_mie": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+        "srmd_set_pair_potential": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _dp, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int]),
         "srmd_set_integrator_nve": (st, [sysp, ctypes.c_double]),
         "srmd_set_integrator_nvt": (st, [sysp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
@@ -312,6 +315,21 @@ class System:
             for b in range(a, self.ntypes):
                 _check(lib.srmd_set_pair_mie(self._h, a, b, float(A[a, b]), float(B[a, b]), int(m[a, b]),
                                              int(n[a, b]), float(sigma[a, b]), float(rc[a, b]), mth), self._h)
+
+    def set_pairs_potential(self, kind, params, sigma, rc, method):
+        """A further potential (srmd_set_pair_potential) for every type pair: kind a name
+        of POTENTIALS, params ntypes x ntypes x 4, sigma and rc ntypes x ntypes."""
+        lib = load()
+        k = POTENTIALS[kind] if isinstance(kind, str) else int(kind)
+        mth = CUTOFF[method] if isinstance(method, str) else int(method)
+        nt = self.ntypes
+        params = np.asarray(params, np.float64).reshape(nt, nt, 4)
+        sigma, rc = (np.asarray(x, np.float64).reshape(nt, nt) for x in (sigma, rc))
+        for a in range(nt):
+            for b in range(a, nt):
+                p = np.ascontiguousarray(params[a, b])
+                _check(lib.srmd_set_pair_potential(self._h, a, b, k, _ptr(p, _dp), float(sigma[a, b]),
+                                                   float(rc[a, b]), mth), self._h)
 
     def set_coulomb_sf(self, charges, rcut):
         """Shifted-force Coulomb term (paper section 9): one charge per type, one cutoff;
@@ -518,7 +536,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
             "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf",
-            "srmd_set_pair_mie"]
+            "srmd_set_pair_mie", "srmd_set_pair_potential"]
 
 
 def _export_c_names():
