@@ -451,6 +451,21 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
 srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
                             int64_t trace_cap);
 
+/* Choose the batch's thread layout by timing short batched runs from a stored copy
+ * of every replica's state (paper appendix: each trial starts from the same stored
+ * configuration): first the threads per particle shared by all replicas (1, 2, 4,
+ * ... at 256 threads per block, with the appendix's stop rules: three trials in a
+ * row slower than the best, one 5 % slower, or a resource limit), then per replica
+ * size bucket (the replicas in quartiles of their particle count) the threads per
+ * block (64 ... 1024; particles per block = threads / tp), stopping a bucket's loop
+ * 10 % above its best.  The chosen shape becomes every replica's launch shape, as
+ * srmd_set_launch would set it, and the states are put back (the next step rebuilds
+ * the lists).  steps_per_trial >= 1 timed batch steps per trial.  *tp_out (nullable)
+ * receives tp; ppb_out (nullable, count entries) each replica's particles per block.
+ * A batched replica then follows its single-system trajectory at that shape bit for
+ * bit, as at any shape. */
+srmd_status srmd_batch_autotune(srmd_batch *b, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out);
+
 /* Release the batch (not the systems). NULL is a no-op. */
 srmd_status srmd_batch_destroy(srmd_batch *b);
 

@@ -3,6 +3,7 @@
 // and the original-order views of the state.
 #include <algorithm>
 #include <cctype>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -838,6 +839,7 @@ struct srmd_batch {
   hipStream_t stream = nullptr;
   int tp = 0, method = 0;
   size_t lds = 0;
+  int max_wg = 0;                // the caller's workgroup limit (0: none)
   std::string err;
 };
 
@@ -992,6 +994,17 @@ srmd_status batch_plan(srmd_batch *b, int W) {
     e = hipMemcpy(b->d_job_off, b->job_off.data(), sizeof(int) * b->job_off.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) return bfail(b, SRMD_ENOMEM, std::string("batch job tables: ") + hipGetErrorString(e));
   return SRMD_OK;
+}
+
+// Descriptors and workgroup plan of the batch for the systems' current launch shapes
+// (all replicas share b->tp).
+srmd_status batch_replan(srmd_batch *b) {
+  srmd_status st = batch_sync_desc(b);
+  if (st != SRMD_OK) return st;
+  int W = multi_max_groups(b->tp, b->method, false, b->lds);
+  if (b->max_wg > 0) W = std::min(W, b->max_wg);
+  if (W < 1) return bfail(b, SRMD_EUNSUPPORTED, "the persistent kernel does not fit on the device");
+  return batch_plan(b, W);
 }
 
 // Put the call-start snapshot back after a list overflow (cur0: the position
@@ -2673,11 +2686,8 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
     srmd_batch_destroy(b);
     return bfail(nullptr, SRMD_ENOMEM, "batch descriptor allocation failed");
   }
-  srmd_status st = batch_sync_desc(b);
-  int W = multi_max_groups(b->tp, b->method, false, b->lds);
-  if (max_workgroups > 0) W = std::min(W, max_workgroups);
-  if (st == SRMD_OK && W < 1) st = bfail(b, SRMD_EUNSUPPORTED, "the persistent kernel does not fit on the device");
-  if (st == SRMD_OK) st = batch_plan(b, W);
+  b->max_wg = max_workgroups;
+  srmd_status st = batch_replan(b);
   if (st != SRMD_OK) {
     std::string m = b->err;
     srmd_batch_destroy(b);
@@ -2754,6 +2764,112 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
     if (st != SRMD_OK && result == SRMD_OK) result = bfail(b, st, std::string("replica ") + std::to_string(r) + ": " + s->err);
   }
   return result;
+}
+
+srmd_status srmd_batch_autotune(srmd_batch *b, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out) {
+  if (!b) return bfail(nullptr, SRMD_EINVAL, "batch is NULL");
+  if (steps_per_trial < 1) return bfail(b, SRMD_EINVAL, "steps_per_trial must be >= 1");
+  const size_t R = b->sys.size();
+  // the stored configuration every trial starts from (paper appendix)
+  std::vector<HostState> saved(R);
+  for (size_t r = 0; r < R; ++r) {
+    srmd_system *s = b->sys[r];
+    srmd_status st = prepare(s);
+    if (st == SRMD_OK) st = save_host_state(s, &saved[r]);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+  }
+  // replicas in size buckets (quartiles of N): each bucket gets its own block size
+  std::vector<int> order(R);
+  for (size_t r = 0; r < R; ++r) order[r] = (int)r;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->sys[x]->n < b->sys[y]->n; });
+  const int nb = (int)std::min<size_t>(4, R);
+  std::vector<int> bucket(R);
+  for (size_t q = 0; q < R; ++q) bucket[(size_t)order[q]] = (int)(q * (size_t)nb / R);
+  const int kThreads[] = {64, 128, 256, 512, 1024};
+  auto ok_shape = [](int tp, int threads) { return threads % tp == 0 && threads >= tp && threads <= 1024; };
+  // one timed trial: every replica at threads-per-block thr[bucket] and tp, from the stored state
+  auto trial = [&](int tp, const std::vector<int> &thr, double *ms) -> srmd_status {
+    for (size_t r = 0; r < R; ++r) {
+      srmd_system *s = b->sys[r];
+      s->tp_req = tp;
+      s->ppb_req = thr[(size_t)bucket[r]] / tp;
+      s->dirty = true;
+      srmd_status st = restore_host_state(s, saved[r]);
+      if (st == SRMD_OK) st = prepare(s);
+      if (st != SRMD_OK) return bfail(b, st, s->err);
+    }
+    b->tp = tp;
+    srmd_status st = batch_replan(b);
+    if (st == SRMD_EUNSUPPORTED) {  // a resource limit: this shape cannot run
+      *ms = 1e30;
+      return SRMD_OK;
+    }
+    if (st != SRMD_OK) return st;
+    st = srmd_batch_step(b, std::min(steps_per_trial, 50), 0, nullptr, 0);  // first build, untimed
+    if (st != SRMD_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    st = srmd_batch_step(b, steps_per_trial, 0, nullptr, 0);
+    if (st != SRMD_OK) return st;
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / steps_per_trial;
+    return SRMD_OK;
+  };
+  std::vector<int> thr((size_t)nb, 256);
+  int best_tp = 0;
+  double best = 1e30;
+  // t_p from 1 up at 256 threads per block; the appendix's stop rules: three trials in
+  // a row slower than the best, or one 5 % slower, or a resource limit
+  int worse = 0;
+  for (int tp = 1; tp <= 64; tp *= 2) {
+    if (!multi_max_groups(tp, b->method, false, b->lds)) break;
+    double ms;
+    srmd_status st = trial(tp, thr, &ms);
+    if (st != SRMD_OK) return st;
+    if (ms >= 1e30) break;
+    if (ms < best) {
+      best = ms;
+      best_tp = tp;
+      worse = 0;
+    } else if (++worse >= 3 || ms > 1.05 * best) {
+      break;
+    }
+  }
+  if (!best_tp) return bfail(b, SRMD_EUNSUPPORTED, "no thread layout of the batch could run");
+  // threads per block per bucket (the appendix's p_b loop; replicas of one bucket share
+  // it), the rest fixed at their best; a bucket's loop stops 10 % above its best
+  for (int k = 0; k < nb; ++k) {
+    int best_thr = thr[(size_t)k];
+    for (int t : kThreads) {
+      if (t == best_thr || !ok_shape(best_tp, t)) continue;
+      std::vector<int> cand = thr;
+      cand[(size_t)k] = t;
+      double ms;
+      srmd_status st = trial(best_tp, cand, &ms);
+      if (st != SRMD_OK) return st;
+      if (ms < best) {
+        best = ms;
+        best_thr = t;
+      } else if (ms > 1.10 * best && t > best_thr) {
+        break;
+      }
+    }
+    thr[(size_t)k] = best_thr;
+  }
+  // the chosen layout becomes each replica's launch shape; the stored state is put back
+  for (size_t r = 0; r < R; ++r) {
+    srmd_system *s = b->sys[r];
+    s->tp_req = best_tp;
+    s->ppb_req = thr[(size_t)bucket[r]] / best_tp;
+    s->dirty = true;
+    srmd_status st = restore_host_state(s, saved[r]);
+    if (st == SRMD_OK) st = prepare(s);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+    if (ppb_out) ppb_out[r] = s->ppb_req;
+  }
+  b->tp = best_tp;
+  srmd_status st = batch_replan(b);
+  if (st != SRMD_OK) return st;
+  if (tp_out) *tp_out = best_tp;
+  return SRMD_OK;
 }
 
 srmd_status srmd_batch_destroy(srmd_batch *b) {

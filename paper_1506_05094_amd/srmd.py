@@ -173,6 +173,7 @@ def load():
                                            ctypes.c_int32, ctypes.c_int32]),
         "srmd_batch_step": (st, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
         "srmd_batch_destroy": (st, [ctypes.c_void_p]),
+        "srmd_batch_autotune": (st, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip]),
         "srmd_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
         "srmd_autotune": (st, [sysp, ctypes.c_int32, _ip, _ip]),
         "srmd_tuning_key_of": (st, [sysp, ctypes.POINTER(srmd_tuning_key)]),
@@ -506,6 +507,14 @@ class Batch:
         _bcheck(lib.srmd_batch_step(self._h, int(nsteps), 0, None, 0), self._h)
         return None
 
+    def autotune(self, steps_per_trial=200):
+        """srmd_batch_autotune: returns (tp, particles per block of each replica)."""
+        tp = ctypes.c_int32()
+        ppb = np.zeros(len(self.systems), np.int32)
+        _bcheck(load().srmd_batch_autotune(self._h, int(steps_per_trial), ctypes.byref(tp), _ptr(ppb, _ip)),
+                self._h)
+        return tp.value, ppb
+
     def close(self):
         if getattr(self, "_h", None):
             load().srmd_batch_destroy(self._h)
@@ -535,7 +544,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
             "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent",
             "srmd_batch_create", "srmd_batch_create_limited",
-            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf",
+            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_batch_autotune", "srmd_set_coulomb_sf",
             "srmd_set_pair_mie", "srmd_set_pair_potential"]
 
 
