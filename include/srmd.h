@@ -200,6 +200,16 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
  * pairs from its LDS copy of the positions for mode 4. */
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
 
+/* The periodic spatial re-sort of the all-pairs lists (list mode 4 of
+ * srmd_set_rebuild_path; the paper's appendix, step 5, for its n2 method): the
+ * particles keep their order between builds, which loses the locality of the force
+ * kernel's neighbour reads as they diffuse; with builds = k > 0 they are spatially
+ * sorted (as the cell methods sort at every build) before list builds 0, k, 2k, ...
+ * counted from the start of the run.  0 (the default): never.  Other list modes
+ * ignore it.  The result is the same pair set; the order of particles and list
+ * entries (and so the float32 summation order) follows the sort. */
+srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds);
+
 /* Run the steps of a small system as persistent launches (one launch per 500
  * steps) instead of graph-captured launch chains (three launches per step).  Small systems are bound by latency, not by
  * arithmetic (section 3); the paper keeps their whole run on the device without
@@ -274,6 +284,8 @@ typedef struct {
   double tuned_ms_per_step;       /* the chosen parameters (appendix step 7); 0 from the cache */
   int32_t trials;                 /* timed trials run; 0 from the cache */
   int32_t from_cache;             /* 1: read from the cache file, nothing timed */
+  int32_t sort_every;             /* re-sort interval of the all-pairs lists, as srmd_set_sort_interval */
+  int32_t reserved;
 } srmd_tuning;
 
 /* Fill *key with the user parameters of s (integrator and pair potential set).
@@ -304,13 +316,16 @@ srmd_status srmd_tuning_cache_store(const char *path, const srmd_tuning_key *key
  * for each method within 20 % of the fastest, block size x tp with the
  * appendix's stop rules and the skin re-optimised in steps of 10 % from the
  * last optimum at every layout; for systems the persistent kernel can run, the
- * same t_p loop in persistent mode; a final trial of the chosen set.  A skin step
+ * same t_p loop in persistent mode; with the all-pairs lists chosen, the re-sort
+ * interval (srmd_set_sort_interval: never, 64, 16, 4, 1 builds) with a single
+ * minimum (appendix step 5); a final trial of the chosen set.  A skin step
  * multiplies the current value by 1.2 or 0.8 (1.1 or 0.9) and the search
  * goes on in the direction that was faster until a trial is slower; skins that
  * would put r_c + skin past half a box side, or that the chosen list method
  * cannot run, count as slower.  The chosen layout, list method, mode and skin
- * are applied as srmd_set_launch, srmd_set_rebuild_path, srmd_set_persistent
- * and srmd_set_skin would (they override earlier explicit choices), the state
+ * are applied as srmd_set_launch, srmd_set_rebuild_path, srmd_set_persistent,
+ * srmd_set_skin and srmd_set_sort_interval would (they override earlier explicit
+ * choices), the state
  * is restored, and with cache_path non-NULL a record is appended.  out may be NULL. */
 srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const char *cache_path, srmd_tuning *out);
 

@@ -595,6 +595,14 @@ __device__ __forceinline__ void begin_build(Control *ctl) {
   ctl->n_rebuilds += 1;
 }
 
+// All-pairs lists keep the particle order between builds; with sort_every = k > 0
+// the particles are spatially sorted again before builds 0, k, 2k, ... (the
+// periodic re-sort of the paper's n2 method, appendix step 5), counted by the builds
+// so far.
+__device__ __forceinline__ bool resort_due(const SysConst &c, long long builds) {
+  return c.sort_every > 0 && (builds % c.sort_every) == 0;
+}
+
 // The counting sort of large systems (section 7 steps 1-3) in four phases, each a
 // grid-wide pass over particles or cells: bin, scan, scatter, gather.  The launch
 // chain runs them as four kernels; the persistent kernel runs the same functions
@@ -775,6 +783,7 @@ __device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur, u
   if (tid == 0) {
     s_carry = 0u;
     begin_build(p.ctl);
+    p.ctl->resorted = 1;
   }
   unsigned my_cell[PER], my_slot[PER];
   int my_id[PER];
@@ -860,10 +869,18 @@ __device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur, u
 __global__ __launch_bounds__(1024) void k_sort_small(SysConst c, SysPtrs p, int cur) {
   __shared__ unsigned s_cnt[kSmallCells + 1];
   __shared__ int s_id[kSmallN];
+  __shared__ int s_due;
   if (p.ctl->rebuild == 0) return;
-  if (c.list_kind == 4) {  // all-pairs lists need no sort, only the build counters reset
-    if (threadIdx.x == 0) begin_build(p.ctl);
-    return;
+  if (c.list_kind == 4) {  // all-pairs lists sort only when a periodic re-sort is due
+    if (threadIdx.x == 0) s_due = resort_due(c, p.ctl->n_rebuilds) ? 1 : 0;
+    __syncthreads();
+    if (!s_due) {
+      if (threadIdx.x == 0) {
+        begin_build(p.ctl);
+        p.ctl->resorted = 0;
+      }
+      return;
+    }
   }
   sort_small_block<1024>(c, p, cur, s_cnt, s_id);
 }
@@ -1028,8 +1045,8 @@ __device__ int list_allpairs_one(const SysConst &c, const SysPtrs &p, int i, con
   return kept;
 }
 
-// All-pairs lists for the launch chain, one wave per particle, four per block;
-// the particles keep their order (no sort).
+// All-pairs lists for the launch chain, one wave per particle, four per block; the
+// particles keep their order unless a periodic re-sort ran before this build.
 __global__ __launch_bounds__(256) void k_list_allpairs(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
@@ -1037,9 +1054,14 @@ __global__ __launch_bounds__(256) void k_list_allpairs(SysConst c, SysPtrs p, in
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+  // after a periodic re-sort the candidates come from the sorted copy, and each wave
+  // moves its own particle's slot into place
+  const bool resorted = p.ctl->resorted != 0;
+  const float4 *src = resorted ? p.t_pos : p.pos[cur];
   int kept = 0, longest = 0;
   if (t < c.n) {  // uniform across the wave
-    const int k = list_allpairs_one(c, p, t, s_cs2, p.pos[cur], longest);
+    if (resorted && lane == 0) place_sorted(p, cur, t, src[t]);
+    const int k = list_allpairs_one(c, p, t, s_cs2, src, longest);
     if (lane == 0) kept = k;
   }
   list_tally(kept, longest, c.n_max, p.ctl);
@@ -1589,7 +1611,7 @@ __device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockParti
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, int next) {
   __shared__ BlockPartial s_waves[16];
-  __shared__ int s_rebuild;
+  __shared__ int s_rebuild, s_due;
   __shared__ unsigned s_cnt[MODE == 0 ? kSmallCells + 1 : 1];
   __shared__ int s_id[MODE == 0 ? kSmallN : 1];
   // the control words are final (the kernels before this one in the stream wrote
@@ -1630,13 +1652,17 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
       if (a.nonfinite) ctl->error |= 1;
     } else {
       rebuild = finish_step(c, p, a, cv);
+      s_due = resort_due(c, cv.n_rebuilds) ? 1 : 0;
     }
     s_rebuild = rebuild;
   }
   __syncthreads();
   if (MODE == 0 && s_rebuild && c.small_sort) {
-    if (c.list_kind == 4) {
-      if (threadIdx.x == 0) begin_build(p.ctl);
+    if (c.list_kind == 4 && !s_due) {
+      if (threadIdx.x == 0) {
+        begin_build(p.ctl);
+        p.ctl->resorted = 0;
+      }
     } else {
       sort_small_block<1024>(c, p, next, s_cnt, s_id);
     }
@@ -1816,8 +1842,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
   __shared__ BlockPartial s_waves[16];
   __shared__ BlockPartial s_wp[kLdsUnits];
   __shared__ float s_cs2[kMaxPairs];
-  __shared__ int s_ok, s_any, s_bit;
-  __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs];
+  __shared__ int s_ok, s_any, s_bit, s_due;
+  __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs], s_resorted[kMaxJobs];
   __shared__ unsigned s_k[kMaxJobs];
   __shared__ double s_xi[kMaxJobs];
   __shared__ unsigned s_scan[16];
@@ -1830,6 +1856,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
     const ReplicaDesc &R = reps[J.rep];
     if (tid == 0) {
       s_rebuild[j] = R.p.ctl->rebuild;
+      s_resorted[j] = R.p.ctl->resorted;
       s_xi[j] = R.c.thermostat ? R.p.ctl->xi : 0.0;
       s_cur[j] = R.cur;
       s_k[j] = 1u;
@@ -1868,8 +1895,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
       if (!BIG && rebuild && c.list_kind == 4) {
-        // all pairs from the positions of the step in LDS; no sort, no cells
-        fill_positions(s_dyn, p.pos[cur], c.n);
+        // all pairs from the positions of the step in LDS, no cells; after a periodic
+        // re-sort from the sorted copy, with this piece's slots moved into place
+        const bool resorted = s_resorted[j] != 0;
+        fill_positions(s_dyn, resorted ? p.t_pos : p.pos[cur], c.n);
+        if (resorted)
+          for (int t = J.w * kBatchThreads + tid; t < c.n; t += J.g * kBatchThreads)
+            place_sorted(p, cur, t, gload(p.t_pos, t));
         __syncthreads();
         int kept = 0, longest = 0;
         for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves) {
@@ -2036,7 +2068,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         for (int q = 1; q < used; ++q) fold(a, s_waves[q]);
         a.t0 = 0ull;
         a.t1 = 0ull;
-        if (J.w == 0) finish_step(c, p, a, cv);  // the one writer of the control block
+        if (J.w == 0) {
+          finish_step(c, p, a, cv);  // the one writer of the control block
+          s_due = resort_due(c, cv.n_rebuilds) ? 1 : 0;
+        }
         if (c.thermostat) s_xi[j] = xi_next(c, xi, a.ke_half);
         s_rebuild[j] = s_any;  // = (max displacement^2 > (skin/2)^2), as finish_step decides
       }
@@ -2045,14 +2080,21 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       if (!BIG && s_rebuild[j]) {
         // spatial sort of the new positions by piece 0, as k_finish does
         if (J.w == 0) {
-          if (c.list_kind == 4) {  // all-pairs lists need no sort
-            if (tid == 0) begin_build(p.ctl);
+          if (c.list_kind == 4 && !s_due) {  // all-pairs lists sort only when a re-sort is due
+            if (tid == 0) {
+              begin_build(p.ctl);
+              p.ctl->resorted = 0;
+            }
           } else {
             unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
             sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
           }
         }
-        if (step + 1 < nsteps && !coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+        // every piece learns whether the build ahead starts from a re-sort (its
+        // decision depends on the build count, which piece 0 holds)
+        if (step + 1 < nsteps && !coop_barrier(p.bar_flags, J.g, J.w, ++k, J.w == 0 ? s_due : 0, p.ctl, &s_ok, &s_any))
+          return;
+        if (tid == 0) s_resorted[j] = c.list_kind == 4 ? s_any : 1;
       }
       if (tid == 0) {
         s_cur[j] = cur;

@@ -89,6 +89,7 @@ struct srmd_system {
   int tp_req = 0, ppb_req = 0, tp = 0, ppb = 0;
   int tp_tuned = 0, ppb_tuned = 0;
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
+  int sort_every = 0;                // all-pairs lists: spatial sort at every k-th build (0: never)
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -390,6 +391,7 @@ srmd_status fill_const(srmd_system *s) {
                                 "with the one-workgroup sort mode");
   c.list_blocks = std::max(1, std::min((s->n + 255) / 256, 2048));
   c.pot_kind = s->pot >= 2 ? s->pot : 0;
+  c.sort_every = c.list_kind == 4 ? s->sort_every : 0;
   // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
   const double rho = s->n / V;
   int nmax = (int)std::ceil(1.5 * 4.0 / 3.0 * M_PI * reach * reach * reach * rho + 32.0);
@@ -1395,6 +1397,14 @@ srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t lis
   return SRMD_OK;
 }
 
+srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (builds < 0) return fail(s, SRMD_EINVAL, "the sort interval must be >= 0");
+  s->sort_every = builds;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
 srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
   int a, b;
@@ -2089,10 +2099,10 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
 
 // ---------------------------------------------------------------------------
 // Tuned-parameter file (paper appendix, step 8).  One text line per record:
-//   srmd-tuning-v2 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
+//   srmd-tuning-v3 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
 //   count=<c_0,...> dt=<x> temperature=<x> density=<x> sigma=<k*k values>
 //   epsilon=<k*k values> rcut=<k*k values> potential=<n> param=<4*k*k values>
-//   charge=<k values> rcc=<x> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x>
+//   charge=<k values> rcc=<x> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x> sort=<n>
 // (records of another version are skipped)
 // Floating-point fields are printed with 17 significant digits, so they read back
 // to the same double.
@@ -2100,7 +2110,7 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
 
 namespace {
 
-constexpr const char *kTuneTag = "srmd-tuning-v2";
+constexpr const char *kTuneTag = "srmd-tuning-v3";
 constexpr double kTuneRelTol = 1e-6;   // dt, density and pair parameters
 constexpr double kTuneTempTol = 0.02;  // temperature
 
@@ -2119,7 +2129,7 @@ bool tuning_valid(const srmd_tuning &t) {
   const bool tp_ok = t.tp >= 1 && t.tp <= 64 && (t.tp & (t.tp - 1)) == 0;
   const bool ppb_ok = t.ppb >= 1 && (long long)t.tp * t.ppb <= 1024 && (t.tp * t.ppb) % 64 == 0;
   return tp_ok && ppb_ok && t.list_mode >= 1 && t.list_mode <= 4 && (t.persistent == 0 || t.persistent == -1) &&
-         t.skin >= 0 && std::isfinite(t.skin);
+         t.skin >= 0 && std::isfinite(t.skin) && t.sort_every >= 0;
 }
 
 bool key_match(const srmd_tuning_key &a, const srmd_tuning_key &b) {
@@ -2186,6 +2196,7 @@ std::string tuning_line(const srmd_tuning_key &k, const srmd_tuning &t) {
   field("list", std::to_string(t.list_mode));
   field("persistent", std::to_string(t.persistent));
   field("skin", num(t.skin));
+  field("sort", std::to_string(t.sort_every));
   return o;
 }
 
@@ -2276,8 +2287,9 @@ bool parse_tuning_line(const std::string &line, srmd_tuning_key *k, srmd_tuning 
     k->potential = (int32_t)v[0];
   }
   if (!one_int("tp", &v[0]) || !one_int("ppb", &v[1]) || !one_int("list", &v[2]) || !one_int("persistent", &v[3]) ||
-      !one_num("skin", &t->skin))
+      !one_num("skin", &t->skin) || !one_int("sort", &v[4]) || v[4] < 0 || v[4] > (1 << 20))
     return false;
+  t->sort_every = (int32_t)v[4];
   for (int q = 0; q < 4; ++q)
     if (v[q] < -1 || v[q] > 1024) return false;
   t->tp = (int32_t)v[0];
@@ -2403,6 +2415,7 @@ void apply_tuning(srmd_system *s, const srmd_tuning &t) {
   s->persist_req = t.persistent;
   s->persist_set = true;
   s->skin = t.skin;
+  s->sort_every = t.sort_every;
   s->dirty = true;
 }
 
@@ -2463,7 +2476,9 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
   const bool pset0 = s->persist_set;
   const int nmax0 = s->n_max;
   const double skin0 = s->skin;
+  const int sort0 = s->sort_every;
   const bool persist0 = pset0 ? preq0 != 0 : s->persist_tuned != 0;
+  int sort_trial = sort0;  // the re-sort interval of the all-pairs lists in the trials
   hipEvent_t e0, e1;
   HIPCHK(s, hipEventCreate(&e0));
   HIPCHK(s, hipEventCreate(&e1));
@@ -2480,6 +2495,7 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
     s->persist_set = true;
     s->persist_req = persistent ? -1 : 0;
     s->skin = skin;
+    s->sort_every = sort_trial;
     s->n_max = nmax0;  // the list capacity follows the trial's skin
     s->dirty = true;
     srmd_status r = restore_host_state(s, saved);
@@ -2617,6 +2633,26 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
       if (slower >= 3 || t > 1.05 * pbest) break;
     }
   }
+  // step 5: with the all-pairs lists chosen, the interval of their periodic spatial
+  // re-sort (in list builds; 0: never), a single minimum from the longest interval down
+  best.sort_every = sort0;
+  if (result == SRMD_OK && best_t < 1e30 && best.list_mode == 4) {
+    const int intervals[] = {0, 64, 16, 4, 1};
+    for (int q = 0; q < 5 && result == SRMD_OK; ++q) {
+      if (intervals[q] == best.sort_every) continue;
+      sort_trial = intervals[q];
+      double t;
+      result = trial(best.tp, best.ppb, 4, best.persistent != 0, best.skin, &t);
+      if (result != SRMD_OK) break;
+      if (t < best_t) {
+        best_t = t;
+        best.sort_every = intervals[q];
+      } else if (intervals[q] < best.sort_every || best.sort_every == 0) {
+        if (q > 1) break;  // past the minimum
+      }
+    }
+    sort_trial = best.sort_every;
+  }
   // step 7: the chosen set, timed as the baseline was
   double t_final = 1e30;
   if (result == SRMD_OK && best_t < 1e30)
@@ -2629,6 +2665,7 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
   s->persist_req = preq0;
   s->persist_set = pset0;
   s->skin = skin0;
+  s->sort_every = sort0;
   s->n_max = nmax0;
   if (result == SRMD_OK && !(best_t < 1e30)) result = fail(s, SRMD_ESTATE, "no trial of the autotuner completed");
   if (result == SRMD_OK) apply_tuning(s, best);

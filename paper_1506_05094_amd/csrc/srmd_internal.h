@@ -71,6 +71,8 @@ struct SysConst {
   int list_kind;     // list builder of the launch chain: 1 wave per particle, 2 thread per particle, 3 wave per cell
   int list_blocks;   // grid of the thread-per-particle list build and the sort kernels
   int pot_kind;      // kernel method 5: 2 Yukawa, 3 Buckingham, 4 Gaussian core, 5 Dzugutov, 6 Girifalco
+  int sort_every;    // all-pairs lists (list_kind 4): spatial sort at every k-th build (0: never)
+  int pad1;
   float inv_mass[kMaxTypes];
   double mass[kMaxTypes];
   PairTable pt;
@@ -92,7 +94,8 @@ struct Control {
   double xi_int;           // its time integral
   unsigned long long prof_ticks;  // accumulated step-kernel durations (device clock ticks)
   long long prof_count;           // step kernels accumulated
-  int pad[42];
+  int resorted;                   // all-pairs lists: the build ahead starts from a fresh spatial sort
+  int pad[41];
 };
 
 static_assert(sizeof(Control) == 256, "control block layout");

@@ -97,7 +97,8 @@ class srmd_tuning(ctypes.Structure):
     _fields_ = [("tp", ctypes.c_int32), ("ppb", ctypes.c_int32), ("list_mode", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("skin", ctypes.c_double),
                 ("baseline_ms_per_step", ctypes.c_double), ("tuned_ms_per_step", ctypes.c_double),
-                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("sort_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -168,6 +169,7 @@ def load():
         "srmd_get_launch": (st, [sysp, _ip, _ip]),
         "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_set_persistent": (st, [sysp, ctypes.c_int32]),
+        "srmd_set_sort_interval": (st, [sysp, ctypes.c_int32]),
         "srmd_batch_create": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
         "srmd_batch_create_limited": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.c_int32, ctypes.c_int32]),
@@ -358,6 +360,10 @@ class System:
         systems, no sort).  Every mode gives the same pair set."""
         _check(load().srmd_set_rebuild_path(self._h, int(sort_mode), int(list_mode)), self._h)
 
+    def set_sort_interval(self, builds):
+        """All-pairs lists: spatial re-sort before every builds-th list build (0: never)."""
+        _check(load().srmd_set_sort_interval(self._h, int(builds)), self._h)
+
     def set_persistent(self, groups=-1):
         """Run steps as persistent launches of 500 steps each (groups > 0 workgroups,
         or -1 for the library's choice); 0 returns to graph-captured launch chains."""
@@ -542,7 +548,7 @@ EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_
             "srmd_autotune", "srmd_tuning_key_of", "srmd_tuning_cache_find", "srmd_tuning_cache_store",
             "srmd_autotune_full", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
             "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent",
+            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent", "srmd_set_sort_interval",
             "srmd_batch_create", "srmd_batch_create_limited",
             "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_batch_autotune", "srmd_set_coulomb_sf",
             "srmd_set_pair_mie", "srmd_set_pair_potential"]
