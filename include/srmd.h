@@ -82,7 +82,8 @@ typedef struct {
 } srmd_thermo;
 
 /* Create a system of n >= 2 particles of ntypes types (1..4) in an orthorhombic
- * periodic box.  pos: host float32 n*3 (x,y,z per particle), wrapped into
+ * periodic box (paper section 2 figure of the Python interface: a simulation object
+ * made from a configuration of particle positions, types and box).  pos: host float32 n*3 (x,y,z per particle), wrapped into
  * [-L/2, L/2) on entry.  type: host int32 n, each in [0, ntypes).  vel: host float32
  * n*3 read as v(-dt/2), or NULL for zero.  mass: host float64 per type, or NULL for
  * unit masses.  hip_stream: a hipStream_t to enqueue on, or NULL for a stream the
@@ -171,11 +172,15 @@ srmd_status srmd_set_coulomb_sf(srmd_system *s, const double *charge, double rcu
  * build (section 6).  Default 0.3. */
 srmd_status srmd_set_skin(srmd_system *s, double skin);
 
-/* Leapfrog NVE with time step dt > 0. */
+/* Leapfrog NVE with time step dt > 0 (paper section 2, integrators: NVE Verlet /
+ * leap-frog; velocities are half-step velocities v(n - 1/2)). */
 srmd_status srmd_set_integrator_nve(srmd_system *s, double dt);
 
-/* Nose-Hoover NVT leapfrog: time step dt > 0, target temperature T0 > 0,
- * thermostat relaxation time tau > 0 (mass Q = g T0 tau^2, g = 3N - 3). */
+/* Nose-Hoover NVT leapfrog (paper section 2, integrators: NVT Nose-Hoover; the
+ * example's IntegratorNVT(timeStep, targetTemperature)): time step dt > 0, target
+ * temperature T0 > 0, thermostat relaxation time tau > 0 (mass Q = g T0 tau^2,
+ * g = 3N - 3; the paper gives no discretisation: v(n+1/2) = [v(n-1/2)(1 - xi dt/2)
+ * + F/m dt] / (1 + xi dt/2), xi(n+1) = xi(n) + dt (T(n+1/2)/T0 - 1) / tau^2). */
 srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double tau);
 
 /* Thread layout of the force kernel (paper section 4 table of code conventions):
@@ -329,23 +334,33 @@ srmd_status srmd_tuning_cache_store(const char *path, const srmd_tuning_key *key
  * is restored, and with cache_path non-NULL a record is appended.  out may be NULL. */
 srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const char *cache_path, srmd_tuning *out);
 
-/* Bin, sort and rebuild the neighbour list now, whatever the displacement. */
+/* Bin, sort and rebuild the neighbour list now, whatever the displacement (paper
+ * section 7: cell index of every particle, sort and rearrangement of all particle
+ * data by cell, then the list of every particle from its neighbouring cells within
+ * r_c + skin; section 6 for the all-pairs method of list mode 4). */
 srmd_status srmd_build_neighbor_list(srmd_system *s);
 
-/* Forces, potential energy and virial at the current positions (no time step).
+/* Forces, potential energy and virial at the current positions (no time step;
+ * paper section 5, the force kernel figure: each particle's force and half its pair
+ * energies summed over its list, t_p threads per particle).
  * The list is rebuilt first if the displacement criterion or a parameter change
  * asks for it.  out (nullable) receives pe and virial; its other fields describe
  * the current velocities. */
 srmd_status srmd_compute_forces(srmd_system *s, srmd_thermo *out);
 
-/* Advance nsteps time steps.  If thermo_every > 0, the record of every step n with
+/* Advance nsteps time steps (paper section 2 example: Run(nsteps); each step checks
+ * the displacement since the last build and rebuilds the list on the device when a
+ * particle moved more than half the skin, section 6, then forces, section 5, and
+ * the integrator).  If thermo_every > 0, the record of every step n with
  * n % thermo_every == 0 is written to trace (caller-owned, trace_cap entries; extra
  * records are dropped).  Synchronises once at the end.  Returns SRMD_ESTATE if a
  * non-finite force or position appeared. */
 srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
                       int64_t trace_cap);
 
-/* Copy the state to host arrays in original particle order; each pointer may be NULL.
+/* Copy the state to host arrays in original particle order (the paper's sort
+ * rearranges all particle data on the device, section 7; the original order is
+ * restored here); each pointer may be NULL.
  * pos, vel, force: float32 n*3; image: int32 n*3 (box crossings); pos64: float64 n*3
  * (the float64 master positions in the F64POS variant, else the float32 positions
  * widened). force holds the forces of the last force evaluation. */
@@ -389,7 +404,9 @@ srmd_status srmd_save_state(srmd_system *s, void *buf, size_t bytes, size_t *nee
  * integrator and pair potential are those set on s.  Sticky error bits clear. */
 srmd_status srmd_load_state(srmd_system *s, const void *buf, size_t bytes);
 
-/* The neighbour list as (id_i, id_j) pairs in original ids, lexicographically sorted.
+/* The neighbour list (paper sections 4, 6 and 7: every j within r_c,ij + skin of i,
+ * both directions, strict less-than) as (id_i, id_j) pairs in original ids,
+ * lexicographically sorted (the list order itself is not specified by the paper).
  * pairs holds 2*cap int32; *count receives the total number of pairs (the call fails
  * with SRMD_EINVAL, writing nothing, when cap is too small). */
 srmd_status srmd_get_neighbor_pairs(srmd_system *s, int32_t *pairs, int64_t cap, int64_t *count);

@@ -136,7 +136,9 @@ srmd_status fail(srmd_system *s, srmd_status st, const std::string &msg) {
       return fail((s), SRMD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));                 \
   } while (0)
 
-void *dev_alloc(srmd_system *s, size_t bytes) {
+// One device buffer from the allocator hook in force (hipMalloc without one); the
+// buffer remembers how it was made so that it is released the same way.
+DevBuf raw_alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   DevBuf b;
   b.bytes = bytes;
@@ -146,6 +148,21 @@ void *dev_alloc(srmd_system *s, size_t bytes) {
   } else {
     if (hipMalloc(&b.ptr, bytes) != hipSuccess) b.ptr = nullptr;
   }
+  return b;
+}
+
+void raw_free(DevBuf &b) {
+  if (b.ptr) {
+    if (b.how.free_fn)
+      b.how.free_fn(b.ptr, b.how.ctx);
+    else if (!b.how.alloc)
+      (void)hipFree(b.ptr);
+  }
+  b = DevBuf{};
+}
+
+void *dev_alloc(srmd_system *s, size_t bytes) {
+  DevBuf b = raw_alloc(bytes);
   if (!b.ptr) return nullptr;
   s->bufs.push_back(b);
   return b.ptr;
@@ -155,11 +172,7 @@ void dev_free(srmd_system *s, void *ptr) {
   if (!ptr) return;
   for (size_t k = 0; k < s->bufs.size(); ++k) {
     if (s->bufs[k].ptr == ptr) {
-      const DevBuf b = s->bufs[k];
-      if (b.how.free_fn)
-        b.how.free_fn(b.ptr, b.how.ctx);
-      else if (!b.how.alloc)
-        (void)hipFree(b.ptr);
+      raw_free(s->bufs[k]);
       s->bufs.erase(s->bufs.begin() + (long)k);
       return;
     }
@@ -831,6 +844,7 @@ struct srmd_batch {
   std::vector<srmd_system *> sys;
   std::vector<ReplicaDesc> host_desc;
   ReplicaDesc *d_desc = nullptr;
+  DevBuf desc_buf, jobs_buf, joboff_buf;  // device tables, from the allocator hook
   std::vector<CoopJob> jobs;     // per workgroup, in replica order
   std::vector<int> job_off;      // workgroup b runs jobs[job_off[b] .. job_off[b + 1])
   std::vector<int> pieces;       // workgroups of each replica
@@ -988,13 +1002,24 @@ srmd_status batch_plan(srmd_batch *b, int W) {
     b->job_off.push_back((int)b->jobs.size());
   }
   b->nwg = (int)per.size();
-  hipError_t e = hipMalloc(&b->d_jobs, sizeof(CoopJob) * b->jobs.size());
-  if (e == hipSuccess) e = hipMalloc(&b->d_job_off, sizeof(int) * b->job_off.size());
+  // the tables of an earlier plan are released once no launch can still read them
+  if (b->jobs_buf.ptr || b->joboff_buf.ptr) {
+    (void)hipStreamSynchronize(b->stream);
+    raw_free(b->jobs_buf);
+    raw_free(b->joboff_buf);
+  }
+  b->jobs_buf = raw_alloc(sizeof(CoopJob) * b->jobs.size());
+  b->joboff_buf = raw_alloc(sizeof(int) * b->job_off.size());
+  b->d_jobs = (CoopJob *)b->jobs_buf.ptr;
+  b->d_job_off = (int *)b->joboff_buf.ptr;
+  if (!b->d_jobs || !b->d_job_off) return bfail(b, SRMD_ENOMEM, "batch job tables: allocation failed");
+  hipError_t e = hipMemcpyAsync(b->d_jobs, b->jobs.data(), sizeof(CoopJob) * b->jobs.size(), hipMemcpyHostToDevice,
+                                b->stream);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(CoopJob) * b->jobs.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_job_off, b->job_off.data(), sizeof(int) * b->job_off.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bfail(b, SRMD_ENOMEM, std::string("batch job tables: ") + hipGetErrorString(e));
+    e = hipMemcpyAsync(b->d_job_off, b->job_off.data(), sizeof(int) * b->job_off.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("batch job tables: ") + hipGetErrorString(e));
   return SRMD_OK;
 }
 
@@ -2719,7 +2744,9 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
   b->lds = batch_lds_bytes(nmax);
   b->host_desc.assign((size_t)count, ReplicaDesc{});
   std::memset(b->host_desc.data(), 0xff, sizeof(ReplicaDesc) * (size_t)count);  // forces the first upload
-  if (hipMalloc(&b->d_desc, sizeof(ReplicaDesc) * (size_t)count) != hipSuccess) {
+  b->desc_buf = raw_alloc(sizeof(ReplicaDesc) * (size_t)count);
+  b->d_desc = (ReplicaDesc *)b->desc_buf.ptr;
+  if (!b->d_desc) {
     srmd_batch_destroy(b);
     return bfail(nullptr, SRMD_ENOMEM, "batch descriptor allocation failed");
   }
@@ -2912,9 +2939,9 @@ srmd_status srmd_batch_autotune(srmd_batch *b, int32_t steps_per_trial, int32_t 
 srmd_status srmd_batch_destroy(srmd_batch *b) {
   if (!b) return SRMD_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  if (b->d_desc) (void)hipFree(b->d_desc);
-  if (b->d_jobs) (void)hipFree(b->d_jobs);
-  if (b->d_job_off) (void)hipFree(b->d_job_off);
+  raw_free(b->desc_buf);
+  raw_free(b->jobs_buf);
+  raw_free(b->joboff_buf);
   delete b;
   return SRMD_OK;
 }

@@ -543,15 +543,16 @@ class Batch:
         self.close()
 
 
-EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_lj", "srmd_set_skin",
-            "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
-            "srmd_autotune", "srmd_tuning_key_of", "srmd_tuning_cache_find", "srmd_tuning_cache_store",
-            "srmd_autotune_full", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
-            "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_set_rebuild_path", "srmd_set_persistent", "srmd_set_sort_interval",
-            "srmd_batch_create", "srmd_batch_create_limited",
-            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_batch_autotune", "srmd_set_coulomb_sf",
-            "srmd_set_pair_mie", "srmd_set_pair_potential"]
+EXPORTED = ["srmd_autotune", "srmd_autotune_full", "srmd_batch_autotune", "srmd_batch_create",
+            "srmd_batch_create_limited", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_batch_step",
+            "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_create", "srmd_destroy", "srmd_get_box",
+            "srmd_get_launch", "srmd_get_neighbor_pairs", "srmd_get_particle_terms", "srmd_get_state",
+            "srmd_get_stats", "srmd_get_thermo", "srmd_last_error", "srmd_load_state",
+            "srmd_profile_step_kernel", "srmd_save_state", "srmd_set_allocator", "srmd_set_coulomb_sf",
+            "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_set_pair_lj",
+            "srmd_set_pair_mie", "srmd_set_pair_potential", "srmd_set_persistent", "srmd_set_rebuild_path",
+            "srmd_set_skin", "srmd_set_sort_interval", "srmd_set_state", "srmd_step", "srmd_tuning_cache_find",
+            "srmd_tuning_cache_store", "srmd_tuning_key_of"]
 
 
 def _export_c_names():
