@@ -82,7 +82,8 @@ typedef struct {
 } srmd_thermo;
 
 /* Create a system of n >= 2 particles of ntypes types (1..4) in an orthorhombic
- * periodic box.  pos: host float32 n*3 (x,y,z per particle), wrapped into
+ * periodic box (paper section 2 figure of the Python interface: a simulation object
+ * made from a configuration of particle positions, types and box).  pos: host float32 n*3 (x,y,z per particle), wrapped into
  * [-L/2, L/2) on entry.  type: host int32 n, each in [0, ntypes).  vel: host float32
  * n*3 read as v(-dt/2), or NULL for zero.  mass: host float64 per type, or NULL for
  * unit masses.  hip_stream: a hipStream_t to enqueue on, or NULL for a stream the
@@ -121,6 +122,40 @@ srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigm
 srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, double B, int32_t m, int32_t n,
                               double sigma, double rcut, srmd_cutoff method);
 
+/* Further pair potentials among those paper section 2 lists by name; the library
+ * takes their textbook forms (x = r / sigma):
+ *   SRMD_POT_YUKAWA         U = eps (sigma/r) exp(-kappa (r - sigma)),  params {eps, kappa},
+ *                           kappa >= 0, kappa sigma <= 60 (screened Coulomb);
+ *   SRMD_POT_BUCKINGHAM     U = A exp(-r/rho) - C / r^6,  params {A, rho, C}, A, C >= 0,
+ *                           rho > 0 (sigma unused but must be positive);
+ *   SRMD_POT_GAUSSIAN_CORE  U = eps exp(-x^2),  params {eps};
+ *   SRMD_POT_DZUGUTOV       U = eps [5.82 (x^-16 - 1.28) exp(1.1/(x - 1.87)) for x < 1.87
+ *                           + 1.28 exp(0.27/(x - 1.94)) for x < 1.94],  params {eps}
+ *                           (smoothly zero from 1.94 sigma on: rcut = 1.94 sigma is natural);
+ *   SRMD_POT_GIRIFALCO      U = -alpha [1/(x(x-1)^3) + 1/(x(x+1)^3) - 2/x^4]
+ *                           + beta [1/(x(x-1)^9) + 1/(x(x+1)^9) - 2/x^10],  params {alpha, beta},
+ *                           sigma = the sphere diameter, rcut > sigma.
+ * Unused params entries are ignored.  Pair forces are evaluated in float32 on the
+ * device (exp from the device library); energy sums in float64. */
+typedef enum {
+  SRMD_POT_YUKAWA = 2,
+  SRMD_POT_BUCKINGHAM = 3,
+  SRMD_POT_GAUSSIAN_CORE = 4,
+  SRMD_POT_DZUGUTOV = 5,
+  SRMD_POT_GIRIFALCO = 6
+} srmd_potential;
+
+/* One of the further potentials between types ti and tj (symmetric) in place of
+ * Lennard-Jones: params holds 4 doubles (host; see srmd_potential), modified by the
+ * cutoff method as srmd_set_pair_lj (paper section 2 cutoff methods: the shifts use
+ * the potential's own U(rcut) and F(rcut)).  All type pairs of a system use one
+ * potential kind and one method (mixing kinds, or with srmd_set_pair_lj /
+ * srmd_set_pair_mie: SRMD_EINVAL).  The Coulomb term does not combine with it
+ * (SRMD_EUNSUPPORTED at the next step).  rcut + skin must stay below half of every
+ * box side. */
+srmd_status srmd_set_pair_potential(srmd_system *s, int32_t ti, int32_t tj, srmd_potential kind,
+                                    const double *params, double sigma, double rcut, srmd_cutoff method);
+
 /* Coulomb interactions with a shifted-force cutoff (paper section 9, the molten
  * salt benchmark): charge[t] per type (host array of ntypes doubles, reduced units
  * in which the Coulomb constant is one), one cutoff rcut > 0 for every type pair.
@@ -137,11 +172,15 @@ srmd_status srmd_set_coulomb_sf(srmd_system *s, const double *charge, double rcu
  * build (section 6).  Default 0.3. */
 srmd_status srmd_set_skin(srmd_system *s, double skin);
 
-/* Leapfrog NVE with time step dt > 0. */
+/* Leapfrog NVE with time step dt > 0 (paper section 2, integrators: NVE Verlet /
+ * leap-frog; velocities are half-step velocities v(n - 1/2)). */
 srmd_status srmd_set_integrator_nve(srmd_system *s, double dt);
 
-/* Nose-Hoover NVT leapfrog: time step dt > 0, target temperature T0 > 0,
- * thermostat relaxation time tau > 0 (mass Q = g T0 tau^2, g = 3N - 3). */
+/* Nose-Hoover NVT leapfrog (paper section 2, integrators: NVT Nose-Hoover; the
+ * example's IntegratorNVT(timeStep, targetTemperature)): time step dt > 0, target
+ * temperature T0 > 0, thermostat relaxation time tau > 0 (mass Q = g T0 tau^2,
+ * g = 3N - 3; the paper gives no discretisation: v(n+1/2) = [v(n-1/2)(1 - xi dt/2)
+ * + F/m dt] / (1 + xi dt/2), xi(n+1) = xi(n) + dt (T(n+1/2)/T0 - 1) / tau^2). */
 srmd_status srmd_set_integrator_nvt(srmd_system *s, double dt, double T0, double tau);
 
 /* Thread layout of the force kernel (paper section 4 table of code conventions):
@@ -165,6 +204,16 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
  * persistent kernel builds one wave per particle or per cell for modes 1-3, and all
  * pairs from its LDS copy of the positions for mode 4. */
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
+
+/* The periodic spatial re-sort of the all-pairs lists (list mode 4 of
+ * srmd_set_rebuild_path; the paper's appendix, step 5, for its n2 method): the
+ * particles keep their order between builds, which loses the locality of the force
+ * kernel's neighbour reads as they diffuse; with builds = k > 0 they are spatially
+ * sorted (as the cell methods sort at every build) before list builds 0, k, 2k, ...
+ * counted from the start of the run.  0 (the default): never.  Other list modes
+ * ignore it.  The result is the same pair set; the order of particles and list
+ * entries (and so the float32 summation order) follows the sort. */
+srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds);
 
 /* Run the steps of a small system as persistent launches (one launch per 500
  * steps) instead of graph-captured launch chains (three launches per step).  Small systems are bound by latency, not by
@@ -211,7 +260,8 @@ typedef struct {
   char gpu[64];          /* device architecture name (hipDeviceProp_t::gcnArchName) */
   int32_t compute_units; /* of that device */
   int32_t precision;     /* srmd_precision */
-  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term, 4 two-power potential */
+  int32_t cutoff_method; /* srmd_cutoff; 3 with the shifted-force Coulomb term, 4 two-power potential,
+                            5 an srmd_potential (its kind in potential) */
   int32_t thermostat;    /* 0 NVE, 1 Nose-Hoover NVT */
   int32_t ntypes;
   int32_t reserved;
@@ -220,10 +270,11 @@ typedef struct {
   double temperature;    /* T0 under NVT; under NVE the kinetic temperature 2 KE / (3N - 3) of the state */
   double dt;
   double sigma[16], epsilon[16], rcut[16];
-  int32_t potential;        /* 0 12-6 Lennard-Jones, 1 the two-power potential */
+  int32_t potential;        /* 0 12-6 Lennard-Jones, 1 the two-power potential, 2..6 srmd_potential */
   int32_t reserved2;
   double pot_param[16][4];  /* per type pair, the potential's parameters besides sigma and rcut
-                               (two-power: A, B, m, n); zero for Lennard-Jones */
+                               (two-power: A, B, m, n; srmd_potential: its params); zero for
+                               Lennard-Jones */
   double charge[4];         /* Coulomb charges per type (zero without the Coulomb term) */
   double rc_coulomb;        /* Coulomb cutoff (zero without the term) */
 } srmd_tuning_key;
@@ -238,6 +289,8 @@ typedef struct {
   double tuned_ms_per_step;       /* the chosen parameters (appendix step 7); 0 from the cache */
   int32_t trials;                 /* timed trials run; 0 from the cache */
   int32_t from_cache;             /* 1: read from the cache file, nothing timed */
+  int32_t sort_every;             /* re-sort interval of the all-pairs lists, as srmd_set_sort_interval */
+  int32_t reserved;
 } srmd_tuning;
 
 /* Fill *key with the user parameters of s (integrator and pair potential set).
@@ -268,33 +321,46 @@ srmd_status srmd_tuning_cache_store(const char *path, const srmd_tuning_key *key
  * for each method within 20 % of the fastest, block size x tp with the
  * appendix's stop rules and the skin re-optimised in steps of 10 % from the
  * last optimum at every layout; for systems the persistent kernel can run, the
- * same t_p loop in persistent mode; a final trial of the chosen set.  A skin step
+ * same t_p loop in persistent mode; with the all-pairs lists chosen, the re-sort
+ * interval (srmd_set_sort_interval: never, 64, 16, 4, 1 builds) with a single
+ * minimum (appendix step 5); a final trial of the chosen set.  A skin step
  * multiplies the current value by 1.2 or 0.8 (1.1 or 0.9) and the search
  * goes on in the direction that was faster until a trial is slower; skins that
  * would put r_c + skin past half a box side, or that the chosen list method
  * cannot run, count as slower.  The chosen layout, list method, mode and skin
- * are applied as srmd_set_launch, srmd_set_rebuild_path, srmd_set_persistent
- * and srmd_set_skin would (they override earlier explicit choices), the state
+ * are applied as srmd_set_launch, srmd_set_rebuild_path, srmd_set_persistent,
+ * srmd_set_skin and srmd_set_sort_interval would (they override earlier explicit
+ * choices), the state
  * is restored, and with cache_path non-NULL a record is appended.  out may be NULL. */
 srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const char *cache_path, srmd_tuning *out);
 
-/* Bin, sort and rebuild the neighbour list now, whatever the displacement. */
+/* Bin, sort and rebuild the neighbour list now, whatever the displacement (paper
+ * section 7: cell index of every particle, sort and rearrangement of all particle
+ * data by cell, then the list of every particle from its neighbouring cells within
+ * r_c + skin; section 6 for the all-pairs method of list mode 4). */
 srmd_status srmd_build_neighbor_list(srmd_system *s);
 
-/* Forces, potential energy and virial at the current positions (no time step).
+/* Forces, potential energy and virial at the current positions (no time step;
+ * paper section 5, the force kernel figure: each particle's force and half its pair
+ * energies summed over its list, t_p threads per particle).
  * The list is rebuilt first if the displacement criterion or a parameter change
  * asks for it.  out (nullable) receives pe and virial; its other fields describe
  * the current velocities. */
 srmd_status srmd_compute_forces(srmd_system *s, srmd_thermo *out);
 
-/* Advance nsteps time steps.  If thermo_every > 0, the record of every step n with
+/* Advance nsteps time steps (paper section 2 example: Run(nsteps); each step checks
+ * the displacement since the last build and rebuilds the list on the device when a
+ * particle moved more than half the skin, section 6, then forces, section 5, and
+ * the integrator).  If thermo_every > 0, the record of every step n with
  * n % thermo_every == 0 is written to trace (caller-owned, trace_cap entries; extra
  * records are dropped).  Synchronises once at the end.  Returns SRMD_ESTATE if a
  * non-finite force or position appeared. */
 srmd_status srmd_step(srmd_system *s, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
                       int64_t trace_cap);
 
-/* Copy the state to host arrays in original particle order; each pointer may be NULL.
+/* Copy the state to host arrays in original particle order (the paper's sort
+ * rearranges all particle data on the device, section 7; the original order is
+ * restored here); each pointer may be NULL.
  * pos, vel, force: float32 n*3; image: int32 n*3 (box crossings); pos64: float64 n*3
  * (the float64 master positions in the F64POS variant, else the float32 positions
  * widened). force holds the forces of the last force evaluation. */
@@ -338,7 +404,9 @@ srmd_status srmd_save_state(srmd_system *s, void *buf, size_t bytes, size_t *nee
  * integrator and pair potential are those set on s.  Sticky error bits clear. */
 srmd_status srmd_load_state(srmd_system *s, const void *buf, size_t bytes);
 
-/* The neighbour list as (id_i, id_j) pairs in original ids, lexicographically sorted.
+/* The neighbour list (paper sections 4, 6 and 7: every j within r_c,ij + skin of i,
+ * both directions, strict less-than) as (id_i, id_j) pairs in original ids,
+ * lexicographically sorted (the list order itself is not specified by the paper).
  * pairs holds 2*cap int32; *count receives the total number of pairs (the call fails
  * with SRMD_EINVAL, writing nothing, when cap is too small). */
 srmd_status srmd_get_neighbor_pairs(srmd_system *s, int32_t *pairs, int64_t cap, int64_t *count);
@@ -447,6 +515,21 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
  * call returns SRMD_ESTATE after finishing every other replica. */
 srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every, srmd_thermo *trace,
                             int64_t trace_cap);
+
+/* Choose the batch's thread layout by timing short batched runs from a stored copy
+ * of every replica's state (paper appendix: each trial starts from the same stored
+ * configuration): first the threads per particle shared by all replicas (1, 2, 4,
+ * ... at 256 threads per block, with the appendix's stop rules: three trials in a
+ * row slower than the best, one 5 % slower, or a resource limit), then per replica
+ * size bucket (the replicas in quartiles of their particle count) the threads per
+ * block (64 ... 1024; particles per block = threads / tp), stopping a bucket's loop
+ * 10 % above its best.  The chosen shape becomes every replica's launch shape, as
+ * srmd_set_launch would set it, and the states are put back (the next step rebuilds
+ * the lists).  steps_per_trial >= 1 timed batch steps per trial.  *tp_out (nullable)
+ * receives tp; ppb_out (nullable, count entries) each replica's particles per block.
+ * A batched replica then follows its single-system trajectory at that shape bit for
+ * bit, as at any shape. */
+srmd_status srmd_batch_autotune(srmd_batch *b, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out);
 
 /* Release the batch (not the systems). NULL is a no-op. */
 srmd_status srmd_batch_destroy(srmd_batch *b);

@@ -33,6 +33,10 @@
  *    lists generalised Lennard-Jones and inverse-power-law potentials among the
  *    pair potentials: both are of this form), with the same three cutoff methods.
  *
+ *  - optionally, the further pair potentials paper section 2 names (Yukawa,
+ *    Buckingham, Gaussian core, Dzugutov, Girifalco) in their textbook forms (see
+ *    gen_uf and girifalco_uf), with the same three cutoff methods.
+ *
  *  - optionally, Coulomb interactions with a shifted-force cutoff (paper section
  *    9): between charges q_a, q_b (per type, reduced units in which the Coulomb
  *    constant is one) U(r) = q_a q_b (1/r - 1/r_cc + (r - r_cc)/r_cc^2) and
@@ -238,15 +242,108 @@ void oracle_pair_mie(double r, double A, double B, int m, int n, double sig, dou
   }
 }
 
-/* One pair's short-range term: Lennard-Jones, or the two-power potential when mie is
- * given (per type pair ab: mie[4 ab .. 4 ab + 3] = A, B, m, n). */
-static void short_pair(const double *mie, int ab, double r, const double *sigma, const double *eps, const double *rc,
-                       int method, double *u, double *f) {
-  if (mie)
-    oracle_pair_mie(r, mie[4 * ab], mie[4 * ab + 1], (int)mie[4 * ab + 2], (int)mie[4 * ab + 3], sigma[ab], rc[ab],
-                    method, u, f);
+/* ---- further pair potentials of paper section 2 ------------------------------ */
+/* The paper names these potentials only; the forms are the textbook ones:
+ *   kind 2, Yukawa (screened Coulomb):  U = eps (sig/r) exp(-kappa (r - sig)),       p = {eps, kappa}
+ *   kind 3, Buckingham (exp-6):         U = A exp(-r/rho) - C / r^6,                  p = {A, rho, C}
+ *   kind 4, Gaussian core:              U = eps exp(-(r/sig)^2),                      p = {eps}
+ *   kind 5, Dzugutov (reduced x = r/sig, scaled by eps):
+ *     U = eps [ a1 (x^-16 - b1) exp(c1 / (x - x1)) for x < x1
+ *              + b1 exp(d1 / (x - x2))             for x < x2 ],
+ *     a1 = 5.82, b1 = 1.28, c1 = 1.1, x1 = 1.87, d1 = 0.27, x2 = 1.94         p = {eps}
+ * F(r) = -dU/dr in closed form; kind 1 is the two-power potential above. */
+static const double DZ_A = 5.82, DZ_B = 1.28, DZ_C = 1.1, DZ_X1 = 1.87, DZ_D = 0.27, DZ_X2 = 1.94;
+static const int DZ_M = 16;
+
+static void gen_uf(int kind, const double *p, double sig, double r, double *u, double *f) {
+  if (kind == 2) {
+    double e = exp(-p[1] * (r - sig));
+    *u = p[0] * sig / r * e;
+    *f = p[0] * sig * e * (1.0 + p[1] * r) / (r * r);
+  } else if (kind == 3) {
+    double e = exp(-r / p[1]);
+    double r6 = r * r * r * r * r * r;
+    *u = p[0] * e - p[2] / r6;
+    *f = p[0] / p[1] * e - 6.0 * p[2] / (r6 * r);
+  } else if (kind == 4) {
+    double e = exp(-(r / sig) * (r / sig));
+    *u = p[0] * e;
+    *f = 2.0 * p[0] * r / (sig * sig) * e;
+  } else { /* Dzugutov */
+    double x = r / sig, du = 0.0, uu = 0.0;
+    if (x < DZ_X1) {
+      double e = exp(DZ_C / (x - DZ_X1)), xm = pow(x, -(double)DZ_M);
+      uu += DZ_A * (xm - DZ_B) * e;
+      du += DZ_A * e * (-(double)DZ_M * xm / x - (xm - DZ_B) * DZ_C / ((x - DZ_X1) * (x - DZ_X1)));
+    }
+    if (x < DZ_X2) {
+      double e = exp(DZ_D / (x - DZ_X2));
+      uu += DZ_B * e;
+      du += -DZ_B * e * DZ_D / ((x - DZ_X2) * (x - DZ_X2));
+    }
+    *u = p[0] * uu;
+    *f = -p[0] * du / sig;
+  }
+}
+
+/* Girifalco (kind 6; the sphere-sphere form, s = r/sig with sig the sphere
+ * diameter d, p = {alpha, beta}):
+ *   U = -alpha [1/(s(s-1)^3) + 1/(s(s+1)^3) - 2/s^4] + beta [1/(s(s-1)^9) + 1/(s(s+1)^9) - 2/s^10]. */
+static void girifalco_uf(const double *p, double sig, double r, double *u, double *f) {
+  double s = r / sig, a = s - 1.0, b = s + 1.0;
+  double a3 = a * a * a, b3 = b * b * b, a9 = a3 * a3 * a3, b9 = b3 * b3 * b3;
+  double s4 = s * s * s * s, s10 = s4 * s4 * s * s;
+  double att = 1.0 / (s * a3) + 1.0 / (s * b3) - 2.0 / s4;
+  double rep = 1.0 / (s * a9) + 1.0 / (s * b9) - 2.0 / s10;
+  /* d/ds of each bracket */
+  double datt = -(1.0 / (s * s * a3) + 3.0 / (s * a3 * a)) - (1.0 / (s * s * b3) + 3.0 / (s * b3 * b)) + 8.0 / (s4 * s);
+  double drep = -(1.0 / (s * s * a9) + 9.0 / (s * a9 * a)) - (1.0 / (s * s * b9) + 9.0 / (s * b9 * b)) + 20.0 / (s10 * s);
+  *u = -p[0] * att + p[1] * rep;
+  *f = -(-p[0] * datt + p[1] * drep) / sig;
+}
+
+/* pair energy and radial force of the further potentials (kind 2..6) under a cutoff method */
+static void further_uf(int kind, const double *p, double sig, double r, double *u, double *f) {
+  if (kind == 6)
+    girifalco_uf(p, sig, r, u, f);
   else
+    gen_uf(kind, p, sig, r, u, f);
+}
+
+void oracle_pair_further(double r, int kind, const double *p, double sig, double rc, int method, double *u, double *f) {
+  double ur, fr;
+  further_uf(kind, p, sig, r, &ur, &fr);
+  if (method == ORACLE_TRUNC) {
+    *u = ur;
+    *f = fr;
+    return;
+  }
+  double uc, fc;
+  further_uf(kind, p, sig, rc, &uc, &fc);
+  if (method == ORACLE_SP) {
+    *u = ur - uc;
+    *f = fr;
+  } else {
+    *u = ur - uc + (r - rc) * fc;
+    *f = fr - fc;
+  }
+}
+
+/* One pair's short-range term: Lennard-Jones, or, when pot is given, the potential
+ * of kind pot[0] (1 the two-power potential, 2..6 the further potentials above) with
+ * the parameters of type pair ab at pot[1 + 4 ab .. 4 + 4 ab] (two-power: A, B, m, n). */
+static void short_pair(const double *pot, int ab, double r, const double *sigma, const double *eps, const double *rc,
+                       int method, double *u, double *f) {
+  if (!pot) {
     oracle_pair(r, sigma[ab], eps[ab], rc[ab], method, u, f);
+    return;
+  }
+  const int kind = (int)pot[0];
+  const double *q = pot + 1 + 4 * ab;
+  if (kind == 1)
+    oracle_pair_mie(r, q[0], q[1], (int)q[2], (int)q[3], sigma[ab], rc[ab], method, u, f);
+  else
+    oracle_pair_further(r, kind, q, sigma[ab], rc[ab], method, u, f);
 }
 
 /* ---- Coulomb with a shifted-force cutoff (paper section 9) ---------------- */
@@ -262,9 +359,10 @@ void oracle_coulomb_sf(double r, double qq, double rcc, double *u, double *f) {
  *  sel == NULL: every particle; else the nsel particles listed in sel.
  *  Outputs (length nsel or n): F[3*k..], pe[k] = 1/2 sum_j u_ij,
  *  w[k] = 1/2 * 1/3 sum_j (r_i - r_j) . F_ij.   Totals (over the selection):
- *  totals[0] = sum pe, totals[1] = sum w.  In/out decision: r2_f32 < rc2_f32. */
+ *  totals[0] = sum pe, totals[1] = sum w.  In/out decision: r2_f32 < rc2_f32.
+ *  pot: NULL for Lennard-Jones, else the potential block of short_pair. */
 void oracle_forces_f32_g(int n, const float *pos, const int *type, const double *box, int ntypes,
-                         const double *sigma, const double *eps, const double *rc, int method, const double *mie,
+                         const double *sigma, const double *eps, const double *rc, int method, const double *pot,
                          const double *charge, double rcc, int nsel, const int *sel, double *F, double *pe,
                          double *w, double *totals) {
   float L32[3], invL[3];
@@ -291,7 +389,7 @@ void oracle_forces_f32_g(int n, const float *pos, const int *type, const double 
       }
       double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
       double u = 0.0, f = 0.0;
-      if (in_lj) short_pair(mie, ab, r, sigma, eps, rc, method, &u, &f);
+      if (in_lj) short_pair(pot, ab, r, sigma, eps, rc, method, &u, &f);
       if (in_c) {
         double uc, fc;
         oracle_coulomb_sf(r, charge[type[i]] * charge[type[j]], rcc, &uc, &fc);
@@ -341,7 +439,7 @@ void oracle_forces_f32(int n, const float *pos, const int *type, const double *b
  * (and r^2 < r_cc^2 for the Coulomb term when charge != NULL).
  * Used by the reference integrator. */
 void oracle_forces_f64_g(int n, const double *pos, const int *type, const double *box, int ntypes,
-                         const double *sigma, const double *eps, const double *rc, int method, const double *mie,
+                         const double *sigma, const double *eps, const double *rc, int method, const double *pot,
                          const double *charge, double rcc, double *F, double *pe, double *w, double *totals) {
 #pragma omp parallel for schedule(dynamic, 8)
   for (int i = 0; i < n; ++i) {
@@ -359,7 +457,7 @@ void oracle_forces_f64_g(int n, const double *pos, const int *type, const double
       if (!in_lj && !in_c) continue;
       double r = sqrt(r2);
       double u = 0.0, f = 0.0;
-      if (in_lj) short_pair(mie, ab, r, sigma, eps, rc, method, &u, &f);
+      if (in_lj) short_pair(pot, ab, r, sigma, eps, rc, method, &u, &f);
       if (in_c) {
         double uc, fc;
         oracle_coulomb_sf(r, charge[type[i]] * charge[type[j]], rcc, &uc, &fc);
@@ -449,7 +547,7 @@ int oracle_rebuild_needed(int n, const float *pos, const float *pos0, const doub
  */
 int oracle_integrate_g(int n, double *pos, double *vel, int *image, const int *type, const double *mass,
                        const double *box, int ntypes, const double *sigma, const double *eps, const double *rc,
-                       int method, const double *mie, const double *charge, double rcc, double dt, int thermostat,
+                       int method, const double *pot, const double *charge, double rcc, double dt, int thermostat,
                        double T0, double inv_tau2, double *xi, double *xi_int, int nsteps, double *thermo) {
   double *F = (double *)malloc(sizeof(double) * 3 * (size_t)n);
   double *pe = (double *)malloc(sizeof(double) * (size_t)n);
@@ -461,7 +559,7 @@ int oracle_integrate_g(int n, double *pos, double *vel, int *image, const int *t
   double V = box[0] * box[1] * box[2];
   for (int step = 0; step < nsteps; ++step) {
     double tot[2];
-    oracle_forces_f64_g(n, pos, type, box, ntypes, sigma, eps, rc, method, mie, charge, rcc, F, pe, w, tot);
+    oracle_forces_f64_g(n, pos, type, box, ntypes, sigma, eps, rc, method, pot, charge, rcc, F, pe, w, tot);
     double x = thermostat ? *xi : 0.0;
     double a = 1.0 - x * dt / 2.0, b = 1.0 + x * dt / 2.0;
     for (int i = 0; i < n; ++i) {

@@ -21,7 +21,7 @@ METHODS = {"trunc": TRUNC, "sp": SP, "sf": SF}
 __all__ = [
     "build", "load", "TRUNC", "SP", "SF", "METHODS", "cut_tables", "pair_set", "neighbors_of",
     "forces_f32", "forces_f64", "pair", "kinetic", "max_disp2", "rebuild_needed", "integrate", "num_threads",
-    "coulomb_sf", "pair_mie", "set_num_threads",
+    "coulomb_sf", "pair_mie", "set_num_threads", "pair_potential", "POTENTIAL_KINDS",
 ]
 
 
@@ -71,6 +71,9 @@ def load():
     lib.oracle_pair_mie.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, _dp, _dp]
     lib.oracle_pair_mie.restype = None
+    lib.oracle_pair_further.argtypes = [ctypes.c_double, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int, _dp, _dp]
+    lib.oracle_pair_further.restype = None
     lib.oracle_forces_f32_g.argtypes = [ctypes.c_int, _fp, _ip, _dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int,
                                         _dp, _dp, ctypes.c_double, ctypes.c_int, _ip, _dp, _dp, _dp, _dp]
     lib.oracle_forces_f32_g.restype = None
@@ -182,12 +185,34 @@ def pair_mie(r, A, B, m, n, sigma, rc, method):
     return u.value, f.value
 
 
-def _mie(mie, ntypes):
-    """Pack (A, B, m, n), each ntypes x ntypes, as 4 doubles per type pair."""
+# kinds of the potential block (1 the two-power potential; 2..6 the further potentials)
+POTENTIAL_KINDS = {"yukawa": 2, "buckingham": 3, "gaussian": 4, "dzugutov": 5, "girifalco": 6}
+
+
+def pair_potential(kind, r, params, sigma, rc, method):
+    """(u, f) of one pair of a further potential (yukawa, buckingham, gaussian,
+    dzugutov, girifalco) with 4 parameters (see oracle.c), f positive = repulsive."""
+    u = ctypes.c_double()
+    f = ctypes.c_double()
+    p = np.zeros(4)
+    p[:len(params)] = params
+    load().oracle_pair_further(float(r), POTENTIAL_KINDS[kind], _p(p), float(sigma), float(rc), _method(method),
+                               ctypes.byref(u), ctypes.byref(f))
+    return u.value, f.value
+
+
+def _mie(mie, ntypes, pot=None):
+    """The potential block: kind, then 4 doubles per type pair.  mie = (A, B, m, n),
+    each ntypes x ntypes, gives kind 1; pot = (kind name, ntypes x ntypes x 4 array)
+    a further potential."""
+    if pot is not None:
+        kind, params = pot
+        p = np.asarray(params, np.float64).reshape(ntypes * ntypes * 4)
+        return np.ascontiguousarray(np.concatenate([[float(POTENTIAL_KINDS[kind])], p]))
     if mie is None:
         return None
     parts = [np.asarray(x, np.float64).reshape(ntypes, ntypes) for x in mie]
-    return np.ascontiguousarray(np.stack(parts, -1).reshape(-1))
+    return np.ascontiguousarray(np.concatenate([[1.0], np.stack(parts, -1).reshape(-1)]))
 
 
 def _charges(charges, ntypes):
@@ -199,11 +224,12 @@ def _charges(charges, ntypes):
     return q
 
 
-def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, rc_coul=0.0, mie=None):
+def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, rc_coul=0.0, mie=None, pot=None):
     """Forces (k, 3), per-particle PE (k,), per-particle virial (k,), total PE, total W on float32 positions.
     With charges (one per type), the shifted-force Coulomb term with cutoff rc_coul is added.
     With mie = (A, B, m, n) (each ntypes x ntypes), the two-power potential replaces
-    Lennard-Jones (eps is then unused)."""
+    Lennard-Jones (eps is then unused); with pot = (kind, ntypes x ntypes x 4 params)
+    one of the further potentials does (see pair_potential)."""
     pos = _c(pos, np.float32)
     types = _c(types, np.int32)
     box = _c(box, np.float64)
@@ -223,14 +249,14 @@ def forces_f32(pos, types, box, sigma, eps, rc, method, sel=None, charges=None, 
     w = np.zeros(k)
     tot = np.zeros(2)
     q = _charges(charges, sigma.shape[0])
-    g = _mie(mie, sigma.shape[0])
+    g = _mie(mie, sigma.shape[0], pot)
     load().oracle_forces_f32_g(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
                                _method(method), None if g is None else _p(g), None if q is None else _p(q),
                                float(rc_coul), k, selp, _p(F), _p(pe), _p(w), _p(tot))
     return F, pe, w, float(tot[0]), float(tot[1])
 
 
-def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.0, mie=None):
+def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.0, mie=None, pot=None):
     pos = _c(pos, np.float64)
     types = _c(types, np.int32)
     box = _c(box, np.float64)
@@ -243,7 +269,7 @@ def forces_f64(pos, types, box, sigma, eps, rc, method, charges=None, rc_coul=0.
     w = np.zeros(n)
     tot = np.zeros(2)
     q = _charges(charges, sigma.shape[0])
-    g = _mie(mie, sigma.shape[0])
+    g = _mie(mie, sigma.shape[0], pot)
     load().oracle_forces_f64_g(n, _p(pos), _p(types), _p(box), sigma.shape[0], _p(sigma), _p(eps), _p(rc),
                                _method(method), None if g is None else _p(g), None if q is None else _p(q),
                                float(rc_coul), _p(F), _p(pe), _p(w), _p(tot))
@@ -275,7 +301,7 @@ THERMO_FIELDS = ("pe", "ke", "virial", "temperature", "pressure", "xi", "xi_inte
 
 
 def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, thermostat=False, T0=1.0,
-              tau=None, xi=0.0, xi_int=0.0, image=None, charges=None, rc_coul=0.0, mie=None):
+              tau=None, xi=0.0, xi_int=0.0, image=None, charges=None, rc_coul=0.0, mie=None, pot=None):
     """Run nsteps of leapfrog (NVE) or Nose-Hoover leapfrog (NVT) in FP64.
 
     Returns dict(pos, vel, image, xi, xi_int, thermo) with thermo an (nsteps, 9) array whose
@@ -296,7 +322,7 @@ def integrate(pos, vel, types, mass, box, sigma, eps, rc, method, dt, nsteps, th
     xi_i = ctypes.c_double(xi_int)
     thermo = np.zeros((nsteps, 9))
     q = _charges(charges, sigma.shape[0])
-    g = _mie(mie, sigma.shape[0])
+    g = _mie(mie, sigma.shape[0], pot)
     rc_ = load().oracle_integrate_g(n, _p(pos), _p(vel), _p(image), _p(types), _p(mass), _p(box), sigma.shape[0],
                                     _p(sigma), _p(eps), _p(rc), _method(method), None if g is None else _p(g),
                                     None if q is None else _p(q), float(rc_coul), float(dt), int(bool(thermostat)), float(T0), float(inv_tau2),

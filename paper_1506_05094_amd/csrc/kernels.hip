@@ -135,10 +135,16 @@ struct alignas(16) MieRow {
   int hm, hn;
 };
 
+// Constants of a further potential of a type pair (kernel method 5).
+struct alignas(16) GenRow {
+  float g0, g1, g2, g3;
+};
+
 struct SharedPairs {
   PairRow row[kMaxPairs];
   CoulRow crow[kMaxPairs];
   MieRow mrow[kMaxPairs];
+  GenRow grow[kMaxPairs];
 };
 
 __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) {
@@ -166,6 +172,7 @@ __device__ __forceinline__ void stage_pairs(SharedPairs &sp, const SysConst &c) 
     g.hm = c.pt.mie_hm[t];
     g.hn = c.pt.mie_hn[t];
     sp.mrow[t] = g;
+    sp.grow[t] = GenRow{c.pt.gen[t][0], c.pt.gen[t][1], c.pt.gen[t][2], c.pt.gen[t][3]};
   }
 }
 
@@ -193,6 +200,67 @@ __device__ __forceinline__ float pow_int(float x, int h) {
     x *= x;
   }
   return r;
+}
+
+// Energy u and force over distance fr = F(r)/r (F = -dU/dr, positive repulsive) of
+// the further pair potentials of paper section 2 (the paper names them only; these
+// are the textbook forms), in float32 from the pair's constants g (kind uniform over
+// the system):
+//  2 Yukawa        U = eps (sig/r) exp(-kappa (r - sig)) = g0 exp(-g1 r) / r
+//                  (g0 = eps sig exp(kappa sig), g1 = kappa)
+//  3 Buckingham    U = A exp(-r/rho) - C / r^6               (g0 = A, g1 = 1/rho, g2 = C)
+//  4 Gaussian core U = eps exp(-(r/sig)^2)                    (g0 = eps, g1 = 1/sig^2)
+//  5 Dzugutov      U = eps [5.82 (x^-16 - 1.28) exp(1.1 / (x - 1.87)) (x < 1.87)
+//                         + 1.28 exp(0.27 / (x - 1.94)) (x < 1.94)],  x = r/sig
+//                                                            (g0 = eps, g1 = 1/sig)
+//  6 Girifalco     U = -alpha [1/(s(s-1)^3) + 1/(s(s+1)^3) - 2/s^4]
+//                      + beta [1/(s(s-1)^9) + 1/(s(s+1)^9) - 2/s^10],  s = r/d
+//                                                            (g0 = alpha, g1 = beta, g2 = 1/d)
+__device__ __forceinline__ void pair_further(int kind, const GenRow &g, float r, float inv_r, float &u, float &fr) {
+  const float inv_r2 = inv_r * inv_r;
+  if (kind == 2) {
+    u = g.g0 * expf(-g.g1 * r) * inv_r;
+    fr = u * __builtin_fmaf(g.g1, r, 1.0f) * inv_r2;
+  } else if (kind == 3) {
+    const float e = g.g0 * expf(-g.g1 * r);
+    const float d6 = g.g2 * inv_r2 * inv_r2 * inv_r2;
+    u = e - d6;
+    fr = (e * g.g1 * inv_r - 6.0f * d6 * inv_r2);
+  } else if (kind == 4) {
+    const float e = g.g0 * expf(-r * r * g.g1);
+    u = e;
+    fr = 2.0f * g.g1 * e;
+  } else if (kind == 5) {
+    const float x = r * g.g1;
+    float uu = 0.0f, du = 0.0f;
+    if (x < 1.87f) {
+      const float q = 1.0f / (x - 1.87f);
+      const float e = expf(1.1f * q);
+      const float ix2 = 1.0f / (x * x);
+      const float xm = pow_int(ix2, 8);
+      uu = 5.82f * (xm - 1.28f) * e;
+      du = 5.82f * e * (-16.0f * xm / x - (xm - 1.28f) * 1.1f * q * q);
+    }
+    if (x < 1.94f) {
+      const float q = 1.0f / (x - 1.94f);
+      const float e = 1.28f * expf(0.27f * q);
+      uu += e;
+      du -= e * 0.27f * q * q;
+    }
+    u = g.g0 * uu;
+    fr = -g.g0 * du * g.g1 * inv_r;
+  } else {
+    const float s = r * g.g2, is = 1.0f / s;
+    const float ia = 1.0f / (s - 1.0f), ib = 1.0f / (s + 1.0f);
+    const float ia3 = ia * ia * ia, ib3 = ib * ib * ib, ia9 = ia3 * ia3 * ia3, ib9 = ib3 * ib3 * ib3;
+    const float is4 = is * is * is * is, is10 = is4 * is4 * is * is;
+    const float att = is * (ia3 + ib3) - 2.0f * is4;
+    const float rep = is * (ia9 + ib9) - 2.0f * is10;
+    const float datt = -is * is * (ia3 + ib3) - 3.0f * is * (ia3 * ia + ib3 * ib) + 8.0f * is4 * is;
+    const float drep = -is * is * (ia9 + ib9) - 9.0f * is * (ia9 * ia + ib9 * ib) + 20.0f * is10 * is;
+    u = -g.g0 * att + g.g1 * rep;
+    fr = (g.g0 * datt - g.g1 * drep) * g.g2 * inv_r;
+  }
 }
 
 template <int METHOD>
@@ -224,6 +292,27 @@ __device__ __forceinline__ void pair_acc(const float4 pi, const Wide &wi, const 
       const float r = r2 * inv_r;
       fr = __builtin_fmaf(-pr.fc, inv_r, fr);
       e = __builtin_fmaf(r - pr.rc, pr.fc, e);
+      fx = __builtin_fmaf(-fr, dx, fx);
+      fy = __builtin_fmaf(-fr, dy, fy);
+      fz = __builtin_fmaf(-fr, dz, fz);
+      u += e;
+      w = __builtin_fmaf(fr, r2, w);
+    }
+    return;
+  }
+  if (METHOD == 5) {
+    // a further potential of paper section 2, cutoff method by U(rc) and F(rc)
+    if (r2s < pr.rc2) {
+      dx = (float)(((double)pj.x - wi.x) - (double)mx * c.Ld[0]);
+      dy = (float)(((double)pj.y - wi.y) - (double)my * c.Ld[1]);
+      dz = (float)(((double)pj.z - wi.z) - (double)mz * c.Ld[2]);
+      const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+      const float inv_r = __builtin_amdgcn_rsqf(r2);
+      const float r = r2 * inv_r;
+      float e, fr;
+      pair_further(c.pot_kind, sp.grow[pidx], r, inv_r, e, fr);
+      fr = __builtin_fmaf(-pr.fc, inv_r, fr);
+      e = __builtin_fmaf(r - pr.rc, pr.fc, e - pr.ushift);
       fx = __builtin_fmaf(-fr, dx, fx);
       fy = __builtin_fmaf(-fr, dy, fy);
       fz = __builtin_fmaf(-fr, dz, fz);
@@ -506,6 +595,14 @@ __device__ __forceinline__ void begin_build(Control *ctl) {
   ctl->n_rebuilds += 1;
 }
 
+// All-pairs lists keep the particle order between builds; with sort_every = k > 0
+// the particles are spatially sorted again before builds 0, k, 2k, ... (the
+// periodic re-sort of the paper's n2 method, appendix step 5), counted by the builds
+// so far.
+__device__ __forceinline__ bool resort_due(const SysConst &c, long long builds) {
+  return c.sort_every > 0 && (builds % c.sort_every) == 0;
+}
+
 // The counting sort of large systems (section 7 steps 1-3) in four phases, each a
 // grid-wide pass over particles or cells: bin, scan, scatter, gather.  The launch
 // chain runs them as four kernels; the persistent kernel runs the same functions
@@ -686,6 +783,7 @@ __device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur, u
   if (tid == 0) {
     s_carry = 0u;
     begin_build(p.ctl);
+    p.ctl->resorted = 1;
   }
   unsigned my_cell[PER], my_slot[PER];
   int my_id[PER];
@@ -771,10 +869,18 @@ __device__ void sort_small_block(const SysConst &c, const SysPtrs &p, int cur, u
 __global__ __launch_bounds__(1024) void k_sort_small(SysConst c, SysPtrs p, int cur) {
   __shared__ unsigned s_cnt[kSmallCells + 1];
   __shared__ int s_id[kSmallN];
+  __shared__ int s_due;
   if (p.ctl->rebuild == 0) return;
-  if (c.list_kind == 4) {  // all-pairs lists need no sort, only the build counters reset
-    if (threadIdx.x == 0) begin_build(p.ctl);
-    return;
+  if (c.list_kind == 4) {  // all-pairs lists sort only when a periodic re-sort is due
+    if (threadIdx.x == 0) s_due = resort_due(c, p.ctl->n_rebuilds) ? 1 : 0;
+    __syncthreads();
+    if (!s_due) {
+      if (threadIdx.x == 0) {
+        begin_build(p.ctl);
+        p.ctl->resorted = 0;
+      }
+      return;
+    }
   }
   sort_small_block<1024>(c, p, cur, s_cnt, s_id);
 }
@@ -939,8 +1045,8 @@ __device__ int list_allpairs_one(const SysConst &c, const SysPtrs &p, int i, con
   return kept;
 }
 
-// All-pairs lists for the launch chain, one wave per particle, four per block;
-// the particles keep their order (no sort).
+// All-pairs lists for the launch chain, one wave per particle, four per block; the
+// particles keep their order unless a periodic re-sort ran before this build.
 __global__ __launch_bounds__(256) void k_list_allpairs(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
@@ -948,9 +1054,14 @@ __global__ __launch_bounds__(256) void k_list_allpairs(SysConst c, SysPtrs p, in
   __syncthreads();
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int t = xcd_remap(blockIdx.x, gridDim.x) * 4 + wv;
+  // after a periodic re-sort the candidates come from the sorted copy, and each wave
+  // moves its own particle's slot into place
+  const bool resorted = p.ctl->resorted != 0;
+  const float4 *src = resorted ? p.t_pos : p.pos[cur];
   int kept = 0, longest = 0;
   if (t < c.n) {  // uniform across the wave
-    const int k = list_allpairs_one(c, p, t, s_cs2, p.pos[cur], longest);
+    if (resorted && lane == 0) place_sorted(p, cur, t, src[t]);
+    const int k = list_allpairs_one(c, p, t, s_cs2, src, longest);
     if (lane == 0) kept = k;
   }
   list_tally(kept, longest, c.n_max, p.ctl);
@@ -1500,7 +1611,7 @@ __device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockParti
 template <int MODE>
 __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, int next) {
   __shared__ BlockPartial s_waves[16];
-  __shared__ int s_rebuild;
+  __shared__ int s_rebuild, s_due;
   __shared__ unsigned s_cnt[MODE == 0 ? kSmallCells + 1 : 1];
   __shared__ int s_id[MODE == 0 ? kSmallN : 1];
   // the control words are final (the kernels before this one in the stream wrote
@@ -1541,13 +1652,17 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
       if (a.nonfinite) ctl->error |= 1;
     } else {
       rebuild = finish_step(c, p, a, cv);
+      s_due = resort_due(c, cv.n_rebuilds) ? 1 : 0;
     }
     s_rebuild = rebuild;
   }
   __syncthreads();
   if (MODE == 0 && s_rebuild && c.small_sort) {
-    if (c.list_kind == 4) {
-      if (threadIdx.x == 0) begin_build(p.ctl);
+    if (c.list_kind == 4 && !s_due) {
+      if (threadIdx.x == 0) {
+        begin_build(p.ctl);
+        p.ctl->resorted = 0;
+      }
     } else {
       sort_small_block<1024>(c, p, next, s_cnt, s_id);
     }
@@ -1727,8 +1842,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
   __shared__ BlockPartial s_waves[16];
   __shared__ BlockPartial s_wp[kLdsUnits];
   __shared__ float s_cs2[kMaxPairs];
-  __shared__ int s_ok, s_any, s_bit;
-  __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs];
+  __shared__ int s_ok, s_any, s_bit, s_due;
+  __shared__ int s_rebuild[kMaxJobs], s_cur[kMaxJobs], s_resorted[kMaxJobs];
   __shared__ unsigned s_k[kMaxJobs];
   __shared__ double s_xi[kMaxJobs];
   __shared__ unsigned s_scan[16];
@@ -1741,6 +1856,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
     const ReplicaDesc &R = reps[J.rep];
     if (tid == 0) {
       s_rebuild[j] = R.p.ctl->rebuild;
+      s_resorted[j] = R.p.ctl->resorted;
       s_xi[j] = R.c.thermostat ? R.p.ctl->xi : 0.0;
       s_cur[j] = R.cur;
       s_k[j] = 1u;
@@ -1779,8 +1895,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
       if (!BIG && rebuild && c.list_kind == 4) {
-        // all pairs from the positions of the step in LDS; no sort, no cells
-        fill_positions(s_dyn, p.pos[cur], c.n);
+        // all pairs from the positions of the step in LDS, no cells; after a periodic
+        // re-sort from the sorted copy, with this piece's slots moved into place
+        const bool resorted = s_resorted[j] != 0;
+        fill_positions(s_dyn, resorted ? p.t_pos : p.pos[cur], c.n);
+        if (resorted)
+          for (int t = J.w * kBatchThreads + tid; t < c.n; t += J.g * kBatchThreads)
+            place_sorted(p, cur, t, gload(p.t_pos, t));
         __syncthreads();
         int kept = 0, longest = 0;
         for (int t = J.w * kBatchWaves + wv; t < c.n; t += J.g * kBatchWaves) {
@@ -1947,7 +2068,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         for (int q = 1; q < used; ++q) fold(a, s_waves[q]);
         a.t0 = 0ull;
         a.t1 = 0ull;
-        if (J.w == 0) finish_step(c, p, a, cv);  // the one writer of the control block
+        if (J.w == 0) {
+          finish_step(c, p, a, cv);  // the one writer of the control block
+          s_due = resort_due(c, cv.n_rebuilds) ? 1 : 0;
+        }
         if (c.thermostat) s_xi[j] = xi_next(c, xi, a.ke_half);
         s_rebuild[j] = s_any;  // = (max displacement^2 > (skin/2)^2), as finish_step decides
       }
@@ -1956,14 +2080,21 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
       if (!BIG && s_rebuild[j]) {
         // spatial sort of the new positions by piece 0, as k_finish does
         if (J.w == 0) {
-          if (c.list_kind == 4) {  // all-pairs lists need no sort
-            if (tid == 0) begin_build(p.ctl);
+          if (c.list_kind == 4 && !s_due) {  // all-pairs lists sort only when a re-sort is due
+            if (tid == 0) {
+              begin_build(p.ctl);
+              p.ctl->resorted = 0;
+            }
           } else {
             unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
             sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
           }
         }
-        if (step + 1 < nsteps && !coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
+        // every piece learns whether the build ahead starts from a re-sort (its
+        // decision depends on the build count, which piece 0 holds)
+        if (step + 1 < nsteps && !coop_barrier(p.bar_flags, J.g, J.w, ++k, J.w == 0 ? s_due : 0, p.ctl, &s_ok, &s_any))
+          return;
+        if (tid == 0) s_resorted[j] = c.list_kind == 4 ? s_any : 1;
       }
       if (tid == 0) {
         s_cur[j] = cur;
@@ -1979,7 +2110,8 @@ static const void *multi_fn(int method) {
          : method == 1 ? (const void *)k_multi<TP, 1, BIG>
          : method == 2 ? (const void *)k_multi<TP, 2, BIG>
          : method == 3 ? (const void *)k_multi<TP, 3, BIG>
-                       : (const void *)k_multi<TP, 4, BIG>;
+         : method == 4 ? (const void *)k_multi<TP, 4, BIG>
+                       : (const void *)k_multi<TP, 5, BIG>;
 }
 
 // The persistent kernel for (tp, method); the large-system form exists for tp <= 8.
@@ -2178,6 +2310,7 @@ static hipError_t launch_step_tp(int method, int prec, dim3 g, dim3 b, hipStream
   SRMD_STEP_CASE(2, 0) SRMD_STEP_CASE(2, 1) SRMD_STEP_CASE(2, 2)
   SRMD_STEP_CASE(3, 0) SRMD_STEP_CASE(3, 1) SRMD_STEP_CASE(3, 2)
   SRMD_STEP_CASE(4, 0) SRMD_STEP_CASE(4, 1) SRMD_STEP_CASE(4, 2)
+  SRMD_STEP_CASE(5, 0) SRMD_STEP_CASE(5, 1) SRMD_STEP_CASE(5, 2)
 #undef SRMD_STEP_CASE
   return hipErrorInvalidValue;
 }
@@ -2190,6 +2323,7 @@ static hipError_t launch_force_tp(int method, dim3 g, dim3 b, hipStream_t st, co
   else if (method == 2) hipLaunchKernelGGL((k_force<TP, 2>), g, b, 0, st, c, p, cur);
   else if (method == 3) hipLaunchKernelGGL((k_force<TP, 3>), g, b, 0, st, c, p, cur);
   else if (method == 4) hipLaunchKernelGGL((k_force<TP, 4>), g, b, 0, st, c, p, cur);
+  else if (method == 5) hipLaunchKernelGGL((k_force<TP, 5>), g, b, 0, st, c, p, cur);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -3,6 +3,7 @@
 // and the original-order views of the state.
 #include <algorithm>
 #include <cctype>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -76,9 +77,11 @@ struct srmd_system {
   double sigma[kMaxPairs] = {}, eps[kMaxPairs] = {}, rc[kMaxPairs] = {};
   bool pair_given[kMaxPairs] = {};
   int method = -1;
-  int pot = -1;                         // 0 Lennard-Jones, 1 two-power (srmd_set_pair_mie); -1 none yet
+  int pot = -1;                         // 0 Lennard-Jones, 1 two-power (srmd_set_pair_mie), 2..6 the further
+                                        // potentials (srmd_set_pair_potential); -1 none yet
   double mie_a[kMaxPairs] = {}, mie_b[kMaxPairs] = {};
   int mie_m[kMaxPairs] = {}, mie_n[kMaxPairs] = {};
+  double gen_p[kMaxPairs][4] = {};      // parameters of a further potential
   bool coulomb = false;                 // shifted-force Coulomb term on (srmd_set_coulomb_sf)
   double charge[kMaxTypes] = {0, 0, 0, 0};
   double rcc = 0.0;                     // its cutoff
@@ -91,6 +94,7 @@ struct srmd_system {
   int tp_req = 0, ppb_req = 0, tp = 0, ppb = 0;
   int tp_tuned = 0, ppb_tuned = 0;
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
+  int sort_every = 0;                // all-pairs lists: spatial sort at every k-th build (0: never)
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -137,7 +141,9 @@ srmd_status fail(srmd_system *s, srmd_status st, const std::string &msg) {
       return fail((s), SRMD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));                 \
   } while (0)
 
-void *dev_alloc(srmd_system *s, size_t bytes) {
+// One device buffer from the allocator hook in force (hipMalloc without one); the
+// buffer remembers how it was made so that it is released the same way.
+DevBuf raw_alloc(size_t bytes) {
   if (bytes == 0) bytes = 256;
   DevBuf b;
   b.bytes = bytes;
@@ -147,6 +153,21 @@ void *dev_alloc(srmd_system *s, size_t bytes) {
   } else {
     if (hipMalloc(&b.ptr, bytes) != hipSuccess) b.ptr = nullptr;
   }
+  return b;
+}
+
+void raw_free(DevBuf &b) {
+  if (b.ptr) {
+    if (b.how.free_fn)
+      b.how.free_fn(b.ptr, b.how.ctx);
+    else if (!b.how.alloc)
+      (void)hipFree(b.ptr);
+  }
+  b = DevBuf{};
+}
+
+void *dev_alloc(srmd_system *s, size_t bytes) {
+  DevBuf b = raw_alloc(bytes);
   if (!b.ptr) return nullptr;
   s->bufs.push_back(b);
   return b.ptr;
@@ -156,11 +177,7 @@ void dev_free(srmd_system *s, void *ptr) {
   if (!ptr) return;
   for (size_t k = 0; k < s->bufs.size(); ++k) {
     if (s->bufs[k].ptr == ptr) {
-      const DevBuf b = s->bufs[k];
-      if (b.how.free_fn)
-        b.how.free_fn(b.ptr, b.how.ctx);
-      else if (!b.how.alloc)
-        (void)hipFree(b.ptr);
+      raw_free(s->bufs[k]);
       s->bufs.erase(s->bufs.begin() + (long)k);
       return;
     }
@@ -197,6 +214,51 @@ double lj_f(double r, double sig, double eps) {
   return 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r;
 }
 
+// Energy and force -dU/dr of a further potential (kinds 2..6, srmd_set_pair_potential)
+// in float64, for its values at the cutoff.
+void further_uf(int kind, const double *p, double sig, double r, double *u, double *f) {
+  if (kind == 2) {  // Yukawa
+    const double e = std::exp(-p[1] * (r - sig));
+    *u = p[0] * sig / r * e;
+    *f = *u * (1.0 + p[1] * r) / r;
+  } else if (kind == 3) {  // Buckingham
+    const double e = p[0] * std::exp(-r / p[1]), d6 = p[2] / std::pow(r, 6);
+    *u = e - d6;
+    *f = e / p[1] - 6.0 * d6 / r;
+  } else if (kind == 4) {  // Gaussian core
+    const double e = p[0] * std::exp(-(r / sig) * (r / sig));
+    *u = e;
+    *f = 2.0 * r / (sig * sig) * e;
+  } else if (kind == 5) {  // Dzugutov
+    const double x = r / sig;
+    double uu = 0.0, du = 0.0;
+    if (x < 1.87) {
+      const double q = 1.0 / (x - 1.87), e = std::exp(1.1 * q), xm = std::pow(x, -16.0);
+      uu += 5.82 * (xm - 1.28) * e;
+      du += 5.82 * e * (-16.0 * xm / x - (xm - 1.28) * 1.1 * q * q);
+    }
+    if (x < 1.94) {
+      const double q = 1.0 / (x - 1.94), e = 1.28 * std::exp(0.27 * q);
+      uu += e;
+      du -= e * 0.27 * q * q;
+    }
+    *u = p[0] * uu;
+    *f = -p[0] * du / sig;
+  } else {  // Girifalco
+    const double x = r / sig, a = x - 1.0, b = x + 1.0;
+    auto br = [&](int k, double *v, double *dv) {
+      const double ak = std::pow(a, k), bk = std::pow(b, k), xk = std::pow(x, k + 1);
+      *v = 1.0 / (x * ak) + 1.0 / (x * bk) - 2.0 / xk;
+      *dv = -1.0 / (x * x * ak) - k / (x * ak * a) - 1.0 / (x * x * bk) - k / (x * bk * b) + 2.0 * (k + 1) / (xk * x);
+    };
+    double at, dat, rp, drp;
+    br(3, &at, &dat);
+    br(9, &rp, &drp);
+    *u = -p[0] * at + p[1] * rp;
+    *f = (p[0] * dat - p[1] * drp) / sig;
+  }
+}
+
 double rc_max(const srmd_system *s) {
   double m = s->coulomb ? s->rcc : 0.0;
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
@@ -207,7 +269,7 @@ double rc_max(const srmd_system *s) {
 // The method index the kernels are instantiated for: the Lennard-Jones cutoff
 // method, 3 for shifted-force Lennard-Jones plus shifted-force Coulomb, 4 for the
 // two-power potential (any cutoff method).
-int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->pot == 1 ? 4 : s->method; }
+int kmethod(const srmd_system *s) { return s->coulomb ? 3 : s->pot == 1 ? 4 : s->pot >= 2 ? 5 : s->method; }
 
 bool all_pairs_given(const srmd_system *s) {
   for (int a = 0; a < s->ntypes * s->ntypes; ++a)
@@ -346,6 +408,8 @@ srmd_status fill_const(srmd_system *s) {
     return fail(s, SRMD_EINVAL, "the all-pairs list build takes systems of at most 8192 particles and 8192 cells "
                                 "with the one-workgroup sort mode");
   c.list_blocks = std::max(1, std::min((s->n + 255) / 256, 2048));
+  c.pot_kind = s->pot >= 2 ? s->pot : 0;
+  c.sort_every = c.list_kind == 4 ? s->sort_every : 0;
   // list capacity: 1.5 x the mean count in a sphere of radius r_c + s, + 32 (rounded to 32)
   const double rho = s->n / V;
   int nmax = (int)std::ceil(1.5 * 4.0 / 3.0 * M_PI * reach * reach * reach * rho + 32.0);
@@ -394,6 +458,33 @@ srmd_status fill_const(srmd_system *s) {
       c.pt.mie_hn[a] = n / 2;
       c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)mie_u(s->rc[a], A, B, m, n, s->sigma[a]);
       c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)mie_f(s->rc[a], A, B, m, n, s->sigma[a]) : 0.0f;
+    }
+    if (s->pot >= 2) {
+      const double *q = s->gen_p[a], sg = s->sigma[a];
+      double uc, fcut;
+      further_uf(s->pot, q, sg, s->rc[a], &uc, &fcut);
+      c.pt.eps4[a] = c.pt.eps24[a] = 0.0f;
+      c.pt.ushift[a] = s->method == SRMD_CUT_TRUNC ? 0.0f : (float)uc;
+      c.pt.fc[a] = s->method == SRMD_CUT_SF ? (float)fcut : 0.0f;
+      float *g = c.pt.gen[a];
+      if (s->pot == 2) {
+        g[0] = (float)(q[0] * sg * std::exp(q[1] * sg));
+        g[1] = (float)q[1];
+      } else if (s->pot == 3) {
+        g[0] = (float)q[0];
+        g[1] = (float)(1.0 / q[1]);
+        g[2] = (float)q[2];
+      } else if (s->pot == 4) {
+        g[0] = (float)q[0];
+        g[1] = (float)(1.0 / (sg * sg));
+      } else if (s->pot == 5) {
+        g[0] = (float)q[0];
+        g[1] = (float)(1.0 / sg);
+      } else {
+        g[0] = (float)q[0];
+        g[1] = (float)q[1];
+        g[2] = (float)(1.0 / sg);
+      }
     }
   }
   return SRMD_OK;
@@ -758,6 +849,7 @@ struct srmd_batch {
   std::vector<srmd_system *> sys;
   std::vector<ReplicaDesc> host_desc;
   ReplicaDesc *d_desc = nullptr;
+  DevBuf desc_buf, jobs_buf, joboff_buf;  // device tables, from the allocator hook
   std::vector<CoopJob> jobs;     // per workgroup, in replica order
   std::vector<int> job_off;      // workgroup b runs jobs[job_off[b] .. job_off[b + 1])
   std::vector<int> pieces;       // workgroups of each replica
@@ -768,6 +860,7 @@ struct srmd_batch {
   hipStream_t stream = nullptr;
   int tp = 0, method = 0;
   size_t lds = 0;
+  int max_wg = 0;                // the caller's workgroup limit (0: none)
   std::string err;
 };
 
@@ -914,14 +1007,36 @@ srmd_status batch_plan(srmd_batch *b, int W) {
     b->job_off.push_back((int)b->jobs.size());
   }
   b->nwg = (int)per.size();
-  hipError_t e = hipMalloc(&b->d_jobs, sizeof(CoopJob) * b->jobs.size());
-  if (e == hipSuccess) e = hipMalloc(&b->d_job_off, sizeof(int) * b->job_off.size());
+  // the tables of an earlier plan are released once no launch can still read them
+  if (b->jobs_buf.ptr || b->joboff_buf.ptr) {
+    (void)hipStreamSynchronize(b->stream);
+    raw_free(b->jobs_buf);
+    raw_free(b->joboff_buf);
+  }
+  b->jobs_buf = raw_alloc(sizeof(CoopJob) * b->jobs.size());
+  b->joboff_buf = raw_alloc(sizeof(int) * b->job_off.size());
+  b->d_jobs = (CoopJob *)b->jobs_buf.ptr;
+  b->d_job_off = (int *)b->joboff_buf.ptr;
+  if (!b->d_jobs || !b->d_job_off) return bfail(b, SRMD_ENOMEM, "batch job tables: allocation failed");
+  hipError_t e = hipMemcpyAsync(b->d_jobs, b->jobs.data(), sizeof(CoopJob) * b->jobs.size(), hipMemcpyHostToDevice,
+                                b->stream);
   if (e == hipSuccess)
-    e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(CoopJob) * b->jobs.size(), hipMemcpyHostToDevice);
-  if (e == hipSuccess)
-    e = hipMemcpy(b->d_job_off, b->job_off.data(), sizeof(int) * b->job_off.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bfail(b, SRMD_ENOMEM, std::string("batch job tables: ") + hipGetErrorString(e));
+    e = hipMemcpyAsync(b->d_job_off, b->job_off.data(), sizeof(int) * b->job_off.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, SRMD_EHIP, std::string("batch job tables: ") + hipGetErrorString(e));
   return SRMD_OK;
+}
+
+// Descriptors and workgroup plan of the batch for the systems' current launch shapes
+// (all replicas share b->tp).
+srmd_status batch_replan(srmd_batch *b) {
+  srmd_status st = batch_sync_desc(b);
+  if (st != SRMD_OK) return st;
+  int W = multi_max_groups(b->tp, b->method, false, b->lds);
+  if (b->max_wg > 0) W = std::min(W, b->max_wg);
+  if (W < 1) return bfail(b, SRMD_EUNSUPPORTED, "the persistent kernel does not fit on the device");
+  return batch_plan(b, W);
 }
 
 // Put the call-start snapshot back after a list overflow (cur0: the position
@@ -1123,7 +1238,7 @@ srmd_status srmd_set_pair_lj(srmd_system *s, int32_t ti, int32_t tj, double sigm
     return fail(s, SRMD_EINVAL, "unknown cutoff method");
   if (s->method >= 0 && s->method != (int)method)
     return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
-  if (s->pot == 1) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (two-power set before)");
+  if (s->pot >= 1) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (another one set before)");
   for (int k = 0; k < 3; ++k)
     if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
       return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
@@ -1153,7 +1268,7 @@ srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, 
     return fail(s, SRMD_EINVAL, "unknown cutoff method");
   if (s->method >= 0 && s->method != (int)method)
     return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
-  if (s->pot == 0) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (Lennard-Jones set before)");
+  if (s->pot == 0 || s->pot >= 2) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential (another one set before)");
   for (int k = 0; k < 3; ++k)
     if (!(rcut + s->skin < 0.5 * (double)s->Lf[k]))
       return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
@@ -1168,6 +1283,46 @@ srmd_status srmd_set_pair_mie(srmd_system *s, int32_t ti, int32_t tj, double A, 
     s->mie_b[a] = B;
     s->mie_m[a] = m;
     s->mie_n[a] = n;
+    s->pair_given[a] = true;
+  }
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_pair_potential(srmd_system *s, int32_t ti, int32_t tj, srmd_potential kind,
+                                    const double *params, double sigma, double rcut, srmd_cutoff method) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (ti < 0 || tj < 0 || ti >= s->ntypes || tj >= s->ntypes) return fail(s, SRMD_EINVAL, "type index out of range");
+  const int k = (int)kind;
+  if (k < SRMD_POT_YUKAWA || k > SRMD_POT_GIRIFALCO) return fail(s, SRMD_EINVAL, "unknown potential kind");
+  if (!params) return fail(s, SRMD_EINVAL, "params is NULL");
+  if (!(sigma > 0) || !std::isfinite(sigma) || !(rcut > 0) || !std::isfinite(rcut))
+    return fail(s, SRMD_EINVAL, "sigma and rcut must be positive");
+  double p[4] = {params[0], params[1], params[2], params[3]};
+  for (double v : p)
+    if (!std::isfinite(v)) return fail(s, SRMD_EINVAL, "parameters must be finite");
+  if (k == SRMD_POT_YUKAWA && !(p[1] >= 0 && p[1] * sigma <= 60.0))
+    return fail(s, SRMD_EINVAL, "Yukawa: kappa >= 0 and kappa sigma <= 60");
+  if (k == SRMD_POT_BUCKINGHAM && !(p[0] >= 0 && p[1] > 0 && p[2] >= 0))
+    return fail(s, SRMD_EINVAL, "Buckingham: A >= 0, rho > 0, C >= 0");
+  if (k == SRMD_POT_GIRIFALCO && !(rcut > sigma))
+    return fail(s, SRMD_EINVAL, "Girifalco: rcut must exceed the diameter sigma");
+  if (method != SRMD_CUT_TRUNC && method != SRMD_CUT_SP && method != SRMD_CUT_SF)
+    return fail(s, SRMD_EINVAL, "unknown cutoff method");
+  if (s->method >= 0 && s->method != (int)method)
+    return fail(s, SRMD_EINVAL, "all type pairs must use the same cutoff method");
+  if (s->pot >= 0 && s->pot != k) return fail(s, SRMD_EINVAL, "all type pairs must use the same potential");
+  for (int q = 0; q < 3; ++q)
+    if (!(rcut + s->skin < 0.5 * (double)s->Lf[q]))
+      return fail(s, SRMD_EINVAL, "cutoff + skin must stay below half of every box side");
+  s->method = (int)method;
+  s->pot = k;
+  for (int pass = 0; pass < 2; ++pass) {
+    const int a = pass ? pair_index(s, tj, ti) : pair_index(s, ti, tj);
+    s->sigma[a] = sigma;
+    s->eps[a] = 0.0;
+    s->rc[a] = rcut;
+    for (int q = 0; q < 4; ++q) s->gen_p[a][q] = p[q];
     s->pair_given[a] = true;
   }
   s->dirty = true;
@@ -1268,6 +1423,14 @@ srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t lis
     return fail(s, SRMD_EINVAL, "sort mode must be 0 (auto), 1 or 2 and list mode 0 (auto), 1, 2, 3 or 4");
   s->sort_mode = sort_mode;
   s->list_mode = list_mode;
+  s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (builds < 0) return fail(s, SRMD_EINVAL, "the sort interval must be >= 0");
+  s->sort_every = builds;
   s->dirty = true;
   return SRMD_OK;
 }
@@ -1966,10 +2129,10 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
 
 // ---------------------------------------------------------------------------
 // Tuned-parameter file (paper appendix, step 8).  One text line per record:
-//   srmd-tuning-v2 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
+//   srmd-tuning-v3 gpu=<name> cus=<n> prec=<p> method=<m> thermostat=<t> ntypes=<k>
 //   count=<c_0,...> dt=<x> temperature=<x> density=<x> sigma=<k*k values>
 //   epsilon=<k*k values> rcut=<k*k values> potential=<n> param=<4*k*k values>
-//   charge=<k values> rcc=<x> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x>
+//   charge=<k values> rcc=<x> tp=<n> ppb=<n> list=<n> persistent=<n> skin=<x> sort=<n>
 // (records of another version are skipped)
 // Floating-point fields are printed with 17 significant digits, so they read back
 // to the same double.
@@ -1977,7 +2140,7 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
 
 namespace {
 
-constexpr const char *kTuneTag = "srmd-tuning-v2";
+constexpr const char *kTuneTag = "srmd-tuning-v3";
 constexpr double kTuneRelTol = 1e-6;   // dt, density and pair parameters
 constexpr double kTuneTempTol = 0.02;  // temperature
 
@@ -1996,7 +2159,7 @@ bool tuning_valid(const srmd_tuning &t) {
   const bool tp_ok = t.tp >= 1 && t.tp <= 64 && (t.tp & (t.tp - 1)) == 0;
   const bool ppb_ok = t.ppb >= 1 && (long long)t.tp * t.ppb <= 1024 && (t.tp * t.ppb) % 64 == 0;
   return tp_ok && ppb_ok && t.list_mode >= 1 && t.list_mode <= 4 && (t.persistent == 0 || t.persistent == -1) &&
-         t.skin >= 0 && std::isfinite(t.skin);
+         t.skin >= 0 && std::isfinite(t.skin) && t.sort_every >= 0;
 }
 
 bool key_match(const srmd_tuning_key &a, const srmd_tuning_key &b) {
@@ -2063,6 +2226,7 @@ std::string tuning_line(const srmd_tuning_key &k, const srmd_tuning &t) {
   field("list", std::to_string(t.list_mode));
   field("persistent", std::to_string(t.persistent));
   field("skin", num(t.skin));
+  field("sort", std::to_string(t.sort_every));
   return o;
 }
 
@@ -2146,15 +2310,16 @@ bool parse_tuning_line(const std::string &line, srmd_tuning_key *k, srmd_tuning 
   }
   {
     auto pi = kv.find("param"), qi = kv.find("charge");
-    if (!one_int("potential", &v[0]) || v[0] < 0 || v[0] > 1 || pi == kv.end() || qi == kv.end() ||
+    if (!one_int("potential", &v[0]) || v[0] < 0 || v[0] > 6 || pi == kv.end() || qi == kv.end() ||
         !parse_list(pi->second, 4 * nt * nt, &k->pot_param[0][0], nullptr) ||
         !parse_list(qi->second, nt, k->charge, nullptr) || !one_num("rcc", &k->rc_coulomb))
       return false;
     k->potential = (int32_t)v[0];
   }
   if (!one_int("tp", &v[0]) || !one_int("ppb", &v[1]) || !one_int("list", &v[2]) || !one_int("persistent", &v[3]) ||
-      !one_num("skin", &t->skin))
+      !one_num("skin", &t->skin) || !one_int("sort", &v[4]) || v[4] < 0 || v[4] > (1 << 20))
     return false;
+  t->sort_every = (int32_t)v[4];
   for (int q = 0; q < 4; ++q)
     if (v[q] < -1 || v[q] > 1024) return false;
   t->tp = (int32_t)v[0];
@@ -2256,9 +2421,11 @@ srmd_status srmd_tuning_key_of(srmd_system *s, srmd_tuning_key *key) {
         key->pot_param[q][1] = s->mie_b[pi];
         key->pot_param[q][2] = s->mie_m[pi];
         key->pot_param[q][3] = s->mie_n[pi];
+      } else if (s->pot >= 2) {
+        for (int r = 0; r < 4; ++r) key->pot_param[q][r] = s->gen_p[pi][r];
       }
     }
-  key->potential = s->pot == 1 ? 1 : 0;
+  key->potential = s->pot >= 1 ? s->pot : 0;
   if (s->coulomb) {
     for (int t = 0; t < s->ntypes; ++t) key->charge[t] = s->charge[t];
     key->rc_coulomb = s->rcc;
@@ -2278,6 +2445,7 @@ void apply_tuning(srmd_system *s, const srmd_tuning &t) {
   s->persist_req = t.persistent;
   s->persist_set = true;
   s->skin = t.skin;
+  s->sort_every = t.sort_every;
   s->dirty = true;
 }
 
@@ -2338,7 +2506,9 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
   const bool pset0 = s->persist_set;
   const int nmax0 = s->n_max;
   const double skin0 = s->skin;
+  const int sort0 = s->sort_every;
   const bool persist0 = pset0 ? preq0 != 0 : s->persist_tuned != 0;
+  int sort_trial = sort0;  // the re-sort interval of the all-pairs lists in the trials
   hipEvent_t e0, e1;
   HIPCHK(s, hipEventCreate(&e0));
   HIPCHK(s, hipEventCreate(&e1));
@@ -2355,6 +2525,7 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
     s->persist_set = true;
     s->persist_req = persistent ? -1 : 0;
     s->skin = skin;
+    s->sort_every = sort_trial;
     s->n_max = nmax0;  // the list capacity follows the trial's skin
     s->dirty = true;
     srmd_status r = restore_host_state(s, saved);
@@ -2492,6 +2663,26 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
       if (slower >= 3 || t > 1.05 * pbest) break;
     }
   }
+  // step 5: with the all-pairs lists chosen, the interval of their periodic spatial
+  // re-sort (in list builds; 0: never), a single minimum from the longest interval down
+  best.sort_every = sort0;
+  if (result == SRMD_OK && best_t < 1e30 && best.list_mode == 4) {
+    const int intervals[] = {0, 64, 16, 4, 1};
+    for (int q = 0; q < 5 && result == SRMD_OK; ++q) {
+      if (intervals[q] == best.sort_every) continue;
+      sort_trial = intervals[q];
+      double t;
+      result = trial(best.tp, best.ppb, 4, best.persistent != 0, best.skin, &t);
+      if (result != SRMD_OK) break;
+      if (t < best_t) {
+        best_t = t;
+        best.sort_every = intervals[q];
+      } else if (intervals[q] < best.sort_every || best.sort_every == 0) {
+        if (q > 1) break;  // past the minimum
+      }
+    }
+    sort_trial = best.sort_every;
+  }
   // step 7: the chosen set, timed as the baseline was
   double t_final = 1e30;
   if (result == SRMD_OK && best_t < 1e30)
@@ -2504,6 +2695,7 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
   s->persist_req = preq0;
   s->persist_set = pset0;
   s->skin = skin0;
+  s->sort_every = sort0;
   s->n_max = nmax0;
   if (result == SRMD_OK && !(best_t < 1e30)) result = fail(s, SRMD_ESTATE, "no trial of the autotuner completed");
   if (result == SRMD_OK) apply_tuning(s, best);
@@ -2557,15 +2749,14 @@ srmd_status srmd_batch_create_limited(srmd_batch **out, srmd_system *const *syst
   b->lds = batch_lds_bytes(nmax);
   b->host_desc.assign((size_t)count, ReplicaDesc{});
   std::memset(b->host_desc.data(), 0xff, sizeof(ReplicaDesc) * (size_t)count);  // forces the first upload
-  if (hipMalloc(&b->d_desc, sizeof(ReplicaDesc) * (size_t)count) != hipSuccess) {
+  b->desc_buf = raw_alloc(sizeof(ReplicaDesc) * (size_t)count);
+  b->d_desc = (ReplicaDesc *)b->desc_buf.ptr;
+  if (!b->d_desc) {
     srmd_batch_destroy(b);
     return bfail(nullptr, SRMD_ENOMEM, "batch descriptor allocation failed");
   }
-  srmd_status st = batch_sync_desc(b);
-  int W = multi_max_groups(b->tp, b->method, false, b->lds);
-  if (max_workgroups > 0) W = std::min(W, max_workgroups);
-  if (st == SRMD_OK && W < 1) st = bfail(b, SRMD_EUNSUPPORTED, "the persistent kernel does not fit on the device");
-  if (st == SRMD_OK) st = batch_plan(b, W);
+  b->max_wg = max_workgroups;
+  srmd_status st = batch_replan(b);
   if (st != SRMD_OK) {
     std::string m = b->err;
     srmd_batch_destroy(b);
@@ -2644,12 +2835,118 @@ srmd_status srmd_batch_step(srmd_batch *b, int64_t nsteps, int32_t thermo_every,
   return result;
 }
 
+srmd_status srmd_batch_autotune(srmd_batch *b, int32_t steps_per_trial, int32_t *tp_out, int32_t *ppb_out) {
+  if (!b) return bfail(nullptr, SRMD_EINVAL, "batch is NULL");
+  if (steps_per_trial < 1) return bfail(b, SRMD_EINVAL, "steps_per_trial must be >= 1");
+  const size_t R = b->sys.size();
+  // the stored configuration every trial starts from (paper appendix)
+  std::vector<HostState> saved(R);
+  for (size_t r = 0; r < R; ++r) {
+    srmd_system *s = b->sys[r];
+    srmd_status st = prepare(s);
+    if (st == SRMD_OK) st = save_host_state(s, &saved[r]);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+  }
+  // replicas in size buckets (quartiles of N): each bucket gets its own block size
+  std::vector<int> order(R);
+  for (size_t r = 0; r < R; ++r) order[r] = (int)r;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return b->sys[x]->n < b->sys[y]->n; });
+  const int nb = (int)std::min<size_t>(4, R);
+  std::vector<int> bucket(R);
+  for (size_t q = 0; q < R; ++q) bucket[(size_t)order[q]] = (int)(q * (size_t)nb / R);
+  const int kThreads[] = {64, 128, 256, 512, 1024};
+  auto ok_shape = [](int tp, int threads) { return threads % tp == 0 && threads >= tp && threads <= 1024; };
+  // one timed trial: every replica at threads-per-block thr[bucket] and tp, from the stored state
+  auto trial = [&](int tp, const std::vector<int> &thr, double *ms) -> srmd_status {
+    for (size_t r = 0; r < R; ++r) {
+      srmd_system *s = b->sys[r];
+      s->tp_req = tp;
+      s->ppb_req = thr[(size_t)bucket[r]] / tp;
+      s->dirty = true;
+      srmd_status st = restore_host_state(s, saved[r]);
+      if (st == SRMD_OK) st = prepare(s);
+      if (st != SRMD_OK) return bfail(b, st, s->err);
+    }
+    b->tp = tp;
+    srmd_status st = batch_replan(b);
+    if (st == SRMD_EUNSUPPORTED) {  // a resource limit: this shape cannot run
+      *ms = 1e30;
+      return SRMD_OK;
+    }
+    if (st != SRMD_OK) return st;
+    st = srmd_batch_step(b, std::min(steps_per_trial, 50), 0, nullptr, 0);  // first build, untimed
+    if (st != SRMD_OK) return st;
+    const auto t0 = std::chrono::steady_clock::now();
+    st = srmd_batch_step(b, steps_per_trial, 0, nullptr, 0);
+    if (st != SRMD_OK) return st;
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / steps_per_trial;
+    return SRMD_OK;
+  };
+  std::vector<int> thr((size_t)nb, 256);
+  int best_tp = 0;
+  double best = 1e30;
+  // t_p from 1 up at 256 threads per block; the appendix's stop rules: three trials in
+  // a row slower than the best, or one 5 % slower, or a resource limit
+  int worse = 0;
+  for (int tp = 1; tp <= 64; tp *= 2) {
+    if (!multi_max_groups(tp, b->method, false, b->lds)) break;
+    double ms;
+    srmd_status st = trial(tp, thr, &ms);
+    if (st != SRMD_OK) return st;
+    if (ms >= 1e30) break;
+    if (ms < best) {
+      best = ms;
+      best_tp = tp;
+      worse = 0;
+    } else if (++worse >= 3 || ms > 1.05 * best) {
+      break;
+    }
+  }
+  if (!best_tp) return bfail(b, SRMD_EUNSUPPORTED, "no thread layout of the batch could run");
+  // threads per block per bucket (the appendix's p_b loop; replicas of one bucket share
+  // it), the rest fixed at their best; a bucket's loop stops 10 % above its best
+  for (int k = 0; k < nb; ++k) {
+    int best_thr = thr[(size_t)k];
+    for (int t : kThreads) {
+      if (t == best_thr || !ok_shape(best_tp, t)) continue;
+      std::vector<int> cand = thr;
+      cand[(size_t)k] = t;
+      double ms;
+      srmd_status st = trial(best_tp, cand, &ms);
+      if (st != SRMD_OK) return st;
+      if (ms < best) {
+        best = ms;
+        best_thr = t;
+      } else if (ms > 1.10 * best && t > best_thr) {
+        break;
+      }
+    }
+    thr[(size_t)k] = best_thr;
+  }
+  // the chosen layout becomes each replica's launch shape; the stored state is put back
+  for (size_t r = 0; r < R; ++r) {
+    srmd_system *s = b->sys[r];
+    s->tp_req = best_tp;
+    s->ppb_req = thr[(size_t)bucket[r]] / best_tp;
+    s->dirty = true;
+    srmd_status st = restore_host_state(s, saved[r]);
+    if (st == SRMD_OK) st = prepare(s);
+    if (st != SRMD_OK) return bfail(b, st, s->err);
+    if (ppb_out) ppb_out[r] = s->ppb_req;
+  }
+  b->tp = best_tp;
+  srmd_status st = batch_replan(b);
+  if (st != SRMD_OK) return st;
+  if (tp_out) *tp_out = best_tp;
+  return SRMD_OK;
+}
+
 srmd_status srmd_batch_destroy(srmd_batch *b) {
   if (!b) return SRMD_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  if (b->d_desc) (void)hipFree(b->d_desc);
-  if (b->d_jobs) (void)hipFree(b->d_jobs);
-  if (b->d_job_off) (void)hipFree(b->d_job_off);
+  raw_free(b->desc_buf);
+  raw_free(b->jobs_buf);
+  raw_free(b->joboff_buf);
   delete b;
   return SRMD_OK;
 }

@@ -38,6 +38,9 @@ struct PairTable {
   // travel in eps4 and eps24): B, n B and the half exponents m/2, n/2
   float mie_b[kMaxPairs], mie_nb[kMaxPairs];
   int mie_hm[kMaxPairs], mie_hn[kMaxPairs];
+  // further potentials (kernel method 5, kind in SysConst::pot_kind): four float32
+  // constants per pair derived from the parameters (see pair_further)
+  float gen[kMaxPairs][4];
 };
 
 // Everything a kernel needs besides pointers; passed by value.
@@ -67,6 +70,8 @@ struct SysConst {
   int small_sort;    // 1: the spatial sort runs in one workgroup (small systems)
   int list_kind;     // list builder of the launch chain: 1 wave per particle, 2 thread per particle, 3 wave per cell
   int list_blocks;   // grid of the thread-per-particle list build and the sort kernels
+  int pot_kind;      // kernel method 5: 2 Yukawa, 3 Buckingham, 4 Gaussian core, 5 Dzugutov, 6 Girifalco
+  int sort_every;    // all-pairs lists (list_kind 4): spatial sort at every k-th build (0: never)
   int pad1;
   float inv_mass[kMaxTypes];
   double mass[kMaxTypes];
@@ -89,7 +94,8 @@ struct Control {
   double xi_int;           // its time integral
   unsigned long long prof_ticks;  // accumulated step-kernel durations (device clock ticks)
   long long prof_count;           // step kernels accumulated
-  int pad[42];
+  int resorted;                   // all-pairs lists: the build ahead starts from a fresh spatial sort
+  int pad[41];
 };
 
 static_assert(sizeof(Control) == 256, "control block layout");

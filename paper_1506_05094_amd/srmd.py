@@ -20,6 +20,7 @@ SRMD_OK, SRMD_EINVAL, SRMD_ENOMEM, SRMD_EHIP, SRMD_ESTATE, SRMD_EUNSUPPORTED = 0
 SRMD_CUT_TRUNC, SRMD_CUT_SP, SRMD_CUT_SF = 0, 1, 2
 SRMD_PREC_F32, SRMD_PREC_F32_KAHAN, SRMD_PREC_F64POS = 0, 1, 2
 CUTOFF = {"trunc": SRMD_CUT_TRUNC, "sp": SRMD_CUT_SP, "sf": SRMD_CUT_SF}
+POTENTIALS = {"yukawa": 2, "buckingham": 3, "gaussian": 4, "dzugutov": 5, "girifalco": 6}
 PRECISION = {"f32": SRMD_PREC_F32, "f32_kahan": SRMD_PREC_F32_KAHAN, "f64pos": SRMD_PREC_F64POS}
 
 
@@ -102,7 +103,8 @@ class srmd_tuning(ctypes.Structure):
     _fields_ = [("tp", ctypes.c_int32), ("ppb", ctypes.c_int32), ("list_mode", ctypes.c_int32),
                 ("persistent", ctypes.c_int32), ("skin", ctypes.c_double),
                 ("baseline_ms_per_step", ctypes.c_double), ("tuned_ms_per_step", ctypes.c_double),
-                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32)]
+                ("trials", ctypes.c_int32), ("from_cache", ctypes.c_int32), ("sort_every", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -165,17 +167,21 @@ def load():
         "srmd_set_coulomb_sf": (st, [sysp, _dp, ctypes.c_double]),
         "srmd_set_pair_mie": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
+        "srmd_set_pair_potential": (st, [sysp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int, _dp, ctypes.c_double,
+                                         ctypes.c_double, ctypes.c_int]),
         "srmd_set_integrator_nve": (st, [sysp, ctypes.c_double]),
         "srmd_set_integrator_nvt": (st, [sysp, ctypes.c_double, ctypes.c_double, ctypes.c_double]),
         "srmd_set_launch": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_get_launch": (st, [sysp, _ip, _ip]),
         "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_set_persistent": (st, [sysp, ctypes.c_int32]),
+        "srmd_set_sort_interval": (st, [sysp, ctypes.c_int32]),
         "srmd_batch_create": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
         "srmd_batch_create_limited": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.c_int32, ctypes.c_int32]),
         "srmd_batch_step": (st, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, _vp, ctypes.c_int64]),
         "srmd_batch_destroy": (st, [ctypes.c_void_p]),
+        "srmd_batch_autotune": (st, [ctypes.c_void_p, ctypes.c_int32, _ip, _ip]),
         "srmd_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
         "srmd_autotune": (st, [sysp, ctypes.c_int32, _ip, _ip]),
         "srmd_tuning_key_of": (st, [sysp, ctypes.POINTER(srmd_tuning_key)]),
@@ -320,6 +326,21 @@ class System:
                 _check(lib.srmd_set_pair_mie(self._h, a, b, float(A[a, b]), float(B[a, b]), int(m[a, b]),
                                              int(n[a, b]), float(sigma[a, b]), float(rc[a, b]), mth), self._h)
 
+    def set_pairs_potential(self, kind, params, sigma, rc, method):
+        """A further potential (srmd_set_pair_potential) for every type pair: kind a name
+        of POTENTIALS, params ntypes x ntypes x 4, sigma and rc ntypes x ntypes."""
+        lib = load()
+        k = POTENTIALS[kind] if isinstance(kind, str) else int(kind)
+        mth = CUTOFF[method] if isinstance(method, str) else int(method)
+        nt = self.ntypes
+        params = np.asarray(params, np.float64).reshape(nt, nt, 4)
+        sigma, rc = (np.asarray(x, np.float64).reshape(nt, nt) for x in (sigma, rc))
+        for a in range(nt):
+            for b in range(a, nt):
+                p = np.ascontiguousarray(params[a, b])
+                _check(lib.srmd_set_pair_potential(self._h, a, b, k, _ptr(p, _dp), float(sigma[a, b]),
+                                                   float(rc[a, b]), mth), self._h)
+
     def set_coulomb_sf(self, charges, rcut):
         """Shifted-force Coulomb term (paper section 9): one charge per type, one cutoff;
         charges=None removes it."""
@@ -345,6 +366,10 @@ class System:
         1 wave per particle, 2 thread per particle, 3 wave per cell, 4 all pairs (small
         systems, no sort).  Every mode gives the same pair set."""
         _check(load().srmd_set_rebuild_path(self._h, int(sort_mode), int(list_mode)), self._h)
+
+    def set_sort_interval(self, builds):
+        """All-pairs lists: spatial re-sort before every builds-th list build (0: never)."""
+        _check(load().srmd_set_sort_interval(self._h, int(builds)), self._h)
 
     def set_persistent(self, groups=-1):
         """Run steps as persistent launches of 500 steps each (groups > 0 workgroups,
@@ -495,6 +520,14 @@ class Batch:
         _bcheck(lib.srmd_batch_step(self._h, int(nsteps), 0, None, 0), self._h)
         return None
 
+    def autotune(self, steps_per_trial=200):
+        """srmd_batch_autotune: returns (tp, particles per block of each replica)."""
+        tp = ctypes.c_int32()
+        ppb = np.zeros(len(self.systems), np.int32)
+        _bcheck(load().srmd_batch_autotune(self._h, int(steps_per_trial), ctypes.byref(tp), _ptr(ppb, _ip)),
+                self._h)
+        return tp.value, ppb
+
     def close(self):
         if getattr(self, "_h", None):
             load().srmd_batch_destroy(self._h)
@@ -517,15 +550,16 @@ class Batch:
         self.close()
 
 
-EXPORTED = ["srmd_create", "srmd_destroy", "srmd_set_allocator", "srmd_set_pair_lj", "srmd_set_skin",
-            "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch", "srmd_get_launch",
-            "srmd_autotune", "srmd_tuning_key_of", "srmd_tuning_cache_find", "srmd_tuning_cache_store",
-            "srmd_autotune_full", "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_step", "srmd_get_state",
-            "srmd_set_state", "srmd_get_neighbor_pairs", "srmd_get_thermo", "srmd_get_box", "srmd_last_error",
-            "srmd_get_stats", "srmd_profile_step_kernel", "srmd_get_particle_terms", "srmd_save_state", "srmd_load_state", "srmd_compute_forces_noalloc", "srmd_set_rebuild_path", "srmd_set_persistent",
-            "srmd_batch_create", "srmd_batch_create_limited",
-            "srmd_batch_step", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_set_coulomb_sf",
-            "srmd_set_pair_mie"]
+EXPORTED = ["srmd_autotune", "srmd_autotune_full", "srmd_batch_autotune", "srmd_batch_create",
+            "srmd_batch_create_limited", "srmd_batch_destroy", "srmd_batch_last_error", "srmd_batch_step",
+            "srmd_build_neighbor_list", "srmd_compute_forces", "srmd_compute_forces_noalloc", "srmd_create",
+            "srmd_destroy", "srmd_get_box", "srmd_get_launch", "srmd_get_neighbor_pairs",
+            "srmd_get_particle_terms", "srmd_get_state", "srmd_get_stats", "srmd_get_thermo", "srmd_last_error",
+            "srmd_load_state", "srmd_profile_step_kernel", "srmd_save_state", "srmd_set_allocator",
+            "srmd_set_coulomb_sf", "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch",
+            "srmd_set_pair_lj", "srmd_set_pair_mie", "srmd_set_pair_potential", "srmd_set_persistent",
+            "srmd_set_rebuild_path", "srmd_set_skin", "srmd_set_sort_interval", "srmd_set_state", "srmd_step",
+            "srmd_tuning_cache_find", "srmd_tuning_cache_store", "srmd_tuning_key_of"]
 
 
 def _export_c_names():

@@ -190,3 +190,49 @@ def test_batch_mixed_block_sizes():
         np.testing.assert_array_equal(x.get_state()["pos"], y.get_state()["pos"])
         x.close()
         y.close()
+
+
+def test_batch_autotune_keeps_states_and_bitwise_replicas():
+    """srmd_batch_autotune (paper appendix, per replica size bucket): the states are
+    put back, the chosen shape is every replica's launch shape, and each batched
+    replica then follows its single-system run at that shape bit for bit."""
+    from paper_1506_05094_amd import srmd
+    states = [gen.ka_random_state(n, 1.2, T, seed) for (n, T, seed) in
+              [(600, 0.5, 21), (900, 0.6, 22), (1500, 0.7, 23), (2100, 0.8, 24), (3000, 0.9, 25), (4000, 1.0, 26)]]
+    sig, eps, rc = gen.ka_params()
+
+    def mk(st, T, launch=None):
+        s = make_system(st, sig, eps, rc, "sf", launch=launch)
+        s.set_integrator_nvt(0.002, T, 0.2)
+        return s
+
+    temps = [0.5, 0.6, 0.7, 0.8, 0.9, 1.0]
+    systems = [mk(st, T) for st, T in zip(states, temps)]
+    for s in systems:
+        s.step(20)
+    before = [s.get_state() for s in systems]
+    with srmd.Batch(systems) as b:
+        tp, ppb = b.autotune(40)
+        print(f"tuned tp={tp} ppb={list(ppb)}", flush=True)
+        assert tp in (1, 2, 4, 8, 16, 32, 64)
+        for s, p in zip(systems, ppb):
+            assert s.get_launch() == (tp, int(p)) and (tp * p) % 64 == 0 and tp * p <= 1024
+        for s, st0 in zip(systems, before):
+            now = s.get_state()
+            np.testing.assert_array_equal(now["pos"], st0["pos"])
+            np.testing.assert_array_equal(now["vel"], st0["vel"])
+        blobs = [s.save_state() for s in systems]
+        b.step(120)
+    # single-system runs at the tuned shapes from the same full states
+    singles = []
+    for blob, st, T, p in zip(blobs, states, temps, ppb):
+        s = mk(st, T, launch=(tp, int(p)))
+        s.load_state(blob)
+        singles.append(s)
+    for s, x in zip(singles, systems):
+        s.step(120)
+        a, c = s.get_state(), x.get_state()
+        for k in ("pos", "vel", "image", "force"):
+            np.testing.assert_array_equal(a[k], c[k], err_msg=k)
+    for s in systems + singles:
+        s.close()

@@ -427,3 +427,56 @@ def test_autotune_restores_state_and_keeps_parity():
     Fr, _, _, U, W = oracle.forces_f32(after["pos"], state.types, state.box, sig, eps, rc, "sf")
     assert force_error(F, Fr) <= FORCE_TOL
     assert rel(th["pe"], U) <= ENERGY_TOL
+
+
+@pytest.mark.parametrize("every", [1, 3])
+def test_all_pairs_periodic_resort(every):
+    """All-pairs lists with the periodic spatial re-sort (the n2 method's sort
+    interval): the pair set stays bit-exact against the oracle after re-sorted
+    builds, the forces at parity, and the launch chain and the persistent kernel
+    follow the same trajectory bit for bit."""
+    state = gen.config1_state()
+    sig, eps, rc = gen.ka_params()
+
+    def mk(persistent):
+        s = make_system(state, sig, eps, rc, "sf", launch=(8, 32))
+        s.set_rebuild_path(1, 4)
+        s.set_sort_interval(every)
+        s.set_integrator_nvt(0.005, 0.45, 0.2)
+        if persistent:
+            s.set_persistent(-1)
+        return s
+
+    with mk(False) as a, mk(True) as b:
+        a.step(150)
+        b.step(150)
+        assert a.stats()["n_rebuilds"] > 4
+        sa, sb = a.get_state(), b.get_state()
+        np.testing.assert_array_equal(sa["pos"], sb["pos"])
+        np.testing.assert_array_equal(sa["vel"], sb["vel"])
+        a.build_neighbor_list()
+        pairs = a.neighbor_pairs()
+        th = a.compute_forces()
+        F = a.get_state()["force"]
+    cs2, _ = oracle.cut_tables(rc, 0.3)
+    np.testing.assert_array_equal(pairs, oracle.pair_set(sa["pos"], state.types, state.box, cs2))
+    Fr, _, _, U, W = oracle.forces_f32(sa["pos"], state.types, state.box, sig, eps, rc, "sf")
+    assert force_error(F, Fr) <= FORCE_TOL
+    assert rel(th["pe"], U) <= ENERGY_TOL
+
+
+def test_all_pairs_resort_changes_order_not_physics():
+    """A re-sort every build gives the sorted order of the cell methods; without it the
+    particles keep their creation order.  Both runs stay at parity with each other
+    (same physics, other float32 summation order)."""
+    state = gen.config1_state()
+    sig, eps, rc = gen.ka_params()
+    res = {}
+    for every in (0, 1):
+        with make_system(state, sig, eps, rc, "sf", launch=(8, 32)) as s:
+            s.set_rebuild_path(1, 4)
+            s.set_sort_interval(every)
+            s.set_integrator_nvt(0.002, 0.45, 0.2)
+            tr = s.step(20, thermo_every=1)
+            res[every] = tr
+    np.testing.assert_allclose(res[0]["pe"], res[1]["pe"], rtol=1e-5)

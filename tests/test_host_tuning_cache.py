@@ -38,6 +38,17 @@ def test_missing_file_is_no_match(srmd, tmp_path):
     assert srmd.tuning_cache_find(str(tmp_path / "none.txt"), _key()) is None
 
 
+def test_sort_interval_round_trip(srmd, tmp_path):
+    path = str(tmp_path / "tuned.txt")
+    srmd.tuning_cache_store(path, _key(), {**_tuning(), "list_mode": 4, "sort_every": 16})
+    got = srmd.tuning_cache_find(path, _key())
+    assert got["list_mode"] == 4 and got["sort_every"] == 16
+    good = open(path).read().strip()
+    with open(path, "a") as f:
+        f.write(good.replace(" sort=16", " sort=-1").replace(" tp=16", " tp=8") + "\n")  # damaged: skipped
+    assert srmd.tuning_cache_find(path, _key())["tp"] == 16
+
+
 def test_round_trip_is_exact(srmd, tmp_path):
     path = str(tmp_path / "tuned.txt")
     srmd.tuning_cache_store(path, _key(), _tuning())
@@ -47,7 +58,7 @@ def test_round_trip_is_exact(srmd, tmp_path):
     assert got["skin"] == 0.3 + 1e-13  # 17 significant digits read back to the same double
     assert got["baseline_ms_per_step"] == 0.0 and got["tuned_ms_per_step"] == 0.0
     line = open(path).read()
-    assert line.startswith("srmd-tuning-v2 ") and line.count("\n") == 1 and "count=3277,819" in line
+    assert line.startswith("srmd-tuning-v3 ") and line.count("\n") == 1 and "count=3277,819" in line
 
 
 @pytest.mark.parametrize("field,value,match", [
@@ -145,7 +156,7 @@ def test_damaged_lines_are_skipped(srmd, tmp_path):
     bad = [
         "garbage",
         "",
-        good.replace("srmd-tuning-v2", "srmd-tuning-v1"),  # older record format
+        good.replace("srmd-tuning-v3", "srmd-tuning-v2"),  # older record format
         good.replace(" tp=4", " tp=3"),              # not a power of two
         good.replace(" ppb=64", " ppb=40"),          # tp * ppb not a multiple of 64
         good.replace(" list=1", " list=7"),
@@ -190,4 +201,4 @@ def test_invalid_arguments(srmd, tmp_path):
 def test_struct_layouts(srmd):
     assert ctypes.sizeof(srmd.srmd_tuning_key) == (64 + 6 * 4 + 4 * 8 + 3 * 8 + 3 * 16 * 8 + 2 * 4 + 64 * 8
                                                    + 4 * 8 + 8)
-    assert ctypes.sizeof(srmd.srmd_tuning) == 4 * 4 + 3 * 8 + 2 * 4
+    assert ctypes.sizeof(srmd.srmd_tuning) == 4 * 4 + 3 * 8 + 4 * 4
