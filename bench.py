@@ -404,6 +404,10 @@ def main():
                     help="persistent: 500 steps per launch of one kernel (systems up to 8192 particles here); "
                          "chain: graph-captured launch chains")
     ap.add_argument("--groups", type=int, default=-1, help="workgroups of the persistent kernel (-1: automatic)")
+    ap.add_argument("--list-mode", type=int, default=0,
+                    help="list builder (0 automatic, 1 wave, 2 thread, 3 cell, 4 all pairs)")
+    ap.add_argument("--sort-interval", type=int, default=0,
+                    help="all-pairs lists: spatial re-sort before every k-th build (0: never)")
     ap.add_argument("--profile-steps", type=int, default=1000,
                     help="steps of the untimed pass that times the dominant kernel's launches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -449,6 +453,10 @@ def main():
         s.set_coulomb_sf(params[3], params[4])
     if args.tp:
         s.set_launch(args.tp, args.ppb or max(1, 256 // args.tp))
+    if args.list_mode:
+        s.set_rebuild_path(0, args.list_mode)
+    if args.sort_interval:
+        s.set_sort_interval(args.sort_interval)
     persistent = args.mode == "persistent" and state.n <= 8192
     if not (args.tune or args.tune_full):
         s.set_persistent(args.groups if persistent else 0)
@@ -543,7 +551,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"], mode="persistent" if persistent else "chain",
-                       groups=st1["persistent_groups"]),
+                       groups=st1["persistent_groups"], list_mode=args.list_mode or "automatic",
+                       sort_interval=args.sort_interval),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],
         "final_temperature": th["temperature"],
