@@ -98,7 +98,11 @@ def test_short_trajectory_and_forms_agree(kind):
     ref = oracle.integrate(st.pos, st.vel, st.types, st.mass, st.box, sig, one, rc, "sf", 0.002, 10,
                            pot=(kind, params))
     assert np.abs(min_image(sa["pos"].astype(np.float64) - ref["pos"], st.box)).max() <= 1e-4
-    np.testing.assert_allclose(tr["pe"], ref["thermo"][:, 0], rtol=1e-5)
+    # the float32 pair energies carry ~1e-6 relative error each; where attractive and
+    # repulsive pairs cancel in the total (the Dzugutov start: the total is a quarter
+    # of the sum of per-particle magnitudes), the bound is relative to that sum
+    _, pe_i, _, _, _ = oracle.forces_f32(st.pos, st.types, st.box, sig, one, rc, "sf", pot=(kind, params))
+    assert np.abs(tr["pe"] - ref["thermo"][:, 0]).max() <= 1e-5 * np.abs(pe_i).sum()
 
 
 def test_two_types_mixed_parameters():
