@@ -207,7 +207,7 @@ def test_batch_autotune_keeps_states_and_bitwise_replicas():
         return s
 
     temps = [0.5, 0.6, 0.7, 0.8, 0.9, 1.0]
-    systems = [mk(st, T) for st, T in zip(states, temps)]
+    systems = [mk(st, T, launch=(4, 64)) for st, T in zip(states, temps)]  # a batch shares its t_p
     for s in systems:
         s.step(20)
     before = [s.get_state() for s in systems]
