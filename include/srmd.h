@@ -200,9 +200,12 @@ srmd_status srmd_set_launch(srmd_system *s, int32_t tp, int32_t ppb);
  * cell share one load of their stencil's candidates), 4 all pairs (the paper's
  * O(N^2) builder for small systems, section 6: every particle against every other
  * in index order, no cells and no spatial sort; systems of at most 8192 particles
- * and 8192 cells, sort_mode 0 or 1, else SRMD_EINVAL at the next step).  The
- * persistent kernel builds one wave per particle or per cell for modes 1-3, and all
- * pairs from its LDS copy of the positions for mode 4. */
+ * and 8192 cells, sort_mode 0 or 1, else SRMD_EINVAL at the next step), 5 one
+ * workgroup per x-row of cells (the 25 stencil rows staged in LDS one after the
+ * other, each thread testing its particle's five x cells there; the section 7 thread
+ * per particle with shared, coalesced candidate loads).  The persistent kernel
+ * builds one wave per particle or per cell for modes 1-3 and 5, and all pairs from
+ * its LDS copy of the positions for mode 4. */
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode);
 
 /* The periodic spatial re-sort of the all-pairs lists (list mode 4 of

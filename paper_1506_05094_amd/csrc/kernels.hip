@@ -1206,6 +1206,102 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
   list_tally(kept_sum, longest, nmax, p.ctl);
 }
 
+// Row-staged list build (list mode 5): one workgroup per x-row of cells.  The
+// particles of a row are consecutive sorted slots, and so is every full x-row of
+// the stencil, so for each of the 25 stencil rows (in the order of the other
+// builders: z offset, then y offset) the workgroup copies that row's positions and
+// cell starts into LDS with coalesced loads; each thread then tests its particle
+// against the candidates of its five x cells from LDS, in the same slot order as
+// k_list_thread, so the lists are the same entry for entry.  The per-lane gathers
+// of the thread builder (a cache line per lane and candidate batch) become one
+// contiguous copy per row that every particle of the row shares.  A stencil row of
+// more than kRowCap particles is read from device memory instead.
+constexpr int kRowCap = 1024;    // particles of a stencil row staged in LDS
+constexpr int kRowCells = 1024;  // cells per x-row the cell starts of LDS hold (nc <= 1024)
+
+__global__ __launch_bounds__(256) void k_list_row(SysConst c, SysPtrs p, int cur) {
+  if (p.ctl->rebuild == 0) return;
+  __shared__ float s_cs2[kMaxPairs];
+  __shared__ int s_ring[4][kRing][64];
+  __shared__ float4 s_row[kRowCap];
+  __shared__ unsigned s_cs[kRowCells + 1];
+  if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
+  const int lane = threadIdx.x & 63;
+  int(*ring)[64] = s_ring[threadIdx.x >> 6];
+  const int nmax = c.n_max;
+  const int nx = c.nc[0], ny = c.nc[1], nz = c.nc[2];
+  const bool fy = c.full_axis & 2, fz = c.full_axis & 4;
+  const int ny_eff = fy ? ny : 5, nz_eff = fz ? nz : 5, nrows = ny_eff * nz_eff;
+  const unsigned nu = (unsigned)c.n;
+  const int row = xcd_remap(blockIdx.x, gridDim.x);  // x-row (cy, cz) of this workgroup
+  const int cy = row % ny, cz = row / ny;
+  const unsigned r0 = min(p.cell_start[row * nx], nu), r1 = min(p.cell_start[row * nx + nx], nu);
+  int kept_sum = 0, longest = 0;
+  for (unsigned t0 = r0; t0 < r1; t0 += blockDim.x) {  // uniform over the block
+    const unsigned tt = t0 + threadIdx.x;
+    const bool act = tt < r1;
+    const int t = (int)(act ? tt : r0);
+    const float4 r = p.t_pos[t];
+    if (act) place_sorted(p, cur, t, r);
+    const int ti = ptype(r);
+    int cx, cyy, czz;
+    cell_coords(r, c, cx, cyy, czz);
+    int a0, a1, b0, b1;
+    row_runs(cx, nx, c.full_axis & 1, a0, a1, b0, b1);
+    const bool two = b1 >= b0;
+    int count = 0, ring_end = 0, flushed = 0;
+    bool spill = false;
+    auto flush = [&](int upto) {
+      for (int k = flushed; k < upto; ++k)
+        if (act && k < ring_end && k < nmax) p.nbl[nbl_addr(t, k, c.tp, c.nvp)] = ring[k % kRing][lane];
+      flushed = upto;
+    };
+    for (int rr = 0; rr < nrows; ++rr) {
+      const int oz = rr / ny_eff, oy = rr - oz * ny_eff;
+      const int zz = fz ? oz : (cz + oz - 2 + nz) % nz;
+      const int yy = fy ? oy : (cy + oy - 2 + ny) % ny;
+      const int rb = (zz * ny + yy) * nx;
+      __syncthreads();  // the previous row's LDS copy is no longer read
+      for (int k = threadIdx.x; k <= nx; k += blockDim.x) s_cs[k] = min(p.cell_start[rb + k], nu);
+      __syncthreads();
+      const unsigned q0 = s_cs[0], q1 = s_cs[nx];
+      const bool staged = q1 - q0 <= (unsigned)kRowCap;
+      if (staged)
+        for (unsigned k = threadIdx.x; k < q1 - q0; k += blockDim.x) s_row[k] = p.t_pos[q0 + k];
+      __syncthreads();
+      const unsigned sa0 = s_cs[a0], sa1 = s_cs[a1 + 1];
+      const unsigned sb0 = two ? s_cs[b0] : 0u, sb1 = two ? s_cs[b1 + 1] : 0u;
+      const unsigned la = sa1 - sa0, lt = act ? la + (sb1 - sb0) : 0u;
+      for (unsigned o = 0; o < lt; ++o) {
+        const unsigned u = o < la ? sa0 + o : sb0 + (o - la);
+        if ((int)u == t) continue;
+        const float4 q = staged ? s_row[u - q0] : p.t_pos[u];
+        float dx, dy, dz;
+        const float r2 = dist2(r, q, c, dx, dy, dz);
+        if (r2 < s_cs2[ti * c.ntypes + ptype(q)]) {
+          if (!spill && count - flushed >= kRing) spill = true;
+          if (spill) {
+            if (count < nmax) p.nbl[nbl_addr(t, count, c.tp, c.nvp)] = (int)u;
+          } else {
+            ring[count % kRing][lane] = (int)u;
+            ring_end = count + 1;
+          }
+          ++count;
+        }
+      }
+      // write out the slots every lane has passed, once half the ring is in use
+      if (__any(act && !spill && count - flushed >= kRing / 2))
+        flush(min(wave_min_int(act && !spill ? count : 0x7fffffff), flushed + kRing));
+    }
+    flush(flushed + kRing);
+    const int kept = act ? min(count, nmax) : 0;
+    if (act) p.nnb[t] = kept;
+    longest = max(longest, act ? count : 0);
+    kept_sum += kept;
+  }
+  list_tally(kept_sum, longest, nmax, p.ctl);
+}
+
 constexpr int kCellChunks = 8;  // 64-candidate chunks held in registers (one window)
 constexpr int kCellWindow = 64 * kCellChunks;
 
@@ -2391,6 +2487,8 @@ hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, i
     hipLaunchKernelGGL(k_list_wave, dim3(lb), dim3(tb), 0, st, c, p, cur);
   } else if (c.list_kind == 2) {
     hipLaunchKernelGGL(k_list_thread, dim3(gb), dim3(tb), 0, st, c, p, cur);
+  } else if (c.list_kind == 5) {
+    hipLaunchKernelGGL(k_list_row, dim3(c.nc[1] * c.nc[2]), dim3(256), 0, st, c, p, cur);
   } else {
     const int lb = (c.n + kCellSlots - 1) / kCellSlots;
     hipLaunchKernelGGL(k_list_cell, dim3(lb), dim3(128), 0, st, c, p, cur);

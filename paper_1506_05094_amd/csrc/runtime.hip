@@ -1419,7 +1419,7 @@ srmd_status srmd_set_persistent(srmd_system *s, int32_t groups) {
 
 srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t list_mode) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
-  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 4)
+  if (sort_mode < 0 || sort_mode > 2 || list_mode < 0 || list_mode > 5)
     return fail(s, SRMD_EINVAL, "sort mode must be 0 (auto), 1 or 2 and list mode 0 (auto), 1, 2, 3 or 4");
   s->sort_mode = sort_mode;
   s->list_mode = list_mode;
@@ -2037,7 +2037,8 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   int dtp, dppb;
   s->tp_req = s->ppb_req = 0;
   launch_of(s, &dtp, &dppb);
-  for (int lm = 1; lm <= (s->c.small_sort ? 4 : 3) && result == SRMD_OK; ++lm) {
+  for (int lm = 1; lm <= 5 && result == SRMD_OK; ++lm) {
+    if (lm == 4 && !s->c.small_sort) continue;  // all pairs: small systems only
     double t;
     result = trial(dtp, dppb, lm, false, &t);
     if (result == SRMD_OK && t < best) {
@@ -2158,7 +2159,7 @@ bool key_valid(const srmd_tuning_key &k) { return k.ntypes >= 1 && k.ntypes <= k
 bool tuning_valid(const srmd_tuning &t) {
   const bool tp_ok = t.tp >= 1 && t.tp <= 64 && (t.tp & (t.tp - 1)) == 0;
   const bool ppb_ok = t.ppb >= 1 && (long long)t.tp * t.ppb <= 1024 && (t.tp * t.ppb) % 64 == 0;
-  return tp_ok && ppb_ok && t.list_mode >= 1 && t.list_mode <= 4 && (t.persistent == 0 || t.persistent == -1) &&
+  return tp_ok && ppb_ok && t.list_mode >= 1 && t.list_mode <= 5 && (t.persistent == 0 || t.persistent == -1) &&
          t.skin >= 0 && std::isfinite(t.skin) && t.sort_every >= 0;
 }
 
@@ -2593,9 +2594,12 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
   s->persist_set = true;
   s->persist_req = 0;  // the default layout of the launch chains
   launch_of(s, &dtp, &dppb);
-  const int n_lm = s->c.small_sort ? 4 : 3;
-  double t1[5] = {1e30, 1e30, 1e30, 1e30, 1e30}, sk1[5] = {start, start, start, start, start};
-  for (int lm = 1; lm <= n_lm && result == SRMD_OK; ++lm) result = skin_search(dtp, dppb, lm, false, start, 0.2, &sk1[lm], &t1[lm]);
+  // list methods: wave, thread, cell and row-staged per particle; all pairs for small systems
+  auto lm_used = [&](int lm) { return lm != 4 || s->c.small_sort; };
+  const int n_lm = 5;
+  double t1[6] = {1e30, 1e30, 1e30, 1e30, 1e30, 1e30}, sk1[6] = {start, start, start, start, start, start};
+  for (int lm = 1; lm <= n_lm && result == SRMD_OK; ++lm)
+    if (lm_used(lm)) result = skin_search(dtp, dppb, lm, false, start, 0.2, &sk1[lm], &t1[lm]);
   double t1_best = 1e30;
   for (int lm = 1; lm <= n_lm; ++lm) t1_best = std::min(t1_best, t1[lm]);
   srmd_tuning best{};
@@ -2610,7 +2614,8 @@ srmd_status srmd_autotune_full(srmd_system *s, int32_t steps_per_trial, const ch
       best.skin = skin;
     }
   };
-  for (int lm = 1; lm <= n_lm; ++lm) consider(dtp, dppb, lm, false, sk1[lm], t1[lm]);
+  for (int lm = 1; lm <= n_lm; ++lm)
+    if (lm_used(lm)) consider(dtp, dppb, lm, false, sk1[lm], t1[lm]);
   // phase II (step 4): methods within 20 % of the fastest; block size x t_p with the
   // stop rules of phase II of srmd_autotune, the skin re-optimised at every layout
   const int blocks[] = {64, 128, 256, 512, 1024};

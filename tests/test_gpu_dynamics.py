@@ -35,7 +35,7 @@ def _in_range_pairs(pos, types, box, rc):
     return both[:, 0].astype(np.int64) * len(pos) + both[:, 1]
 
 
-PATHS = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 3), (2, 3)]
+PATHS = [(1, 1), (2, 1), (1, 2), (2, 2), (1, 3), (2, 3), (1, 5), (2, 5)]
 
 
 @pytest.mark.parametrize("paths", PATHS + [(1, 4), (0, 4)])
@@ -56,14 +56,14 @@ def test_multi_kernel_sort_and_thread_builder_mixture():
     """Kob-Andersen mixture, N = 12000: the multi-kernel sort scans its cell histogram in
     several tiles (15^3 cells), and in the thread-per-particle builder A and B lanes of a
     wave find their entries at different rates (about 100 and 65), so entries are both
-    staged and written directly.  The wave, thread and cell list builders must give the
-    oracle's pair set and the same trajectory bit for bit."""
+    staged and written directly.  The wave, thread, cell and row-staged list builders
+    must give the oracle's pair set and the same trajectory bit for bit."""
     state = gen.ka_random_state(12000, 1.2, 0.45, 5)
     sig, eps, rc = gen.ka_params()
     cs2, _ = oracle.cut_tables(rc, 0.3)
     ref = oracle.pair_set(state.pos, state.types, state.box, cs2)
     out = []
-    for paths in [(2, 1), (2, 2), (2, 3)]:
+    for paths in [(2, 1), (2, 2), (2, 3), (2, 5)]:
         print(f"N=12000 KA paths {paths}", flush=True)
         with make_system(state, sig, eps, rc, "sf") as s:
             s.set_rebuild_path(*paths)
@@ -480,3 +480,34 @@ def test_all_pairs_resort_changes_order_not_physics():
             tr = s.step(20, thermo_every=1)
             res[every] = tr
     np.testing.assert_allclose(res[0]["pe"], res[1]["pe"], rtol=1e-5)
+
+
+def test_row_builder_long_rows_and_full_axes():
+    """Row-staged builder (list mode 5) on an elongated box whose y and z axes hold
+    fewer than 5 cells (every row of the stencil a full axis) and whose x-rows hold
+    about 1400 particles: more than a workgroup (the row's particles in chunks) and
+    more than the rows staged in LDS (candidates read from device memory).  The pair
+    set equals the oracle's, and the trajectory equals the thread builder's bit for
+    bit."""
+    rng = np.random.default_rng(41)
+    g = np.stack(np.meshgrid(np.arange(900), np.arange(5), np.arange(5), indexing="ij"), -1).reshape(-1, 3)
+    box = np.array([1000.0, 6.0, 6.0])
+    pos = (g * np.array([1000.0 / 900, 1.2, 1.2]) - box / 2 + 0.3 + rng.uniform(-0.05, 0.05, g.shape)).astype(np.float32)
+    n = len(pos)
+    from workloads.generators import State
+    st = State(pos=pos, vel=(rng.normal(0, 0.5, (n, 3))).astype(np.float32), types=np.zeros(n, np.int32),
+               box=box, mass=np.ones(1), ntypes=1, seed=41, recipe="elongated lattice")
+    sig, eps, rc = gen.lj_params()
+    cs2, _ = oracle.cut_tables(rc, 0.3)
+    ref = oracle.pair_set(st.pos, st.types, st.box, cs2)
+    out = []
+    for lm in (2, 5):
+        with make_system(st, sig, eps, rc, "sp") as s:
+            s.set_rebuild_path(2, lm)
+            s.build_neighbor_list()
+            np.testing.assert_array_equal(s.neighbor_pairs(), ref)
+            s.set_integrator_nve(0.002)
+            s.step(60)
+            out.append(s.get_state())
+    np.testing.assert_array_equal(out[0]["pos"], out[1]["pos"])
+    np.testing.assert_array_equal(out[0]["vel"], out[1]["vel"])
