@@ -6,8 +6,9 @@ density 1.2, Nose-Hoover NVT at T = 0.45 (tau = 0.2), dt = 0.005, shifted-force
 cutoff 2.5 sigma_ab, skin 0.3, float32 positions and forces with float64
 reductions.  Seeded random non-overlapping start, relaxed by an untimed
 2000-step NVT run at dt = 0.001 and untimed NVT steps at dt = 0.005 until the
-temperature is within 3 % of T0, then W untimed and K timed steps (one
-srmd_step call).  A step is one pass of the whole hot path: displacement check,
+temperature is within 3 % of T0; the layout autotuner (untimed) then picks
+threads per particle, block size, list builder and launch form at skin 0.3,
+and W untimed and K timed steps follow (one srmd_step call).  A step is one pass of the whole hot path: displacement check,
 list rebuild when due (cell binning, counting sort, reorder, cell-stencil list),
 pair forces, integrator and thermostat.
 
@@ -390,7 +391,7 @@ def main():
     ap.add_argument("--workload", default="ka4096", choices=["ka4096", "lj", "salt", "ka-replicas", "precision", "sweep"])
     ap.add_argument("--frames", type=int, default=4, help="force checks in the precision study")
     ap.add_argument("--tune", action="store_true",
-                    help="run the autotuner (untimed) after the relaxation; the tuned layout and mode are timed")
+                    help="run the layout autotuner (the default unless --no-tune, --tp or --mode is given)")
     ap.add_argument("--skin", type=float, default=0.3,
                     help="neighbour-list skin of the ka4096, lj and salt workloads (default 0.3)")
     ap.add_argument("--tune-full", action="store_true",
@@ -407,9 +408,12 @@ def main():
     ap.add_argument("--n", type=int, default=864, help="particles for --workload lj (salt: 2000 unless given)")
     ap.add_argument("--tp", type=int, default=0, help="threads per particle (0: default / tuned)")
     ap.add_argument("--ppb", type=int, default=0)
-    ap.add_argument("--mode", default="persistent", choices=["persistent", "chain"],
+    ap.add_argument("--mode", default=None, choices=["persistent", "chain"],
                     help="persistent: 500 steps per launch of one kernel (systems up to 8192 particles here); "
-                         "chain: graph-captured launch chains")
+                         "chain: graph-captured launch chains (default: the layout autotuner's choice)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the layout autotuner: the persistent kernel (or --mode) at the default layout "
+                         "(or --tp / --ppb)")
     ap.add_argument("--groups", type=int, default=-1, help="workgroups of the persistent kernel (-1: automatic)")
     ap.add_argument("--list-mode", type=int, default=0,
                     help="list builder (0 automatic, 1 wave, 2 thread, 3 cell, 4 all pairs)")
@@ -464,8 +468,11 @@ def main():
         s.set_rebuild_path(0, args.list_mode)
     if args.sort_interval:
         s.set_sort_interval(args.sort_interval)
-    persistent = args.mode == "persistent" and state.n <= 8192
-    if not (args.tune or args.tune_full):
+    # the layout autotuner (untimed, after the relaxation) picks t_p, block size, list
+    # builder and launch form at the configured skin unless a layout or form is given
+    layout_tune = args.tune or not (args.no_tune or args.tp or args.mode or args.tune_full)
+    persistent = (args.mode or "persistent") == "persistent" and state.n <= 8192
+    if not (layout_tune or args.tune_full):
         s.set_persistent(args.groups if persistent else 0)
     if integ[0] == "nvt":
         s.set_integrator_nvt(0.001, integ[2], integ[3])
@@ -485,9 +492,12 @@ def main():
         log(f"autotune_full: {tuned}")
         desc["skin_tuned"] = tuned["skin"]
         persistent = s.stats()["persistent_groups"] > 0
-    elif args.tune:
+    elif layout_tune:
         # untimed: the autotuner picks layout, list builder and mode from this state
+        t0 = time.perf_counter()
         s.autotune(args.tune_steps)
+        desc["tuned"] = (f"srmd_autotune: t_p, block size, list builder and launch form at skin {args.skin} "
+                         f"({time.perf_counter() - t0:.1f} s, untimed)")
         persistent = s.stats()["persistent_groups"] > 0
     s.step(args.warmup)
     torch.cuda.synchronize()
@@ -558,7 +568,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"], mode="persistent" if persistent else "chain",
-                       groups=st1["persistent_groups"], list_mode=args.list_mode or "automatic",
+                       groups=st1["persistent_groups"],
+                       list_mode=args.list_mode or ("autotuned" if layout_tune else "automatic"),
                        sort_interval=args.sort_interval),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],

@@ -1570,60 +1570,6 @@ __device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &
     v.nonfinite = (finite3(fx, fy, fz) && finite3(rn.x, rn.y, rn.z)) ? 0 : 1;
 }
 
-// ---------------------------------------------------------------- fused step
-
-template <int TP, int METHOD, int PREC>
-__global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur) {
-  __shared__ SharedPairs sp;
-  __shared__ BlockPartial s_waves[16];
-  const unsigned long long tstart = wall_clock64();
-  stage_pairs(sp, c);
-  __syncthreads();
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int gt = lb * blockDim.x + threadIdx.x;
-  const int i = gt / TP, t = gt % TP;
-  const bool active = i < c.n;
-  const float4 *pos = p.pos[cur];
-  float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
-  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
-  // integrator operands are loaded before the force loop so their latency overlaps it
-  float4 vo = pi, l0 = pi, kc = pi;
-  int4 im = make_int4(0, 0, 0, 0);
-  double x64 = 0.0, y64 = 0.0, z64 = 0.0;
-  const double xi = c.thermostat ? p.ctl->xi : 0.0;
-  if (active) {
-    pi = pos[i];
-    if (t == 0) {
-      vo = p.vel[i];
-      im = p.img[i];
-      l0 = p.last[i];
-      if (PREC == 1) kc = p.kahan[i];
-      if (PREC == 2) {
-        x64 = p.pos64[3 * i];
-        y64 = p.pos64[3 * i + 1];
-        z64 = p.pos64[3 * i + 2];
-      }
-    }
-    force_lane<TP, METHOD, StepBatch<TP>::value, true>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
-                                             fz, u, w);
-  }
-  fx = lane_sum<TP>(fx);
-  fy = lane_sum<TP>(fy);
-  fz = lane_sum<TP>(fz);
-  u = lane_sum<TP>(u);
-  w = lane_sum<TP>(w);
-  BlockPartial v = zero_partial();
-  if (active && t == 0)
-    integrate_one<PREC>(c, p, cur, i, pi, vo, im, l0, kc, x64, y64, z64, xi, fx, fy, fz, u, w, v);
-  v.t0 = tstart;
-  v.t1 = wall_clock64();
-  block_reduce(v, s_waves);
-  if (threadIdx.x == 0) {
-    p.part[lb] = v;
-    if (blockIdx.x == 0) p.ctl->rebuild = 0;  // the list of this step has been consumed
-  }
-}
-
 // ---------------------------------------------------------------- end of step
 
 // Nose-Hoover friction of the next step from the half-step kinetic energy.
@@ -1697,6 +1643,250 @@ __device__ int finish_step(const SysConst &c, const SysPtrs &p, const BlockParti
   ctl->rebuild = rebuild;
   if (a.nonfinite) atomicOr(&ctl->error, 1);
   return rebuild;
+}
+
+// ---------------------------------------------------------------- end of step in the step kernel
+
+// The fold of one block partial into a running sum, with the operations and order
+// of k_finish and group_reduce (the device-clock stamps included).
+__device__ __forceinline__ void fold_timed(BlockPartial &a, const BlockPartial &q) {
+  a.pe += q.pe;
+  a.w += q.w;
+  a.ke_half += q.ke_half;
+  a.ke_int += q.ke_int;
+  a.disp2 = fmax(a.disp2, q.disp2);
+  a.nonfinite |= q.nonfinite;
+  a.t0 = q.t0 < a.t0 ? q.t0 : a.t0;
+  a.t1 = q.t1 > a.t1 ? q.t1 : a.t1;
+}
+
+// Arrival of a workgroup at the end of a step kernel that finishes the step itself.
+// Every wave's stores reach the L2, one release at agent scope writes the L2 back
+// (it acts on the whole cache), and one device-scope increment of the system's
+// arrival counter takes a ticket.  The workgroup with the last ticket acquires
+// (the invalidation of its compute unit's L1 and of its L2 precedes, through the
+// workgroup barrier, every later load of its waves), puts the counter back to zero
+// for the next launch, and returns true in all its threads.  Every workgroup of the
+// grid has arrived, hence started and finished reading the step's control words,
+// before the last one writes them.
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned G, int *s_last) {
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // the write-back must complete before the ticket is taken
+    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    const unsigned k = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int last = (k + 1u == G) ? 1 : 0;
+    if (last) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    *s_last = last;
+  }
+  __syncthreads();
+  return *s_last != 0;
+}
+
+// The reduction of k_finish<0> (1024 threads: thread t sums the block partials t,
+// t + 1024, ... in order, a butterfly per wave, then thread 0 folds in order the
+// waves that hold data) by a workgroup of any multiple of 64 threads, its wave v
+// standing in for the waves v, v + W, ... of that workgroup.  Bitwise the result of
+// k_finish; valid in thread 0.
+__device__ BlockPartial finish_reduce(const BlockPartial *part, int G, BlockPartial *s_waves) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  const int used = min(16, (G + 63) / 64);
+  for (int vw = wv; vw < used; vw += nw) {
+    BlockPartial a = zero_partial();
+    for (int b = vw * 64 + lane; b < G; b += 1024) fold_timed(a, part[b]);
+    a.pe = wave_sum(a.pe);
+    a.w = wave_sum(a.w);
+    a.ke_half = wave_sum(a.ke_half);
+    a.ke_int = wave_sum(a.ke_int);
+    a.disp2 = wave_max(a.disp2);
+    a.t0 = wave_min_u64(a.t0);
+    a.t1 = wave_max_u64(a.t1);
+    int bad = a.nonfinite;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
+    a.nonfinite = bad;
+    if (lane == 0) s_waves[vw] = a;
+  }
+  __syncthreads();
+  BlockPartial a = zero_partial();
+  if (threadIdx.x == 0) {
+    a = s_waves[0];
+    for (int k = 1; k < used; ++k) fold_timed(a, s_waves[k]);
+  }
+  return a;
+}
+
+// The spatial sort of sort_small_block (order by cell, then particle id; the same
+// cell starts and gathered arrays) by a workgroup of any size, its working arrays
+// in LDS only: s_cnt (ncell + 1 words) and s_id (n words).  A histogram pass, the
+// exclusive scan (also written to cell_start), a placement pass that moves each
+// cell's cursor past its particles (so that afterwards s_cnt[k] ends cell k), and a
+// rank-and-gather pass; cells are recomputed from the positions in every pass.
+__device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, unsigned *s_cnt, int *s_id) {
+  __shared__ unsigned s_w[16];
+  __shared__ unsigned s_carry;
+  const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = (nthr + 63) >> 6;
+  const int ncell = c.ncell, n = c.n;
+  const float4 *pos = p.pos[cur];
+  for (int k = tid; k <= ncell; k += nthr) s_cnt[k] = 0u;
+  if (tid == 0) {
+    s_carry = 0u;
+    begin_build(p.ctl);
+    p.ctl->resorted = 1;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nthr) {
+    int cx, cy, cz;
+    cell_coords(pos[i], c, cx, cy, cz);
+    atomicAdd(&s_cnt[(cz * c.nc[1] + cy) * c.nc[0] + cx], 1u);
+  }
+  __syncthreads();
+  for (int base = 0; base <= ncell; base += nthr) {
+    const int idx = base + tid;
+    const unsigned v = idx <= ncell ? s_cnt[idx] : 0u;
+    unsigned x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63 || tid == nthr - 1) s_w[wv] = x;
+    __syncthreads();
+    unsigned wbase = 0;
+    for (int k = 0; k < wv; ++k) wbase += s_w[k];
+    if (idx <= ncell) {
+      const unsigned e = s_carry + wbase + x - v;
+      s_cnt[idx] = e;
+      p.cell_start[idx] = e;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      unsigned tot = 0;
+      for (int k = 0; k < nw; ++k) tot += s_w[k];
+      s_carry += tot;
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += nthr) {
+    int cx, cy, cz;
+    cell_coords(pos[i], c, cx, cy, cz);
+    const unsigned at = atomicAdd(&s_cnt[(cz * c.nc[1] + cy) * c.nc[0] + cx], 1u);
+    s_id[at] = p.img[i].w;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += nthr) {
+    const float4 r = pos[i];
+    const int id = p.img[i].w;
+    int cx, cy, cz;
+    cell_coords(r, c, cx, cy, cz);
+    const int cell = (cz * c.nc[1] + cy) * c.nc[0] + cx;
+    const unsigned beg = cell > 0 ? s_cnt[cell - 1] : 0u, end = s_cnt[cell];
+    unsigned rank = 0;
+    for (unsigned q = beg; q < end; ++q) rank += (s_id[q] < id) ? 1u : 0u;
+    const unsigned dst = beg + rank;
+    p.t_pos[dst] = r;
+    p.t_vel[dst] = p.vel[i];
+    p.t_img[dst] = p.img[i];
+    if (p.pos64) {
+      p.t_pos64[3 * dst] = p.pos64[3 * i];
+      p.t_pos64[3 * dst + 1] = p.pos64[3 * i + 1];
+      p.t_pos64[3 * dst + 2] = p.pos64[3 * i + 2];
+    }
+    if (p.kahan) p.t_kahan[dst] = p.kahan[i];
+  }
+}
+
+// LDS bytes of sort_small_shared for n particles in ncell cells.
+__host__ __device__ constexpr size_t tail_sort_lds(int n, int ncell) { return 4 * ((size_t)ncell + 1 + (size_t)n); }
+
+// The end of a step in the workgroup that arrived last (arrive_last): the
+// reduction, record, thermostat update and rebuild decision of k_finish<0>, and on
+// a small system's step that decides a rebuild the spatial sort of the new
+// positions pos[next] (dynamic LDS of tail_sort_lds bytes).
+__device__ void step_tail(const SysConst &c, const SysPtrs &p, int G, int next, BlockPartial *s_waves, int *s_flag,
+                          unsigned *s_dyn) {
+  CtlView cv{};
+  if (threadIdx.x == 0) cv = load_ctl(p.ctl);  // beside the partials: one round trip
+  const BlockPartial a = finish_reduce(p.part, G, s_waves);
+  if (threadIdx.x == 0) {
+    s_flag[0] = finish_step(c, p, a, cv);
+    s_flag[1] = resort_due(c, cv.n_rebuilds) ? 1 : 0;
+  }
+  __syncthreads();
+  if (s_flag[0] && c.small_sort) {
+    if (c.list_kind == 4 && !s_flag[1]) {  // all-pairs lists sort only when a re-sort is due
+      if (threadIdx.x == 0) {
+        begin_build(p.ctl);
+        p.ctl->resorted = 0;
+      }
+    } else {
+      sort_small_shared(c, p, next, s_dyn, reinterpret_cast<int *>(s_dyn + c.ncell + 1));
+    }
+  }
+}
+
+// ---------------------------------------------------------------- fused step
+
+template <int TP, int METHOD, int PREC>
+__global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, int tail) {
+  extern __shared__ unsigned s_tail_lds[];
+  __shared__ SharedPairs sp;
+  __shared__ BlockPartial s_waves[16];
+  __shared__ int s_flag[2];
+  const unsigned long long tstart = wall_clock64();
+  stage_pairs(sp, c);
+  __syncthreads();
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int gt = lb * blockDim.x + threadIdx.x;
+  const int i = gt / TP, t = gt % TP;
+  const bool active = i < c.n;
+  const float4 *pos = p.pos[cur];
+  float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
+  float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
+  // integrator operands are loaded before the force loop so their latency overlaps it
+  float4 vo = pi, l0 = pi, kc = pi;
+  int4 im = make_int4(0, 0, 0, 0);
+  double x64 = 0.0, y64 = 0.0, z64 = 0.0;
+  const double xi = c.thermostat ? p.ctl->xi : 0.0;
+  if (active) {
+    pi = pos[i];
+    if (t == 0) {
+      vo = p.vel[i];
+      im = p.img[i];
+      l0 = p.last[i];
+      if (PREC == 1) kc = p.kahan[i];
+      if (PREC == 2) {
+        x64 = p.pos64[3 * i];
+        y64 = p.pos64[3 * i + 1];
+        z64 = p.pos64[3 * i + 2];
+      }
+    }
+    force_lane<TP, METHOD, StepBatch<TP>::value, true>(i, t, pi, pos, (const int *)p.nbl, (const int *)p.nnb, sp, c, fx, fy,
+                                             fz, u, w);
+  }
+  fx = lane_sum<TP>(fx);
+  fy = lane_sum<TP>(fy);
+  fz = lane_sum<TP>(fz);
+  u = lane_sum<TP>(u);
+  w = lane_sum<TP>(w);
+  BlockPartial v = zero_partial();
+  if (active && t == 0)
+    integrate_one<PREC>(c, p, cur, i, pi, vo, im, l0, kc, x64, y64, z64, xi, fx, fy, fz, u, w, v);
+  v.t0 = tstart;
+  v.t1 = wall_clock64();
+  block_reduce(v, s_waves);
+  if (threadIdx.x == 0) {
+    p.part[lb] = v;
+    // the list of this step has been consumed (with the tail, finish_step decides the flag)
+    if (blockIdx.x == 0 && !tail) p.ctl->rebuild = 0;
+  }
+  // tail: the last workgroup to arrive ends the step (k_finish<0> not launched)
+  if (tail && arrive_last(p.arrive, gridDim.x, &s_flag[0])) step_tail(c, p, gridDim.x, cur ^ 1, s_waves, s_flag, s_tail_lds);
 }
 
 // One workgroup after the step (MODE 0) or force-only (MODE 1) kernel: fixed-order
@@ -2395,10 +2585,10 @@ hipError_t launch_call_begin(hipStream_t st, const SysConst &c, const SysPtrs &p
 
 template <int TP>
 static hipError_t launch_step_tp(int method, int prec, dim3 g, dim3 b, hipStream_t st, const SysConst &c,
-                                 const SysPtrs &p, int cur) {
+                                 const SysPtrs &p, int cur, int tail, size_t lds) {
 #define SRMD_STEP_CASE(M, P)                                                   \
   if (method == M && prec == P) {                                              \
-    hipLaunchKernelGGL((k_step<TP, M, P>), g, b, 0, st, c, p, cur);            \
+    hipLaunchKernelGGL((k_step<TP, M, P>), g, b, lds, st, c, p, cur, tail);    \
     return hipGetLastError();                                                  \
   }
   SRMD_STEP_CASE(0, 0) SRMD_STEP_CASE(0, 1) SRMD_STEP_CASE(0, 2)
@@ -2424,20 +2614,26 @@ static hipError_t launch_force_tp(int method, dim3 g, dim3 b, hipStream_t st, co
   return hipGetLastError();
 }
 
+// tail = 1: the step kernel ends the step in its last workgroup (no k_finish<0>
+// launch); lds = tail_lds_bytes for small systems, else 0.
 hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hipStream_t st, const SysConst &c,
-                       const SysPtrs &p, int cur) {
+                       const SysPtrs &p, int cur, int tail, size_t lds) {
   const dim3 g(blocks), b(threads);
   switch (tp) {
-    case 1: return launch_step_tp<1>(method, prec, g, b, st, c, p, cur);
-    case 2: return launch_step_tp<2>(method, prec, g, b, st, c, p, cur);
-    case 4: return launch_step_tp<4>(method, prec, g, b, st, c, p, cur);
-    case 8: return launch_step_tp<8>(method, prec, g, b, st, c, p, cur);
-    case 16: return launch_step_tp<16>(method, prec, g, b, st, c, p, cur);
-    case 32: return launch_step_tp<32>(method, prec, g, b, st, c, p, cur);
-    case 64: return launch_step_tp<64>(method, prec, g, b, st, c, p, cur);
+    case 1: return launch_step_tp<1>(method, prec, g, b, st, c, p, cur, tail, lds);
+    case 2: return launch_step_tp<2>(method, prec, g, b, st, c, p, cur, tail, lds);
+    case 4: return launch_step_tp<4>(method, prec, g, b, st, c, p, cur, tail, lds);
+    case 8: return launch_step_tp<8>(method, prec, g, b, st, c, p, cur, tail, lds);
+    case 16: return launch_step_tp<16>(method, prec, g, b, st, c, p, cur, tail, lds);
+    case 32: return launch_step_tp<32>(method, prec, g, b, st, c, p, cur, tail, lds);
+    case 64: return launch_step_tp<64>(method, prec, g, b, st, c, p, cur, tail, lds);
     default: return hipErrorInvalidValue;
   }
 }
+
+// Dynamic LDS of a step kernel with the tail: the spatial sort's arrays for small
+// systems (sorted in the tail), none otherwise.
+size_t tail_lds_bytes(const SysConst &c) { return c.small_sort ? tail_sort_lds(c.n, c.ncell) : 0; }
 
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur) {

@@ -19,7 +19,8 @@
 
 namespace srmd {
 hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hipStream_t st, const SysConst &c,
-                       const SysPtrs &p, int cur);
+                       const SysPtrs &p, int cur, int tail, size_t lds);
+size_t tail_lds_bytes(const SysConst &c);
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur);
 hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
@@ -62,6 +63,7 @@ struct DevBuf {
 };
 
 constexpr int kChunk = 64;  // steps per captured graph (even: the position buffers alternate)
+constexpr size_t kTailLdsMax = 60 * 1024;  // dynamic LDS of a step kernel that sorts in its last workgroup
 constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel (even)
 
 }  // namespace
@@ -95,6 +97,7 @@ struct srmd_system {
   int tp_tuned = 0, ppb_tuned = 0;
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
   int sort_every = 0;                // all-pairs lists: spatial sort at every k-th build (0: never)
+  int tail_req = 1;                  // launch chains: the step kernel's last workgroup ends the step (1) or k_finish does (0)
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -538,13 +541,26 @@ srmd_status prepare(srmd_system *s) {
 }
 
 
+// The step kernel ends the step itself (its last workgroup runs the reduction,
+// thermostat and record, and a small system's sort) when asked to, when its
+// workgroups are whole waves and when the sort's arrays fit the LDS of a launch.
+bool use_tail(const srmd_system *s) {
+  return s->tail_req && (s->tp * s->ppb) % 64 == 0 && tail_lds_bytes(s->c) <= kTailLdsMax;
+}
+
+// Enqueue one launch-chain step on position buffer cb.
+hipError_t enqueue_step(srmd_system *s, int cb) {
+  hipError_t e = launch_rebuild(s->stream, s->c, s->p, cb);
+  const bool tail = use_tail(s);
+  if (e == hipSuccess)
+    e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb,
+                    tail ? 1 : 0, tail ? tail_lds_bytes(s->c) : 0);
+  if (e == hipSuccess && !tail) e = launch_finish(0, step_blocks(s), cb ^ 1, s->stream, s->c, s->p);
+  return e;
+}
+
 srmd_status enqueue_steps(srmd_system *s, int count, int cur) {
-  for (int k = 0; k < count; ++k) {
-    const int cb = (cur + k) & 1;
-    HIPCHK(s, launch_rebuild(s->stream, s->c, s->p, cb));
-    HIPCHK(s, launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb));
-    HIPCHK(s, launch_finish(0, step_blocks(s), cb ^ 1, s->stream, s->c, s->p));
-  }
+  for (int k = 0; k < count; ++k) HIPCHK(s, enqueue_step(s, (cur + k) & 1));
   return SRMD_OK;
 }
 
@@ -1178,6 +1194,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   s->p.ctl = (Control *)A(sizeof(Control));
   s->p.thermo = (Thermo *)A(sizeof(Thermo));
   s->p.bar_flags = (unsigned *)A(sizeof(unsigned) * 2 * 256);
+  s->p.arrive = (unsigned *)A(256);
   s->p.tile_count = (unsigned *)A(sizeof(unsigned) * kScanMaxTiles);
   if (prec == SRMD_PREC_F64POS) {
     s->p.pos64 = (double *)A(sizeof(double) * 3 * N);
@@ -1202,6 +1219,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
       hipMemsetAsync(s->p.wpart, 0, sizeof(float) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.tile_count, 0, sizeof(unsigned) * kScanMaxTiles, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.arrive, 0, 256, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.t_pos, 0, sizeof(float4) * N, s->stream) != hipSuccess) {
     srmd_destroy(s);
     return fail(nullptr, SRMD_EHIP, "initial upload failed");
@@ -1432,6 +1450,14 @@ srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds) {
   if (builds < 0) return fail(s, SRMD_EINVAL, "the sort interval must be >= 0");
   s->sort_every = builds;
   s->dirty = true;
+  return SRMD_OK;
+}
+
+srmd_status srmd_set_fused_reduction(srmd_system *s, int32_t enable) {
+  if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
+  if (enable != 0 && enable != 1) return fail(s, SRMD_EINVAL, "enable must be 0 or 1");
+  s->tail_req = enable;
+  s->dirty = true;  // the captured graphs hold the other form
   return SRMD_OK;
 }
 
@@ -1938,11 +1964,13 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
     const int cnt = (int)std::min<long long>(batch, nsteps - done);
     for (int k = 0; k < cnt && result == SRMD_OK; ++k) {
       hipError_t e = launch_rebuild(s->stream, s->c, s->p, s->cur);
+      const bool tail = use_tail(s);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k], s->stream);
       if (e == hipSuccess)
-        e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur);
+        e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur,
+                        tail ? 1 : 0, tail ? tail_lds_bytes(s->c) : 0);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s->stream);
-      if (e == hipSuccess) e = launch_finish(0, step_blocks(s), s->cur ^ 1, s->stream, s->c, s->p);
+      if (e == hipSuccess && !tail) e = launch_finish(0, step_blocks(s), s->cur ^ 1, s->stream, s->c, s->p);
       if (e != hipSuccess) result = fail(s, SRMD_EHIP, std::string("profiled launch: ") + hipGetErrorString(e));
       s->cur ^= 1;
     }

@@ -176,6 +176,7 @@ def load():
         "srmd_set_rebuild_path": (st, [sysp, ctypes.c_int32, ctypes.c_int32]),
         "srmd_set_persistent": (st, [sysp, ctypes.c_int32]),
         "srmd_set_sort_interval": (st, [sysp, ctypes.c_int32]),
+        "srmd_set_fused_reduction": (st, [sysp, ctypes.c_int32]),
         "srmd_batch_create": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32]),
         "srmd_batch_create_limited": (st, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.c_int32, ctypes.c_int32]),
@@ -285,10 +286,12 @@ class System:
             load().srmd_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be gone: leave the
-        # memory to the process exit instead of calling into the library
-        if sys.is_finalizing():
+        # memory to the process exit instead of calling into the library (the
+        # check is bound at definition: module globals such as sys may already
+        # be cleared when a late finaliser runs)
+        if _finalizing():
             return
         try:
             self.close()
@@ -370,6 +373,11 @@ class System:
     def set_sort_interval(self, builds):
         """All-pairs lists: spatial re-sort before every builds-th list build (0: never)."""
         _check(load().srmd_set_sort_interval(self._h, int(builds)), self._h)
+
+    def set_fused_reduction(self, enable=True):
+        """Launch chains: the step kernel's last workgroup ends each step (True) or a
+        separate one-workgroup kernel does (False); bitwise the same results."""
+        _check(load().srmd_set_fused_reduction(self._h, 1 if enable else 0), self._h)
 
     def set_persistent(self, groups=-1):
         """Run steps as persistent launches of 500 steps each (groups > 0 workgroups,
@@ -533,10 +541,12 @@ class Batch:
             load().srmd_batch_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be gone: leave the
-        # memory to the process exit instead of calling into the library
-        if sys.is_finalizing():
+        # memory to the process exit instead of calling into the library (the
+        # check is bound at definition: module globals such as sys may already
+        # be cleared when a late finaliser runs)
+        if _finalizing():
             return
         try:
             self.close()
@@ -556,7 +566,7 @@ EXPORTED = ["srmd_autotune", "srmd_autotune_full", "srmd_batch_autotune", "srmd_
             "srmd_destroy", "srmd_get_box", "srmd_get_launch", "srmd_get_neighbor_pairs",
             "srmd_get_particle_terms", "srmd_get_state", "srmd_get_stats", "srmd_get_thermo", "srmd_last_error",
             "srmd_load_state", "srmd_profile_step_kernel", "srmd_save_state", "srmd_set_allocator",
-            "srmd_set_coulomb_sf", "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch",
+            "srmd_set_coulomb_sf", "srmd_set_fused_reduction", "srmd_set_integrator_nve", "srmd_set_integrator_nvt", "srmd_set_launch",
             "srmd_set_pair_lj", "srmd_set_pair_mie", "srmd_set_pair_potential", "srmd_set_persistent",
             "srmd_set_rebuild_path", "srmd_set_skin", "srmd_set_sort_interval", "srmd_set_state", "srmd_step",
             "srmd_tuning_cache_find", "srmd_tuning_cache_store", "srmd_tuning_key_of"]
