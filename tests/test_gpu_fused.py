@@ -99,11 +99,11 @@ def test_fused_equals_separate_large_system(launch):
 
 
 def test_sort_arrays_past_the_lds_limit_fall_back():
-    """A dilute LJ gas of N = 8000 in 20^3 cells: the sort's LDS arrays (4 (8001 + 8000)
-    bytes) exceed the tail's 60 KiB, so the separate kernel ends the steps, with the
-    same results."""
-    print("fused vs separate: LJ gas 8000 in 8000 cells", flush=True)
-    st = gen.lj_fcc_state(8000, 0.042, 0.722, 35)
+    """A dilute LJ fluid of N = 8000 at density 0.34 in 20^3 cells (a cell side is at
+    least half of r_c + skin): the sort's LDS arrays (4 (8001 + 8000) bytes) exceed the
+    tail's 60 KiB, so the separate kernel ends the steps, with the same results."""
+    print("fused vs separate: LJ 8000 at density 0.34 in 8000 cells", flush=True)
+    st = gen.lj_fcc_state(8000, 0.34, 0.722, 35)
     runs = _pair_runs(st, gen.lj_params(), "sp", (8, 32), steps=160, nvt=False)
     assert runs[0][0].stats()["ncell"] == 8000
     _assert_same(runs, "LJ gas 8000")
