@@ -1487,6 +1487,28 @@ __global__ __launch_bounds__(1024) void k_force(SysConst c, SysPtrs p, int cur) 
   }
 }
 
+// A store that writes through the L2 to memory: agent-scope relaxed atomic stores of
+// its 8-byte words (the XCDs' L2s are not coherent with each other).  Once the
+// storing wave's vmcnt has drained the words are visible to loads from any XCD
+// that miss their own L2, with no write-back of a whole L2.
+template <class T>
+__device__ __forceinline__ void store_through(T *dst, const T &v) {
+  static_assert(sizeof(T) % 8 == 0, "whole 8-byte words");
+  unsigned long long w[sizeof(T) / 8];
+  __builtin_memcpy(w, &v, sizeof(T));
+  unsigned long long *d = reinterpret_cast<unsigned long long *>(dst);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 8); ++k) __hip_atomic_store(d + k, w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ void store_to(T *dst, const T &v, bool through) {
+  if (through)
+    store_through(dst, v);
+  else
+    *dst = v;
+}
+
 // Leapfrog / Nose-Hoover update of particle i (sorted slot) from its force, and
 // its float64 contributions to the step's sums (paper section 2 integrators;
 // kinetic energy at the half step for the thermostat and at the integer step for
@@ -1496,7 +1518,8 @@ template <int PREC>
 __device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &p, int cur, int i, const float4 pi,
                                               const float4 vo, int4 im, const float4 l0, float4 kc, double x64,
                                               double y64, double z64, double xi, float fx, float fy, float fz,
-                                              float u, float w, BlockPartial &v) {
+                                              float u, float w, BlockPartial &v, bool through = false) {
+    // through: the arrays the end-of-step sort reads are written through the L2
     const int ti = ptype(pi);
     // v(n+1/2) = [v(n-1/2) (1 - xi dt/2) + F/m dt] / (1 + xi dt/2); a = b = 1 without thermostat
     const double hx = 0.5 * xi * c.dtd;
@@ -1506,7 +1529,7 @@ __device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &
     const float vx = __builtin_fmaf(vo.x, a, fx * dtm) * ib;
     const float vy = __builtin_fmaf(vo.y, a, fy * dtm) * ib;
     const float vz = __builtin_fmaf(vo.z, a, fz * dtm) * ib;
-    p.vel[i] = make_float4(vx, vy, vz, vo.w);
+    store_to(&p.vel[i], make_float4(vx, vy, vz, vo.w), through);
     p.force[i] = make_float4(fx, fy, fz, 0.5f * u);
     float4 rn;
     rn.w = pi.w;
@@ -1517,9 +1540,9 @@ __device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &
       if (x >= 0.5 * c.Ld[0]) { x -= c.Ld[0]; im.x += 1; } else if (x < -0.5 * c.Ld[0]) { x += c.Ld[0]; im.x -= 1; }
       if (y >= 0.5 * c.Ld[1]) { y -= c.Ld[1]; im.y += 1; } else if (y < -0.5 * c.Ld[1]) { y += c.Ld[1]; im.y -= 1; }
       if (z >= 0.5 * c.Ld[2]) { z -= c.Ld[2]; im.z += 1; } else if (z < -0.5 * c.Ld[2]) { z += c.Ld[2]; im.z -= 1; }
-      p.pos64[3 * i] = x;
-      p.pos64[3 * i + 1] = y;
-      p.pos64[3 * i + 2] = z;
+      store_to(&p.pos64[3 * i], x, through);
+      store_to(&p.pos64[3 * i + 1], y, through);
+      store_to(&p.pos64[3 * i + 2], z, through);
       rn.x = (float)x;
       rn.y = (float)y;
       rn.z = (float)z;
@@ -1537,7 +1560,7 @@ __device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &
         kc.x = (x - pi.x) - yx;
         kc.y = (y - pi.y) - yy;
         kc.z = (z - pi.z) - yz;
-        p.kahan[i] = kc;
+        store_to(&p.kahan[i], kc, through);
       } else {
         x = __builtin_fmaf(vx, c.dt, pi.x);
         y = __builtin_fmaf(vy, c.dt, pi.y);
@@ -1551,8 +1574,8 @@ __device__ __forceinline__ void integrate_one(const SysConst &c, const SysPtrs &
       rn.y = y;
       rn.z = z;
     }
-    p.pos[cur ^ 1][i] = rn;
-    p.img[i] = im;
+    store_to(&p.pos[cur ^ 1][i], rn, through);
+    store_to(&p.img[i], im, through);
     // float64 reductions
     const double m = c.mass[ti];
     const double dvx = vx, dvy = vy, dvz = vz;
@@ -1660,22 +1683,21 @@ __device__ __forceinline__ void fold_timed(BlockPartial &a, const BlockPartial &
   a.t1 = q.t1 > a.t1 ? q.t1 : a.t1;
 }
 
-// Arrival of a workgroup at the end of a step kernel that finishes the step itself.
-// Every wave's stores reach the L2, one release at agent scope writes the L2 back
-// (it acts on the whole cache), and one device-scope increment of the system's
-// arrival counter takes a ticket.  The workgroup with the last ticket acquires
-// (the invalidation of its compute unit's L1 and of its L2 precedes, through the
-// workgroup barrier, every later load of its waves), puts the counter back to zero
-// for the next launch, and returns true in all its threads.  Every workgroup of the
-// grid has arrived, hence started and finished reading the step's control words,
-// before the last one writes them.
+// Arrival of a workgroup at the end of a step kernel that ends the step itself.
+// What the last workgroup reads from the others (their block partials and, for a
+// small system, the arrays its sort reads) was written through the L2
+// (store_through); every wave waits for its stores to complete, and one
+// device-scope increment of the system's arrival counter takes a ticket.  No L2
+// write-back is needed (one per workgroup would cost the XCD's L2 a walk each).
+// The workgroup with the last ticket acquires at agent scope (the invalidation of
+// its compute unit's L1 and of its L2 precedes, through the workgroup barrier,
+// every later load of its waves), puts the counter back to zero for the next
+// launch, and returns true in all its threads.  Every workgroup has arrived, hence
+// read the step's control words, before the last one writes them.
 __device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned G, int *s_last) {
-  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
+  __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are complete
   __syncthreads();
   if (threadIdx.x == 0) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    // the write-back must complete before the ticket is taken
-    __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");
     const unsigned k = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int last = (k + 1u == G) ? 1 : 0;
     if (last) {
@@ -1876,12 +1898,13 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, i
   w = lane_sum<TP>(w);
   BlockPartial v = zero_partial();
   if (active && t == 0)
-    integrate_one<PREC>(c, p, cur, i, pi, vo, im, l0, kc, x64, y64, z64, xi, fx, fy, fz, u, w, v);
+    integrate_one<PREC>(c, p, cur, i, pi, vo, im, l0, kc, x64, y64, z64, xi, fx, fy, fz, u, w, v,
+                        tail && c.small_sort);
   v.t0 = tstart;
   v.t1 = wall_clock64();
   block_reduce(v, s_waves);
   if (threadIdx.x == 0) {
-    p.part[lb] = v;
+    store_to(&p.part[lb], v, tail != 0);
     // the list of this step has been consumed (with the tail, finish_step decides the flag)
     if (blockIdx.x == 0 && !tail) p.ctl->rebuild = 0;
   }
