@@ -1683,26 +1683,42 @@ __device__ __forceinline__ void fold_timed(BlockPartial &a, const BlockPartial &
   a.t1 = q.t1 > a.t1 ? q.t1 : a.t1;
 }
 
+// Arrival counters of a step kernel that ends the step itself: kArriveGroups group
+// counters and one top counter, each on its own 128-byte line.
+constexpr unsigned kArriveGroups = 16;
+constexpr unsigned kArriveStride = 32;  // unsigned words per counter line
+constexpr size_t kArriveBytes = sizeof(unsigned) * kArriveStride * (kArriveGroups + 1);
+
 // Arrival of a workgroup at the end of a step kernel that ends the step itself.
 // What the last workgroup reads from the others (their block partials and, for a
 // small system, the arrays its sort reads) was written through the L2
-// (store_through); every wave waits for its stores to complete, and one
-// device-scope increment of the system's arrival counter takes a ticket.  No L2
-// write-back is needed (one per workgroup would cost the XCD's L2 a walk each).
-// The workgroup with the last ticket acquires at agent scope (the invalidation of
+// (store_through); every wave waits for its stores to complete before its
+// workgroup takes a ticket.  No L2 write-back is needed (one per workgroup would
+// cost the XCD's L2 a walk each).  Tickets are taken in two levels, so that the
+// workgroups that end together do not all queue on one word: workgroup b counts on
+// group counter b % 16, and the last of each group on the top counter.  The
+// workgroup with the last top ticket acquires at agent scope (the invalidation of
 // its compute unit's L1 and of its L2 precedes, through the workgroup barrier,
-// every later load of its waves), puts the counter back to zero for the next
-// launch, and returns true in all its threads.  Every workgroup has arrived, hence
-// read the step's control words, before the last one writes them.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned G, int *s_last) {
+// every later load of its waves) and returns true in all its threads.  Each counter
+// is put back to zero by the workgroup that takes its last ticket, for the next
+// launch.  Every workgroup has arrived, hence read the step's control words, before
+// the last one writes them.
+__device__ __forceinline__ bool arrive_last(unsigned *ctr, unsigned G, unsigned b, int *s_last) {
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are complete
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned k = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int last = (k + 1u == G) ? 1 : 0;
-    if (last) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g = b % kArriveGroups;
+    const unsigned members = G / kArriveGroups + (g < G % kArriveGroups ? 1u : 0u);
+    const unsigned groups = G < kArriveGroups ? G : kArriveGroups;
+    int last = 0;
+    unsigned *gc = ctr + g * kArriveStride, *top = ctr + kArriveGroups * kArriveStride;
+    if (__hip_atomic_fetch_add(gc, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == members) {
+      __hip_atomic_store(gc, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u == groups) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        last = 1;
+      }
     }
     *s_last = last;
   }
@@ -1909,7 +1925,7 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, i
     if (blockIdx.x == 0 && !tail) p.ctl->rebuild = 0;
   }
   // tail: the last workgroup to arrive ends the step (k_finish<0> not launched)
-  if (tail && arrive_last(p.arrive, gridDim.x, &s_flag[0])) step_tail(c, p, gridDim.x, cur ^ 1, s_waves, s_flag, s_tail_lds);
+  if (tail && arrive_last(p.arrive, gridDim.x, blockIdx.x, &s_flag[0])) step_tail(c, p, gridDim.x, cur ^ 1, s_waves, s_flag, s_tail_lds);
 }
 
 // One workgroup after the step (MODE 0) or force-only (MODE 1) kernel: fixed-order
@@ -2657,6 +2673,9 @@ hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hi
 // Dynamic LDS of a step kernel with the tail: the spatial sort's arrays for small
 // systems (sorted in the tail), none otherwise.
 size_t tail_lds_bytes(const SysConst &c) { return c.small_sort ? tail_sort_lds(c.n, c.ncell) : 0; }
+
+// Bytes of a system's arrival counters (zeroed at allocation).
+size_t arrive_bytes() { return kArriveBytes; }
 
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur) {

@@ -21,6 +21,7 @@ namespace srmd {
 hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hipStream_t st, const SysConst &c,
                        const SysPtrs &p, int cur, int tail, size_t lds);
 size_t tail_lds_bytes(const SysConst &c);
+size_t arrive_bytes();
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur);
 hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
@@ -1194,7 +1195,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   s->p.ctl = (Control *)A(sizeof(Control));
   s->p.thermo = (Thermo *)A(sizeof(Thermo));
   s->p.bar_flags = (unsigned *)A(sizeof(unsigned) * 2 * 256);
-  s->p.arrive = (unsigned *)A(256);
+  s->p.arrive = (unsigned *)A(arrive_bytes());
   s->p.tile_count = (unsigned *)A(sizeof(unsigned) * kScanMaxTiles);
   if (prec == SRMD_PREC_F64POS) {
     s->p.pos64 = (double *)A(sizeof(double) * 3 * N);
@@ -1219,7 +1220,7 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
       hipMemsetAsync(s->p.wpart, 0, sizeof(float) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.tile_count, 0, sizeof(unsigned) * kScanMaxTiles, s->stream) != hipSuccess ||
-      hipMemsetAsync(s->p.arrive, 0, 256, s->stream) != hipSuccess ||
+      hipMemsetAsync(s->p.arrive, 0, arrive_bytes(), s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.t_pos, 0, sizeof(float4) * N, s->stream) != hipSuccess) {
     srmd_destroy(s);
     return fail(nullptr, SRMD_EHIP, "initial upload failed");

@@ -143,7 +143,7 @@ struct SysPtrs {
   Thermo *thermo;   // last record
   Thermo *trace;    // device trace (trace_cap records)
   unsigned *bar_flags;  // arrival words of the persistent kernel's grid barrier (2 x 256)
-  unsigned *arrive;     // arrival counter of a step kernel that ends the step itself (0 between launches)
+  unsigned *arrive;     // arrival counters of a step kernel that ends the step itself (0 between launches)
 };
 
 // The call-start copy of a system's dynamic state, put back when a list overflow
