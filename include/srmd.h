@@ -218,15 +218,17 @@ srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t lis
  * entries (and so the float32 summation order) follows the sort. */
 srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds);
 
-/* Launch chains: end each step inside the step kernel (enable = 1, the default) or
- * in a separate one-workgroup kernel (0).  With 1 the workgroup of the step kernel
- * that arrives last reduces the block partials in the fixed order of the separate
+/* Launch chains: end each step inside the step kernel (enable = 1), in a separate
+ * one-workgroup kernel (0), or by the library's choice (-1, the default: inside the
+ * step kernel except for a small system whose step grid has more than 256
+ * workgroups, measured slower there).  Inside the step kernel the workgroup that
+ * arrives last reduces the block partials in the fixed order of the separate
  * kernel, updates the Nose-Hoover friction, writes the record, takes the rebuild
  * decision of the paper's section 6 and, for a small system, runs the spatial sort
  * of section 7, so a step needs one launch fewer.  The trajectory and records are
- * bitwise the same either way.  Layouts whose blocks are not whole 64-thread waves,
- * and small systems whose sort arrays exceed 60 KiB of LDS, use the separate
- * kernel whatever is asked.  The persistent kernel and batches ignore it. */
+ * bitwise the same either way.  Small systems whose sort arrays exceed 60 KiB of
+ * LDS use the separate kernel whatever is asked.  The persistent kernel and
+ * batches ignore it.  Errors: SRMD_EINVAL for another value. */
 srmd_status srmd_set_fused_reduction(srmd_system *s, int32_t enable);
 
 /* Run the steps of a small system as persistent launches (one launch per 500

@@ -65,6 +65,7 @@ struct DevBuf {
 
 constexpr int kChunk = 64;  // steps per captured graph (even: the position buffers alternate)
 constexpr size_t kTailLdsMax = 60 * 1024;  // dynamic LDS of a step kernel that sorts in its last workgroup
+constexpr int kTailAutoBlocks = 256;       // largest small-system grid that ends its steps itself by default
 constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel (even)
 
 }  // namespace
@@ -98,7 +99,7 @@ struct srmd_system {
   int tp_tuned = 0, ppb_tuned = 0;
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
   int sort_every = 0;                // all-pairs lists: spatial sort at every k-th build (0: never)
-  int tail_req = 1;                  // launch chains: the step kernel's last workgroup ends the step (1) or k_finish does (0)
+  int tail_req = -1;                 // launch chains: the step kernel's last workgroup ends the step (1), k_finish does (0), automatic (-1)
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -546,7 +547,10 @@ srmd_status prepare(srmd_system *s) {
 // thermostat and record, and a small system's sort) when asked to, when its
 // workgroups are whole waves and when the sort's arrays fit the LDS of a launch.
 bool use_tail(const srmd_system *s) {
-  return s->tail_req && (s->tp * s->ppb) % 64 == 0 && tail_lds_bytes(s->c) <= kTailLdsMax;
+  if (s->tail_req == 0 || (s->tp * s->ppb) % 64 != 0 || tail_lds_bytes(s->c) > kTailLdsMax) return false;
+  // automatic: not for a small system's grid of more than 256 workgroups, which all
+  // end at about the same time and queue on the arrival counters (measured slower)
+  return s->tail_req == 1 || !s->c.small_sort || step_blocks(s) <= kTailAutoBlocks;
 }
 
 // Enqueue one launch-chain step on position buffer cb.
@@ -856,8 +860,11 @@ srmd_status ensure_trace(srmd_system *s, long long cap) {
   s->p.trace = (Thermo *)dev_alloc(s, sizeof(Thermo) * (size_t)cap);
   if (!s->p.trace) return fail(s, SRMD_ENOMEM, "trace allocation failed");
   s->trace_alloc = cap;
-  s->dirty = true;  // the pointer is baked into the graphs
-  return prepare(s);
+  // the pointer is baked into the captured graphs (the persistent and batch
+  // descriptors are compared with the system before every launch); the list and
+  // the trajectory do not depend on the trace, so no rebuild is requested
+  drop_graphs(s);
+  return SRMD_OK;
 }
 
 }  // namespace
@@ -1456,7 +1463,7 @@ srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds) {
 
 srmd_status srmd_set_fused_reduction(srmd_system *s, int32_t enable) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
-  if (enable != 0 && enable != 1) return fail(s, SRMD_EINVAL, "enable must be 0 or 1");
+  if (enable < -1 || enable > 1) return fail(s, SRMD_EINVAL, "enable must be -1, 0 or 1");
   s->tail_req = enable;
   s->dirty = true;  // the captured graphs hold the other form
   return SRMD_OK;

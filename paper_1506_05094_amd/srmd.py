@@ -375,9 +375,10 @@ class System:
         _check(load().srmd_set_sort_interval(self._h, int(builds)), self._h)
 
     def set_fused_reduction(self, enable=True):
-        """Launch chains: the step kernel's last workgroup ends each step (True) or a
-        separate one-workgroup kernel does (False); bitwise the same results."""
-        _check(load().srmd_set_fused_reduction(self._h, 1 if enable else 0), self._h)
+        """Launch chains: the step kernel's last workgroup ends each step (True), a
+        separate one-workgroup kernel does (False), or the library chooses (None, the
+        default); bitwise the same results."""
+        _check(load().srmd_set_fused_reduction(self._h, -1 if enable is None else (1 if enable else 0)), self._h)
 
     def set_persistent(self, groups=-1):
         """Run steps as persistent launches of 500 steps each (groups > 0 workgroups,

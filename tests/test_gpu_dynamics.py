@@ -511,3 +511,41 @@ def test_row_builder_long_rows_and_full_axes():
             out.append(s.get_state())
     np.testing.assert_array_equal(out[0]["pos"], out[1]["pos"])
     np.testing.assert_array_equal(out[0]["vel"], out[1]["vel"])
+
+
+@pytest.mark.parametrize("mode", ["chain", "persistent", "batch"])
+def test_trace_settings_do_not_change_trajectory(mode):
+    """Asking for a thermodynamic trace mid-run (the first one, then a longer one, so
+    its buffer grows twice) leaves the list and the trajectory alone: bitwise the run
+    without traces, with the same rebuild count."""
+    from paper_1506_05094_amd import srmd
+
+    print(f"trace settings vs trajectory: {mode}", flush=True)
+    st = gen.ka_random_state(1500, 1.2, 0.6, 41)
+    sig, eps, rc = gen.ka_params()
+
+    def mk():
+        s = make_system(st, sig, eps, rc, "sf", launch=(8, 32))
+        s.set_integrator_nvt(0.002, 0.6, 0.2)
+        if mode == "persistent":
+            s.set_persistent(-1)
+        return s
+
+    a, b = mk(), mk()
+    if mode == "batch":
+        with srmd.Batch([a]) as ba, srmd.Batch([b]) as bb:
+            ba.step(60)
+            ba.step(60, thermo_every=1)
+            ba.step(120, thermo_every=1)
+            bb.step(240)
+    else:
+        a.step(60)
+        a.step(60, thermo_every=1)
+        a.step(120, thermo_every=1)
+        b.step(240)
+    sa, sb = a.get_state(), b.get_state()
+    np.testing.assert_array_equal(sa["pos"], sb["pos"])
+    np.testing.assert_array_equal(sa["vel"], sb["vel"])
+    assert a.stats()["n_rebuilds"] == b.stats()["n_rebuilds"]
+    a.close()
+    b.close()

@@ -130,6 +130,23 @@ def test_fused_chain_equals_persistent():
     sb.close()
 
 
+def test_automatic_choice_matches_both_forms():
+    """The default (the library's choice) gives the same trajectory as either form,
+    for a grid the automatic rule keeps separate (KA 4096 at t_p = 32: 512 blocks)."""
+    print("fused: automatic choice, KA 4096 (32, 8)", flush=True)
+    st, (sig, eps, rc), method = _ka(4096, 38)
+    finals = []
+    for flag in (None, True, False):
+        s = make_system(st, sig, eps, rc, method, launch=(32, 8))
+        s.set_fused_reduction(flag)
+        s.set_integrator_nvt(0.002, 0.6, 0.2)
+        s.step(150)
+        finals.append(s.get_state()["pos"])
+        s.close()
+    np.testing.assert_array_equal(finals[0], finals[1])
+    np.testing.assert_array_equal(finals[0], finals[2])
+
+
 def test_rejects_bad_flag():
     from paper_1506_05094_amd import srmd
 
