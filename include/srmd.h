@@ -218,17 +218,22 @@ srmd_status srmd_set_rebuild_path(srmd_system *s, int32_t sort_mode, int32_t lis
  * entries (and so the float32 summation order) follows the sort. */
 srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds);
 
-/* Launch chains: end each step inside the step kernel (enable = 1), in a separate
- * one-workgroup kernel (0), or by the library's choice (-1, the default: inside the
- * step kernel except for a small system whose step grid has more than 256
- * workgroups, measured slower there).  Inside the step kernel the workgroup that
- * arrives last reduces the block partials in the fixed order of the separate
- * kernel, updates the Nose-Hoover friction, writes the record, takes the rebuild
- * decision of the paper's section 6 and, for a small system, runs the spatial sort
- * of section 7, so a step needs one launch fewer.  The trajectory and records are
- * bitwise the same either way.  Small systems whose sort arrays exceed 60 KiB of
- * LDS use the separate kernel whatever is asked.  The persistent kernel and
- * batches ignore it.  Errors: SRMD_EINVAL for another value. */
+/* Launch chains: how much of a step the step kernel does.  0: a separate
+ * one-workgroup kernel ends each step and a list kernel (which exits unless the
+ * rebuild flag is set) starts it.  1: the workgroup of the step kernel that arrives
+ * last ends the step: it reduces the block partials in the fixed order of the
+ * separate kernel, updates the Nose-Hoover friction, writes the record, takes the
+ * rebuild decision of the paper's section 6 and, for a small system, runs the
+ * spatial sort of section 7.  2: as 1, and a small system with the wave-per-particle
+ * list builder builds its lists at the start of the step kernel when the flag is
+ * set (each wave builds the lists of its block's particles), so a step is one
+ * launch.  -1 (the default): the library's choice, 2 where it applies, except 0 for a
+ * small system whose step grid has more than 256 workgroups (measured slower).  The
+ * trajectory, records and lists are bitwise the same in every form.  Forms that do
+ * not apply (blocks that are not whole 64-thread waves, LDS arrays past 60 KiB, more
+ * than 8 particles per wave to build, another list builder) fall back to the next
+ * lower one.  The persistent kernel and batches ignore it.  Errors: SRMD_EINVAL for
+ * another value. */
 srmd_status srmd_set_fused_reduction(srmd_system *s, int32_t enable);
 
 /* Run the steps of a small system as persistent launches (one launch per 500

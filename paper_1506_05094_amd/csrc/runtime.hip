@@ -20,7 +20,7 @@
 namespace srmd {
 hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hipStream_t st, const SysConst &c,
                        const SysPtrs &p, int cur, int tail, size_t lds);
-size_t tail_lds_bytes(const SysConst &c);
+size_t tail_lds_bytes(const SysConst &c, int threads, int tail);
 size_t arrive_bytes();
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur);
@@ -66,6 +66,7 @@ struct DevBuf {
 constexpr int kChunk = 64;  // steps per captured graph (even: the position buffers alternate)
 constexpr size_t kTailLdsMax = 60 * 1024;  // dynamic LDS of a step kernel that sorts in its last workgroup
 constexpr int kTailAutoBlocks = 256;       // largest small-system grid that ends its steps itself by default
+constexpr int kBuildPerWave = 8;          // most particles a wave of the step kernel builds the lists of
 constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel (even)
 
 }  // namespace
@@ -99,7 +100,7 @@ struct srmd_system {
   int tp_tuned = 0, ppb_tuned = 0;
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
   int sort_every = 0;                // all-pairs lists: spatial sort at every k-th build (0: never)
-  int tail_req = -1;                 // launch chains: the step kernel's last workgroup ends the step (1), k_finish does (0), automatic (-1)
+  int tail_req = -1;                 // launch chains: step kernel ends the step (1), also builds small systems' lists (2), k_finish (0), automatic (-1)
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -546,20 +547,29 @@ srmd_status prepare(srmd_system *s) {
 // The step kernel ends the step itself (its last workgroup runs the reduction,
 // thermostat and record, and a small system's sort) when asked to, when its
 // workgroups are whole waves and when the sort's arrays fit the LDS of a launch.
-bool use_tail(const srmd_system *s) {
-  if (s->tail_req == 0 || (s->tp * s->ppb) % 64 != 0 || tail_lds_bytes(s->c) > kTailLdsMax) return false;
+// How a launch-chain step ends and builds its list: 0 the separate end-of-step
+// kernel; 1 the step kernel's last workgroup ends the step; 2 as 1, and a small
+// system's wave-builder lists are built at the start of the step kernel (no list
+// kernel in the chain) when each wave has at most kBuildPerWave particles to build.
+int step_tail(const srmd_system *s) {
+  const int threads = s->tp * s->ppb;
+  if (s->tail_req == 0 || threads % 64 != 0 || tail_lds_bytes(s->c, threads, 1) > kTailLdsMax) return 0;
   // automatic: not for a small system's grid of more than 256 workgroups, which all
   // end at about the same time and queue on the arrival counters (measured slower)
-  return s->tail_req == 1 || !s->c.small_sort || step_blocks(s) <= kTailAutoBlocks;
+  if (s->tail_req < 0 && s->c.small_sort && step_blocks(s) > kTailAutoBlocks) return 0;
+  if (s->tail_req != 1 && s->c.small_sort && s->c.list_kind == 1 && s->ppb <= kBuildPerWave * (threads / 64) &&
+      tail_lds_bytes(s->c, threads, 2) <= kTailLdsMax)
+    return 2;
+  return 1;
 }
 
 // Enqueue one launch-chain step on position buffer cb.
 hipError_t enqueue_step(srmd_system *s, int cb) {
-  hipError_t e = launch_rebuild(s->stream, s->c, s->p, cb);
-  const bool tail = use_tail(s);
+  const int tail = step_tail(s);
+  hipError_t e = tail == 2 ? hipSuccess : launch_rebuild(s->stream, s->c, s->p, cb);
   if (e == hipSuccess)
     e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb,
-                    tail ? 1 : 0, tail ? tail_lds_bytes(s->c) : 0);
+                    tail, tail ? tail_lds_bytes(s->c, s->tp * s->ppb, tail) : 0);
   if (e == hipSuccess && !tail) e = launch_finish(0, step_blocks(s), cb ^ 1, s->stream, s->c, s->p);
   return e;
 }
@@ -1463,7 +1473,7 @@ srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds) {
 
 srmd_status srmd_set_fused_reduction(srmd_system *s, int32_t enable) {
   if (!s) return fail(nullptr, SRMD_EINVAL, "system is NULL");
-  if (enable < -1 || enable > 1) return fail(s, SRMD_EINVAL, "enable must be -1, 0 or 1");
+  if (enable < -1 || enable > 2) return fail(s, SRMD_EINVAL, "enable must be -1, 0, 1 or 2");
   s->tail_req = enable;
   s->dirty = true;  // the captured graphs hold the other form
   return SRMD_OK;
@@ -1971,12 +1981,12 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
   while (done < nsteps && result == SRMD_OK) {
     const int cnt = (int)std::min<long long>(batch, nsteps - done);
     for (int k = 0; k < cnt && result == SRMD_OK; ++k) {
-      hipError_t e = launch_rebuild(s->stream, s->c, s->p, s->cur);
-      const bool tail = use_tail(s);
+      const int tail = step_tail(s);
+      hipError_t e = tail == 2 ? hipSuccess : launch_rebuild(s->stream, s->c, s->p, s->cur);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k], s->stream);
       if (e == hipSuccess)
         e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur,
-                        tail ? 1 : 0, tail ? tail_lds_bytes(s->c) : 0);
+                        tail, tail ? tail_lds_bytes(s->c, s->tp * s->ppb, tail) : 0);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k + 1], s->stream);
       if (e == hipSuccess && !tail) e = launch_finish(0, step_blocks(s), s->cur ^ 1, s->stream, s->c, s->p);
       if (e != hipSuccess) result = fail(s, SRMD_EHIP, std::string("profiled launch: ") + hipGetErrorString(e));

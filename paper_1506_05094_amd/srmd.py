@@ -375,10 +375,12 @@ class System:
         _check(load().srmd_set_sort_interval(self._h, int(builds)), self._h)
 
     def set_fused_reduction(self, enable=True):
-        """Launch chains: the step kernel's last workgroup ends each step (True), a
-        separate one-workgroup kernel does (False), or the library chooses (None, the
-        default); bitwise the same results."""
-        _check(load().srmd_set_fused_reduction(self._h, -1 if enable is None else (1 if enable else 0)), self._h)
+        """Launch chains: the step kernel's last workgroup ends each step (True or 1),
+        and also builds a small system's lists at the start of the step (2); separate
+        kernels (False or 0); the library's choice (None, the default).  Bitwise the
+        same results in every form."""
+        v = -1 if enable is None else int(enable)
+        _check(load().srmd_set_fused_reduction(self._h, v), self._h)
 
     def set_persistent(self, groups=-1):
         """Run steps as persistent launches of 500 steps each (groups > 0 workgroups,

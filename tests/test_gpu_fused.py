@@ -35,7 +35,7 @@ def _lj(n, seed):
 def _pair_runs(state, params, method, launch, precision="f32", list_mode=0, sort_every=0, steps=200, nvt=True):
     sig, eps, rc = params
     out = []
-    for fused in (True, False):
+    for fused in (2, 1, 0):  # lists built in the step kernel too; end of step only; separate kernels
         s = make_system(state, sig, eps, rc, method, precision=precision, launch=launch)
         s.set_fused_reduction(fused)
         if list_mode:
@@ -53,21 +53,24 @@ def _pair_runs(state, params, method, launch, precision="f32", list_mode=0, sort
 
 
 def _assert_same(runs, label):
-    (sa, ta, xa), (sb, tb, xb) = runs
-    for k in ("pos", "vel", "image", "pos64"):
-        np.testing.assert_array_equal(xa[k], xb[k], err_msg=f"{label}: {k}")
-    for f in ta.dtype.names:
-        np.testing.assert_array_equal(ta[f], tb[f], err_msg=f"{label}: record field {f}")
-    assert ta["n_rebuilds"][-1] > ta["n_rebuilds"][0], f"{label}: no rebuild in the run"
-    pa, pb = sa.neighbor_pairs(), sb.neighbor_pairs()
-    np.testing.assert_array_equal(pa, pb, err_msg=f"{label}: neighbour pairs")
-    for s in (sa, sb):
+    sb, tb, xb = runs[-1]  # separate kernels
+    pb = sb.neighbor_pairs()
+    for form, (sa, ta, xa) in zip((2, 1), runs[:-1]):
+        for k in ("pos", "vel", "image", "pos64"):
+            np.testing.assert_array_equal(xa[k], xb[k], err_msg=f"{label} form {form}: {k}")
+        for f in ta.dtype.names:
+            np.testing.assert_array_equal(ta[f], tb[f], err_msg=f"{label} form {form}: record field {f}")
+        np.testing.assert_array_equal(sa.neighbor_pairs(), pb, err_msg=f"{label} form {form}: neighbour pairs")
+    assert tb["n_rebuilds"][-1] > tb["n_rebuilds"][0], f"{label}: no rebuild in the run"
+    for s, _, _ in runs:
         s.close()
 
 
-@pytest.mark.parametrize("launch", [(16, 16), (8, 32), (1, 256), (4, 64), (64, 16)])
+@pytest.mark.parametrize("launch", [(16, 16), (8, 32), (32, 8), (1, 256), (4, 64), (64, 16)])
 def test_fused_equals_separate_small_ka(launch):
-    """KA N = 1500 NVT (small system: the sort runs in the last workgroup)."""
+    """KA N = 1500 NVT (small system: the sort runs in the last workgroup; the lists
+    are built in the step kernel at (16, 16), (8, 32) and (32, 8); the other layouts
+    have more particles per wave or more LDS than that form takes and fall back)."""
     print(f"fused vs separate: KA 1500 launch={launch}", flush=True)
     st, params, method = _ka(1500, 31)
     _assert_same(_pair_runs(st, params, method, launch), f"KA 1500 {launch}")
@@ -110,13 +113,14 @@ def test_sort_arrays_past_the_lds_limit_fall_back():
 
 
 def test_fused_chain_equals_persistent():
-    """The fused chain follows the persistent kernel's trajectory bit for bit."""
+    """The one-launch chain (lists built in the step kernel) follows the persistent
+    kernel's trajectory bit for bit."""
     print("fused chain vs persistent: KA 3000 (16, 16)", flush=True)
     st, (sig, eps, rc), method = _ka(3000, 36)
     runs = []
     for mode in (0, -1):
         s = make_system(st, sig, eps, rc, method, launch=(16, 16))
-        s.set_fused_reduction(True)
+        s.set_fused_reduction(2)
         s.set_persistent(mode)
         s.set_integrator_nvt(0.002, 0.6, 0.2)
         tr = s.step(600, thermo_every=20)
@@ -136,15 +140,15 @@ def test_automatic_choice_matches_both_forms():
     print("fused: automatic choice, KA 4096 (32, 8)", flush=True)
     st, (sig, eps, rc), method = _ka(4096, 38)
     finals = []
-    for flag in (None, True, False):
+    for flag in (None, 2, 1, 0):
         s = make_system(st, sig, eps, rc, method, launch=(32, 8))
         s.set_fused_reduction(flag)
         s.set_integrator_nvt(0.002, 0.6, 0.2)
         s.step(150)
         finals.append(s.get_state()["pos"])
         s.close()
-    np.testing.assert_array_equal(finals[0], finals[1])
-    np.testing.assert_array_equal(finals[0], finals[2])
+    for f in finals[1:]:
+        np.testing.assert_array_equal(finals[0], f)
 
 
 def test_rejects_bad_flag():
@@ -153,5 +157,5 @@ def test_rejects_bad_flag():
     st, (sig, eps, rc), method = _ka(500, 37)
     s = make_system(st, sig, eps, rc, method)
     with pytest.raises(srmd.SrmdError):
-        srmd._check(srmd.load().srmd_set_fused_reduction(s._h, 2), s._h)
+        srmd._check(srmd.load().srmd_set_fused_reduction(s._h, 3), s._h)
     s.close()
