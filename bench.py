@@ -31,6 +31,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/sec & timesteps/sec, LJ/KA N=1k-1M; batched replicas vs single"
+LIST_MODES = {1: "wave per particle", 2: "thread per particle", 3: "wave per cell", 4: "all pairs",
+              5: "row-staged threads"}
+STEP_FORMS = {0: "list kernel, step kernel, end-of-step kernel", 1: "list kernel, step kernel ending the step",
+              2: "one step kernel (list build, forces, integrator, end of step)"}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -512,7 +516,8 @@ def main():
     value = n * args.steps / wall
     log(f"timed {args.steps} steps in {wall:.4f} s: {value:.4e} particle-steps/s, {args.steps / wall:.1f} steps/s, "
         f"rebuilds {st1['n_rebuilds'] - st0['n_rebuilds']}, tp {st1['tp']} ppb {st1['ppb']}, "
-        f"groups {st1['persistent_groups']}, T {th['temperature']:.4f}")
+        f"groups {st1['persistent_groups']}, list mode {st1['list_mode']}, step form {st1['step_form']}, "
+        f"T {th['temperature']:.4f}")
     # untimed: the dominant kernel's launches timed one by one with HIP events on the
     # system's stream (persistent: launches of 500 steps; chains: the step kernel)
     prof_steps = max(args.profile_steps, 1000 if persistent else 200)
@@ -568,8 +573,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": dict(desc, tp=st1["tp"], ppb=st1["ppb"], mode="persistent" if persistent else "chain",
-                       groups=st1["persistent_groups"],
-                       list_mode=args.list_mode or ("autotuned" if layout_tune else "automatic"),
+                       groups=st1["persistent_groups"], list_mode=LIST_MODES.get(st1["list_mode"], st1["list_mode"]),
+                       list_mode_chosen_by="autotuner" if layout_tune else ("caller" if args.list_mode else "default"),
+                       step_form=None if persistent else STEP_FORMS.get(st1["step_form"]),
                        sort_interval=args.sort_interval),
         "timesteps_per_sec": args.steps / wall,
         "rebuilds_in_timed_region": st1["n_rebuilds"] - st0["n_rebuilds"],

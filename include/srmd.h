@@ -225,9 +225,9 @@ srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds);
  * separate kernel, updates the Nose-Hoover friction, writes the record, takes the
  * rebuild decision of the paper's section 6 and, for a small system, runs the
  * spatial sort of section 7.  2: as 1, and a small system with the wave-per-particle
- * list builder builds its lists at the start of the step kernel when the flag is
- * set (each wave builds the lists of its block's particles), so a step is one
- * launch.  -1 (the default): the library's choice, 2 where it applies, except 0 for a
+ * or the all-pairs list builder builds its lists at the start of the step kernel
+ * when the flag is set (each wave builds the lists of its block's particles), so a
+ * step is one launch.  -1 (the default): the library's choice, 2 where it applies, except 0 for a
  * small system whose step grid has more than 256 workgroups (measured slower).  The
  * trajectory, records and lists are bitwise the same in every form.  Forms that do
  * not apply (blocks that are not whole 64-thread waves, LDS arrays past 60 KiB, more
@@ -441,11 +441,15 @@ srmd_status srmd_get_box(const srmd_system *s, double box[3]);
 
 /* Counters of a system: steps taken, list builds, entries of the current list,
  * the longest list of the last build, the list capacity per particle, the launch
- * shape in use (tp, ppb, blocks of the step kernel), the cell grid size and the
- * workgroups of the persistent kernel (0 when steps run as launch chains). */
+ * shape in use (tp, ppb, blocks of the step kernel), the cell grid size, the
+ * workgroups of the persistent kernel (0 when steps run as launch chains), the
+ * list-build method in use (1 wave per particle, 2 thread per particle, 3 wave per
+ * cell, 4 all pairs, 5 row-staged threads) and, for launch chains, the form of a
+ * step (0, 1 or 2, as srmd_set_fused_reduction describes them). */
 typedef struct {
   int64_t steps, n_rebuilds, list_entries;
-  int32_t max_nbrs, n_max, tp, ppb, blocks, ncell, persistent_groups, reserved;
+  int32_t max_nbrs, n_max, tp, ppb, blocks, ncell, persistent_groups, list_mode;
+  int32_t step_form, reserved;
 } srmd_stats;
 
 srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out);

@@ -1881,21 +1881,32 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, i
   stage_pairs(sp, c);
   // tail 2: a small system's list is built here, at the start of a step whose
   // rebuild flag is set (no list kernel in the chain): each wave builds the lists of
-  // the block's own particles one after the other (the wave builder: the same
-  // lists), placing their sorted data; the step then reads positions from the
-  // sorted copy, which the other workgroups may not have placed yet
+  // the block's own particles one after the other (the wave builder or the all-pairs
+  // builder: the same lists as their list kernels), placing their sorted data; the
+  // step then reads positions from the sorted copy, which the other workgroups may
+  // not have placed yet
   const int build = tail == 2 ? p.ctl->rebuild : 0;
   if (build && threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
   __syncthreads();
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  // the positions of the step: the sorted copy on a build step after a sort, else in place
+  const float4 *pos = p.pos[cur];
   if (build) {
     const int wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6), ppb = (int)blockDim.x / TP;
+    const bool allp = c.list_kind == 4;  // all pairs: sorted only when a periodic re-sort was due
+    const bool sorted = !allp || p.ctl->resorted != 0;
+    if (sorted) pos = p.t_pos;
     int kept = 0, longest = 0;
     for (int q = wv; q < ppb; q += nw) {
       const int slot = lb * ppb + q;
       if (slot < c.n) {  // uniform across the wave
-        const int k = list_wave_one<true>(c, p, cur, slot, s_tail_lds + wv * kWaveCand, s_cs2, p.t_pos,
-                                          p.cell_start, longest);
+        int k;
+        if (allp) {
+          if (sorted && (threadIdx.x & 63) == 0) place_sorted(p, cur, slot, pos[slot]);
+          k = list_allpairs_one(c, p, slot, s_cs2, pos, longest);
+        } else {
+          k = list_wave_one<true>(c, p, cur, slot, s_tail_lds + wv * kWaveCand, s_cs2, pos, p.cell_start, longest);
+        }
         if ((threadIdx.x & 63) == 0) kept += k;
       }
     }
@@ -1905,7 +1916,6 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, i
   const int gt = lb * blockDim.x + threadIdx.x;
   const int i = gt / TP, t = gt % TP;
   const bool active = i < c.n;
-  const float4 *pos = build ? p.t_pos : p.pos[cur];
   float fx = 0.f, fy = 0.f, fz = 0.f, u = 0.f, w = 0.f;
   float4 pi = make_float4(0.f, 0.f, 0.f, 0.f);
   // integrator operands are loaded before the force loop so their latency overlaps it
@@ -2697,7 +2707,7 @@ hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hi
 // (tail 2), at least the wave builder's candidate windows (the two uses alias).
 size_t tail_lds_bytes(const SysConst &c, int threads, int tail) {
   const size_t sort = c.small_sort ? tail_sort_lds(c.n, c.ncell) : 0;
-  const size_t windows = tail == 2 ? sizeof(unsigned) * kWaveCand * (size_t)(threads / 64) : 0;
+  const size_t windows = tail == 2 && c.list_kind == 1 ? sizeof(unsigned) * kWaveCand * (size_t)(threads / 64) : 0;
   return std::max(sort, windows);
 }
 

@@ -549,15 +549,17 @@ srmd_status prepare(srmd_system *s) {
 // workgroups are whole waves and when the sort's arrays fit the LDS of a launch.
 // How a launch-chain step ends and builds its list: 0 the separate end-of-step
 // kernel; 1 the step kernel's last workgroup ends the step; 2 as 1, and a small
-// system's wave-builder lists are built at the start of the step kernel (no list
-// kernel in the chain) when each wave has at most kBuildPerWave particles to build.
+// system's wave-builder or all-pairs lists are built at the start of the step
+// kernel (no list kernel in the chain) when each wave has at most kBuildPerWave
+// particles to build.
 int step_tail(const srmd_system *s) {
   const int threads = s->tp * s->ppb;
   if (s->tail_req == 0 || threads % 64 != 0 || tail_lds_bytes(s->c, threads, 1) > kTailLdsMax) return 0;
   // automatic: not for a small system's grid of more than 256 workgroups, which all
   // end at about the same time and queue on the arrival counters (measured slower)
   if (s->tail_req < 0 && s->c.small_sort && step_blocks(s) > kTailAutoBlocks) return 0;
-  if (s->tail_req != 1 && s->c.small_sort && s->c.list_kind == 1 && s->ppb <= kBuildPerWave * (threads / 64) &&
+  if (s->tail_req != 1 && s->c.small_sort && (s->c.list_kind == 1 || s->c.list_kind == 4) &&
+      s->ppb <= kBuildPerWave * (threads / 64) &&
       tail_lds_bytes(s->c, threads, 2) <= kTailLdsMax)
     return 2;
   return 1;
@@ -1908,6 +1910,8 @@ srmd_status srmd_get_stats(srmd_system *s, srmd_stats *out) {
   out->blocks = step_blocks(s);
   out->ncell = s->c.ncell;
   out->persistent_groups = s->persist_groups;
+  out->list_mode = s->c.list_kind;
+  out->step_form = s->persist_groups > 0 ? 0 : step_tail(s);
   out->reserved = 0;
   return SRMD_OK;
 }

@@ -38,7 +38,8 @@ class srmd_stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("n_rebuilds", ctypes.c_int64), ("list_entries", ctypes.c_int64),
                 ("max_nbrs", ctypes.c_int32), ("n_max", ctypes.c_int32), ("tp", ctypes.c_int32),
                 ("ppb", ctypes.c_int32), ("blocks", ctypes.c_int32), ("ncell", ctypes.c_int32),
-                ("persistent_groups", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("persistent_groups", ctypes.c_int32), ("list_mode", ctypes.c_int32), ("step_form", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -46,7 +46,7 @@ def test_binding_covers_header():
 def test_thermo_struct_layout():
     from paper_1506_05094_amd import srmd
     assert ctypes.sizeof(srmd.srmd_thermo) == 9 * 8 + 2 * 8 + 2 * 4
-    assert ctypes.sizeof(srmd.srmd_stats) == 3 * 8 + 8 * 4
+    assert ctypes.sizeof(srmd.srmd_stats) == 3 * 8 + 10 * 4
 
 
 def test_null_arguments_rejected_without_gpu(lib):
