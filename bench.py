@@ -372,9 +372,10 @@ def run_sweep(args):
         st = s.stats()
         row = {"n": state.n, "tp": tp, "ppb": ppb, "mode": "persistent" if groups else "chain", "groups": groups,
                "steps_per_s": args.steps / wall, "particle_steps_per_s": state.n * args.steps / wall,
-               "rebuilds": st["n_rebuilds"]}
+               "rebuilds": st["n_rebuilds"], "list_mode": st["list_mode"],
+               "step_form": None if groups else st["step_form"]}
         if tuned:
-            row.update({"skin": tuned["skin"], "list_mode": tuned["list_mode"], "trials": tuned["trials"],
+            row.update({"skin": tuned["skin"], "trials": tuned["trials"],
                         "from_cache": tuned["from_cache"],
                         "trial_steps_per_s_baseline": 1e3 / tuned["baseline_ms_per_step"]
                         if tuned["baseline_ms_per_step"] > 0 else None,

@@ -231,8 +231,8 @@ srmd_status srmd_set_sort_interval(srmd_system *s, int32_t builds);
  * small system whose step grid has more than 256 workgroups (measured slower).  The
  * trajectory, records and lists are bitwise the same in every form.  Forms that do
  * not apply (blocks that are not whole 64-thread waves, LDS arrays past 60 KiB, more
- * than 8 particles per wave to build, another list builder) fall back to the next
- * lower one.  The persistent kernel and batches ignore it.  Errors: SRMD_EINVAL for
+ * than 8 particles per wave to build (2 with all-pairs lists), another list builder)
+ * fall back to the next lower one.  The persistent kernel and batches ignore it.  Errors: SRMD_EINVAL for
  * another value. */
 srmd_status srmd_set_fused_reduction(srmd_system *s, int32_t enable);
 

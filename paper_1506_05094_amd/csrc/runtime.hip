@@ -67,6 +67,7 @@ constexpr int kChunk = 64;  // steps per captured graph (even: the position buff
 constexpr size_t kTailLdsMax = 60 * 1024;  // dynamic LDS of a step kernel that sorts in its last workgroup
 constexpr int kTailAutoBlocks = 256;       // largest small-system grid that ends its steps itself by default
 constexpr int kBuildPerWave = 8;          // most particles a wave of the step kernel builds the lists of
+constexpr int kBuildPerWaveAllPairs = 2;  // the same with all-pairs lists (N candidates each: measured slower at 4 and 8)
 constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel (even)
 
 }  // namespace
@@ -551,15 +552,16 @@ srmd_status prepare(srmd_system *s) {
 // kernel; 1 the step kernel's last workgroup ends the step; 2 as 1, and a small
 // system's wave-builder or all-pairs lists are built at the start of the step
 // kernel (no list kernel in the chain) when each wave has at most kBuildPerWave
-// particles to build.
+// (all pairs: kBuildPerWaveAllPairs) particles to build.
 int step_tail(const srmd_system *s) {
   const int threads = s->tp * s->ppb;
   if (s->tail_req == 0 || threads % 64 != 0 || tail_lds_bytes(s->c, threads, 1) > kTailLdsMax) return 0;
   // automatic: not for a small system's grid of more than 256 workgroups, which all
   // end at about the same time and queue on the arrival counters (measured slower)
   if (s->tail_req < 0 && s->c.small_sort && step_blocks(s) > kTailAutoBlocks) return 0;
+  const int per_wave = s->c.list_kind == 4 ? kBuildPerWaveAllPairs : kBuildPerWave;
   if (s->tail_req != 1 && s->c.small_sort && (s->c.list_kind == 1 || s->c.list_kind == 4) &&
-      s->ppb <= kBuildPerWave * (threads / 64) &&
+      s->ppb <= per_wave * (threads / 64) &&
       tail_lds_bytes(s->c, threads, 2) <= kTailLdsMax)
     return 2;
   return 1;

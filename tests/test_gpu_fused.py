@@ -83,13 +83,32 @@ def test_fused_equals_separate_precisions(precision):
     _assert_same(_pair_runs(st, params, method, (8, 32), precision=precision, nvt=False), f"LJ {precision}")
 
 
+@pytest.mark.parametrize("launch", [(16, 16), (32, 8)])
 @pytest.mark.parametrize("sort_every", [0, 3])
-def test_fused_equals_separate_all_pairs(sort_every):
-    """All-pairs lists: the tail re-sorts only when the periodic re-sort is due."""
-    print(f"fused vs separate: KA 1000 all pairs, re-sort every {sort_every}", flush=True)
+def test_fused_equals_separate_all_pairs(sort_every, launch):
+    """All-pairs lists: the tail re-sorts only when the periodic re-sort is due; at
+    (32, 8) the lists are built in the step kernel (two particles per wave), at
+    (16, 16) form 2 falls back to form 1."""
+    print(f"fused vs separate: KA 1000 all pairs {launch}, re-sort every {sort_every}", flush=True)
     st, params, method = _ka(1000, 33)
-    _assert_same(_pair_runs(st, params, method, (16, 16), list_mode=4, sort_every=sort_every),
-                 f"all pairs re-sort {sort_every}")
+    _assert_same(_pair_runs(st, params, method, launch, list_mode=4, sort_every=sort_every),
+                 f"all pairs {launch} re-sort {sort_every}")
+
+
+def test_step_form_reported():
+    """The stats report the form each request resolves to."""
+    st, (sig, eps, rc), method = _ka(1500, 39)
+    s = make_system(st, sig, eps, rc, method, launch=(16, 16))
+    got = []
+    for flag in (0, 1, 2, None):
+        s.set_fused_reduction(flag)
+        got.append(s.stats()["step_form"])
+    s.set_launch(1, 256)  # 64 particles per wave to build: form 2 falls back to 1
+    s.set_fused_reduction(2)
+    got.append(s.stats()["step_form"])
+    assert got == [0, 1, 2, 2, 1], got
+    assert s.stats()["list_mode"] == 1
+    s.close()
 
 
 @pytest.mark.parametrize("launch", [(1, 256), (4, 16)])
