@@ -8,9 +8,10 @@ reductions.  Seeded random non-overlapping start, relaxed by an untimed
 2000-step NVT run at dt = 0.001 and untimed NVT steps at dt = 0.005 until the
 temperature is within 3 % of T0; the layout autotuner (untimed) then picks
 threads per particle, block size, list builder and launch form at skin 0.3,
-and W untimed and K timed steps follow (one srmd_step call).  A step is one pass of the whole hot path: displacement check,
-list rebuild when due (cell binning, counting sort, reorder, cell-stencil list),
-pair forces, integrator and thermostat.
+and W untimed and K timed steps follow (one srmd_step call).  A step is one
+pass of the whole hot path: displacement check, list rebuild when due (cell
+binning, counting sort, reorder, cell-stencil list), pair forces, integrator
+and thermostat.
 
 Prints one JSON line with particle-steps/s (whole job), the roofline position of
 the dominant kernel (per step: algorithmic bytes and FLOPs against HBM and FP32
@@ -77,8 +78,8 @@ def path_bytes_per_particle_step(list_len, steps_per_rebuild, whole_path):
     """Algorithmic bytes per particle-step: force kernel 4 per list entry + 40 (list
     length, own position, force and energy out, virial), integrator 96 (position,
     velocity, force and last-build position in; position and velocity out), and for
-    the whole path (the persistent kernel) the rebuild's 170 + 4 per list entry
-    amortised over the steps between rebuilds.  The neighbours' positions count once:
+    the whole path (the persistent kernel, the one-launch chain) the rebuild's 170 +
+    4 per list entry amortised over the steps between rebuilds.  The neighbours' positions count once:
     the spatially sorted position array serves every neighbour read."""
     b = 4.0 * list_len + 40.0 + 96.0
     if whole_path:
@@ -107,11 +108,12 @@ def in_range_pairs_per_particle(pos, types, box, rc):
     return 2.0 * keep.sum() / len(pos)
 
 
-def hbm_traffic_per_step(workload_name, n, mode, tp, ppb, skin):
+def hbm_traffic_per_step(workload_name, n, mode, tp, ppb, skin, list_mode):
     """HBM bytes per step of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (profiles/traffic.json; per dispatch, divided by
     the steps of that dispatch), or None when they were taken with another kernel
-    source or another workload / launch shape."""
+    source (each entry records the hash of the kernel source it was taken with) or
+    another workload / launch shape."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", "traffic.json")
@@ -123,10 +125,11 @@ def hbm_traffic_per_step(workload_name, n, mode, tp, ppb, skin):
             digest = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if table.get("kernels_hip_sha256") != digest:
-        return None
     for e in table.get("entries", []):
-        if (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"]) == (workload_name, n, mode, tp, ppb, skin):
+        if e.get("kernels_hip_sha256") != digest:
+            continue  # counters of another kernel source are never reported
+        if (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"], e["list_mode"]) == (
+                workload_name, n, mode, tp, ppb, skin, list_mode):
             per_dispatch = 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
             return per_dispatch / e["steps_per_launch"]
     return None
@@ -202,7 +205,8 @@ def replica_comparison(args, steps=None, base_steps=None):
     sig, eps, rc = gen.ka_params()
     temps = [T for (_, T, _) in gen.config3_states(args.replicas)]
     stream = torch.cuda.current_stream().cuda_stream
-    # t_p = 1, 256 particles per block: the fastest batch layout measured on MI355X
+    # start layout t_p = 1, 256 particles per block; the batch autotuner picks the
+    # layout below unless --tp is given
     tp, ppb = args.tp or 1, args.ppb or max(1, 256 // (args.tp or 1))
     systems = []
     for st, T in zip(states, temps):
@@ -210,6 +214,7 @@ def replica_comparison(args, steps=None, base_steps=None):
         s.set_launch(tp, ppb)
         s.set_integrator_nvt(0.001, T, 0.2)
         systems.append(s)
+    shapes = [(tp, ppb)] * len(systems)
     ntot = sum(s.n for s in systems)
     nr = np.array([s.n for s in systems])
     every = max(1, steps // 50)
@@ -225,6 +230,16 @@ def replica_comparison(args, steps=None, base_steps=None):
     for s, T in zip(systems, temps):
         s.set_integrator_nvt(0.005, T, 0.2)
     batch.step(max(args.warmup, 200))
+    tuned = None
+    if not args.tp:
+        # untimed: the batch autotuner (shared t_p, then a block size per replica size
+        # bucket); every trial starts from the stored states, which it restores
+        t0 = time.perf_counter()
+        tp, ppb_r = batch.autotune(200)
+        shapes = [(tp, int(b)) for b in ppb_r]
+        tuned = {"tp": tp, "ppb_counts": {str(b): int(c) for b, c in zip(*np.unique(ppb_r, return_counts=True))},
+                 "seconds": round(time.perf_counter() - t0, 1)}
+        log(f"batch autotune: {tuned}")
     blobs = [s.save_state() for s in systems]  # the common start of every form
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -235,12 +250,12 @@ def replica_comparison(args, steps=None, base_steps=None):
     batch.close()
     log(f"batched: {steps} steps of {len(systems)} replicas in {wall_b:.3f} s -> {value_b:.4e} particle-steps/s")
     baselines = {}
-    for name, shape, mode, nst in (("chain_same_shape", (tp, ppb), 0, steps),
-                                   ("chain_default_shape", (0, 0), 0, min(steps, base_steps)),
-                                   ("persistent_default_shape", (0, 0), -1, min(steps, base_steps))):
+    for name, same, mode, nst in (("chain_same_shape", True, 0, steps),
+                                  ("chain_default_shape", False, 0, min(steps, base_steps)),
+                                  ("persistent_default_shape", False, -1, min(steps, base_steps))):
         k = max(1, nst // 50)
-        for s, blob in zip(systems, blobs):
-            s.set_launch(*shape)
+        for s, blob, shape in zip(systems, blobs, shapes):
+            s.set_launch(*(shape if same else (0, 0)))
             s.set_persistent(mode)
             s.step(nst)  # graphs of these lengths captured, first build at this shape (untimed)
             s.load_state(blob)
@@ -263,7 +278,9 @@ def replica_comparison(args, steps=None, base_steps=None):
     return {
         "workload": f"{len(systems)} Kob-Andersen replicas, N ~ U[500, 8000], T ~ U[0.4, 1.0], NVT dt 0.005, "
                     "one persistent launch per 500 steps",
-        "n_total": ntot, "tp": tp, "ppb": ppb, "steps": steps, "value": value_b, "unit": "particle-steps/s",
+        "n_total": ntot, "tp": tp, "ppb": ppb if tuned is None else tuned["ppb_counts"],
+        "layout": "srmd_batch_autotune" if tuned else "given", "autotune": tuned,
+        "steps": steps, "value": value_b, "unit": "particle-steps/s",
         "wall_s": wall_b, "one_launch_per_system": baselines,
         "batched_over_single_same_shape": value_b / baselines["chain_same_shape"]["value"],
         "batched_over_single_best": value_b / best["value"],
@@ -507,10 +524,15 @@ def main():
     s.step(args.warmup)
     torch.cuda.synchronize()
     st0 = s.stats()
+    # HIP events on the system's stream (the current stream) bracket the timed region
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    ev0.record()
     s.step(args.steps)  # the product call: every timed step in one srmd_step
+    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    region_ms = ev0.elapsed_time(ev1)
     st1 = s.stats()
     th = s.thermo()
     n = state.n
@@ -536,16 +558,25 @@ def main():
     # the Coulomb term's cutoff widens the pairs whose force is evaluated (molten salt)
     rc_eval = np.maximum(rc, params[4]) if len(params) == 5 else rc
     in_range = in_range_pairs_per_particle(fin["pos"], state.types, state.box, rc_eval)
-    step_s = ev_ms / 1e3 / launches / steps_per_launch  # dominant kernel, per step
-    bytes_step = n * path_bytes_per_particle_step(list_len, steps_per_rebuild, persistent)
+    # dominant kernel, per step: when it is the only kernel of a step (the one-launch
+    # chain), the events over the timed region (HIP events around single launches add
+    # the dispatch latency, a third of a step here); otherwise the per-launch events
+    one_kernel = not persistent and st1["step_form"] == 2
+    step_s = region_ms / 1e3 / args.steps if one_kernel else ev_ms / 1e3 / launches / steps_per_launch
+    # the whole path runs in the dominant kernel in the persistent form and in the
+    # one-launch chain (step form 2: list build, forces, integrator, end of step)
+    whole = persistent or st1["step_form"] == 2
+    bytes_step = n * path_bytes_per_particle_step(list_len, steps_per_rebuild, whole)
     flops_step = n * flops_per_particle_step(list_len, in_range, method)
     hbm_gbs = bytes_step / step_s / 1e9
     tflops = flops_step / step_s / 1e12
     hbm_frac, fp32_frac = hbm_gbs / HBM_PEAK_GBS, tflops / FP32_PEAK_TFLOPS
     kname = ("k_multi (persistent: list build, sort, pair force, integrator, reductions)" if persistent
-             else "k_step (fused pair force + integrator)")
+             else "k_step (list build, pair force, integrator, end of step and sort)" if whole
+             else "k_step (pair force, integrator, end of step)" if st1["step_form"] == 1
+             else "k_step (pair force, integrator)")
     traffic = hbm_traffic_per_step(desc["workload"], n, "persistent" if persistent else "chain", st1["tp"],
-                                   st1["ppb"], desc["skin"])
+                                   st1["ppb"], desc["skin"], st1["list_mode"])
     # the arithmetic intensity sits below the FP32 ridge (157.3 / 8 = 19.7 FLOP/B), so
     # the roofline bound is HBM; when both fractions are far below one the kernel is
     # held by latency and synchronisation instead (small systems, paper section 3)
@@ -562,6 +593,9 @@ def main():
                 "fp32": {"achieved": round(tflops, 4), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(fp32_frac, 5), "flops_per_step": flops_step},
                 "kernel": kname, "steps_per_launch": steps_per_launch, "us_per_step": round(step_s * 1e6, 3),
+                "timing": ("HIP events over the timed region (the step kernel is the only kernel of a step)"
+                           if one_kernel else "HIP events around each launch of the kernel (untimed pass)"),
+                "us_per_step_events_per_launch": round(ev_ms * 1e3 / launches / steps_per_launch, 3),
                 "profiled_steps": prof_steps, "list_entries_per_particle": round(list_len, 2),
                 "in_range_per_particle": round(in_range, 2), "steps_per_rebuild": round(steps_per_rebuild, 2)}
     s.close()

@@ -25,21 +25,26 @@ def test_traffic_is_reported_only_for_the_profiled_kernel_source():
     with open(os.path.join(ROOT, "paper_1506_05094_amd", "csrc", "kernels.hip"), "rb") as f:
         digest = hashlib.sha256(f.read()).hexdigest()
     bench = _bench()
-    current = _table()["kernels_hip_sha256"] == digest
+
+    def key(e):
+        return (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"], e["list_mode"])
+
+    current = {}
     for e in _table()["entries"]:
-        t = bench.hbm_traffic_per_step(e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"])
-        if current:
-            per_dispatch = 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
-            assert t == per_dispatch / e["steps_per_launch"]
-        else:
-            assert t is None  # counters of other kernel source are never reported
+        if e["kernels_hip_sha256"] == digest:
+            current.setdefault(key(e), 1024.0 * (e["fetch_kib"] * e["fetch_scale"] + e["write_kib"] * e["write_scale"])
+                               / e["steps_per_launch"])
+    for e in _table()["entries"]:
+        # counters of another kernel source are never reported: the lookup gives the
+        # current source's entry for the same key, or nothing
+        assert bench.hbm_traffic_per_step(*key(e)) == current.get(key(e))
 
 
 def test_every_entry_names_an_existing_summary():
     for e in _table()["entries"]:
         assert os.path.exists(os.path.join(ROOT, e["profile"])), e["profile"]
         for k in ("workload", "n", "mode", "tp", "ppb", "skin", "fetch_kib", "write_kib", "fetch_scale",
-                  "write_scale"):
+                  "write_scale", "kernels_hip_sha256", "steps_per_launch", "list_mode"):
             assert k in e, (e["profile"], k)
         assert e["fetch_kib"] > 0 and e["write_kib"] > 0
 
@@ -47,8 +52,10 @@ def test_every_entry_names_an_existing_summary():
 def test_bench_lookup_needs_the_same_shape():
     bench = _bench()
     for e in _table()["entries"]:
-        assert bench.hbm_traffic_per_step(e["workload"], e["n"], e["mode"], e["tp"] * 2, e["ppb"], e["skin"]) is None
-        assert bench.hbm_traffic_per_step(e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"] + 0.1) is None
+        key = (e["workload"], e["n"], e["mode"], e["tp"], e["ppb"], e["skin"], e["list_mode"])
+        assert bench.hbm_traffic_per_step(*key[:3], e["tp"] * 128, *key[4:]) is None
+        assert bench.hbm_traffic_per_step(*key[:5], e["skin"] + 0.1, key[6]) is None
+        assert bench.hbm_traffic_per_step(*key[:6], key[6] + 1) is None
 
 
 def test_bench_work_counts():
