@@ -2642,13 +2642,14 @@ int rebuild_grid_max_groups() {
   return std::min(per_cu * cus, (int)kGridMaxGroups);
 }
 
-// The one-launch rebuild of groups workgroups, at most half of what the device holds
-// at once (rebuild_grid_max_groups): all of them are resident together once the
-// previous launch of the stream has ended.  An ordinary launch: a cooperative one,
-// also possible inside the captured graphs, cost about 25 µs more per step (LJ 16 000).
+// The one-launch rebuild, as a cooperative launch of groups workgroups (captured in
+// the step graphs like the other launches of a step).
 hipError_t launch_rebuild_grid(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur, int groups) {
-  hipLaunchKernelGGL(k_rebuild_grid, dim3(groups), dim3(256), 0, st, c, p, cur);
-  return hipGetLastError();
+  SysConst cc = c;
+  SysPtrs pp = p;
+  int cu = cur;
+  void *args[] = {&cc, &pp, &cu};
+  return hipLaunchCooperativeKernel((const void *)k_rebuild_grid, dim3(groups), dim3(256), args, 0, st);
 }
 
 // One launch at the start of srmd_step: the call's trace settings go into the

@@ -576,7 +576,7 @@ int step_tail(srmd_system *s) {
   }
   if (s->c.list_kind < 1 || s->c.list_kind > 3) return 1;
   if (s->grid_groups < 0) s->grid_groups = rebuild_grid_max_groups();
-  return s->grid_groups >= 2 ? 2 : 1;
+  return s->grid_groups > 0 ? 2 : 1;
 }
 
 // The tail argument of the step kernel for a step form.
@@ -587,7 +587,7 @@ hipError_t enqueue_rebuild(srmd_system *s, int cb, int form) {
   if (form == 2 && s->c.small_sort) return hipSuccess;  // built in the step kernel
   if (form == 2) {
     const int need = (int)((s->n + 255) / 256);
-    return launch_rebuild_grid(s->stream, s->c, s->p, cb, std::max(1, std::min(s->grid_groups / 2, need)));
+    return launch_rebuild_grid(s->stream, s->c, s->p, cb, std::max(1, std::min(s->grid_groups, need)));
   }
   return launch_rebuild(s->stream, s->c, s->p, cb);
 }
