@@ -1105,22 +1105,12 @@ __device__ __forceinline__ int wave_min_int(int v) {
 // LDS, and every slot that all lanes of the wave have passed is written out as one
 // span.  A lane that runs kRing slots ahead of the slowest lane writes its later
 // entries directly.
-__device__ __forceinline__ void list_thread_all(const SysConst &c, const SysPtrs &p, int cur, const float *s_cs2,
-                                                int (*s_ring)[kRing][64]);
-
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_list_thread(SysConst c, SysPtrs p, int cur) {
   if (p.ctl->rebuild == 0) return;
   __shared__ float s_cs2[kMaxPairs];
   __shared__ int s_ring[4][kRing][64];
   if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
   __syncthreads();
-  list_thread_all(c, p, cur, s_cs2, s_ring);
-}
-
-// The thread builder over the whole grid (every particle of the system, a thread
-// each, blocks of 256 threads); s_ring: the block's four per-wave LDS rings.
-__device__ __forceinline__ void list_thread_all(const SysConst &c, const SysPtrs &p, int cur, const float *s_cs2,
-                                                int (*s_ring)[kRing][64]) {
   const int lane = threadIdx.x & 63;
   int(*ring)[64] = s_ring[threadIdx.x >> 6];
   const int nmax = c.n_max;
@@ -2036,49 +2026,6 @@ __global__ __launch_bounds__(1024) void k_finish(SysConst c, SysPtrs p, int G, i
   }
 }
 
-// Lists of the sorted particles by waves spread over several workgroups: wave unit
-// u of nunits takes particles u, u + nunits, ... (the wave builder), or with by_cell
-// the cells u, u + nunits, ... (the wave-per-cell builder, a cell of more particles
-// than its count slots one particle at a time).  cand: the wave's LDS window of
-// kWaveCand words (the second part holds a cell's counts); tpos and cstart: the
-// sorted positions and cell starts (device memory or LDS copies).  The sorted data
-// must already be in place.  kept (lane 0) and longest accumulate.
-__device__ __forceinline__ void build_lists_units(const SysConst &c, const SysPtrs &p, int cur, int unit, int nunits,
-                                                  bool by_cell, unsigned *cand, const float *s_cs2,
-                                                  const float4 *tpos, const unsigned *cstart, int &kept,
-                                                  int &longest) {
-  const int lane = threadIdx.x & 63;
-  int *wcnt = reinterpret_cast<int *>(cand + kCellWindow);
-  auto direct = [&](int i, int kk, int jj) {
-    if (kk < c.n_max) p.nbl[nbl_addr(i, kk, c.tp, c.nvp)] = jj;
-  };
-  for (int t = unit; !by_cell && t < c.n; t += nunits) {
-    const int kt = list_wave_one<false>(c, p, cur, t, cand, s_cs2, tpos, cstart, longest);
-    if (lane == 0) kept += kt;
-  }
-  for (int cell = unit; by_cell && cell < c.ncell; cell += nunits) {
-    const unsigned e1 = min(cstart[cell + 1], (unsigned)c.n), e0 = min(cstart[cell], e1);
-    const int ne = (int)(e1 - e0);
-    if (ne == 0) continue;  // uniform over the wave
-    if (ne > kWaveCand - kCellWindow) {  // more particles than count slots: one at a time
-      for (unsigned t = e0; t < e1; ++t) {
-        const int kt = list_wave_one<false>(c, p, cur, (int)t, cand, s_cs2, tpos, cstart, longest);
-        if (lane == 0) kept += kt;
-      }
-      continue;
-    }
-    for (int l = lane; l < ne; l += 64) wcnt[l] = 0;
-    const int cx = cell % c.nc[0], cy = (cell / c.nc[0]) % c.nc[1], cz = cell / (c.nc[0] * c.nc[1]);
-    list_cell_particles(c, p, cx, cy, cz, (int)e0, (int)e1, cand, wcnt, s_cs2, tpos, cstart, direct);
-    for (int l = lane; l < ne; l += 64) {
-      const int cn = wcnt[l];
-      p.nnb[e0 + l] = min(cn, c.n_max);
-      kept += min(cn, c.n_max);
-      longest = max(longest, cn);
-    }
-  }
-}
-
 // ---------------------------------------------------------------- persistent launches
 
 // Butterfly of a BlockPartial over the 64 lanes of a wave (the first step of
@@ -2153,8 +2100,7 @@ constexpr int kLdsUnits = 64;        // wave partials of one piece kept in LDS (
 // compute unit's L1 and of the L2 precedes, through the workgroup barrier, every
 // later load of the other waves.  With G = 1 the barrier is the workgroup barrier.
 __device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsigned w, unsigned k, int bit,
-                                             Control *ctl, int *s_ok, int *s_any,
-                                             unsigned stride = kCoopMaxGroups) {
+                                             Control *ctl, int *s_ok, int *s_any) {
   if (G == 1) {
     __syncthreads();
     if (threadIdx.x == 0) *s_any = bit;
@@ -2163,7 +2109,7 @@ __device__ __forceinline__ bool coop_barrier(unsigned *flags, unsigned G, unsign
   }
   __asm__ volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
   __syncthreads();
-  unsigned *slot = flags + (k & 1u) * stride;  // stride: words per parity (at least G)
+  unsigned *slot = flags + (k & 1u) * kCoopMaxGroups;
   if (threadIdx.x == 0) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     // the L2 write-back must complete before the arrival is visible; the compiler's own
@@ -2349,8 +2295,35 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
         // particle.  The second half of the wave's window holds the counts.
         int kept = 0, longest = 0;
         const bool by_cell = 4 * J.g * kBatchWaves <= c.ncell;
-        build_lists_units(c, p, cur, J.w * kBatchWaves + wv, J.g * kBatchWaves, by_cell, cand, s_cs2, tpos, cstart,
-                          kept, longest);
+        int *wcnt = reinterpret_cast<int *>(cand + kCellWindow);
+        auto direct = [&](int i, int kk, int jj) {
+          if (kk < c.n_max) p.nbl[nbl_addr(i, kk, c.tp, c.nvp)] = jj;
+        };
+        for (int t = J.w * kBatchWaves + wv; !by_cell && t < c.n; t += J.g * kBatchWaves) {
+          const int kt = list_wave_one<false>(c, p, cur, t, cand, s_cs2, tpos, cstart, longest);
+          if (lane == 0) kept += kt;
+        }
+        for (int cell = J.w * kBatchWaves + wv; by_cell && cell < c.ncell; cell += J.g * kBatchWaves) {
+          const unsigned e1 = min(cstart[cell + 1], (unsigned)c.n), e0 = min(cstart[cell], e1);
+          const int ne = (int)(e1 - e0);
+          if (ne == 0) continue;  // uniform over the wave
+          if (ne > kWaveCand - kCellWindow) {  // more particles than count slots: one at a time
+            for (unsigned t = e0; t < e1; ++t) {
+              const int kt = list_wave_one<false>(c, p, cur, (int)t, cand, s_cs2, tpos, cstart, longest);
+              if (lane == 0) kept += kt;
+            }
+            continue;
+          }
+          for (int l = lane; l < ne; l += 64) wcnt[l] = 0;
+          const int cx = cell % c.nc[0], cy = (cell / c.nc[0]) % c.nc[1], cz = cell / (c.nc[0] * c.nc[1]);
+          list_cell_particles(c, p, cx, cy, cz, (int)e0, (int)e1, cand, wcnt, s_cs2, tpos, cstart, direct);
+          for (int l = lane; l < ne; l += 64) {
+            const int cn = wcnt[l];
+            p.nnb[e0 + l] = min(cn, c.n_max);
+            kept += min(cn, c.n_max);
+            longest = max(longest, cn);
+          }
+        }
         list_tally(kept, longest, c.n_max, p.ctl);
         if (!coop_barrier(p.bar_flags, J.g, J.w, ++k, 0, p.ctl, &s_ok, &s_any)) return;
       }
@@ -2571,86 +2544,6 @@ int batch_max_particles() { return kSmallN; }
 size_t big_lds_bytes() { return 4 * (size_t)(kBatchWaves * kWaveCand); }
 
 // ---------------------------------------------------------------- start of a stepping call
-
-// ---------------------------------------------------------------- rebuild of a large system in one launch
-
-constexpr unsigned kGridMaxGroups = 1024;  // workgroups of the one-launch rebuild (arrival words per parity)
-constexpr unsigned kGridEpochWord = 2 * kGridMaxGroups;  // launch counter, on its own line after the words
-
-// Words of a system's one-launch-rebuild barrier: two parities of kGridMaxGroups
-// arrival words and the launch counter (zeroed at allocation, never reset).
-size_t grid_sync_words() { return kGridEpochWord + 32; }
-
-// The whole list rebuild of a large system (more than 8192 particles or cells) in
-// one launch of G <= 1024 co-resident workgroups of 256 threads, when the device
-// flag is set: the four phases of the counting sort of the launch chain (k_bin,
-// k_scan, k_scatter, k_gather) with a grid barrier after each, then the list build
-// (thread per particle, wave per particle or wave per cell: the same lists as their
-// own kernels).  Otherwise it exits at once, so a step of a large system is two
-// launches instead of six.  Barrier numbers continue from launch to launch (8 per
-// launch, from the counter in sync[kGridEpochWord], which workgroup 0 advances at
-// its end, after every workgroup has read it): the arrival words never need the
-// host memset that a captured graph must not contain.  Waits are bounded (error bit
-// 4, the kernel ends).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_rebuild_grid(SysConst c, SysPtrs p,
-                                                                                               int cur) {
-  if (p.ctl->rebuild == 0) return;
-  __shared__ float s_cs2[kMaxPairs];
-  // the thread builder's rings or the wave builders' candidate windows (one or the other)
-  constexpr int kWords = 4 * kRing * 64 > 4 * kWaveCand ? 4 * kRing * 64 : 4 * kWaveCand;
-  __shared__ unsigned s_lds[kWords];
-  __shared__ unsigned s_scan[16];
-  __shared__ int s_ok, s_any;
-  __shared__ unsigned s_epoch;
-  const unsigned G = gridDim.x, w = blockIdx.x;
-  unsigned *sync = p.grid_sync;
-  if (threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
-  if (threadIdx.x == 0) s_epoch = __hip_atomic_load(sync + kGridEpochWord, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __syncthreads();
-  unsigned k = 8u * s_epoch;
-  const int first = (int)(w * blockDim.x), stride = (int)(G * blockDim.x);
-  sort_bin(c, p, cur, first, stride);
-  if (!coop_barrier(sync, G, w, ++k, 0, p.ctl, &s_ok, &s_any, kGridMaxGroups)) return;
-  if (w == 0 && threadIdx.x == 0) begin_build(p.ctl);
-  for (int b = (int)w; b < scan_tiles(c.ncell); b += (int)G) sort_scan_tile(c, p, b, s_scan);
-  if (!coop_barrier(sync, G, w, ++k, 0, p.ctl, &s_ok, &s_any, kGridMaxGroups)) return;
-  sort_scatter(c, p, first + (int)threadIdx.x, stride, w == 0);
-  if (!coop_barrier(sync, G, w, ++k, 0, p.ctl, &s_ok, &s_any, kGridMaxGroups)) return;
-  sort_gather(c, p, cur, first + (int)threadIdx.x, stride);
-  if (!coop_barrier(sync, G, w, ++k, 0, p.ctl, &s_ok, &s_any, kGridMaxGroups)) return;
-  if (c.list_kind == 2) {
-    // places each particle's sorted data itself
-    list_thread_all(c, p, cur, s_cs2, reinterpret_cast<int(*)[kRing][64]>(s_lds));
-  } else {
-    for (int t = first + (int)threadIdx.x; t < c.n; t += stride) place_sorted(p, cur, t, p.t_pos[t]);
-    const int wv = threadIdx.x >> 6;
-    int kept = 0, longest = 0;
-    build_lists_units(c, p, cur, (int)w * 4 + wv, (int)G * 4, c.list_kind == 3, s_lds + wv * kWaveCand, s_cs2,
-                      p.t_pos, p.cell_start, kept, longest);
-    list_tally(kept, longest, c.n_max, p.ctl);
-  }
-  if (w == 0 && threadIdx.x == 0)
-    __hip_atomic_store(sync + kGridEpochWord, s_epoch + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Co-resident workgroups of the one-launch rebuild on this device (0 on failure).
-int rebuild_grid_max_groups() {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_rebuild_grid, 256, 0) != hipSuccess) return 0;
-  return std::min(per_cu * cus, (int)kGridMaxGroups);
-}
-
-// The one-launch rebuild, as a cooperative launch of groups workgroups (captured in
-// the step graphs like the other launches of a step).
-hipError_t launch_rebuild_grid(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur, int groups) {
-  SysConst cc = c;
-  SysPtrs pp = p;
-  int cu = cur;
-  void *args[] = {&cc, &pp, &cu};
-  return hipLaunchCooperativeKernel((const void *)k_rebuild_grid, dim3(groups), dim3(256), args, 0, st);
-}
 
 // One launch at the start of srmd_step: the call's trace settings go into the
 // control block, and the dynamic state the call starts from (positions, velocities,

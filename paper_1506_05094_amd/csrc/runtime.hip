@@ -22,9 +22,6 @@ hipError_t launch_step(int tp, int method, int prec, int blocks, int threads, hi
                        const SysPtrs &p, int cur, int tail, size_t lds);
 size_t tail_lds_bytes(const SysConst &c, int threads, int tail);
 size_t arrive_bytes();
-size_t grid_sync_words();
-int rebuild_grid_max_groups();
-hipError_t launch_rebuild_grid(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur, int groups);
 hipError_t launch_force(int tp, int method, int blocks, int threads, hipStream_t st, const SysConst &c,
                         const SysPtrs &p, int cur);
 hipError_t launch_rebuild(hipStream_t st, const SysConst &c, const SysPtrs &p, int cur);
@@ -105,7 +102,6 @@ struct srmd_system {
   int sort_mode = 0, list_mode = 0;  // 0 auto; sort 1 one workgroup / 2 multi-kernel; list 1 wave / 2 thread / 3 cell / 4 all pairs
   int sort_every = 0;                // all-pairs lists: spatial sort at every k-th build (0: never)
   int tail_req = -1;                 // launch chains: step kernel ends the step (1), also builds small systems' lists (2), k_finish (0), automatic (-1)
-  int grid_groups = -1;              // co-resident workgroups of the one-launch rebuild (-1: not yet asked)
   bool sort_pending = false;         // a host-requested rebuild still needs its one-workgroup sort
   int persist_req = 0;               // persistent kernel: 0 off, -1 automatic group count, > 0 groups
   bool persist_set = false;          // persist_req given by the caller (else the tuned choice applies)
@@ -543,7 +539,6 @@ srmd_status prepare(srmd_system *s) {
     s->part_alloc = nparts;
   }
   resolve_persistent(s);
-  if (s->grid_groups < 0) s->grid_groups = rebuild_grid_max_groups();  // outside any stream capture
   drop_graphs(s);
   s->dirty = false;
   return request_rebuild(s);
@@ -553,49 +548,29 @@ srmd_status prepare(srmd_system *s) {
 // The step kernel ends the step itself (its last workgroup runs the reduction,
 // thermostat and record, and a small system's sort) when asked to, when its
 // workgroups are whole waves and when the sort's arrays fit the LDS of a launch.
-// How a launch-chain step ends and rebuilds its list: 0 the separate end-of-step
-// kernel; 1 the step kernel's last workgroup ends the step; 2 as 1 with fewer
-// launches for the rebuild: a small system's wave-builder or all-pairs lists are
-// built at the start of the step kernel (when each wave has at most kBuildPerWave,
-// all pairs kBuildPerWaveAllPairs, particles to build), and a large system's sort
-// and list build run in one gated cooperative launch (wave, thread or cell
-// builder), so a step is one launch or two.
-int step_tail(srmd_system *s) {
+// How a launch-chain step ends and builds its list: 0 the separate end-of-step
+// kernel; 1 the step kernel's last workgroup ends the step; 2 as 1, and a small
+// system's wave-builder or all-pairs lists are built at the start of the step
+// kernel (no list kernel in the chain) when each wave has at most kBuildPerWave
+// (all pairs: kBuildPerWaveAllPairs) particles to build.
+int step_tail(const srmd_system *s) {
   const int threads = s->tp * s->ppb;
   if (s->tail_req == 0 || threads % 64 != 0 || tail_lds_bytes(s->c, threads, 1) > kTailLdsMax) return 0;
   // automatic: not for a small system's grid of more than 256 workgroups, which all
   // end at about the same time and queue on the arrival counters (measured slower)
   if (s->tail_req < 0 && s->c.small_sort && step_blocks(s) > kTailAutoBlocks) return 0;
-  if (s->tail_req == 1) return 1;
-  if (s->c.small_sort) {
-    const int per_wave = s->c.list_kind == 4 ? kBuildPerWaveAllPairs : kBuildPerWave;
-    if ((s->c.list_kind == 1 || s->c.list_kind == 4) && s->ppb <= per_wave * (threads / 64) &&
-        tail_lds_bytes(s->c, threads, 2) <= kTailLdsMax)
-      return 2;
-    return 1;
-  }
-  if (s->c.list_kind < 1 || s->c.list_kind > 3) return 1;
-  if (s->grid_groups < 0) s->grid_groups = rebuild_grid_max_groups();
-  return s->grid_groups > 0 ? 2 : 1;
-}
-
-// The tail argument of the step kernel for a step form.
-int kernel_tail(const srmd_system *s, int form) { return form == 2 ? (s->c.small_sort ? 2 : 1) : form; }
-
-// The start of a launch-chain step in form `form`: the gated rebuild launches.
-hipError_t enqueue_rebuild(srmd_system *s, int cb, int form) {
-  if (form == 2 && s->c.small_sort) return hipSuccess;  // built in the step kernel
-  if (form == 2) {
-    const int need = (int)((s->n + 255) / 256);
-    return launch_rebuild_grid(s->stream, s->c, s->p, cb, std::max(1, std::min(s->grid_groups, need)));
-  }
-  return launch_rebuild(s->stream, s->c, s->p, cb);
+  const int per_wave = s->c.list_kind == 4 ? kBuildPerWaveAllPairs : kBuildPerWave;
+  if (s->tail_req != 1 && s->c.small_sort && (s->c.list_kind == 1 || s->c.list_kind == 4) &&
+      s->ppb <= per_wave * (threads / 64) &&
+      tail_lds_bytes(s->c, threads, 2) <= kTailLdsMax)
+    return 2;
+  return 1;
 }
 
 // Enqueue one launch-chain step on position buffer cb.
 hipError_t enqueue_step(srmd_system *s, int cb) {
-  const int form = step_tail(s), tail = kernel_tail(s, form);
-  hipError_t e = enqueue_rebuild(s, cb, form);
+  const int tail = step_tail(s);
+  hipError_t e = tail == 2 ? hipSuccess : launch_rebuild(s->stream, s->c, s->p, cb);
   if (e == hipSuccess)
     e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, cb,
                     tail, tail ? tail_lds_bytes(s->c, s->tp * s->ppb, tail) : 0);
@@ -694,7 +669,7 @@ srmd_status check_barrier(srmd_system *s, Control *h) {
   h->error &= ~4;
   srmd_status st = h2d_sync(s, s->p.ctl, h, sizeof(Control));
   if (st != SRMD_OK) return st;
-  return fail(s, SRMD_EHIP, "a device-wide barrier timed out (persistent kernel or one-launch rebuild)");
+  return fail(s, SRMD_EHIP, "persistent kernel: a device-wide barrier timed out");
 }
 
 // The descriptor of this system for a persistent launch.
@@ -1242,7 +1217,6 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
   s->p.thermo = (Thermo *)A(sizeof(Thermo));
   s->p.bar_flags = (unsigned *)A(sizeof(unsigned) * 2 * 256);
   s->p.arrive = (unsigned *)A(arrive_bytes());
-  s->p.grid_sync = (unsigned *)A(sizeof(unsigned) * grid_sync_words());
   s->p.tile_count = (unsigned *)A(sizeof(unsigned) * kScanMaxTiles);
   if (prec == SRMD_PREC_F64POS) {
     s->p.pos64 = (double *)A(sizeof(double) * 3 * N);
@@ -1268,7 +1242,6 @@ srmd_status srmd_create(srmd_system **out, int32_t n, int32_t ntypes, const doub
       hipMemsetAsync(s->p.nnb, 0, sizeof(int) * N, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.tile_count, 0, sizeof(unsigned) * kScanMaxTiles, s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.arrive, 0, arrive_bytes(), s->stream) != hipSuccess ||
-      hipMemsetAsync(s->p.grid_sync, 0, sizeof(unsigned) * grid_sync_words(), s->stream) != hipSuccess ||
       hipMemsetAsync(s->p.t_pos, 0, sizeof(float4) * N, s->stream) != hipSuccess) {
     srmd_destroy(s);
     return fail(nullptr, SRMD_EHIP, "initial upload failed");
@@ -2014,8 +1987,8 @@ srmd_status srmd_profile_step_kernel(srmd_system *s, int64_t nsteps, double *ker
   while (done < nsteps && result == SRMD_OK) {
     const int cnt = (int)std::min<long long>(batch, nsteps - done);
     for (int k = 0; k < cnt && result == SRMD_OK; ++k) {
-      const int form = step_tail(s), tail = kernel_tail(s, form);
-      hipError_t e = enqueue_rebuild(s, s->cur, form);
+      const int tail = step_tail(s);
+      hipError_t e = tail == 2 ? hipSuccess : launch_rebuild(s->stream, s->c, s->p, s->cur);
       if (e == hipSuccess) e = hipEventRecord(ev[2 * k], s->stream);
       if (e == hipSuccess)
         e = launch_step(s->tp, kmethod(s), (int)s->prec, step_blocks(s), s->tp * s->ppb, s->stream, s->c, s->p, s->cur,

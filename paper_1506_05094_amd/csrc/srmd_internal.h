@@ -144,7 +144,6 @@ struct SysPtrs {
   Thermo *trace;    // device trace (trace_cap records)
   unsigned *bar_flags;  // arrival words of the persistent kernel's grid barrier (2 x 256)
   unsigned *arrive;     // arrival counters of a step kernel that ends the step itself (0 between launches)
-  unsigned *grid_sync;  // arrival words and launch counter of the one-launch rebuild of a large system
 };
 
 // The call-start copy of a system's dynamic state, put back when a list overflow

@@ -111,31 +111,13 @@ def test_step_form_reported():
     s.close()
 
 
-@pytest.mark.parametrize("launch,list_mode", [((1, 256), 0), ((4, 16), 0), ((1, 256), 1), ((2, 128), 2),
-                                              ((1, 256), 5)])
-def test_fused_equals_separate_large_system(launch, list_mode):
-    """LJ N = 20 000 (no sort in the tail): in form 2 the sort and the list build run
-    in one cooperative launch (wave per cell by default at this size, wave per
-    particle, thread per particle; the row builder keeps its own kernels); at (4, 16)
-    the grid has 1250 blocks, so each stand-in thread of the tail folds two partials."""
-    print(f"fused vs separate: LJ 20000 launch={launch} list mode {list_mode}", flush=True)
+@pytest.mark.parametrize("launch", [(1, 256), (4, 16)])
+def test_fused_equals_separate_large_system(launch):
+    """LJ N = 20 000 (multi-kernel sort, no sort in the tail); at (4, 16) the grid has
+    1250 blocks, so each stand-in thread of the tail folds two partials."""
+    print(f"fused vs separate: LJ 20000 launch={launch}", flush=True)
     st, params, method = _lj(20000, 34)
-    _assert_same(_pair_runs(st, params, method, launch, list_mode=list_mode, steps=120, nvt=False),
-                 f"LJ 20000 {launch} list mode {list_mode}")
-
-
-def test_large_system_step_form():
-    """A large system's default step is two launches (the gated one-launch rebuild and
-    the step kernel) with the wave, thread or cell builder, one launch more with the row
-    builder."""
-    st, (sig, eps, rc), method = _lj(20000, 36)
-    s = make_system(st, sig, eps, rc, method, launch=(1, 256))
-    forms = []
-    for mode in (1, 2, 3, 5):
-        s.set_rebuild_path(0, mode)
-        forms.append(s.stats()["step_form"])
-    assert forms == [2, 2, 2, 1], forms
-    s.close()
+    _assert_same(_pair_runs(st, params, method, launch, steps=120, nvt=False), f"LJ 20000 {launch}")
 
 
 def test_sort_arrays_past_the_lds_limit_fall_back():
