@@ -111,13 +111,17 @@ def test_step_form_reported():
     s.close()
 
 
-@pytest.mark.parametrize("launch", [(1, 256), (4, 16)])
-def test_fused_equals_separate_large_system(launch):
-    """LJ N = 20 000 (multi-kernel sort, no sort in the tail); at (4, 16) the grid has
-    1250 blocks, so each stand-in thread of the tail folds two partials."""
-    print(f"fused vs separate: LJ 20000 launch={launch}", flush=True)
+@pytest.mark.parametrize("launch,list_mode", [((1, 256), 0), ((4, 16), 0), ((1, 256), 1), ((2, 128), 2),
+                                              ((1, 256), 5)])
+def test_fused_equals_separate_large_system(launch, list_mode):
+    """LJ N = 20 000 (multi-kernel sort, no sort in the tail; form 2 falls back to 1)
+    with each list builder of large systems (wave per cell by default at this size,
+    wave per particle, thread per particle, row-staged threads); at (4, 16) the grid
+    has 1250 blocks, so each stand-in thread of the tail folds two partials."""
+    print(f"fused vs separate: LJ 20000 launch={launch} list mode {list_mode}", flush=True)
     st, params, method = _lj(20000, 34)
-    _assert_same(_pair_runs(st, params, method, launch, steps=120, nvt=False), f"LJ 20000 {launch}")
+    _assert_same(_pair_runs(st, params, method, launch, list_mode=list_mode, steps=120, nvt=False),
+                 f"LJ 20000 {launch} list mode {list_mode}")
 
 
 def test_sort_arrays_past_the_lds_limit_fall_back():
