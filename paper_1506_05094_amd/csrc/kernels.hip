@@ -2189,8 +2189,17 @@ __device__ __forceinline__ void fill_positions(float4 *dst, const float4 *src, i
 // from device memory rather than LDS.  Its spatial sort is the four-phase counting
 // sort of the launch chain, run by all pieces at the start of a step that rebuilds,
 // with a grid barrier after each phase.
+// Waves per SIMD the persistent kernel is compiled for: three from 16 lanes per
+// particle up (measured +12 % at KA 4096, 32 bytes of spills), the register count's
+// own two below, where three would spill 150 bytes per lane (the replica batch at
+// t_p = 1 measured 1 % slower).
+template <int TP>
+struct kMultiWaves {
+  static constexpr int value = TP >= 16 ? 3 : 1;
+};
+
 template <int TP, int METHOD, bool BIG>
-__global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__restrict__ reps,
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(kMultiWaves<TP>::value))) void k_multi(const ReplicaDesc *__restrict__ reps,
                                                          const CoopJob *__restrict__ jobs,
                                                          const int *__restrict__ job_off, int nsteps,
                                                          int lds_bytes) {
@@ -2444,7 +2453,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_multi(const ReplicaDesc *__re
             }
           } else {
             unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
-            sort_small_block<kBatchThreads>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+            sort_small_shared(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
           }
         }
         // every piece learns whether the build ahead starts from a re-sort (its
