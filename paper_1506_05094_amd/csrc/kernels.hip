@@ -73,6 +73,10 @@ __device__ __forceinline__ int cell_coord(float x, float halfL, float scale, int
   return (int)f;
 }
 
+// Native 4-vectors, for whole-element copies that stay in registers.
+typedef float raw_f4 __attribute__((ext_vector_type(4)));
+typedef int raw_i4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void cell_coords(const float4 r, const SysConst &c, int &cx, int &cy, int &cz) {
   cx = cell_coord(r.x, c.halfL[0], c.cscale[0], c.nc[0]);
   cy = cell_coord(r.y, c.halfL[1], c.cscale[1], c.nc[1]);
@@ -1759,13 +1763,25 @@ __device__ BlockPartial finish_reduce(const BlockPartial *part, int G, BlockPart
   return a;
 }
 
+// Cell index of a position (the major key of the spatial sort).
+__device__ __forceinline__ int cell_index(const float4 r, const SysConst &c) {
+  int cx, cy, cz;
+  cell_coords(r, c, cx, cy, cz);
+  return (cz * c.nc[1] + cy) * c.nc[0] + cx;
+}
+
 // The spatial sort of sort_small_block (order by cell, then particle id; the same
 // cell starts and gathered arrays) by a workgroup of any size, its working arrays
 // in LDS only: s_cnt (ncell + 1 words) and s_id (n words).  A histogram pass, the
 // exclusive scan (also written to cell_start), a placement pass that moves each
 // cell's cursor past its particles (so that afterwards s_cnt[k] ends cell k), and a
 // rank-and-gather pass; cells are recomputed from the positions in every pass.
+// Each thread takes B particles of a pass at a time, their loads issued together
+// (B / 2 in the gather pass, which loads three arrays), so that a pass over a few
+// thousand particles costs one memory round trip rather than one per particle.
+template <int B>
 __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, unsigned *s_cnt, int *s_id) {
+  constexpr int BG = B > 1 ? B / 2 : 1;
   __shared__ unsigned s_w[16];
   __shared__ unsigned s_carry;
   const int tid = threadIdx.x, nthr = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = (nthr + 63) >> 6;
@@ -1778,10 +1794,15 @@ __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, 
     p.ctl->resorted = 1;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += nthr) {
-    int cx, cy, cz;
-    cell_coords(pos[i], c, cx, cy, cz);
-    atomicAdd(&s_cnt[(cz * c.nc[1] + cy) * c.nc[0] + cx], 1u);
+  // (loads past n are clamped to the last particle and their results unused, so that
+  // every load is issued unconditionally)
+  for (int base = tid; base < n; base += B * nthr) {
+    float4 r[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) r[k] = pos[min(base + k * nthr, n - 1)];
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (base + k * nthr < n) atomicAdd(&s_cnt[cell_index(r[k], c)], 1u);
   }
   __syncthreads();
   for (int base = 0; base <= ncell; base += nthr) {
@@ -1810,34 +1831,56 @@ __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, 
     }
     __syncthreads();
   }
-  for (int i = tid; i < n; i += nthr) {
-    int cx, cy, cz;
-    cell_coords(pos[i], c, cx, cy, cz);
-    const unsigned at = atomicAdd(&s_cnt[(cz * c.nc[1] + cy) * c.nc[0] + cx], 1u);
-    s_id[at] = p.img[i].w;
+  for (int base = tid; base < n; base += B * nthr) {
+    float4 r[B];
+    int id[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int i = min(base + k * nthr, n - 1);
+      r[k] = pos[i];
+      id[k] = p.img[i].w;
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k)
+      if (base + k * nthr < n) s_id[atomicAdd(&s_cnt[cell_index(r[k], c)], 1u)] = id[k];
   }
   __syncthreads();
-  for (int i = tid; i < n; i += nthr) {
-    const float4 r = pos[i];
-    const int id = p.img[i].w;
-    int cx, cy, cz;
-    cell_coords(r, c, cx, cy, cz);
-    const int cell = (cz * c.nc[1] + cy) * c.nc[0] + cx;
-    const unsigned beg = cell > 0 ? s_cnt[cell - 1] : 0u, end = s_cnt[cell];
-    unsigned rank = 0;
-    for (unsigned q = beg; q < end; ++q) rank += (s_id[q] < id) ? 1u : 0u;
-    const unsigned dst = beg + rank;
-    p.t_pos[dst] = r;
-    p.t_vel[dst] = p.vel[i];
-    p.t_img[dst] = p.img[i];
-    if (p.pos64) {
-      p.t_pos64[3 * dst] = p.pos64[3 * i];
-      p.t_pos64[3 * dst + 1] = p.pos64[3 * i + 1];
-      p.t_pos64[3 * dst + 2] = p.pos64[3 * i + 2];
+  for (int base = tid; base < n; base += BG * nthr) {
+    float4 r[BG];
+    raw_f4 v[BG];
+    raw_i4 im[BG];
+#pragma unroll
+    for (int k = 0; k < BG; ++k) {
+      const int i = min(base + k * nthr, n - 1);
+      r[k] = pos[i];
+      im[k] = reinterpret_cast<const raw_i4 *>(p.img)[i];
+      v[k] = reinterpret_cast<const raw_f4 *>(p.vel)[i];
     }
-    if (p.kahan) p.t_kahan[dst] = p.kahan[i];
+#pragma unroll
+    for (int k = 0; k < BG; ++k) {
+      const int i = base + k * nthr;
+      if (i < n) {
+        const int cell = cell_index(r[k], c);
+        const unsigned beg = cell > 0 ? s_cnt[cell - 1] : 0u, end = s_cnt[cell];
+        unsigned rank = 0;
+        for (unsigned q = beg; q < end; ++q) rank += (s_id[q] < im[k].w) ? 1u : 0u;
+        const unsigned dst = beg + rank;
+        p.t_pos[dst] = r[k];
+        reinterpret_cast<raw_f4 *>(p.t_vel)[dst] = v[k];
+        reinterpret_cast<raw_i4 *>(p.t_img)[dst] = im[k];
+        if (p.pos64) {
+          p.t_pos64[3 * dst] = p.pos64[3 * i];
+          p.t_pos64[3 * dst + 1] = p.pos64[3 * i + 1];
+          p.t_pos64[3 * dst + 2] = p.pos64[3 * i + 2];
+        }
+        if (p.kahan) p.t_kahan[dst] = p.kahan[i];
+      }
+    }
   }
 }
+
+// Particles per thread whose loads the end-of-step sort issues together.
+constexpr int kTailSortBatch = 8;
 
 // LDS bytes of sort_small_shared for n particles in ncell cells.
 __host__ __device__ constexpr size_t tail_sort_lds(int n, int ncell) { return 4 * ((size_t)ncell + 1 + (size_t)n); }
@@ -1863,7 +1906,7 @@ __device__ void step_tail(const SysConst &c, const SysPtrs &p, int G, int next, 
         p.ctl->resorted = 0;
       }
     } else {
-      sort_small_shared(c, p, next, s_dyn, reinterpret_cast<int *>(s_dyn + c.ncell + 1));
+      sort_small_shared<kTailSortBatch>(c, p, next, s_dyn, reinterpret_cast<int *>(s_dyn + c.ncell + 1));
     }
   }
 }
@@ -1886,6 +1929,10 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, i
   // step then reads positions from the sorted copy, which the other workgroups may
   // not have placed yet
   const int build = tail == 2 ? p.ctl->rebuild : 0;
+  // the friction of the step, read before the list build: the build's tallies are
+  // atomics on the same control line from every workgroup, and a load queued behind
+  // them waits several microseconds
+  const double xi = c.thermostat ? p.ctl->xi : 0.0;
   if (build && threadIdx.x < kMaxPairs) s_cs2[threadIdx.x] = c.pt.cs2[threadIdx.x];
   __syncthreads();
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -1922,7 +1969,6 @@ __global__ __launch_bounds__(1024) void k_step(SysConst c, SysPtrs p, int cur, i
   float4 vo = pi, l0 = pi, kc = pi;
   int4 im = make_int4(0, 0, 0, 0);
   double x64 = 0.0, y64 = 0.0, z64 = 0.0;
-  const double xi = c.thermostat ? p.ctl->xi : 0.0;
   if (active) {
     pi = pos[i];
     if (t == 0) {
@@ -2061,9 +2107,6 @@ template <class T>
 __device__ __forceinline__ const SRMD_GLOBAL T *global_view(const T *q) {
   return (const SRMD_GLOBAL T *)q;
 }
-
-typedef float raw_f4 __attribute__((ext_vector_type(4)));
-typedef int raw_i4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float4 gload(const float4 *q, int i) {
   const raw_f4 v = ((const SRMD_GLOBAL raw_f4 *)q)[i];
@@ -2453,7 +2496,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(k
             }
           } else {
             unsigned *scnt = reinterpret_cast<unsigned *>(s_dyn);
-            sort_small_shared(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
+            sort_small_shared<1>(c, p, cur, scnt, reinterpret_cast<int *>(scnt + kSmallCells + 1));
           }
         }
         // every piece learns whether the build ahead starts from a re-sort (its
