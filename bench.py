@@ -421,7 +421,7 @@ def main():
                          "list method within 20 %% of the fastest, and the tuned-parameter file of --tune-cache")
     ap.add_argument("--tune-cache", default=None, help="tuned-parameter file of --tune-full (default: none)")
     ap.add_argument("--sizes", default="1000,4000,16000,64000,256000,1024000", help="N values of the size sweep")
-    ap.add_argument("--tune-steps", type=int, default=300, help="steps per autotuner trial (size sweep, --tune)")
+    ap.add_argument("--tune-steps", type=int, default=1000, help="steps per autotuner trial (size sweep, --tune)")
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--baseline-steps", type=int, default=200,
                     help="steps per system of each one-system-per-launch form in the replica comparison")

@@ -266,7 +266,9 @@ srmd_status srmd_get_launch(const srmd_system *s, int32_t *tp, int32_t *ppb);
 /* Choose tp and ppb by timing short runs from a saved copy of the current state
  * (paper appendix: each trial starts from the same stored configuration): phase I
  * the list-build method at the default layout, phase II block size x tp with the
- * appendix's stop rules, and for systems the persistent kernel can run (see
+ * appendix's stop rules for every method within 5 % of phase I's fastest (two
+ * methods that close can change places at another layout), and for systems the
+ * persistent kernel can run (see
  * srmd_set_persistent) a phase III over tp in persistent mode.  The fastest
  * layout, list method and mode become the system's defaults; an explicit
  * srmd_set_launch / srmd_set_rebuild_path / srmd_set_persistent still wins.  The

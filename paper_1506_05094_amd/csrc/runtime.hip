@@ -68,6 +68,7 @@ constexpr size_t kTailLdsMax = 60 * 1024;  // dynamic LDS of a step kernel that 
 constexpr int kTailAutoBlocks = 256;       // largest small-system grid that ends its steps itself by default
 constexpr int kBuildPerWave = 8;          // most particles a wave of the step kernel builds the lists of
 constexpr int kBuildPerWaveAllPairs = 2;  // the same with all-pairs lists (N candidates each: measured slower at 4 and 8)
+constexpr double kTunerListKeep = 1.05;   // list methods within 5 % of the fastest at the default layout go on to phase II
 constexpr int kPersistChunk = 500;  // steps per launch of the persistent kernel (even)
 
 }  // namespace
@@ -2089,11 +2090,14 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   int dtp, dppb;
   s->tp_req = s->ppb_req = 0;
   launch_of(s, &dtp, &dppb);
+  double phase1[6] = {1e300, 1e300, 1e300, 1e300, 1e300, 1e300};
   for (int lm = 1; lm <= 5 && result == SRMD_OK; ++lm) {
     if (lm == 4 && !s->c.small_sort) continue;  // all pairs: small systems only
     double t;
     result = trial(dtp, dppb, lm, false, &t);
-    if (result == SRMD_OK && t < best) {
+    if (result != SRMD_OK) break;
+    phase1[lm] = t;
+    if (t < best) {
       best = t;
       best_tp = dtp;
       best_ppb = dppb;
@@ -2102,33 +2106,40 @@ srmd_status srmd_autotune(srmd_system *s, int32_t steps_per_trial, int32_t *tp_o
   }
   // Phase II: block size x threads per particle (paper appendix, step 4), with its stop
   // rules: leave the t_p loop after 3 slower trials in a row or one more than 5% slower,
-  // and the block loop once a block size ends more than 10% slower than the best
+  // and the block loop once a block size ends more than 10% slower than the best.  It
+  // runs for every list method within kTunerListKeep of the fastest at the default
+  // layout, as two methods that close can change places at another layout.
   const int blocks[] = {64, 128, 256, 512, 1024};
   const int tp_max = n > 100000 ? 2 : 64;  // size pruning: large systems only need t_p = 1, 2
-  double prev_block_best = 1e300;
-  for (int bi = 0; bi < 5 && result == SRMD_OK; ++bi) {
-    const int bsz = blocks[bi];
-    double block_best = 1e300;
-    int slower = 0;
-    for (int tp = 1; tp <= tp_max && tp <= bsz && result == SRMD_OK; tp <<= 1) {
-      double t;
-      result = trial(tp, bsz / tp, best_list, false, &t);
-      if (result != SRMD_OK) break;
-      if (t < block_best) {
-        block_best = t;
-        slower = 0;
-      } else {
-        ++slower;
+  const double phase1_best = best;
+  for (int lm = 1; lm <= 5 && result == SRMD_OK; ++lm) {
+    if (!(phase1[lm] <= kTunerListKeep * phase1_best)) continue;
+    double prev_block_best = 1e300;
+    for (int bi = 0; bi < 5 && result == SRMD_OK; ++bi) {
+      const int bsz = blocks[bi];
+      double block_best = 1e300;
+      int slower = 0;
+      for (int tp = 1; tp <= tp_max && tp <= bsz && result == SRMD_OK; tp <<= 1) {
+        double t;
+        result = trial(tp, bsz / tp, lm, false, &t);
+        if (result != SRMD_OK) break;
+        if (t < block_best) {
+          block_best = t;
+          slower = 0;
+        } else {
+          ++slower;
+        }
+        if (t < best) {
+          best = t;
+          best_tp = tp;
+          best_ppb = bsz / tp;
+          best_list = lm;
+        }
+        if (slower >= 3 || t > 1.05 * block_best) break;
       }
-      if (t < best) {
-        best = t;
-        best_tp = tp;
-        best_ppb = bsz / tp;
-      }
-      if (slower >= 3 || t > 1.05 * block_best) break;
+      if (block_best > 1.10 * std::min(best, prev_block_best) && bi > 0) break;
+      prev_block_best = std::min(prev_block_best, block_best);
     }
-    if (block_best > 1.10 * std::min(best, prev_block_best) && bi > 0) break;
-    prev_block_best = std::min(prev_block_best, block_best);
   }
   // Phase III (MI355X): the persistent kernel, t_p at 256-thread virtual blocks,
   // with the t_p stop rule of phase II (tp values it cannot run end the phase)
