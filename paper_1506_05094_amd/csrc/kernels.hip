@@ -460,34 +460,73 @@ __device__ __forceinline__ float lane_sum(float v) {
   return v;
 }
 
+// Wave-wide reductions by DPP lane swizzles (VALU operand exchanges, no LDS round
+// trip as in a shuffle).  Within each 16-lane row: the quad exchanges lane ^ 1 and
+// lane ^ 2, the half-row mirror (lane i with 7 - i of its 8) and the row mirror
+// (i with 15 - i), each pairing two disjoint halves, so that every lane of a row
+// ends with the row's total, bitwise the same in all 16 (each step combines the
+// same two values in either order).  Then lane 15 of rows 0 and 2 is combined into
+// rows 1 and 3, and lane 31 into rows 2 and 3, so lane 63 holds
+// (row 3 + row 2) + (row 1 + row 0), which is read back to every lane.  Lanes of the
+// rows a broadcast does not reach combine with the identity.  The whole wave must
+// be active.
+constexpr int kDppXor1 = 0xB1;        // quad_perm [1, 0, 3, 2]
+constexpr int kDppXor2 = 0x4E;        // quad_perm [2, 3, 0, 1]
+constexpr int kDppMirror = 0x140;     // row_mirror
+constexpr int kDppHalfMirror = 0x141; // row_half_mirror
+constexpr int kDppBcast15 = 0x142;    // row_bcast:15
+constexpr int kDppBcast31 = 0x143;    // row_bcast:31
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned dpp32(unsigned old, unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long old, unsigned long long v) {
+  const unsigned lo = dpp32<CTRL, ROWS>((unsigned)old, (unsigned)v);
+  const unsigned hi = dpp32<CTRL, ROWS>((unsigned)(old >> 32), (unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+template <class Op>
+__device__ __forceinline__ unsigned long long wave_reduce64(unsigned long long v, unsigned long long id, Op op) {
+  v = op(v, dpp64<kDppXor1, 0xF>(id, v));
+  v = op(v, dpp64<kDppXor2, 0xF>(id, v));
+  v = op(v, dpp64<kDppHalfMirror, 0xF>(id, v));
+  v = op(v, dpp64<kDppMirror, 0xF>(id, v));
+  v = op(v, dpp64<kDppBcast15, 0xA>(id, v));
+  v = op(v, dpp64<kDppBcast31, 0xC>(id, v));
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double bits_f64(unsigned long long b) { return __longlong_as_double((long long)b); }
+__device__ __forceinline__ unsigned long long f64_bits(double d) { return (unsigned long long)__double_as_longlong(d); }
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  return bits_f64(wave_reduce64(f64_bits(v), f64_bits(0.0), [](unsigned long long a, unsigned long long b) {
+    return f64_bits(bits_f64(a) + bits_f64(b));
+  }));
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  return bits_f64(wave_reduce64(f64_bits(v), f64_bits(-__builtin_inf()), [](unsigned long long a, unsigned long long b) {
+    return f64_bits(fmax(bits_f64(a), bits_f64(b)));
+  }));
 }
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long y = __shfl_xor(v, o, 64);
-    v = y < v ? y : v;
-  }
-  return v;
+  return wave_reduce64(v, ~0ull, [](unsigned long long a, unsigned long long b) { return b < a ? b : a; });
 }
 
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long y = __shfl_xor(v, o, 64);
-    v = y > v ? y : v;
-  }
-  return v;
+  return wave_reduce64(v, 0ull, [](unsigned long long a, unsigned long long b) { return b > a ? b : a; });
+}
+
+__device__ __forceinline__ int wave_or(int v) {
+  return (int)wave_reduce64((unsigned)v, 0ull, [](unsigned long long a, unsigned long long b) { return a | b; });
 }
 
 // Reduction of one BlockPartial over groups of `group` threads (a multiple of 64):
@@ -506,10 +545,7 @@ __device__ void group_reduce(BlockPartial &v, BlockPartial *s_waves, int group, 
   v.disp2 = wave_max(v.disp2);
   v.t0 = wave_min_u64(v.t0);
   v.t1 = wave_max_u64(v.t1);
-  int bad = v.nonfinite;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
-  v.nonfinite = bad;
+  v.nonfinite = wave_or(v.nonfinite);
   if (lane == 0) s_waves[wv] = v;
   __syncthreads();
   if ((threadIdx.x % group) == 0) {
@@ -1748,10 +1784,7 @@ __device__ BlockPartial finish_reduce(const BlockPartial *part, int G, BlockPart
     a.disp2 = wave_max(a.disp2);
     a.t0 = wave_min_u64(a.t0);
     a.t1 = wave_max_u64(a.t1);
-    int bad = a.nonfinite;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
-    a.nonfinite = bad;
+    a.nonfinite = wave_or(a.nonfinite);
     if (lane == 0) s_waves[vw] = a;
   }
   __syncthreads();
@@ -2082,10 +2115,7 @@ __device__ __forceinline__ void wave_reduce(BlockPartial &v) {
   v.ke_half = wave_sum(v.ke_half);
   v.ke_int = wave_sum(v.ke_int);
   v.disp2 = wave_max(v.disp2);
-  int bad = v.nonfinite;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
-  v.nonfinite = bad;
+  v.nonfinite = wave_or(v.nonfinite);
 }
 
 // a += q with the operations of the block and k_finish reductions.
