@@ -453,11 +453,45 @@ struct StepBatch {
   static constexpr int value = Batch<TP>::value > 8 ? 8 : Batch<TP>::value;
 };
 
-template <int TP>
+// The value of lane (this lane) ^ O, O a power of two below 64, by VALU lane
+// exchanges: quad permutations for 1 and 2, two bank-masked row shifts for 4, a
+// row rotation for 8, and the row and half-wave swaps of gfx950 for 16 and 32.
+template <int O>
+__device__ __forceinline__ unsigned xor_lane(unsigned v) {
+  if constexpr (O == 1) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1, 0, 3, 2]
+  } else if constexpr (O == 2) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2, 3, 0, 1]
+  } else if constexpr (O == 4) {
+    // lanes 0-3 and 8-11 of a row read lane + 4 (row_shl:4), lanes 4-7 and 12-15 lane - 4 (row_shr:4)
+    const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x104, 0xF, 0x5, false);
+    return (unsigned)__builtin_amdgcn_update_dpp(t, (int)v, 0x114, 0xF, 0xA, false);
+  } else if constexpr (O == 8) {
+    return (unsigned)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+  } else if constexpr (O == 16) {
+    const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);  // odd rows <-> even rows
+    return ((threadIdx.x >> 4) & 1) ? r[0] : r[1];
+  } else {
+    static_assert(O == 32, "xor_lane: O must be 1, 2, 4, 8, 16 or 32");
+    const auto r = __builtin_amdgcn_permlane32_swap(v, v, false, false);  // upper half <-> lower half
+    return ((threadIdx.x >> 5) & 1) ? r[0] : r[1];
+  }
+}
+
+template <int O>
+__device__ __forceinline__ float xor_lane(float v) {
+  return __uint_as_float(xor_lane<O>(__float_as_uint(v)));
+}
+
+// Sum over the TP lanes of a particle: the butterfly lane ^ TP/2, ..., lane ^ 1 (the
+// whole wave must be active).
+template <int TP, int O = TP / 2>
 __device__ __forceinline__ float lane_sum(float v) {
-#pragma unroll
-  for (int o = TP / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, TP);
-  return v;
+  if constexpr (O == 0) {
+    return v;
+  } else {
+    return lane_sum<TP, O / 2>(v + xor_lane<O>(v));
+  }
 }
 
 // Wave-wide reductions by DPP lane swizzles (VALU operand exchanges, no LDS round
