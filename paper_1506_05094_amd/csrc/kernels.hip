@@ -563,6 +563,21 @@ __device__ __forceinline__ int wave_or(int v) {
   return (int)wave_reduce64((unsigned)v, 0ull, [](unsigned long long a, unsigned long long b) { return a | b; });
 }
 
+// Inclusive prefix sum over the lanes of a wave, exact for integers: within each row
+// the shifted copies by 1, 2 and 3 lanes, then the partial sums shifted by 4 (into
+// the upper three banks of 4 lanes) and by 8 (into the upper two), then the row
+// totals by the broadcasts of lanes 15 and 31.  The whole wave must be active.
+__device__ __forceinline__ unsigned wave_incl_scan(unsigned v) {
+  unsigned t = v + (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  t += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);             // row_shr:2
+  t += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x113, 0xF, 0xF, false);             // row_shr:3
+  t += (unsigned)__builtin_amdgcn_update_dpp(0, (int)t, 0x114, 0xF, 0xE, false);             // row_shr:4
+  t += (unsigned)__builtin_amdgcn_update_dpp(0, (int)t, 0x118, 0xF, 0xC, false);             // row_shr:8
+  t += (unsigned)__builtin_amdgcn_update_dpp(0, (int)t, kDppBcast15, 0xA, 0xF, false);
+  t += (unsigned)__builtin_amdgcn_update_dpp(0, (int)t, kDppBcast31, 0xC, 0xF, false);
+  return t;
+}
+
 // Reduction of one BlockPartial over groups of `group` threads (a multiple of 64):
 // lanes by butterfly, then the group's waves in index order; the result is valid
 // in the first thread of each group.  Every thread of the block must call it.
@@ -998,14 +1013,9 @@ __device__ __forceinline__ void stencil_runs(const SysConst &c, int cx, int cy, 
       run_len = s1 - s0;
     }
   }
-  unsigned incl = run_len;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const unsigned y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
+  const unsigned incl = wave_incl_scan(run_len);
   excl = incl - run_len;
-  total = __shfl(incl, 63, 64);
+  total = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
 }
 
 // Verlet list of particle t (sorted slot), one wave per particle; for small systems,
@@ -1845,7 +1855,9 @@ __device__ __forceinline__ int cell_index(const float4 r, const SysConst &c) {
 // rank-and-gather pass; cells are recomputed from the positions in every pass.
 // Each thread takes B particles of a pass at a time, their loads issued together
 // (B / 2 in the gather pass, which loads three arrays), so that a pass over a few
-// thousand particles costs one memory round trip rather than one per particle.
+// thousand particles costs one memory round trip rather than one per particle; when
+// all particles fit one such batch, the placement works from registers instead
+// (below).  The scan's per-wave prefix sums are DPP lane shifts.
 template <int B>
 __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, unsigned *s_cnt, int *s_id) {
   constexpr int BG = B > 1 ? B / 2 : 1;
@@ -1861,26 +1873,37 @@ __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, 
     p.ctl->resorted = 1;
   }
   __syncthreads();
+  // When each thread has at most B particles (one batch), their cells, ids and slots
+  // within their cells (the histogram counter before their increment) stay in
+  // registers, and the placement needs neither the positions again nor a second
+  // atomic: particle k goes to start(cell) + slot.  key = cell << 13 | slot (cells
+  // and slots below 8192, as N <= 8192).
+  const bool one = B > 1 && n <= B * nthr;
+  unsigned key[B];
+  int idr[B];
   // (loads past n are clamped to the last particle and their results unused, so that
   // every load is issued unconditionally)
   for (int base = tid; base < n; base += B * nthr) {
     float4 r[B];
 #pragma unroll
-    for (int k = 0; k < B; ++k) r[k] = pos[min(base + k * nthr, n - 1)];
+    for (int k = 0; k < B; ++k) {
+      const int i = min(base + k * nthr, n - 1);
+      r[k] = pos[i];
+      if (one) idr[k] = p.img[i].w;
+    }
 #pragma unroll
     for (int k = 0; k < B; ++k)
-      if (base + k * nthr < n) atomicAdd(&s_cnt[cell_index(r[k], c)], 1u);
+      if (base + k * nthr < n) {
+        const unsigned cell = (unsigned)cell_index(r[k], c);
+        const unsigned slot = atomicAdd(&s_cnt[cell], 1u);
+        if (one) key[k] = cell << 13 | slot;
+      }
   }
   __syncthreads();
   for (int base = 0; base <= ncell; base += nthr) {
     const int idx = base + tid;
     const unsigned v = idx <= ncell ? s_cnt[idx] : 0u;
-    unsigned x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const unsigned y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
-    }
+    const unsigned x = wave_incl_scan(v);
     if (lane == 63 || tid == nthr - 1) s_w[wv] = x;
     __syncthreads();
     unsigned wbase = 0;
@@ -1898,18 +1921,25 @@ __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, 
     }
     __syncthreads();
   }
-  for (int base = tid; base < n; base += B * nthr) {
-    float4 r[B];
-    int id[B];
-#pragma unroll
-    for (int k = 0; k < B; ++k) {
-      const int i = min(base + k * nthr, n - 1);
-      r[k] = pos[i];
-      id[k] = p.img[i].w;
-    }
+  if (one) {
+    // s_cnt holds the cell starts (and s_cnt[ncell] = n)
 #pragma unroll
     for (int k = 0; k < B; ++k)
-      if (base + k * nthr < n) s_id[atomicAdd(&s_cnt[cell_index(r[k], c)], 1u)] = id[k];
+      if (tid + k * nthr < n) s_id[s_cnt[key[k] >> 13] + (key[k] & 8191u)] = idr[k];
+  } else {
+    for (int base = tid; base < n; base += B * nthr) {
+      float4 r[B];
+      int id[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int i = min(base + k * nthr, n - 1);
+        r[k] = pos[i];
+        id[k] = p.img[i].w;
+      }
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+        if (base + k * nthr < n) s_id[atomicAdd(&s_cnt[cell_index(r[k], c)], 1u)] = id[k];
+    }
   }
   __syncthreads();
   for (int base = tid; base < n; base += BG * nthr) {
@@ -1928,7 +1958,9 @@ __device__ void sort_small_shared(const SysConst &c, const SysPtrs &p, int cur, 
       const int i = base + k * nthr;
       if (i < n) {
         const int cell = cell_index(r[k], c);
-        const unsigned beg = cell > 0 ? s_cnt[cell - 1] : 0u, end = s_cnt[cell];
+        // cell bounds: starts (one batch) or the cursors moved to the cells' ends
+        const unsigned beg = one ? s_cnt[cell] : cell > 0 ? s_cnt[cell - 1] : 0u;
+        const unsigned end = one ? s_cnt[cell + 1] : s_cnt[cell];
         unsigned rank = 0;
         for (unsigned q = beg; q < end; ++q) rank += (s_id[q] < im[k].w) ? 1u : 0u;
         const unsigned dst = beg + rank;
