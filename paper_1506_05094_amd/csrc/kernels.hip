@@ -1168,7 +1168,7 @@ __global__ __launch_bounds__(256) void k_list_wave(SysConst c, SysPtrs p, int cu
   list_tally(kept, longest, c.n_max, p.ctl);  // every thread of the block reaches this barrier once
 }
 
-constexpr int kThreadBatch = 16;  // candidate positions in flight per thread
+constexpr int kThreadBatch = 10;  // candidate positions in flight per thread (measured best of 8-24)
 constexpr int kRing = 32;         // list slots per lane staged in LDS
 
 __device__ __forceinline__ int wave_min_int(int v) {
